@@ -1,0 +1,220 @@
+"""Function trees of the oracle (test infrastructure only).
+
+  * keys: level << 57 | morton(lx, ly, lz) with x in bit 0 of each bit triple; trees are arrays
+    of nodes sorted by key (level-major, then Morton order).
+  * project_gaussians: Alg. 1 (adaptive function decomposition) for a Gaussian-sum source,
+    level by level from the coarse scale j0; a box is refined when, for any of its 8 children,
+    the values interpolated from the box's coefficients differ from direct values at the child's
+    Gauss-Legendre nodes by more than the threshold in the max norm; boxes at jmax are leaves.
+    A leaf keeps its own coefficients (eq. fvals2coefs in 3-D).
+  * redundant tree (Sec. 2.2.1): every ancestor of a leaf is stored too, with coefficients
+    obtained bottom-up by the decomposition s^j_l = H0 s^{j+1}_{2l} + H1 s^{j+1}_{2l+1} applied
+    along each of the three dimensions (App. A.3, eq. decomp_scaling).
+  * evaluate: f(x) = 2^{3j/2} sum s_abc phi_a(2^j x - l1) phi_b(.) phi_c(.) on the leaf holding x
+    (App. A.1, eqs. func_interp_1d/2d in 3-D); a point on a face belongs to the box with
+    floor(2^j x) clamped to 2^j - 1.
+Readings: the refinement threshold is eps * ||f||_2 with the closed-form L2 norm of the
+Gaussian sum over R^3 (the paper's absolute eps on a function scaled to unit norm); sources are
+unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2).
+"""
+import ctypes
+import numpy as np
+
+from . import mra
+from ._native import lib
+
+__all__ = ["make_keys", "decode_keys", "children_keys", "source_norm", "project_gaussians",
+           "redundant_tree", "compress", "upsample", "evaluate", "uniform_leaves", "Tree"]
+
+
+def _spread3(v):
+    v = np.asarray(v, dtype=np.uint64)
+    r = np.zeros_like(v)
+    for i in range(19):
+        r |= ((v >> np.uint64(i)) & np.uint64(1)) << np.uint64(3 * i)
+    return r
+
+
+def _compact3(v):
+    v = np.asarray(v, dtype=np.uint64)
+    r = np.zeros_like(v)
+    for i in range(19):
+        r |= ((v >> np.uint64(3 * i)) & np.uint64(1)) << np.uint64(i)
+    return r
+
+
+def make_keys(j, lx, ly, lz):
+    j = np.asarray(j, dtype=np.uint64)
+    return (j << np.uint64(57)) | _spread3(lx) | (_spread3(ly) << np.uint64(1)) | (_spread3(lz) << np.uint64(2))
+
+
+def decode_keys(keys):
+    keys = np.asarray(keys, dtype=np.uint64)
+    m = keys & np.uint64((1 << 57) - 1)
+    j = (keys >> np.uint64(57)).astype(np.int64)
+    l = np.stack([_compact3(m), _compact3(m >> np.uint64(1)), _compact3(m >> np.uint64(2))], axis=-1).astype(np.int64)
+    return j, l
+
+
+def children_keys(keys):
+    """The 8 children of each key, child s = sx + 2 sy + 4 sz in Morton order."""
+    j, l = decode_keys(keys)
+    out = []
+    for s in range(8):
+        sx, sy, sz = s & 1, (s >> 1) & 1, (s >> 2) & 1
+        out.append(make_keys(j + 1, 2 * l[:, 0] + sx, 2 * l[:, 1] + sy, 2 * l[:, 2] + sz))
+    return np.stack(out, axis=1).ravel()
+
+
+def source_norm(xyz, a, c):
+    """||f||_2 over R^3 of f = sum_i c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2) (closed form)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    a = np.asarray(a, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    tot = 0.0
+    for i in range(a.size):
+        for q in range(a.size):
+            s = a[i] + a[q]
+            d2 = np.sum((xyz[i] - xyz[q]) ** 2)
+            tot += c[i] * c[q] * (a[i] * a[q] / np.pi ** 2) ** 1.5 * (np.pi / s) ** 1.5 * np.exp(-a[i] * a[q] * d2 / s)
+    return float(np.sqrt(tot))
+
+
+class Tree:
+    """Redundant tree: keys (sorted), leaf flags and coefficient blocks [N, k, k, k]."""
+
+    def __init__(self, k, keys, leaf, coef):
+        self.k = k
+        self.keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        self.leaf = np.ascontiguousarray(leaf, dtype=np.uint8)
+        self.coef = np.ascontiguousarray(coef, dtype=np.float64)
+        self.level, self.l = decode_keys(self.keys)
+
+    @property
+    def depth(self):
+        return int(self.level.max())
+
+    def index(self, keys):
+        keys = np.asarray(keys, dtype=np.uint64)
+        pos = np.searchsorted(self.keys, keys)
+        pos = np.minimum(pos, self.keys.size - 1)
+        return np.where(self.keys[pos] == keys, pos, -1)
+
+
+def project_gaussians(k, eps, j0, jmax, xyz, a, c, with_margins=False):
+    """Alg. 1 for f = sum_i c_i (a_i/pi)^{3/2} exp(-a_i |x-x_i|^2).  Returns (leaf_keys, leaf_coef)
+    sorted by key, and optionally the list of (err, thr) of every test made."""
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    cf = np.ascontiguousarray(np.asarray(c, dtype=np.float64) * (a / np.pi) ** 1.5)
+    thr = eps * source_norm(xyz, a, c)
+    gx, gw = mra.gauss_legendre01(k)
+    n0 = 1 << j0
+    lz, ly, lx = np.meshgrid(np.arange(n0), np.arange(n0), np.arange(n0), indexing="ij")
+    cand = np.sort(make_keys(np.full(lx.size, j0), lx.ravel(), ly.ravel(), lz.ravel()))
+    leaf_keys, leaf_coef, margins = [], [], []
+    L = lib()
+    j = j0
+    while cand.size:
+        n = cand.size
+        s = np.zeros((n, k, k, k))
+        ref = np.zeros(n, dtype=np.uint8)
+        err = np.zeros(n)
+        st = L.orc_project_level(k, j, jmax, n, cand.ctypes.data, a.size, xyz.ctypes.data, a.ctypes.data,
+                                 cf.ctypes.data, thr, gx.ctypes.data, gw.ctypes.data, s.ctypes.data,
+                                 ref.ctypes.data, err.ctypes.data)
+        assert st == 0
+        if j < jmax:
+            margins.append(err)
+        keep = ref == 0
+        leaf_keys.append(cand[keep])
+        leaf_coef.append(s[keep])
+        cand = children_keys(cand[ref == 1])          # parents sorted -> children sorted
+        j += 1
+    keys = np.concatenate(leaf_keys)
+    coef = np.concatenate(leaf_coef)
+    order = np.argsort(keys, kind="stable")
+    out = (keys[order], coef[order])
+    if with_margins:
+        return out + ((np.concatenate(margins) if margins else np.zeros(0), thr),)
+    return out
+
+
+def uniform_leaves(k, n, func_coef=None):
+    """Keys of the uniform tree at level n (all 8^n boxes, sorted)."""
+    m = 1 << n
+    lz, ly, lx = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    return np.sort(make_keys(np.full(lx.size, n), lx.ravel(), ly.ravel(), lz.ravel()))
+
+
+def _apply_sep(A1, A2, A3, x):
+    """(A1 (x) A2 (x) A3) applied to blocks x[..., a, b, c]."""
+    return np.einsum("ia,jb,kc,...abc->...ijk", A1, A2, A3, x)
+
+
+def compress(k, child_coef):
+    """Parent block from its 8 children (child s = sx + 2 sy + 4 sz): eq. decomp_scaling per dim."""
+    H = mra.two_scale_filters(k)
+    out = 0.0
+    for s in range(8):
+        out = out + _apply_sep(H[s & 1], H[(s >> 1) & 1], H[(s >> 2) & 1], child_coef[..., s, :, :, :])
+    return out
+
+
+def upsample(k, parent_coef):
+    """The 8 children of a block with zero details: child_s = (H^{sx}T (x) H^{sy}T (x) H^{sz}T) parent."""
+    H = mra.two_scale_filters(k)
+    return np.stack([_apply_sep(H[s & 1].T, H[(s >> 1) & 1].T, H[(s >> 2) & 1].T, parent_coef)
+                     for s in range(8)], axis=-4)
+
+
+def redundant_tree(k, leaf_keys, leaf_coef):
+    """Redundant tree from the leaves (Sec. 2.2.1): all ancestors are added and their blocks are
+    computed bottom-up with compress()."""
+    leaf_keys = np.asarray(leaf_keys, dtype=np.uint64)
+    j, l = decode_keys(leaf_keys)
+    allk = [leaf_keys]
+    for lev in range(int(j.max()), 0, -1):
+        sel = j >= lev
+        anc_j = np.minimum(j[sel], lev) - 1
+        sh = (j[sel] - anc_j)[:, None]
+        anc = make_keys(anc_j, *(l[sel] >> sh).T)
+        allk.append(anc)
+    keys = np.unique(np.concatenate(allk))
+    N = keys.size
+    leaf = np.zeros(N, dtype=np.uint8)
+    coef = np.zeros((N, k, k, k))
+    pos = np.searchsorted(keys, leaf_keys)
+    leaf[pos] = 1
+    coef[pos] = leaf_coef
+    lev, _ = decode_keys(keys)
+    for lv in range(int(lev.max()) - 1, -1, -1):
+        internal = np.nonzero((lev == lv) & (leaf == 0))[0]
+        if internal.size == 0:
+            continue
+        ch = np.searchsorted(keys, children_keys(keys[internal])).reshape(-1, 8)
+        coef[internal] = compress(k, coef[ch])
+    return Tree(k, keys, leaf, coef)
+
+
+def evaluate(tree, pts):
+    """f at points (P, 3) in [0,1]^3 from the leaf blocks (App. A.1, eq. func_interp in 3-D)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    k = tree.k
+    out = np.full(pts.shape[0], np.nan)
+    todo = np.arange(pts.shape[0])
+    for j in range(tree.depth + 1):
+        if todo.size == 0:
+            break
+        side = 1 << j
+        l = np.minimum(np.floor(pts[todo] * side).astype(np.int64), side - 1)
+        idx = tree.index(make_keys(np.full(todo.size, j), l[:, 0], l[:, 1], l[:, 2]))
+        hit = (idx >= 0)
+        hit[hit] = tree.leaf[idx[hit]] == 1
+        if hit.any():
+            p = todo[hit]
+            u = pts[p] * side - l[hit]
+            px, py, pz = mra.phi(k, u[:, 0]), mra.phi(k, u[:, 1]), mra.phi(k, u[:, 2])
+            out[p] = 2.0 ** (1.5 * j) * np.einsum("pabc,pa,pb,pc->p", tree.coef[idx[hit]], px, py, pz)
+        todo = todo[~hit]
+    return out

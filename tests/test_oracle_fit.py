@@ -1,0 +1,73 @@
+"""Pins of the oracle's Gaussian-sum fit (Sec. 3, eqs. IntegralRepr, KernelApproxByGaussians;
+App. A.5 Prop. trapez)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fit
+
+
+def test_c_alpha_gives_the_coulomb_kernel():
+    # K_{0,1}(r) = 1/(4 pi r)
+    r = np.array([0.01, 0.3, 2.0])
+    assert np.allclose(fit.kernel0(1.0, r), 1.0 / (4 * np.pi * r), rtol=1e-15)
+    # Yukawa at alpha = 1 reduces to e^{-mu r}/(4 pi r)
+    assert np.allclose(fit.kernel(2.5, 1.0, r), np.exp(-2.5 * r) / (4 * np.pi * r), rtol=1e-13)
+
+
+@pytest.mark.parametrize("mu,alpha,eps,delta,R", [
+    (0.0, 1.0, 1e-4, 1e-3, math.sqrt(3)),
+    (0.0, 1.0, 1e-8, 1e-7, 1.0),
+    (4.0, 1.0, 1e-8, 1e-6, math.sqrt(3)),
+    (0.0, 0.3, 1e-6, 1e-5, 1.7),
+    (0.0, 1.4, 1e-6, 1e-5, 1.7),
+    (2.0, 0.7, 1e-6, 1e-5, 1.7),
+])
+def test_fit_meets_the_relative_bound(mu, alpha, eps, delta, R):
+    """|K - sum w e^{-tau r^2}| <= eps K_0 on [delta, R] (eq. KernelApproxByGaussians), measured on an
+    independent random grid with the direct integral representation as a second reference."""
+    tau, w = fit.fit_kernel(mu, alpha, eps, delta, R)
+    rng = np.random.default_rng(0)
+    r = np.exp(rng.uniform(np.log(delta), np.log(R), 400))
+    approx = np.array([np.sum(w * np.exp(-tau * x * x)) for x in r])
+    err = np.abs(fit.kernel(mu, alpha, r) - approx) / fit.kernel0(alpha, r)
+    assert err.max() <= eps
+    assert np.all(tau > 0) and np.all(w >= 0) and np.all(w[-5:] > 0)   # the mu-factor may underflow wide terms to 0
+    # the weights follow the trapezoidal rule of eq. IntegralRepr: tau_{m+1}/tau_m = e^{2h}
+    ratio = tau[1:] / tau[:-1]
+    assert np.allclose(ratio, ratio[0], rtol=1e-12)
+
+
+def test_fit_against_integral_representation():
+    """The Bessel form equals the integral representation (eq. IntegralRepr) by direct quadrature."""
+    from scipy import integrate
+    for mu, alpha in [(0.0, 1.0), (3.0, 1.0), (1.5, 0.6)]:
+        C = fit.c_alpha(alpha)
+        for r in (0.05, 0.7):
+            val = integrate.quad(lambda s: math.exp(-r * r * math.exp(2 * s) - mu * mu * math.exp(-2 * s) / 4
+                                                    + (3 - 2 * alpha) * s), -40, 10, limit=400)[0]
+            assert abs(C * val - fit.kernel(mu, alpha, r)) < 1e-9 * fit.kernel(mu, alpha, r)
+
+
+def test_term_count_grows_like_log_inverse_delta():
+    """Prop. trapez: for fixed eps, M = O(log 1/delta)."""
+    eps = 1e-6
+    ds = np.array([1e-2, 1e-4, 1e-6, 1e-8])
+    Ms = np.array([len(fit.fit_kernel(0.0, 1.0, eps, d, 1.0)[0]) for d in ds])
+    slopes = np.diff(Ms) / np.diff(np.log(1 / ds))
+    assert np.all(slopes > 0)
+    assert slopes.max() / slopes.min() < 1.5
+
+
+def test_figure4_ballpark():
+    """Fig. 4: about 300 terms cover 15 decades at eps = 1e-10 (the paper reports 299)."""
+    tau, w = fit.fit_kernel(0.0, 1.0, 1e-10, 1e-15, 1.0)
+    assert 250 <= len(tau) <= 400
+
+
+def test_invalid_parameters():
+    for args in [(0.0, 1.6, 1e-6, 1e-3, 1.0), (0.0, 1.0, 0.0, 1e-3, 1.0), (0.0, 1.0, 1e-6, 2.0, 1.0),
+                 (-1.0, 1.0, 1e-6, 1e-3, 1.0)]:
+        with pytest.raises(ValueError):
+            fit.fit_kernel(*args)

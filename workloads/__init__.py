@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds only the input recipes (source Gaussians, kernel parameters, accuracy,
+basis order, tree limits, sample points).  It contains none of the method's arithmetic, so
+both the HIP library's callers and the CPU oracle may use it.
+
+Random draws use numpy.random.Generator(PCG64(seed)) in the order listed for each recipe.
+Sources are sums of unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2).
+Kernels are (-Delta + mu^2)^(-alpha): Poisson (mu=0, alpha=1, 1/(4 pi r)), Yukawa / bound-state
+Helmholtz (alpha=1, e^{-mu r}/(4 pi r)) and fractional (mu=0).
+"""
+import numpy as np
+
+__all__ = ["Workload", "c1", "c2", "c3", "c4_member", "c5", "small_adaptive", "points"]
+
+
+class Workload(dict):
+    """Recipe: k, eps, j0, jmax, mu, alpha, xyz (n,3), a (n,), c (n,), name, seed."""
+
+    def __getattr__(self, name):
+        try:
+            return self[name]
+        except KeyError:
+            raise AttributeError(name)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def c1():
+    """3-D Poisson, k=6, uniform level 3 (512 leaves), eps=1e-4; one unit-mass Gaussian with
+    exponent 100 at the centre of the cube (no randomness)."""
+    return Workload(name="poisson_k6_uniform_n3", seed=None, k=6, eps=1e-4, j0=3, jmax=3, mu=0.0, alpha=1.0,
+                    xyz=np.array([[0.5, 0.5, 0.5]]), a=np.array([100.0]), c=np.array([1.0]))
+
+
+def _gauss_sum(rng, n, log10_lo, log10_hi):
+    a = 10.0 ** rng.uniform(log10_lo, log10_hi, n)      # exponents, log-uniform
+    xyz = rng.uniform(0.2, 0.8, (n, 3))                 # centres in [0.2, 0.8]^3
+    c = rng.normal(0.0, 1.0, n)                         # weights N(0,1)
+    return xyz, a, c
+
+
+def c2(seed=2, n=50):
+    """3-D Poisson, k=8, eps=1e-6, adaptive from j0=2 up to jmax=12; 50 Gaussians with
+    exponents log-uniform in [10, 1e4], centres uniform in [0.2, 0.8]^3, weights N(0,1)."""
+    rng = _rng(seed)
+    xyz, a, c = _gauss_sum(rng, n, 1.0, 4.0)
+    return Workload(name="poisson_k8_eps1e-6_50gauss", seed=seed, k=8, eps=1e-6, j0=2, jmax=12, mu=0.0,
+                    alpha=1.0, xyz=xyz, a=a, c=c)
+
+
+def c3(seed=3, n=20):
+    """Bound-state Helmholtz e^{-mu r}/(4 pi r), mu ~ U[1,10] (drawn first), k=10, eps=1e-8,
+    20 Gaussians with the ranges of c2."""
+    rng = _rng(seed)
+    mu = rng.uniform(1.0, 10.0)
+    xyz, a, c = _gauss_sum(rng, n, 1.0, 4.0)
+    return Workload(name="yukawa_k10_eps1e-8_20gauss", seed=seed, k=10, eps=1e-8, j0=2, jmax=12, mu=float(mu),
+                    alpha=1.0, xyz=xyz, a=a, c=c)
+
+
+def c4_member(i):
+    """Member i (0..63) of the batch of uneven solves: kernel uniform over {Poisson, Yukawa
+    mu~U[0.5,10], fractional alpha~U(0.2,1.4)}; (k, eps) uniform over (6,1e-4), (8,1e-6),
+    (10,1e-8); Gaussian count log-uniform in [1, 64] with exponents log-uniform in [10, 10^u],
+    u ~ U[2,4]."""
+    rng = _rng(1000 + i)
+    kind = int(rng.integers(0, 3))
+    mu, alpha = 0.0, 1.0
+    if kind == 1:
+        mu = float(rng.uniform(0.5, 10.0))
+    elif kind == 2:
+        alpha = float(rng.uniform(0.2, 1.4))
+    k, eps = [(6, 1e-4), (8, 1e-6), (10, 1e-8)][int(rng.integers(0, 3))]
+    n = int(round(10.0 ** rng.uniform(0.0, np.log10(64.0))))
+    hi = float(rng.uniform(2.0, 4.0))
+    xyz, a, c = _gauss_sum(rng, n, 1.0, hi)
+    return Workload(name="batch_member_%d" % i, seed=1000 + i, k=k, eps=eps, j0=2, jmax=12, mu=mu,
+                    alpha=alpha, xyz=xyz, a=a, c=c)
+
+
+def c5(seed=5, n=500):
+    """3-D Poisson, k=10, eps=1e-10; 500 Gaussians, exponents log-uniform in [10, 1e5],
+    centres uniform in [0.2, 0.8]^3, weights N(0,1)."""
+    rng = _rng(seed)
+    xyz, a, c = _gauss_sum(rng, n, 1.0, 5.0)
+    return Workload(name="poisson_k10_eps1e-10_500gauss", seed=seed, k=10, eps=1e-10, j0=2, jmax=14, mu=0.0,
+                    alpha=1.0, xyz=xyz, a=a, c=c)
+
+
+def small_adaptive(seed, k=6, eps=1e-4, n=3, jmax=6, mu=0.0, alpha=1.0):
+    """A few Gaussians (exponents log-uniform in [10, 10^2.5], centres in [0.3, 0.7]^3, weights
+    N(0,1)) giving small adaptive trees for fast parity cases."""
+    rng = _rng(seed)
+    a = 10.0 ** rng.uniform(1.0, 2.5, n)
+    xyz = rng.uniform(0.3, 0.7, (n, 3))
+    c = rng.normal(0.0, 1.0, n)
+    return Workload(name="small_adaptive_%d" % seed, seed=seed, k=k, eps=eps, j0=1, jmax=jmax, mu=mu,
+                    alpha=alpha, xyz=xyz, a=a, c=c)
+
+
+def points(n=10000, seed=6):
+    """n evaluation points uniform in [0,1]^3."""
+    return _rng(seed).uniform(0.0, 1.0, (n, 3))
