@@ -1,0 +1,162 @@
+"""Benchmark of the modified ns-form operator apply on one MI355X.
+
+A step is one pass of the whole path on the Poisson workload with k = 8, eps = 1e-6 and a
+50-Gaussian seeded source: Gaussian-sum fit (host FP64), operator build (1-D blocks and screening
+plan, device), adaptive projection to a redundant tree (device), the apply (neighbour closure,
+FP64-MFMA contractions, assembly; device) and evaluation at 1e4 points.  The printed JSON line
+reports NS-apply block-contractions per second of step time, the roofline of the contraction
+kernel (FP64 MFMA) and the CPU oracle timed on a bounded sample of the same apply.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
+    return ap.parse_args()
+
+
+def step(M, ctx, w, pts):
+    """One pass of the whole path; returns (g, stats, depth)."""
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth)
+    g, stats = M.mwns_apply(ctx, op, f)
+    vals = M.mwns_tree_eval(ctx, g, pts)
+    return g, stats, depth, vals
+
+
+def cpu_baseline(w, depth, nsample):
+    """The oracle's modified-form apply on a seeded sample of output nodes of the same tree."""
+    import numpy as np
+    from oracle import apply as A
+    from oracle import fit
+    from oracle import tree as T
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    tr = T.redundant_tree(w.k, keys, coef)
+    tau, wt = fit.fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    op = A.Operator(w.k, tau, wt, w.eps, tr.depth)
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.sort(rng.choice(tr.keys.size, size=min(nsample, tr.keys.size), replace=False))
+    cnt = _count_contractions(op.R, tr, idx)
+    t0 = time.perf_counter()
+    A.apply_modified(op, tr, idx)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cnt / dt, "unit": "block-contractions/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d output nodes (seed 77), %d contractions in %.1f s; plain C, OpenMP over nodes"
+                      % (idx.size, tr.keys.size, cnt, dt)}
+
+
+def _count_contractions(R, tr, idx):
+    """(node, l, m) triples with a non-zero coefficient for the given nodes (the apply's rule:
+    c_m = [m in R_j(L)] - [internal][m in R_{j+1}(l)]), counted from the plan."""
+    import numpy as np
+    e = np.arange(-7, 8)
+    E1, E2, E3 = np.meshgrid(e, e, e, indexing="ij")
+    nlev = R.shape[0]
+    total = 0
+    for i in idx:
+        j = int(tr.level[i])
+        l = tr.l[i]
+        side = 1 << j
+        q = [l[0] - E1, l[1] - E2, l[2] - E3]
+        inside = np.ones(E1.shape, dtype=bool)
+        for d in range(3):
+            inside &= (q[d] >= 0) & (q[d] < side)
+        L = [(l[d] >> 1) - (np.clip(q[d], 0, None) >> 1) for d in range(3)]
+        inL = (np.abs(L[0]) <= 3) & (np.abs(L[1]) <= 3) & (np.abs(L[2]) <= 3)
+        Lc = [np.clip(L[d], -3, 3) + 3 for d in range(3)]
+        rw = R[j][Lc[0], Lc[1], Lc[2]]
+        a1 = np.where(inL, rw[..., 0], 0)
+        b1 = np.where(inL, rw[..., 1], -1)
+        a2 = np.zeros_like(a1)
+        b2 = np.full_like(b1, -1)
+        if tr.leaf[i] == 0 and j + 1 < nlev:
+            inl = (np.abs(E1) <= 3) & (np.abs(E2) <= 3) & (np.abs(E3) <= 3)
+            rd = R[j + 1][np.clip(E1, -3, 3) + 3, np.clip(E2, -3, 3) + 3, np.clip(E3, -3, 3) + 3]
+            a2 = np.where(inl, rd[..., 0], 0)
+            b2 = np.where(inl, rd[..., 1], -1)
+        n1 = np.maximum(0, b1 - a1 + 1)
+        n2 = np.maximum(0, b2 - a2 + 1)
+        ov = np.where((n1 > 0) & (n2 > 0), np.maximum(0, np.minimum(b1, b2) - np.maximum(a1, a2) + 1), 0)
+        total += int(np.sum(np.where(inside, n1 + n2 - 2 * ov, 0)))
+    return total
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0706_0747_amd as M
+    import workloads
+    w = workloads.c2()
+    pts = workloads.points(10000)
+    ctx = M.Context(0)
+    for _ in range(args.warmup):
+        step(M, ctx, w, pts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats_all = []
+    for _ in range(args.steps):
+        g, stats, depth, _ = step(M, ctx, w, pts)
+        stats_all.append(stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    st = stats_all[-1]
+    info = M.mwns_tree_get_info(g)
+    contr = st["contractions"]
+    ms_con = sum(s["ms_contract"] for s in stats_all) / len(stats_all)
+    achieved = st["useful_flops"] / (ms_con * 1e-3) / 1e12
+    line = {
+        "metric": "NS apply block-contractions/s + FP64-MFMA util; mixed-vs-FP64 speedup at eps",
+        "value": contr / (ms_step * 1e-3),
+        "unit": "block-contractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "kernel": "poisson 1/(4 pi r)", "k": w.k, "eps": w.eps,
+                   "sources": int(w.a.size), "seed": w.seed, "leaves": int(info["nleaves"]),
+                   "nodes": int(info["nnodes"]), "depth": int(info["depth"]), "eval_points": int(pts.shape[0])},
+        "contractions_per_step": int(contr),
+        "apply_contractions_per_s": contr / ((st["ms_closure"] + st["ms_contract"] + st["ms_assemble"]) * 1e-3),
+        "apply_ms": {"closure": st["ms_closure"], "contract": ms_con, "assemble": st["ms_assemble"]},
+        "mixed_vs_fp64_speedup": None,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "ns_apply_kernel<8> (all levels of one apply)",
+                     "flops_per_apply": st["useful_flops"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, info["depth"], args.cpu_sample_nodes)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * mwns.h -- C ABI of libmwns: radial-kernel integral operators applied in the modified
+ * non-standard (ns) form to 3-D functions held as order-k Legendre multiwavelet coefficients
+ * on adaptive dyadic trees, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: G. Beylkin, V. Cheruvu, F. Perez, "Fast Adaptive Algorithms in the Non-Standard Form
+ * for Multidimensional Problems".  The calls follow the paper's statement of the problem:
+ * compute g(x) = int K(y - x) f(y) dy for a radial kernel K given only by the exponents and
+ * weights of a Gaussian sum (Sec. 3 and Sec. 5), with f and g represented on adaptive trees
+ * (Sec. 2.2) at a user-supplied accuracy eps:
+ *   (1) fit      mwns_fit_kernel            Gaussian sum of (-Delta+mu^2)^(-alpha)   (Sec. 3, eq. KernelApproxByGaussians)
+ *   (2) operator mwns_op_create             1-D blocks F^{j;m,l} and screening plan   (eq. KernelFactor; Sec. 4)
+ *   (3) project  mwns_project_gaussians     adaptive tree of a Gaussian-sum source    (Alg. 1)
+ *   (4) apply    mwns_apply                 g = T f in the modified ns-form           (eq. apply_algo, Alg. 3)
+ *   (5) evaluate mwns_tree_eval             g at points from its leaves               (App. A.1)
+ *
+ * Conventions shared by every call
+ *  - Every call returns an mwns_status; MWNS_OK is 0.  No C++ exception crosses the ABI.  On a
+ *    non-OK status, outputs are left untouched and no handle is created; mwns_last_error()
+ *    returns a thread-local message describing the last failure on the calling thread.
+ *  - The caller owns every host array passed in or out.  The library owns every handle and every
+ *    device buffer; device memory comes from the context's allocator.
+ *  - All device work of a context is ordered on the context's stream.  Calls that return host
+ *    data synchronise that stream before returning.  A context is not thread-safe: use one
+ *    context per host thread.
+ *  - Orders and sizes: 1 <= k <= 8 (basis order = number of Legendre polynomials per dimension);
+ *    tree levels 0..19.  Coefficient blocks are [a][b][c] with a the x degree, b the y degree and
+ *    c the z degree (c fastest).  Keys are level << 57 | morton(lx, ly, lz) with the x bit lowest
+ *    in each bit triple; a tree's canonical node order is ascending key.
+ *  - The Gaussian source f = sum_i c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2) is a sum of unit-mass
+ *    Gaussians; f is taken as zero outside the unit cube [0,1]^3 (free space).
+ */
+#ifndef MWNS_H
+#define MWNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MWNS_OK = 0,
+    MWNS_EINVAL = 1,   /* an argument is out of range or inconsistent */
+    MWNS_ENOMEM = 2,   /* the allocator failed or the context's byte budget would be exceeded */
+    MWNS_EDEVICE = 3,  /* a HIP runtime call or kernel launch failed */
+    MWNS_ERANGE = 4,   /* a result does not fit: a caller capacity, the term cap of the fit, ... */
+    MWNS_ESTATE = 5    /* a handle is used in a state that does not allow the call */
+} mwns_status;
+
+typedef struct mwns_ctx mwns_ctx;
+typedef struct mwns_op mwns_op;
+typedef struct mwns_tree mwns_tree;
+
+/* Device allocator callbacks: alloc returns a device pointer of at least `bytes` bytes usable on
+ * the context's device and stream (or NULL on failure); free releases it. */
+typedef void* (*mwns_alloc_fn)(size_t bytes, void* user);
+typedef void (*mwns_free_fn)(void* ptr, void* user);
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.
+ *   stream       hipStream_t to order all work on; NULL means the device's null stream.
+ *   alloc/free   device allocator; both NULL means hipMalloc/hipFree.  Both or neither.
+ *   user         passed back to alloc/free unchanged.
+ *   byte_budget  upper bound on device bytes the context may hold at once; 0 = unlimited.
+ * Errors: EINVAL (bad device, one of alloc/free missing), EDEVICE (HIP runtime failure). */
+mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_free_fn free_fn, void* user,
+                            size_t byte_budget, mwns_ctx** out);
+void mwns_ctx_destroy(mwns_ctx* ctx);
+/* Block until all work on the context's stream has completed.  Errors: EDEVICE. */
+mwns_status mwns_ctx_synchronize(mwns_ctx* ctx);
+/* Device bytes currently held by the context (handles included). */
+size_t mwns_ctx_bytes_in_use(const mwns_ctx* ctx);
+/* Thread-local text for the last non-OK status returned on this thread ("" if none). */
+const char* mwns_last_error(void);
+
+/* -------------------------------------------------------------- (1) fit */
+
+/* Exponents tau_m and weights w_m of sum_m w_m exp(-tau_m r^2) approximating `scale` times the
+ * kernel of (-Delta + mu^2)^(-alpha),
+ *   K_{mu,alpha}(r) = C_alpha int exp(-r^2 e^{2s} - mu^2 e^{-2s}/4 + (3 - 2 alpha) s) ds,
+ * by the trapezoidal rule s_m = A + m h, m = 1..M (Sec. 3, eqs. IntegralRepr and
+ * KernelApproxByGaussians), such that
+ *   |K_{mu,alpha}(r) - sum w_m e^{-tau_m r^2}| <= eps K_{0,alpha}(r)   for delta <= r <= R,
+ * verified on 64 points per decade (the fit targets eps/2 there).  Host FP64, no device work.
+ *   mu >= 0, 0 < alpha < 3/2, 0 < eps < 1, 0 < delta < R, scale > 0.
+ *   cap       capacity of tau[] and w[] (caller-owned host arrays).
+ *   *M        on MWNS_OK the number of terms written; on MWNS_ERANGE the number needed.
+ * Errors: EINVAL (parameters), ERANGE (M > cap; tau and w untouched). */
+mwns_status mwns_fit_kernel(double mu, double alpha, double scale, double eps, double delta, double R, int cap,
+                            int* M, double* tau, double* w);
+
+/* --------------------------------------------------------- (2) operator */
+
+typedef struct {
+    /* 1 (default): every coarse displacement L gets the union of the term ranges of its set
+     * Core / Boundary-1 / Boundary-2 / Boundary-3 (Sec. 4); 0: per-L ranges. */
+    int group_regions;
+} mwns_op_opts;
+
+/* Build the operator for basis order k on levels 0..max_level from M Gaussian terms (host arrays
+ * tau[M], w[M], copied):
+ *   - the 1-D blocks F^{j;m,l}_ab = 2^-j int_{-1}^{1} exp(-tau_m (x+l)^2/4^j) Phi_ab(x) dx for
+ *     j = 0..max_level, every m and l = -7..7 (eq. KernelFactor; Phi = cross-correlation of the
+ *     scaling functions, App. A.4), on the device;
+ *   - the screening plan: for every scale j >= 1 and coarse displacement L in [-3,3]^3, the
+ *     inclusive term range R_j(L) kept after discarding terms whose cumulative estimated
+ *     contribution is below eps (Sec. 4, eqs. BlockNorms and NormEstimateUsing1DBlocks).
+ * opts may be NULL (defaults).  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const double* w, double eps,
+                           int max_level, const mwns_op_opts* opts, mwns_op** out);
+/* Plan as int32 [max_level+1][7][7][7][2] (j, L1+3, L2+3, L3+3, {m1, m2}); an empty range has
+ * m2 < m1; row j = 0 holds the root (all terms at L = 0).  Two-call size query: with plan == NULL
+ * only *count (number of int32) is set.  Errors: ERANGE (*count too small; *count set). */
+mwns_status mwns_op_plan_export(const mwns_op* op, int32_t* plan, size_t* count);
+/* Replace the plan with a caller-supplied one of the same layout (e.g. a stored band
+ * structure, Sec. 4).  Errors: EINVAL (count or a range outside [0, M)). */
+mwns_status mwns_op_plan_import(mwns_op* op, const int32_t* plan, size_t count);
+/* F tables as double [max_level+1][M][15][k][k] (row = output degree).  Two-call size query as
+ * above.  Synchronises.  Errors: ERANGE, EDEVICE. */
+mwns_status mwns_op_tables_export(mwns_ctx* ctx, const mwns_op* op, double* F, size_t* count);
+/* theta = eps * sum_m w_m ||F^{0;m,0}||_F^3 used by the screening (Sec. 4). */
+double mwns_op_threshold(const mwns_op* op);
+void mwns_op_destroy(mwns_op* op);
+
+/* --------------------------------------------------------- (3) trees */
+
+/* Adaptive projection (Alg. 1) of f = sum_i c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2), n terms,
+ * host arrays xyz[n][3], a[n] > 0, c[n]: starting from every box of level j0, a box below jmax is
+ * refined when, for any of its 8 children, the values interpolated from the box's coefficients
+ * differ from f at the child's k^3 Gauss-Legendre nodes by more than eps * ||f||_2 (max norm);
+ * leaves keep their own Gauss-Legendre coefficients (App. A.1, eq. fvals2coefs) and every
+ * ancestor receives the two-scale decomposition of its children (redundant tree, Sec. 2.2.1).
+ *   0 <= j0 <= jmax <= 19, eps > 0.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int jmax, int n, const double* xyz,
+                                   const double* a, const double* c, mwns_tree** out);
+/* Tree from caller leaves: keys[nleaves] (any order, no duplicates, leaves must tile the unit cube
+ * without overlap) and coeffs[nleaves][k][k][k] (host).  Ancestors are added and filled by the
+ * two-scale decomposition.  Errors: EINVAL (bad keys / not a tiling), ENOMEM, EDEVICE. */
+mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
+                                  mwns_tree** out);
+
+typedef struct {
+    int k;
+    int depth;              /* deepest level */
+    int64_t nnodes;         /* nodes of the redundant tree */
+    int64_t nleaves;
+    double threshold;       /* refinement threshold of the projection (0 for imported trees) */
+    double min_margin;      /* min over refinement tests of |err - threshold| / threshold (projection) */
+} mwns_tree_info;
+mwns_status mwns_tree_get_info(const mwns_tree* t, mwns_tree_info* info);
+
+/* Export in canonical (ascending key) order.  Two-call size query: with keys == NULL only *nnodes
+ * is set.  keys[nnodes], is_leaf[nnodes] (may be NULL), coeffs[nnodes][k][k][k] (may be NULL).
+ * Synchronises.  Errors: ERANGE (*nnodes too small), EDEVICE. */
+mwns_status mwns_tree_export(mwns_ctx* ctx, const mwns_tree* t, int64_t* nnodes, uint64_t* keys, uint8_t* is_leaf,
+                             double* coeffs);
+void mwns_tree_destroy(mwns_tree* t);
+
+/* ------------------------------------------------------------- (4) apply */
+
+enum {
+    MWNS_F64 = 0,             /* every contraction in FP64 (FP64 MFMA) */
+    MWNS_NO_ASSEMBLY = 1 << 8 /* flag: g holds the per-scale blocks ghat before eq. g_assemble */
+};
+
+typedef struct {
+    int64_t contractions;     /* (node, displacement, term) triples with a non-zero coefficient */
+    int64_t brick_jobs;       /* (output sibling group, region, term) contraction jobs executed */
+    int64_t ghost_bricks;     /* sibling groups interpolated from coarser leaves (Alg. 3 Step 2) */
+    double useful_flops;      /* FP64 flops of the executed contraction schedule, padding excluded */
+    double ms_closure;        /* device time of neighbour closure and interpolation */
+    double ms_contract;       /* device time of the contraction kernels */
+    double ms_assemble;       /* device time of the top-down assembly */
+} mwns_apply_stats;
+
+/* g = T f with T given by `op` (its F tables and plan), in the modified ns-form (eq. apply_algo;
+ * Alg. 3): the output uses the redundant tree of f as its skeleton; every node b at level j
+ * receives ghat_b = sum over displacements l and terms m of c_m w_m (F^{j;m,l1} (x) F^{j;m,l2}
+ * (x) F^{j;m,l3}) f_{b-l} with c_m = [m in R_j(L)] - [b internal][m in R_{j+1}(l)]
+ * (L = coarse displacement of the parents), missing inputs being interpolated from the deepest
+ * existing ancestor (Alg. 3 Step 2), and g = ghat + up(g_parent) top-down (eq. g_assemble).
+ * op->max_level must be >= depth of f.  `mode` is MWNS_F64, optionally | MWNS_NO_ASSEMBLY.
+ * stats may be NULL; filling it synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
+                       mwns_apply_stats* stats);
+
+/* ----------------------------------------------------------- (5) evaluate */
+
+/* Values at npts points xyz[npts][3] (host, inside [0,1]^3) from the leaves of t:
+ * f(x) = 2^{3j/2} sum_abc s_abc phi_a(2^j x - l1) phi_b(2^j y - l2) phi_c(2^j z - l3) on the leaf
+ * holding x (App. A.1); a point on a face belongs to the box floor(2^j x) clamped to 2^j - 1.
+ * out[npts] is a host array.  Synchronises.  Errors: EINVAL (point outside the cube), ENOMEM,
+ * EDEVICE. */
+mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MWNS_H */

@@ -59,9 +59,9 @@ def estimate(NF, NU, ND, Lc):
 def term_range(e, theta):
     """[m1, m2] kept after discarding prefix and suffix with cumulative contribution <= theta/2;
     EMPTY when the whole sum is <= theta (Sec. 4)."""
-    if e.sum() <= theta:
+    c = np.cumsum(e)                                      # sequential cumulative contributions
+    if c[-1] <= theta:
         return EMPTY
-    c = np.cumsum(e)
     m1 = int(np.argmax(c > 0.5 * theta))
     cs = np.cumsum(e[::-1])
     m2 = len(e) - 1 - int(np.argmax(cs > 0.5 * theta))
@@ -81,7 +81,10 @@ def make_plan(Ftab, H0, H1, w, eps, nlev, group=True):
     """Plan R[j, L, 2] for j = 0..nlev (Ftab must hold scales 0..nlev).  Also returns theta."""
     M = Ftab.shape[1]
     w = np.asarray(w, dtype=np.float64)
-    theta = eps * float(np.sum(w * np.array([np.linalg.norm(Ftab[0, m, 7]) ** 3 for m in range(M)])))
+    theta = 0.0
+    for m in range(M):                                    # sequential sum over m
+        theta += w[m] * np.linalg.norm(Ftab[0, m, 7]) ** 3
+    theta *= eps
     n7 = 2 * LMAX + 1
     R = np.empty((nlev + 1, n7, n7, n7, 2), dtype=np.int32)
     R[...] = EMPTY

@@ -1,0 +1,704 @@
+// g = T f in the modified ns-form (eq. apply_algo, Alg. 3) on FP64 MFMA.
+//
+// Work is organised by sibling groups ("bricks"): the 8 children of a node form a (2k)^3 tensor
+// with index u = s*k + a per dimension.  Between the brick of parent P and the brick of parent
+// P - L (coarse displacement L) the fine displacement is l = 2L + s - s', so one Gaussian term acts
+// per dimension as the 2k x 2k super-block
+//     S^{j;m,L} = [[F^{j;m,2L}, F^{j;m,2L-1}], [F^{j;m,2L+1}, F^{j;m,2L}]]      (rows: output parity)
+// and a term applied over a box of displacements L in [lo1,hi1] x [lo2,hi2] x [lo3,hi3] factorises
+// (Sec. 5, the nested-loop factorisation with the term sum last):
+//     Y += c w_m sum_{L1} S^{L1} x_1 [ sum_{L2} S^{L2} x_2 [ sum_{L3} S^{L3} x_3 X_{P-L} ] ].
+// Per output node b and input b - l the method's coefficient of term m is
+//     c_m = [m in R_j(L)] - [b internal] [m in R_{j+1}(l)],
+// so each level runs "whole-band" jobs over boxes of L from the plan row j (all children) and
+// "down-band" jobs from row j+1 expressed on fine l (masked super-blocks, internal children only,
+// c = -1).  The boxes are the cells of the coarsest partition of [-3,3] per dimension on which the
+// plan's ranges are constant (Core / Boundary sets, Sec. 4).
+//
+// MFMA mapping (v_mfma_f64_16x16x4: A[m][k] in lane m+16k, B[k][n] in lane n+16k, D[4i+g][n] in
+// lane 16g+n, register i): 2k <= 16 is padded to one 16 x 16 tile per dimension.  Wave w owns the
+// input slices v1 in {w*TPW..}: mode 3 (contract v3, A = X slice with K index 4g+kk loaded as 4
+// consecutive doubles, B = S3), mode 2 straight from the mode-3 accumulators (their register i
+// holds contraction index 4i+g), an LDS transpose, then mode 1 into the per-wave output tiles.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <memory>
+
+#include "mwns_internal.h"
+
+namespace mwns {
+
+struct LevelTab2 {
+    int64_t node_off[MAXLEV + 2];
+    int64_t brick_off[MAXLEV + 2];
+    int depth;
+};
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct Tpl {
+    int lo[3], hi[3];      // coarse displacement box
+    int mlo[3], mhi[3];    // fine displacement mask per dimension
+    int m1, m2;            // inclusive term range
+    int dpart;             // 0: whole band (all children, +), 1: down band (internal children, -)
+};
+
+constexpr int AT = 256;            // threads per apply block
+constexpr int T2S_V1 = 272;        // LDS strides of the mode-2 result [v1][u2][u3]
+constexpr int T2S_U2 = 16;
+
+template <int K>
+__device__ inline double sop(const double* __restrict__ Fm, int L, int mlo, int mhi, int u, int v) {
+    if (u >= 2 * K || v >= 2 * K) return 0.0;
+    const int su = u >= K, sv = v >= K;
+    const int l = 2 * L + su - sv;
+    if (l < mlo || l > mhi) return 0.0;
+    return Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
+}
+
+template <int K>
+__global__ void __launch_bounds__(AT) ns_apply_kernel(const double* __restrict__ Xr, int64_t nreal,
+                                                      const double* __restrict__ Xg, const int32_t* __restrict__ nbr, int Lr,
+                                                      const uint8_t* __restrict__ cmask, int valid,
+                                                      const Tpl* __restrict__ tpl, int ntpl,
+                                                      const double* __restrict__ Fj, const double* __restrict__ w,
+                                                      double* __restrict__ out) {
+    constexpr int D = 2 * K;
+    constexpr int TPW = (D + 3) / 4;
+    constexpr int64_t E = (int64_t)D * D * D;
+    __shared__ double T2s[16 * T2S_V1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int NL = 2 * Lr + 1;
+    const int32_t* nb = nbr + b * NL * NL * NL;
+    d4 YW[TPW], YD[TPW];
+    for (int t = 0; t < TPW; ++t) {
+        YW[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        YD[t] = (d4){0.0, 0.0, 0.0, 0.0};
+    }
+    const int cmb = cmask[b];
+    for (int ti = 0; ti < ntpl; ++ti) {
+        const Tpl tp = tpl[ti];
+        if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
+        for (int m = tp.m1; m <= tp.m2; ++m) {
+            const double* Fm = Fj + (int64_t)m * NLF * K * K;
+            const double cw = tp.dpart ? -w[m] : w[m];
+            for (int L1 = tp.lo[0]; L1 <= tp.hi[0]; ++L1) {
+                d4 T2[TPW];
+                for (int t = 0; t < TPW; ++t) T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
+                bool any1 = false;
+                for (int L2 = tp.lo[1]; L2 <= tp.hi[1]; ++L2) {
+                    d4 T1[TPW];
+                    for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
+                    bool any2 = false;
+                    for (int L3 = tp.lo[2]; L3 <= tp.hi[2]; ++L3) {
+                        const int idx = nb[((L1 + Lr) * NL + (L2 + Lr)) * NL + (L3 + Lr)];
+                        if (idx < 0) continue;
+                        any2 = true;
+                        const double* X = idx < nreal ? Xr + idx * E : Xg + (idx - nreal) * E;
+                        double s3[4];
+                        for (int kk = 0; kk < 4; ++kk) s3[kk] = sop<K>(Fm, L3, tp.mlo[2], tp.mhi[2], r, 4 * g + kk);
+                        for (int t = 0; t < TPW; ++t) {
+                            const int v1 = wave * TPW + t;
+                            if (v1 >= D) break;
+                            double x[4];
+                            const double* xp = X + ((int64_t)v1 * D + r) * D + 4 * g;
+                            if (r < D && 4 * g + 3 < D && (D % 4) == 0) {
+                                const double2 p0 = *reinterpret_cast<const double2*>(xp);
+                                const double2 p1 = *reinterpret_cast<const double2*>(xp + 2);
+                                x[0] = p0.x; x[1] = p0.y; x[2] = p1.x; x[3] = p1.y;
+                            } else {
+                                for (int kk = 0; kk < 4; ++kk) x[kk] = (r < D && 4 * g + kk < D) ? xp[kk] : 0.0;
+                            }
+                            for (int kk = 0; kk < 4; ++kk)
+                                T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], s3[kk], T1[t], 0, 0, 0);
+                        }
+                    }
+                    if (!any2) continue;
+                    any1 = true;
+                    double s2[4];
+                    for (int i = 0; i < 4; ++i) s2[i] = sop<K>(Fm, L2, tp.mlo[1], tp.mhi[1], r, 4 * i + g);
+                    for (int t = 0; t < TPW; ++t)
+                        for (int i = 0; i < 4; ++i) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                }
+                if (!any1) continue;
+                for (int t = 0; t < TPW; ++t) {
+                    const int v1 = wave * TPW + t;
+                    if (v1 >= D) break;
+                    for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
+                }
+                __syncthreads();
+                double s1[4];
+                for (int kk = 0; kk < 4; ++kk) s1[kk] = cw * sop<K>(Fm, L1, tp.mlo[0], tp.mhi[0], r, 4 * kk + g);
+                for (int t = 0; t < TPW; ++t) {
+                    const int u2 = wave * TPW + t;
+                    if (u2 >= D) break;
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int v1 = 4 * kk + g;
+                        const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
+                        if (tp.dpart) YD[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YD[t], 0, 0, 0);
+                        else YW[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YW[t], 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    double* ob = out + b * E;
+    for (int t = 0; t < TPW; ++t) {
+        const int u2 = wave * TPW + t;
+        if (u2 >= D) break;
+        for (int i = 0; i < 4; ++i) {
+            const int u1 = 4 * i + g, u3 = r;
+            if (u1 >= D || u3 >= D) continue;
+            const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+            double v = ((valid >> child) & 1) ? YW[t][i] : 0.0;
+            if ((cmb >> child) & 1) v += YD[t][i];
+            ob[((int64_t)u1 * D + u2) * D + u3] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- closure
+// For every output brick of level j (parent P at level j-1) and L in [-Lr,Lr]^3: index of the
+// brick whose parent is P - L among the level's real bricks, -1 outside the cube, -2 when P - L is
+// not an internal node (the key is written to miss[] for interpolation).
+__global__ void closure_kernel(int64_t nout, int jm1, const uint64_t* __restrict__ pkeys, int Lr,
+                               int32_t* __restrict__ nbr, uint64_t* __restrict__ miss) {
+    const int NL = 2 * Lr + 1, NL3 = NL * NL * NL;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nout * NL3) return;
+    const int64_t b = idx / NL3;
+    const int e = (int)(idx % NL3);
+    const int L[3] = {e / (NL * NL) - Lr, (e / NL) % NL - Lr, e % NL - Lr};
+    int64_t p[3];
+    key_coords(pkeys[b], p);
+    const int64_t side = (int64_t)1 << jm1;
+    int64_t q[3];
+    bool inside = true;
+    for (int d = 0; d < 3; ++d) {
+        q[d] = p[d] - L[d];
+        inside = inside && q[d] >= 0 && q[d] < side;
+    }
+    miss[idx] = ~0ull;
+    if (!inside) { nbr[idx] = -1; return; }
+    const uint64_t key = make_key(jm1, q[0], q[1], q[2]);
+    const int64_t f = find_sorted(pkeys, nout, key);
+    if (f >= 0) { nbr[idx] = (int32_t)f; return; }
+    nbr[idx] = -2;
+    miss[idx] = key;
+}
+
+__global__ void closure_fill_kernel(int64_t n, const uint64_t* __restrict__ miss, const uint64_t* __restrict__ gkeys,
+                                    int64_t ng, int64_t nreal, int32_t* __restrict__ nbr) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n || nbr[idx] != -2) return;
+    nbr[idx] = (int32_t)(nreal + find_sorted(gkeys, ng, miss[idx]));
+}
+
+// LDS helpers for the two-scale transforms with zero details (App. A.3, eqs. recon_even/odd).
+// out = (A1 (x) A2 (x) A3) in, A_d given as Ht[s][a] = H^(s)^T ... applied per dimension.
+template <int K>
+__device__ void up_one(const double* __restrict__ Ht, const double* in, double* out, double* tmp1, double* tmp2, int s1,
+                       int s2, int s3) {
+    // child s of a block: (H^{s1}^T (x) H^{s2}^T (x) H^{s3}^T) in ; Ht = [H0^T ; H1^T] as [2][K][K] (row = child degree)
+    constexpr int K3 = K * K * K;
+    const double* A1 = Ht + s1 * K * K;
+    const double* A2 = Ht + s2 * K * K;
+    const double* A3 = Ht + s3 * K * K;
+    for (int e = threadIdx.x; e < K3; e += AT) {
+        const int c1 = e / (K * K), c2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int c3 = 0; c3 < K; ++c3) s += A3[a3 * K + c3] * in[(c1 * K + c2) * K + c3];
+        tmp1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K3; e += AT) {
+        const int c1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int c2 = 0; c2 < K; ++c2) s += A2[a2 * K + c2] * tmp1[(c1 * K + c2) * K + a3];
+        tmp2[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K3; e += AT) {
+        const int a1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int c1 = 0; c1 < K; ++c1) s += A1[a1 * K + c1] * tmp2[(c1 * K + a2) * K + a3];
+        out[e] = s;
+    }
+    __syncthreads();
+}
+
+// brick (2K)^3 += or = (Ht (x) Ht (x) Ht) in, Ht = [H0^T; H1^T] (2K x K): all 8 children at once.
+template <int K>
+__device__ void up_brick(const double* __restrict__ Ht, const double* in, double* __restrict__ brick, bool add, double* tmp1,
+                         double* tmp2) {
+    constexpr int P = 2 * K;
+    for (int e = threadIdx.x; e < K * K * P; e += AT) {
+        const int c1 = e / (K * P), c2 = (e / P) % K, u3 = e % P;
+        double s = 0.0;
+        for (int c3 = 0; c3 < K; ++c3) s += Ht[u3 * K + c3] * in[(c1 * K + c2) * K + c3];
+        tmp1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * P * P; e += AT) {
+        const int c1 = e / (P * P), u2 = (e / P) % P, u3 = e % P;
+        double s = 0.0;
+        for (int c2 = 0; c2 < K; ++c2) s += Ht[u2 * K + c2] * tmp1[(c1 * K + c2) * P + u3];
+        tmp2[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * P * P; e += AT) {
+        const int u1 = e / (P * P), u2 = (e / P) % P, u3 = e % P;
+        double s = 0.0;
+        for (int c1 = 0; c1 < K; ++c1) s += Ht[u1 * K + c1] * tmp2[(c1 * P + u2) * P + u3];
+        brick[e] = add ? brick[e] + s : s;
+    }
+    __syncthreads();
+}
+
+template <int K>
+__device__ void load_block(const double* __restrict__ brick, int child, double* out) {
+    constexpr int P = 2 * K, K3 = K * K * K;
+    const int s1 = child & 1, s2 = (child >> 1) & 1, s3 = child >> 2;
+    for (int e = threadIdx.x; e < K3; e += AT) {
+        const int a = e / (K * K), b = (e / K) % K, c = e % K;
+        out[e] = brick[((s1 * K + a) * P + s2 * K + b) * P + s3 * K + c];
+    }
+    __syncthreads();
+}
+
+// Ghost bricks: the children of a node Q of level j-1 that is not internal, interpolated from the
+// deepest existing ancestor (a leaf) by repeated zero-detail reconstruction (Alg. 3 Step 2).
+template <int K>
+__global__ void __launch_bounds__(AT) ghost_kernel(int jm1, const uint64_t* __restrict__ gkeys, const uint64_t* __restrict__ keys,
+                                                   int64_t nnodes, LevelTab2 lt, const double* __restrict__ coef,
+                                                   const double* __restrict__ Htg, double* __restrict__ gout) {
+    constexpr int P = 2 * K, K3 = K * K * K;
+    __shared__ double Ht[2 * K * K];
+    __shared__ double blk[K3], tmp1[K * P * P], tmp2[K * P * P];
+    for (int e = threadIdx.x; e < 2 * K * K; e += AT) Ht[e] = Htg[e];
+    __syncthreads();
+    const uint64_t q = gkeys[blockIdx.x];
+    int64_t l[3];
+    key_coords(q, l);
+    int i = jm1;
+    int64_t node = -1;
+    for (; i >= 0; --i) {
+        node = find_sorted(keys, nnodes, make_key(i, l[0] >> (jm1 - i), l[1] >> (jm1 - i), l[2] >> (jm1 - i)));
+        if (node >= 0) break;
+    }
+    double* go = gout + (int64_t)blockIdx.x * P * P * P;
+    if (node < 0) {   // cannot happen for a tree with a root; keep the brick defined
+        for (int e = threadIdx.x; e < P * P * P; e += AT) go[e] = 0.0;
+        return;
+    }
+    int64_t brick;
+    int child;
+    if (i == 0) { brick = 0; child = 0; }
+    else {
+        const int64_t r = node - lt.node_off[i];
+        brick = lt.brick_off[i] + (r >> 3);
+        child = (int)(r & 7);
+    }
+    load_block<K>(coef + brick * (int64_t)P * P * P, child, blk);
+    for (int t = i + 1; t <= jm1; ++t) {
+        const int sh = jm1 - t;
+        up_one<K>(Ht, blk, blk, tmp1, tmp2, (l[0] >> sh) & 1, (l[1] >> sh) & 1, (l[2] >> sh) & 1);
+    }
+    up_brick<K>(Ht, blk, go, false, tmp1, tmp2);
+}
+
+// Assembly (eq. g_assemble): every brick of level j += the 8-child upsampling of its parent's g.
+template <int K>
+__global__ void __launch_bounds__(AT) assemble_kernel(int j, const int64_t* __restrict__ parent_brick,
+                                                      const int* __restrict__ parent_child, int64_t brick_off,
+                                                      const double* __restrict__ Htg, double* __restrict__ coef) {
+    constexpr int P = 2 * K, K3 = K * K * K;
+    __shared__ double Ht[2 * K * K];
+    __shared__ double blk[K3], tmp1[K * P * P], tmp2[K * P * P];
+    for (int e = threadIdx.x; e < 2 * K * K; e += AT) Ht[e] = Htg[e];
+    __syncthreads();
+    const int64_t b = blockIdx.x;
+    load_block<K>(coef + parent_brick[b] * (int64_t)P * P * P, parent_child[b], blk);
+    up_brick<K>(Ht, blk, coef + (brick_off + b) * (int64_t)P * P * P, true, tmp1, tmp2);
+}
+
+// Number of (node, l, m) triples with a non-zero coefficient, per output brick of level j.
+__global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ pkeys, const uint8_t* __restrict__ cmask,
+                             int valid, const int32_t* __restrict__ Rj, const int32_t* __restrict__ Rj1,
+                             unsigned long long* __restrict__ total) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nout) return;
+    int64_t p[3] = {0, 0, 0};
+    if (j > 0) key_coords(pkeys[b], p);
+    const int64_t side = (int64_t)1 << j;
+    unsigned long long cnt = 0;
+    for (int child = 0; child < 8; ++child) {
+        if (!((valid >> child) & 1)) continue;
+        const int internal = (cmask[b] >> child) & 1;
+        const int64_t o[3] = {2 * p[0] + (child & 1), 2 * p[1] + ((child >> 1) & 1), 2 * p[2] + (child >> 2)};
+        for (int e1 = -LF; e1 <= LF; ++e1)
+            for (int e2 = -LF; e2 <= LF; ++e2)
+                for (int e3 = -LF; e3 <= LF; ++e3) {
+                    const int64_t q[3] = {o[0] - e1, o[1] - e2, o[2] - e3};
+                    if (q[0] < 0 || q[0] >= side || q[1] < 0 || q[1] >= side || q[2] < 0 || q[2] >= side) continue;
+                    const int64_t L[3] = {(o[0] >> 1) - (q[0] >> 1), (o[1] >> 1) - (q[1] >> 1), (o[2] >> 1) - (q[2] >> 1)};
+                    int a1 = 0, b1 = -1, a2 = 0, b2 = -1;
+                    if (L[0] >= -LP && L[0] <= LP && L[1] >= -LP && L[1] <= LP && L[2] >= -LP && L[2] <= LP) {
+                        const int32_t* rr = Rj + (((L[0] + LP) * NLP + (L[1] + LP)) * NLP + (L[2] + LP)) * 2;
+                        a1 = rr[0];
+                        b1 = rr[1];
+                    }
+                    if (internal && Rj1 && e1 >= -LP && e1 <= LP && e2 >= -LP && e2 <= LP && e3 >= -LP && e3 <= LP) {
+                        const int32_t* rr = Rj1 + (((e1 + LP) * NLP + (e2 + LP)) * NLP + (e3 + LP)) * 2;
+                        a2 = rr[0];
+                        b2 = rr[1];
+                    }
+                    const int n1 = b1 >= a1 ? b1 - a1 + 1 : 0, n2 = b2 >= a2 ? b2 - a2 + 1 : 0;
+                    const int ov = (n1 && n2) ? max(0, min(b1, b2) - max(a1, a2) + 1) : 0;
+                    cnt += (unsigned long long)(n1 + n2 - 2 * ov);
+                }
+    }
+    atomicAdd(total, cnt);
+}
+
+template <int K>
+struct ApplyLaunch {
+    static void run(hipStream_t st, int64_t nout, const double* Xr, int64_t nreal, const double* Xg, const int32_t* nbr,
+                    int Lr, const uint8_t* cmask, int valid, const Tpl* tpl, int ntpl, const double* Fj, const double* w,
+                    double* out) {
+        ns_apply_kernel<K><<<(unsigned)nout, AT, 0, st>>>(Xr, nreal, Xg, nbr, Lr, cmask, valid, tpl, ntpl, Fj, w, out);
+    }
+};
+template <int K>
+struct GhostLaunch {
+    static void run(hipStream_t st, int64_t ng, int jm1, const uint64_t* gk, const uint64_t* keys, int64_t nn,
+                    const LevelTab2& lt, const double* coef, const double* Ht, double* gout) {
+        ghost_kernel<K><<<(unsigned)ng, AT, 0, st>>>(jm1, gk, keys, nn, lt, coef, Ht, gout);
+    }
+};
+template <int K>
+struct AssembleLaunch {
+    static void run(hipStream_t st, int64_t nb, int j, const int64_t* pb, const int* pc, int64_t off, const double* Ht,
+                    double* coef) {
+        assemble_kernel<K><<<(unsigned)nb, AT, 0, st>>>(j, pb, pc, off, Ht, coef);
+    }
+};
+
+template <template <int> class Fn, class... Args>
+void dispatch_k(int k, Args&&... args) {
+    switch (k) {
+        case 1: Fn<1>::run(args...); break;
+        case 2: Fn<2>::run(args...); break;
+        case 3: Fn<3>::run(args...); break;
+        case 4: Fn<4>::run(args...); break;
+        case 5: Fn<5>::run(args...); break;
+        case 6: Fn<6>::run(args...); break;
+        case 7: Fn<7>::run(args...); break;
+        case 8: Fn<8>::run(args...); break;
+        default: fail(MWNS_EINVAL, "unsupported k");
+    }
+}
+
+// Coarsest per-dimension partition of [-LP, LP] on which a plan row is constant; returns cells.
+std::vector<std::array<int, 2>> segments(const int32_t* row, int d) {
+    auto slice_equal = [&](int t) {   // plan slices at coordinate t and t+1 along dimension d
+        for (int a = -LP; a <= LP; ++a)
+            for (int b = -LP; b <= LP; ++b) {
+                int c0[3], c1[3];
+                c0[d] = t; c1[d] = t + 1;
+                const int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
+                c0[o1] = c1[o1] = a;
+                c0[o2] = c1[o2] = b;
+                const int32_t* r0 = row + (((c0[0] + LP) * NLP + (c0[1] + LP)) * NLP + (c0[2] + LP)) * 2;
+                const int32_t* r1 = row + (((c1[0] + LP) * NLP + (c1[1] + LP)) * NLP + (c1[2] + LP)) * 2;
+                const bool e0 = r0[1] < r0[0], e1 = r1[1] < r1[0];
+                if (e0 != e1) return false;
+                if (!e0 && (r0[0] != r1[0] || r0[1] != r1[1])) return false;
+            }
+        return true;
+    };
+    std::vector<std::array<int, 2>> seg;
+    int start = -LP;
+    for (int t = -LP; t < LP; ++t)
+        if (!slice_equal(t)) {
+            seg.push_back({start, t});
+            start = t + 1;
+        }
+    seg.push_back({start, LP});
+    return seg;
+}
+
+void append_templates(const int32_t* row, bool down, std::vector<Tpl>& out) {
+    std::vector<std::array<int, 2>> s[3];
+    for (int d = 0; d < 3; ++d) s[d] = segments(row, d);
+    for (auto& a : s[0])
+        for (auto& b : s[1])
+            for (auto& c : s[2]) {
+                const int32_t* rr = row + (((a[0] + LP) * NLP + (b[0] + LP)) * NLP + (c[0] + LP)) * 2;
+                if (rr[1] < rr[0]) continue;
+                Tpl t{};
+                const std::array<int, 2>* cell[3] = {&a, &b, &c};
+                for (int d = 0; d < 3; ++d) {
+                    const int lo = (*cell[d])[0], hi = (*cell[d])[1];
+                    if (down) {   // fine l in [lo, hi]  <=>  coarse L in [ceil((lo-1)/2), floor((hi+1)/2)]
+                        t.lo[d] = (int)std::ceil((lo - 1) / 2.0);
+                        t.hi[d] = (int)std::floor((hi + 1) / 2.0);
+                        t.mlo[d] = lo;
+                        t.mhi[d] = hi;
+                    } else {
+                        t.lo[d] = lo;
+                        t.hi[d] = hi;
+                        t.mlo[d] = -LF;
+                        t.mhi[d] = LF;
+                    }
+                }
+                t.m1 = rr[0];
+                t.m2 = rr[1];
+                t.dpart = down ? 1 : 0;
+                out.push_back(t);
+            }
+}
+
+LevelTab2 level_tab2(const mwns_tree* t) {
+    LevelTab2 lt{};
+    for (int j = 0; j <= t->depth; ++j) {
+        lt.node_off[j] = t->lev[j].node_off;
+        lt.brick_off[j] = t->lev[j].brick_off;
+    }
+    lt.depth = t->depth;
+    return lt;
+}
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        MWNS_HIP(hipEventCreate(&a));
+        MWNS_HIP(hipEventCreate(&b));
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    void start() { MWNS_HIP(hipEventRecord(a, st)); }
+    void stop() { MWNS_HIP(hipEventRecord(b, st)); }
+    double ms() {
+        MWNS_HIP(hipEventSynchronize(b));
+        float v = 0.f;
+        MWNS_HIP(hipEventElapsedTime(&v, a, b));
+        return v;
+    }
+};
+
+}  // namespace
+}  // namespace mwns
+
+using namespace mwns;
+
+extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
+                                  mwns_apply_stats* stats) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
+    if ((mode & 0xff) != MWNS_F64) fail(MWNS_EINVAL, "unsupported precision mode");
+    if (op->k != f->k) fail(MWNS_EINVAL, "operator and tree have different k");
+    if (op->max_level < f->depth) fail(MWNS_EINVAL, "operator max_level is below the tree depth");
+    const int k = f->k;
+    const int64_t E = brick_elems(k);
+    hipStream_t st = ctx->stream;
+    std::unique_ptr<mwns_tree> out(new mwns_tree);
+    out->ctx = ctx;
+    out->k = k;
+    out->depth = f->depth;
+    out->nnodes = f->nnodes;
+    out->nleaves = f->nleaves;
+    out->nbricks = f->nbricks;
+    out->lev = f->lev;
+    out->keys = f->keys;
+    out->leaf = f->leaf;
+    out->brick_parent = f->brick_parent;
+    out->dkeys.reset(ctx, f->nnodes);
+    out->dleaf.reset(ctx, f->nnodes);
+    MWNS_HIP(hipMemcpyAsync(out->dkeys.p, f->dkeys.p, f->nnodes * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    MWNS_HIP(hipMemcpyAsync(out->dleaf.p, f->dleaf.p, f->nnodes, hipMemcpyDeviceToDevice, st));
+    out->coef.reset(ctx, (size_t)f->nbricks * E);
+    LevelTab2 lt = level_tab2(f);
+    std::vector<double> Ht(2 * k * k);
+    {
+        std::vector<double> H(2 * k * k);
+        two_scale_filters(k, H.data(), H.data() + k * k);
+        for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < k; ++a)
+                for (int c = 0; c < k; ++c) Ht[s * k * k + c * k + a] = H[s * k * k + a * k + c];
+    }
+    DevArray<double> dHt(ctx, Ht.size());
+    dHt.upload(Ht.data(), Ht.size(), st);
+    const int depth = f->depth;
+    const int64_t planrow = (int64_t)NLP3 * 2;
+    // ---- per level: templates, closure tables, ghost bricks
+    struct LevelWork {
+        std::vector<Tpl> tpl;
+        int Lr = 0;
+        int64_t nout = 0, nghost = 0, nleafonly = 0;
+        DevArray<int32_t> nbr;
+        DevArray<uint8_t> cmask;
+        DevArray<Tpl> dtpl;
+        DevArray<double> ghosts;
+        DevArray<uint64_t> pkeys;
+        int valid = 0xff;
+    };
+    std::vector<LevelWork> W(depth + 1);
+    Timer tclos(st), tcon(st), tasm(st);
+    tclos.start();
+    int64_t total_ghosts = 0;
+    for (int j = 0; j <= depth; ++j) {
+        LevelWork& lw = W[j];
+        const mwns_level& L = f->lev[j];
+        lw.nout = L.nbricks;
+        if (j == 0) {
+            Tpl t{};
+            for (int d = 0; d < 3; ++d) { t.lo[d] = t.hi[d] = 0; t.mlo[d] = -LF; t.mhi[d] = LF; }
+            const int32_t* r0 = op->plan.data() + (((LP * NLP) + LP) * NLP + LP) * 2;
+            t.m1 = r0[0];
+            t.m2 = r0[1];
+            t.dpart = 0;
+            if (t.m2 >= t.m1) lw.tpl.push_back(t);
+            lw.valid = 0x01;
+        } else {
+            append_templates(op->plan.data() + (int64_t)j * planrow, false, lw.tpl);
+        }
+        if (j < depth && j + 1 <= op->max_level) append_templates(op->plan.data() + (int64_t)(j + 1) * planrow, true, lw.tpl);
+        int Lr = 0;
+        for (const Tpl& t : lw.tpl)
+            for (int d = 0; d < 3; ++d) Lr = std::max(Lr, std::max(std::abs(t.lo[d]), std::abs(t.hi[d])));
+        lw.Lr = Lr;
+        const int NL = 2 * Lr + 1, NL3 = NL * NL * NL;
+        // internal-children masks
+        std::vector<uint8_t> cm(lw.nout, 0);
+        if (j == 0) cm[0] = f->leaf[0] ? 0 : 1;
+        else
+            for (int64_t b = 0; b < lw.nout; ++b)
+                for (int s = 0; s < 8; ++s)
+                    if (!f->leaf[L.node_off + 8 * b + s]) cm[b] |= (uint8_t)(1 << s);
+        lw.cmask.reset(ctx, lw.nout);
+        lw.cmask.upload(cm.data(), lw.nout, st);
+        lw.nbr.reset(ctx, (size_t)lw.nout * NL3);
+        lw.nleafonly = 0;
+        for (int64_t b = 0; b < lw.nout; ++b) lw.nleafonly += cm[b] == 0;
+        if (j > 0) {
+            std::vector<uint64_t> pk(lw.nout);
+            for (int64_t b = 0; b < lw.nout; ++b) pk[b] = f->keys[f->brick_parent[L.brick_off + b]];
+            lw.pkeys.reset(ctx, lw.nout);
+            lw.pkeys.upload(pk.data(), lw.nout, st);
+        }
+        if (lw.tpl.empty()) continue;
+        if (j == 0) {
+            std::vector<int32_t> nb(NL3, -1);
+            nb[(Lr * NL + Lr) * NL + Lr] = 0;
+            lw.nbr.upload(nb.data(), NL3, st);
+            continue;
+        }
+        DevArray<uint64_t> miss(ctx, (size_t)lw.nout * NL3);
+        const int64_t n = lw.nout * NL3;
+        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(lw.nout, j - 1, lw.pkeys.p, Lr, lw.nbr.p, miss.p);
+        MWNS_HIP(hipGetLastError());
+        std::vector<uint64_t> hm(n);
+        miss.download(hm.data(), n, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+        std::vector<uint64_t> gk;
+        for (uint64_t v : hm)
+            if (v != ~0ull) gk.push_back(v);
+        std::sort(gk.begin(), gk.end());
+        gk.erase(std::unique(gk.begin(), gk.end()), gk.end());
+        lw.nghost = (int64_t)gk.size();
+        total_ghosts += lw.nghost;
+        if (lw.nghost) {
+            DevArray<uint64_t> dgk(ctx, gk.size());
+            dgk.upload(gk.data(), gk.size(), st);
+            closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, miss.p, dgk.p, lw.nghost, lw.nout, lw.nbr.p);
+            MWNS_HIP(hipGetLastError());
+            lw.ghosts.reset(ctx, (size_t)lw.nghost * E);
+            dispatch_k<GhostLaunch>(k, st, lw.nghost, j - 1, dgk.p, f->dkeys.p, f->nnodes, lt, f->coef.p, dHt.p, lw.ghosts.p);
+            MWNS_HIP(hipGetLastError());
+            MWNS_HIP(hipStreamSynchronize(st));
+        }
+    }
+    tclos.stop();
+    // ---- contractions
+    tcon.start();
+    int64_t jobs = 0;
+    double flops = 0.0;
+    for (int j = 0; j <= depth; ++j) {
+        LevelWork& lw = W[j];
+        double* outj = out->coef.p + f->lev[j].brick_off * E;
+        if (lw.tpl.empty()) {
+            MWNS_HIP(hipMemsetAsync(outj, 0, lw.nout * E * sizeof(double), st));
+            continue;
+        }
+        lw.dtpl.reset(ctx, lw.tpl.size());
+        lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), st);
+        const double* Xr = f->coef.p + f->lev[j].brick_off * E;
+        const double* Fj = op->F.p + (int64_t)j * op->M * NLF * k * k;
+        dispatch_k<ApplyLaunch>(k, st, lw.nout, Xr, lw.nout, lw.ghosts.p, lw.nbr.p, lw.Lr, lw.cmask.p, lw.valid,
+                                lw.dtpl.p, (int)lw.tpl.size(), Fj, op->dw.p, outj);
+        MWNS_HIP(hipGetLastError());
+        for (const Tpl& t : lw.tpl) {
+            const double n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
+            const double D2 = 2.0 * k;
+            const int64_t nb = t.dpart ? lw.nout - lw.nleafonly : lw.nout;
+            jobs += nb * (t.m2 - t.m1 + 1);
+            flops += (double)nb * (t.m2 - t.m1 + 1) * 2.0 * D2 * D2 * D2 * D2 * (n1 * n2 * n3 + n1 * n2 + n1);
+        }
+    }
+    tcon.stop();
+    // ---- assembly
+    tasm.start();
+    if (!(mode & MWNS_NO_ASSEMBLY)) {
+        for (int j = 1; j <= depth; ++j) {
+            const mwns_level& L = f->lev[j];
+            std::vector<int64_t> pb(L.nbricks);
+            std::vector<int> pc(L.nbricks);
+            for (int64_t b = 0; b < L.nbricks; ++b) node_brick(f, f->brick_parent[L.brick_off + b], &pb[b], &pc[b]);
+            DevArray<int64_t> dpb(ctx, pb.size());
+            DevArray<int> dpc(ctx, pc.size());
+            dpb.upload(pb.data(), pb.size(), st);
+            dpc.upload(pc.data(), pc.size(), st);
+            dispatch_k<AssembleLaunch>(k, st, L.nbricks, j, dpb.p, dpc.p, L.brick_off, dHt.p, out->coef.p);
+            MWNS_HIP(hipGetLastError());
+            MWNS_HIP(hipStreamSynchronize(st));
+        }
+    }
+    tasm.stop();
+    if (stats) {
+        mwns_apply_stats s{};
+        DevArray<unsigned long long> tot(ctx, 1);
+        MWNS_HIP(hipMemsetAsync(tot.p, 0, sizeof(unsigned long long), st));
+        DevArray<int32_t> dplan(ctx, op->plan.size());
+        dplan.upload(op->plan.data(), op->plan.size(), st);
+        for (int j = 0; j <= depth; ++j) {
+            const LevelWork& lw = W[j];
+            const int32_t* Rj1 = (j + 1 <= op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
+            count_kernel<<<(unsigned)((lw.nout + 63) / 64), 64, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
+                                                                         dplan.p + (int64_t)j * planrow, Rj1, tot.p);
+            MWNS_HIP(hipGetLastError());
+        }
+        unsigned long long c = 0;
+        tot.download(&c, 1, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+        s.contractions = (int64_t)c;
+        s.brick_jobs = jobs;
+        s.ghost_bricks = total_ghosts;
+        s.useful_flops = flops;
+        s.ms_closure = tclos.ms();
+        s.ms_contract = tcon.ms();
+        s.ms_assemble = tasm.ms();
+        *stats = s;
+    }
+    *g = out.release();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}

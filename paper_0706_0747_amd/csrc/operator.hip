@@ -1,0 +1,380 @@
+// Operator construction: the 1-D blocks F^{j;m,l} (eq. KernelFactor) and the screening plan
+// (Sec. 4) on the device.
+//
+// F^{j;m,l}_ab = 2^-j int_{-1}^{1} exp(-beta (x+l)^2) Phi_ab(x) dx, beta = tau_m / 4^j.  On [0,1],
+// Phi^+_ab = sum_{n<2k} C_abn phi_n (App. A.4: Phi^+ is a polynomial of degree <= 2k-1), and
+// Phi^-_ab(-x) = (-1)^{a+b} Phi^+_ab(x) (Prop. 1, item 2) folds [-1,0] onto [0,1], so
+//   F^{j;m,l}_ab = 2^-j sum_n C_abn (I_n(l) + (-1)^{a+b} I_n(-l)),
+//   I_n(l) = int_0^1 exp(-beta (x+l)^2) phi_n(x) dx,
+// which needs 2k Gaussian moments per (j, m, l) instead of k^2 integrals.  The moments use a
+// composite 24-point Gauss-Legendre rule on panels graded around the point of [0,1] nearest to the
+// Gaussian centre -l (widths 2^q / sqrt(beta)), plus a uniform split of [0,1] in eighths.
+//
+// Screening: for scale j >= 1, term m and coarse |L| = 0..3 the kernels form the 2k x 2k
+// super-blocks S = [[F^{2L}, F^{2L-1}], [F^{2L+1}, F^{2L}]] and U = [H0 H1]^T F^{j-1;L} [H0 H1] and
+// their Frobenius norms N_F, N_upF, N_dif (eq. BlockNorms); the plan kernel combines them into the
+// 3-D estimate (eq. NormEstimateUsing1DBlocks) for each of the 20 classes of sorted |L| and keeps
+// the term range left after discarding the longest prefix and suffix whose cumulative weighted
+// estimate stays <= theta/2 (empty if the total is <= theta), theta = eps sum_m w_m ||F^{0;m,0}||_F^3.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "mwns_internal.h"
+
+namespace mwns {
+namespace {
+
+constexpr int NGL = 24;          // points per panel
+constexpr int MAXBRK = 40;       // panel end points per integral
+constexpr int MOMW = 64;         // threads per moment block
+
+__global__ void __launch_bounds__(MOMW) moments_kernel(int k, int M, int nlev, const double* __restrict__ tau,
+                                                       const double* __restrict__ glx, const double* __restrict__ glw,
+                                                       double* __restrict__ mom /* [nlev][M][NLF][2k] */) {
+    const int blk = blockIdx.x;
+    const int li = blk % NLF;
+    const int m = (blk / NLF) % M;
+    const int j = blk / (NLF * M);
+    const int K2 = 2 * k;
+    const double l = (double)(li - LF);
+    const double beta = tau[m] * ldexp(1.0, -2 * j);
+    __shared__ double brk[MAXBRK];
+    __shared__ int nbrk;
+    __shared__ double part[MOMW][2 * KMAX];
+    if (threadIdx.x == 0) {
+        const double c = -l;
+        const double p = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
+        const double s = 1.0 / sqrt(beta);
+        double v[MAXBRK];
+        int n = 0;
+        v[n++] = 0.0;
+        v[n++] = 1.0;
+        for (int i = 1; i < 8; ++i) v[n++] = i / 8.0;
+        for (int q = -3; q <= 6; ++q) {
+            double d = s * ldexp(1.0, q);
+            if (p - d > 0.0 && p - d < 1.0) v[n++] = p - d;
+            if (p + d > 0.0 && p + d < 1.0) v[n++] = p + d;
+        }
+        // insertion sort, then drop duplicates
+        for (int a = 1; a < n; ++a) {
+            double x = v[a];
+            int b = a - 1;
+            while (b >= 0 && v[b] > x) { v[b + 1] = v[b]; --b; }
+            v[b + 1] = x;
+        }
+        int u = 0;
+        for (int a = 0; a < n; ++a)
+            if (u == 0 || v[a] > brk[u - 1]) brk[u++] = v[a];
+        nbrk = u;
+    }
+    __syncthreads();
+    double acc[2 * KMAX];
+    for (int n = 0; n < K2; ++n) acc[n] = 0.0;
+    const int npts = (nbrk - 1) * NGL;
+    for (int pt = threadIdx.x; pt < npts; pt += MOMW) {
+        const int pan = pt / NGL, g = pt % NGL;
+        const double a = brk[pan], b = brk[pan + 1];
+        const double x = a + (b - a) * glx[g];
+        const double wt = (b - a) * glw[g] * exp(-beta * (x + l) * (x + l));
+        // phi_n(x) = sqrt(2n+1) P_n(2x-1) by the three-term recurrence
+        const double t = 2.0 * x - 1.0;
+        double p0 = 1.0, p1 = t;
+        acc[0] += wt;
+        if (K2 > 1) acc[1] += wt * t * 1.7320508075688772;
+        for (int n = 2; n < K2; ++n) {
+            double p2 = ((2 * n - 1) * t * p1 - (n - 1) * p0) / n;
+            acc[n] += wt * p2 * sqrt(2.0 * n + 1.0);
+            p0 = p1;
+            p1 = p2;
+        }
+    }
+    for (int n = 0; n < K2; ++n) part[threadIdx.x][n] = acc[n];
+    __syncthreads();
+    if (threadIdx.x < K2) {
+        double s = 0.0;
+        for (int r = 0; r < MOMW; ++r) s += part[r][threadIdx.x];
+        mom[(int64_t)blk * K2 + threadIdx.x] = s;
+    }
+}
+
+__global__ void combine_kernel(int k, int M, int nlev, const double* __restrict__ C, const double* __restrict__ mom,
+                               double* __restrict__ F /* [nlev][M][NLF][k][k] */) {
+    const int64_t total = (int64_t)nlev * M * NLF * k * k;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int b = idx % k;
+    const int a = (idx / k) % k;
+    const int li = (idx / (k * k)) % NLF;
+    const int64_t jm = idx / ((int64_t)k * k * NLF);   // j * M + m
+    const int j = (int)(jm / M);
+    const int K2 = 2 * k;
+    const double* mp = mom + (jm * NLF + li) * K2;
+    const double* mm = mom + (jm * NLF + (2 * LF - li)) * K2;   // I_n(-l)
+    const double sg = ((a + b) & 1) ? -1.0 : 1.0;
+    const double* c = C + (a * k + b) * K2;
+    double s = 0.0;
+    for (int n = 0; n < K2; ++n) s += c[n] * (mp[n] + sg * mm[n]);
+    F[idx] = ldexp(s, -j);
+}
+
+// Frobenius norms of the super-blocks for scales 1..nlev-1, |L| = 0..LP; nf0[m] = ||F^{0;m,0}||_F.
+__global__ void norms_kernel(int k, int M, int nlev, const double* __restrict__ F, const double* __restrict__ H,
+                             double* __restrict__ norms /* [nlev][M][LP+1][3] */, double* __restrict__ nf0) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nL = LP + 1;
+    const int kk = k * k;
+    if (idx < M) {
+        const double* f = F + ((int64_t)idx * NLF + LF) * kk;
+        double s = 0.0;
+        for (int i = 0; i < kk; ++i) s += f[i] * f[i];
+        nf0[idx] = sqrt(s);
+    }
+    if (idx >= (nlev - 1) * M * nL) return;
+    const int L = idx % nL;
+    const int m = (idx / nL) % M;
+    const int j = 1 + idx / (nL * M);
+    const double* Fj = F + ((int64_t)j * M + m) * NLF * kk;
+    const double* Fc = F + ((int64_t)(j - 1) * M + m) * NLF * kk + (L + LF) * kk;
+    const double* Hs[2] = {H, H + kk};
+    double sF = 0.0, sU = 0.0, sD = 0.0;
+    for (int so = 0; so < 2; ++so)
+        for (int si = 0; si < 2; ++si) {
+            const int l = 2 * L + so - si;
+            const double* fb = Fj + (l + LF) * kk;
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) {
+                    double u = 0.0;   // (H^so^T F^{j-1;L} H^si)_ab
+                    for (int p = 0; p < k; ++p) {
+                        double t = 0.0;
+                        for (int q = 0; q < k; ++q) t += Fc[p * k + q] * Hs[si][q * k + b];
+                        u += Hs[so][p * k + a] * t;
+                    }
+                    const double f = fb[a * k + b];
+                    sF += f * f;
+                    sU += u * u;
+                    sD += (f - u) * (f - u);
+                }
+        }
+    double* o = norms + (((int64_t)j * M + m) * nL + L) * 3;
+    o[0] = sqrt(sF);
+    o[1] = sqrt(sU);
+    o[2] = sqrt(sD);
+}
+
+// One thread per (scale j >= 1, canonical class (c0 <= c1 <= c2)): term range.
+__global__ void plan_kernel(int M, int nlev, double eps, const double* __restrict__ w, const double* __restrict__ norms,
+                            const double* __restrict__ nf0, int32_t* __restrict__ ranges /* [nlev][20][2] */) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (nlev - 1) * 20) return;
+    const int cls = idx % 20;
+    const int j = 1 + idx / 20;
+    int c[3] = {0, 0, 0}, cnt = 0;
+    for (int a = 0; a <= LP; ++a)
+        for (int b = a; b <= LP; ++b)
+            for (int d = b; d <= LP; ++d) {
+                if (cnt == cls) { c[0] = a; c[1] = b; c[2] = d; }
+                ++cnt;
+            }
+    double theta = 0.0;
+    for (int m = 0; m < M; ++m) theta += w[m] * nf0[m] * nf0[m] * nf0[m];
+    theta *= eps;
+    const int nL = LP + 1;
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    auto e_of = [&](int m) {
+        const double* nb = norms + ((int64_t)j * M + m) * nL * 3;
+        double tot = 0.0;
+        for (int q = 0; q < 6; ++q) {
+            const double* P = nb + c[perm[q][0]] * 3;
+            const double* Q = nb + c[perm[q][1]] * 3;
+            const double* R = nb + c[perm[q][2]] * 3;
+            // N_dif N_F N_F + N_upF N_dif N_F + N_upF N_upF N_dif
+            tot += P[2] * Q[0] * R[0] + P[1] * Q[2] * R[0] + P[1] * Q[1] * R[2];
+        }
+        return w[m] * (tot / 6.0);
+    };
+    double total = 0.0;
+    int m1 = -1;
+    for (int m = 0; m < M; ++m) {
+        total += e_of(m);
+        if (m1 < 0 && total > 0.5 * theta) m1 = m;
+    }
+    int32_t* out = ranges + (int64_t)idx * 2;
+    if (total <= theta) { out[0] = 0; out[1] = -1; return; }
+    double suf = 0.0;
+    int m2 = M - 1;
+    for (int m = M - 1; m >= 0; --m) {
+        suf += e_of(m);
+        if (suf > 0.5 * theta) { m2 = m; break; }
+    }
+    out[0] = m1;
+    out[1] = m2;
+}
+
+int class_index(int a, int b, int c) {   // a <= b <= c
+    int cnt = 0;
+    for (int x = 0; x <= LP; ++x)
+        for (int y = x; y <= LP; ++y)
+            for (int z = y; z <= LP; ++z) {
+                if (x == a && y == b && z == c) return cnt;
+                ++cnt;
+            }
+    return -1;
+}
+
+}  // namespace
+}  // namespace mwns
+
+using namespace mwns;
+
+extern "C" {
+
+mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const double* w, double eps, int max_level,
+                           const mwns_op_opts* opts, mwns_op** out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !out || !tau || !w) fail(MWNS_EINVAL, "NULL argument");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, 8]");
+    if (M < 1 || max_level < 0 || max_level > MAXLEV || !(eps > 0.0)) fail(MWNS_EINVAL, "M, max_level or eps out of range");
+    for (int m = 0; m < M; ++m)
+        if (!(tau[m] > 0.0) || !(w[m] >= 0.0) || !std::isfinite(tau[m]) || !std::isfinite(w[m]))
+            fail(MWNS_EINVAL, "tau must be > 0 and w >= 0, finite");
+    std::unique_ptr<mwns_op> op(new mwns_op);
+    op->ctx = ctx;
+    op->k = k;
+    op->M = M;
+    op->max_level = max_level;
+    op->eps = eps;
+    op->group = opts ? (opts->group_regions != 0) : 1;
+    op->tau.assign(tau, tau + M);
+    op->w.assign(w, w + M);
+    const int nlev = max_level + 1;
+    const int K2 = 2 * k;
+    hipStream_t st = ctx->stream;
+    // tables
+    std::vector<double> C(k * k * K2);
+    crosscorr_plus_coeffs(k, C.data());
+    Quad gl = gauss_legendre01(NGL);
+    DevArray<double> dC(ctx, C.size()), dtau(ctx, M), dgx(ctx, NGL), dgw(ctx, NGL);
+    dC.upload(C.data(), C.size(), st);
+    dtau.upload(tau, M, st);
+    dgx.upload(gl.x.data(), NGL, st);
+    dgw.upload(gl.w.data(), NGL, st);
+    op->dw.reset(ctx, M);
+    op->dw.upload(w, M, st);
+    DevArray<double> mom(ctx, (size_t)nlev * M * NLF * K2);
+    op->F.reset(ctx, (size_t)nlev * M * NLF * k * k);
+    moments_kernel<<<nlev * M * NLF, MOMW, 0, st>>>(k, M, nlev, dtau.p, dgx.p, dgw.p, mom.p);
+    MWNS_HIP(hipGetLastError());
+    const int64_t nF = (int64_t)nlev * M * NLF * k * k;
+    combine_kernel<<<(unsigned)((nF + 255) / 256), 256, 0, st>>>(k, M, nlev, dC.p, mom.p, op->F.p);
+    MWNS_HIP(hipGetLastError());
+    // screening
+    DevArray<double> dH = upload_filters(ctx, k);
+    const int nL = LP + 1;
+    DevArray<double> norms(ctx, (size_t)nlev * M * nL * 3), nf0(ctx, M);
+    const int nth = std::max(M, (nlev - 1) * M * nL);
+    norms_kernel<<<(nth + 127) / 128, 128, 0, st>>>(k, M, nlev, op->F.p, dH.p, norms.p, nf0.p);
+    MWNS_HIP(hipGetLastError());
+    std::vector<int32_t> ranges(std::max(1, (nlev - 1) * 20) * 2);
+    if (nlev > 1) {
+        DevArray<int32_t> dr(ctx, ranges.size());
+        plan_kernel<<<((nlev - 1) * 20 + 63) / 64, 64, 0, st>>>(M, nlev, eps, op->dw.p, norms.p, nf0.p, dr.p);
+        MWNS_HIP(hipGetLastError());
+        dr.download(ranges.data(), ranges.size(), st);
+    }
+    std::vector<double> hnf0(M);
+    nf0.download(hnf0.data(), M, st);
+    MWNS_HIP(hipStreamSynchronize(st));
+    double theta = 0.0;
+    for (int m = 0; m < M; ++m) theta += w[m] * hnf0[m] * hnf0[m] * hnf0[m];
+    op->theta = theta * eps;
+    // expand to [nlev][7][7][7][2] (grouping: hull of the ranges of Core / Boundary-1/2/3)
+    op->plan.assign((size_t)nlev * NLP3 * 2, 0);
+    for (size_t i = 1; i < op->plan.size(); i += 2) op->plan[i] = -1;
+    const int root = ((LP * NLP) + LP) * NLP + LP;
+    op->plan[root * 2] = 0;
+    op->plan[root * 2 + 1] = M - 1;
+    for (int j = 1; j < nlev; ++j) {
+        const int32_t* rj = ranges.data() + (size_t)(j - 1) * 40;
+        int hull[4][2];
+        for (int g = 0; g < 4; ++g) { hull[g][0] = M; hull[g][1] = -1; }
+        for (int a = 0; a <= LP; ++a)
+            for (int b = a; b <= LP; ++b)
+                for (int c = b; c <= LP; ++c) {
+                    int ci = class_index(a, b, c);
+                    int g = (a > 1) + (b > 1) + (c > 1);
+                    if (rj[ci * 2 + 1] >= rj[ci * 2]) {
+                        hull[g][0] = std::min(hull[g][0], rj[ci * 2]);
+                        hull[g][1] = std::max(hull[g][1], rj[ci * 2 + 1]);
+                    }
+                }
+        for (int x = -LP; x <= LP; ++x)
+            for (int y = -LP; y <= LP; ++y)
+                for (int z = -LP; z <= LP; ++z) {
+                    int s[3] = {std::abs(x), std::abs(y), std::abs(z)};
+                    std::sort(s, s + 3);
+                    int ci = class_index(s[0], s[1], s[2]);
+                    int g = (s[0] > 1) + (s[1] > 1) + (s[2] > 1);
+                    int m1 = rj[ci * 2], m2 = rj[ci * 2 + 1];
+                    if (op->group) {
+                        if (hull[g][1] >= hull[g][0]) { m1 = hull[g][0]; m2 = hull[g][1]; }
+                        else { m1 = 0; m2 = -1; }
+                    }
+                    size_t o = (((size_t)j * NLP3) + ((x + LP) * NLP + (y + LP)) * NLP + (z + LP)) * 2;
+                    op->plan[o] = m1;
+                    op->plan[o + 1] = m2;
+                }
+    }
+    *out = op.release();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_op_plan_export(const mwns_op* op, int32_t* plan, size_t* count) {
+    MWNS_GUARD_BEGIN
+    if (!op || !count) fail(MWNS_EINVAL, "NULL argument");
+    if (!plan) { *count = op->plan.size(); return MWNS_OK; }
+    if (*count < op->plan.size()) {
+        *count = op->plan.size();
+        fail(MWNS_ERANGE, "plan buffer too small");
+    }
+    std::copy(op->plan.begin(), op->plan.end(), plan);
+    *count = op->plan.size();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_op_plan_import(mwns_op* op, const int32_t* plan, size_t count) {
+    MWNS_GUARD_BEGIN
+    if (!op || !plan) fail(MWNS_EINVAL, "NULL argument");
+    if (count != op->plan.size()) fail(MWNS_EINVAL, "plan size mismatch");
+    for (size_t i = 0; i < count; i += 2) {
+        int32_t a = plan[i], b = plan[i + 1];
+        if (b >= a && (a < 0 || b >= op->M)) fail(MWNS_EINVAL, "plan range outside [0, M)");
+    }
+    op->plan.assign(plan, plan + count);
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_op_tables_export(mwns_ctx* ctx, const mwns_op* op, double* F, size_t* count) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !op || !count) fail(MWNS_EINVAL, "NULL argument");
+    const size_t n = op->F.n;
+    if (!F) { *count = n; return MWNS_OK; }
+    if (*count < n) {
+        *count = n;
+        fail(MWNS_ERANGE, "table buffer too small");
+    }
+    op->F.download(F, n, ctx->stream);
+    MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    *count = n;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+double mwns_op_threshold(const mwns_op* op) { return op ? op->theta : 0.0; }
+
+void mwns_op_destroy(mwns_op* op) { delete op; }
+
+}  // extern "C"

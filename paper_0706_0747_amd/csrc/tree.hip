@@ -1,0 +1,728 @@
+// Function trees on the device: adaptive projection of Gaussian sums (Alg. 1), the redundant tree
+// (Sec. 2.2.1) by two-scale decomposition (App. A.3, eq. decomp_scaling), point evaluation
+// (App. A.1), import and export.
+//
+// Storage: nodes in canonical order (ascending key: level-major, then Morton).  The 8 children of
+// every internal node are consecutive and form a "brick"; bricks of level j are ordered like
+// their parents.  Coefficients live per brick as a (2k)^3 tensor with index u = s*k + a in each
+// dimension (s = child parity, a = degree), so the 8 siblings of a level form one dense block; the
+// root occupies child 0 of a level-0 brick whose other 7 children are zero.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <numeric>
+
+#include "mwns_internal.h"
+
+namespace mwns {
+
+struct LevelTab {
+    int64_t node_off[MAXLEV + 2];
+    int64_t brick_off[MAXLEV + 2];
+    int depth;
+};
+
+__device__ inline void node_to_brick(const LevelTab& lt, int j, int64_t node, int64_t* brick, int* child) {
+    if (j == 0) { *brick = 0; *child = 0; return; }
+    int64_t r = node - lt.node_off[j];
+    *brick = lt.brick_off[j] + (r >> 3);
+    *child = (int)(r & 7);
+}
+
+__device__ inline int64_t brick_index(int k, int child, int a, int b, int c) {
+    const int P = 2 * k;
+    return ((int64_t)((child & 1) * k + a) * P + ((child >> 1) & 1) * k + b) * P + ((child >> 2) & 1) * k + c;
+}
+
+namespace {
+
+constexpr int PT = 256;   // threads of the projection / transform blocks
+constexpr int CH = 32;    // source terms per chunk
+
+// One block per candidate box of level j (Alg. 1): source values at the box's k^3 Gauss-Legendre
+// nodes and at the 8 children's nodes, coefficients s (eq. fvals2coefs in 3-D), values
+// interpolated from s at the children's nodes, max |f - f~| and the refinement decision.
+template <int K>
+__global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
+                                                     const double* __restrict__ src /* x,y,z,a,cf per term */,
+                                                     double thr, const double* __restrict__ tab, double* __restrict__ s_out,
+                                                     uint8_t* __restrict__ refine, double* __restrict__ err_out) {
+    constexpr int K3 = K * K * K;
+    constexpr int NQ = 3 * K;                // 1-D points: K own nodes, then 2K children nodes
+    constexpr int NP = 9 * K3;               // own nodes + (2K)^3 children nodes
+    constexpr int PER = (NP + PT - 1) / PT;
+    __shared__ double E[CH][3][NQ];
+    __shared__ double fv[NP];
+    __shared__ double t1[4 * K3];
+    __shared__ double t2[8 * K3];
+    __shared__ double red[PT];
+    // tab: P[a][i] = phi_a(x_i) w_i (K*K), Q[q][a] = phi_a((s + x_i)/2), q = s*K + i (2K*K), gx[K]
+    const double* P = tab;
+    const double* Q = tab + K * K;
+    const double* gx = tab + 3 * K * K;
+    const int box = blockIdx.x;
+    int64_t l[3];
+    key_coords(keys[box], l);
+    const double h = ldexp(1.0, -j);
+    double acc[PER];
+    for (int r = 0; r < PER; ++r) acc[r] = 0.0;
+    for (int c0 = 0; c0 < nsrc; c0 += CH) {
+        const int nc = min(CH, nsrc - c0);
+        for (int e = threadIdx.x; e < nc * 3 * NQ; e += PT) {
+            const int q = e % NQ, d = (e / NQ) % 3, i = e / (3 * NQ);
+            const double* sp = src + (int64_t)(c0 + i) * 5;
+            double x;
+            if (q < K) x = h * (l[d] + gx[q]);
+            else {
+                const int s = (q - K) / K, p = (q - K) % K;
+                x = 0.5 * h * (2 * l[d] + s + gx[p]);
+            }
+            const double dx = x - sp[d];
+            E[i][d][q] = exp(-sp[3] * dx * dx);
+        }
+        __syncthreads();
+        for (int r = 0; r < PER; ++r) {
+            const int pt = threadIdx.x + r * PT;
+            if (pt >= NP) break;
+            int q0, q1, q2;
+            if (pt < K3) {
+                q0 = pt / (K * K);
+                q1 = (pt / K) % K;
+                q2 = pt % K;
+            } else {
+                const int g = pt - K3, P2 = 2 * K;
+                q0 = K + g / (P2 * P2);
+                q1 = K + (g / P2) % P2;
+                q2 = K + g % P2;
+            }
+            double a = acc[r];
+            for (int i = 0; i < nc; ++i) a += src[(int64_t)(c0 + i) * 5 + 4] * E[i][0][q0] * E[i][1][q1] * E[i][2][q2];
+            acc[r] = a;
+        }
+        __syncthreads();
+    }
+    for (int r = 0; r < PER; ++r) {
+        const int pt = threadIdx.x + r * PT;
+        if (pt < NP) fv[pt] = acc[r];
+    }
+    __syncthreads();
+    // s = 2^{-3j/2} (P (x) P (x) P) f_own, contracting the last index first
+    const double nc3 = pow(2.0, -1.5 * j);
+    for (int e = threadIdx.x; e < K3; e += PT) {
+        const int i1 = e / (K * K), i2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int i3 = 0; i3 < K; ++i3) s += P[a3 * K + i3] * fv[(i1 * K + i2) * K + i3];
+        t1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K3; e += PT) {
+        const int i1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int i2 = 0; i2 < K; ++i2) s += P[a2 * K + i2] * t1[(i1 * K + i2) * K + a3];
+        t2[e] = s;
+    }
+    __syncthreads();
+    double* sb = s_out + (int64_t)box * K3;
+    for (int e = threadIdx.x; e < K3; e += PT) {
+        const int a1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int i1 = 0; i1 < K; ++i1) s += P[a1 * K + i1] * t2[(i1 * K + a2) * K + a3];
+        s *= nc3;
+        sb[e] = s;
+        t1[e] = s;   // keep s for the interpolation
+    }
+    __syncthreads();
+    double emax = 0.0;
+    if (j < jmax) {
+        // f~ on the (2K)^3 children grid = 2^{3j/2} (Q (x) Q (x) Q) s
+        constexpr int P2 = 2 * K;
+        const double ni = pow(2.0, 1.5 * j);
+        double* u1 = t2;                     // [a1][a2][q3]   K*K*2K
+        for (int e = threadIdx.x; e < K * K * P2; e += PT) {
+            const int a1 = e / (K * P2), a2 = (e / P2) % K, q3 = e % P2;
+            double s = 0.0;
+            for (int a3 = 0; a3 < K; ++a3) s += Q[q3 * K + a3] * t1[(a1 * K + a2) * K + a3];
+            u1[e] = s;
+        }
+        __syncthreads();
+        double* u2 = t2 + 2 * K3;            // [a1][q2][q3] K*2K*2K
+        for (int e = threadIdx.x; e < K * P2 * P2; e += PT) {
+            const int a1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
+            double s = 0.0;
+            for (int a2 = 0; a2 < K; ++a2) s += Q[q2 * K + a2] * u1[(a1 * K + a2) * P2 + q3];
+            u2[e] = s;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < P2 * P2 * P2; e += PT) {
+            const int q1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
+            double s = 0.0;
+            for (int a1 = 0; a1 < K; ++a1) s += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
+            const double d = fabs(fv[K3 + e] - ni * s);
+            emax = fmax(emax, d);
+        }
+    }
+    red[threadIdx.x] = emax;
+    __syncthreads();
+    for (int s = PT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        err_out[box] = red[0];
+        refine[box] = (uint8_t)((j < jmax) && (red[0] > thr));
+    }
+}
+
+}  // namespace
+}  // namespace mwns
+
+namespace mwns {
+namespace {
+
+// Copy leaf coefficients (node-major [n][k^3], candidates of one level) into their bricks.
+__global__ void scatter_leaves_kernel(int k, int j, int64_t n, const double* __restrict__ s, const uint8_t* __restrict__ is_leaf,
+                                      LevelTab lt, double* __restrict__ coef) {
+    const int k3 = k * k * k;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * k3) return;
+    const int64_t c = idx / k3;
+    if (is_leaf && !is_leaf[c]) return;
+    const int e = (int)(idx % k3);
+    int64_t brick;
+    int child;
+    node_to_brick(lt, j, lt.node_off[j] + c, &brick, &child);
+    const int a = e / (k * k), b = (e / k) % k, cc = e % k;
+    coef[brick * (int64_t)(8 * k3) + brick_index(k, child, a, b, cc)] = s[idx];
+}
+
+// Parent block of every internal node of level j from its brick of level j+1:
+// s^j = sum_s (H^{s1} (x) H^{s2} (x) H^{s3}) s^{j+1}_s = (H (x) H (x) H) X, H = [H0 H1] (k x 2k)
+// (App. A.3, eq. decomp_scaling in each dimension).
+template <int K>
+__global__ void __launch_bounds__(PT) compress_kernel(int j, const int64_t* __restrict__ parent_node,
+                                                      const int64_t* __restrict__ child_brick, LevelTab lt,
+                                                      const double* __restrict__ Hd, double* __restrict__ coef) {
+    constexpr int P2 = 2 * K, K3 = K * K * K;
+    __shared__ double X[P2 * P2 * P2];
+    __shared__ double u1[P2 * P2 * K];
+    __shared__ double u2[P2 * K * K];
+    __shared__ double H[K * P2];
+    const int64_t i = blockIdx.x;
+    const double* xb = coef + child_brick[i] * (int64_t)(P2 * P2 * P2);
+    for (int e = threadIdx.x; e < P2 * P2 * P2; e += PT) X[e] = xb[e];
+    for (int e = threadIdx.x; e < K * P2; e += PT) {
+        const int a = e / P2, u = e % P2;
+        H[e] = Hd[(u / K) * K * K + a * K + (u % K)];     // H[a][s*K + c] = H^s[a][c]
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2 * P2 * K; e += PT) {
+        const int v1 = e / (P2 * K), v2 = (e / K) % P2, a3 = e % K;
+        double s = 0.0;
+        for (int v3 = 0; v3 < P2; ++v3) s += H[a3 * P2 + v3] * X[(v1 * P2 + v2) * P2 + v3];
+        u1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2 * K * K; e += PT) {
+        const int v1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int v2 = 0; v2 < P2; ++v2) s += H[a2 * P2 + v2] * u1[(v1 * P2 + v2) * K + a3];
+        u2[e] = s;
+    }
+    __syncthreads();
+    int64_t brick;
+    int child;
+    node_to_brick(lt, j, parent_node[i], &brick, &child);
+    double* ob = coef + brick * (int64_t)(8 * K3);
+    for (int e = threadIdx.x; e < K3; e += PT) {
+        const int a1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
+        double s = 0.0;
+        for (int v1 = 0; v1 < P2; ++v1) s += H[a1 * P2 + v1] * u2[(v1 * K + a2) * K + a3];
+        ob[brick_index(K, child, a1, a2, a3)] = s;
+    }
+}
+
+// f at points from the leaf holding each point (App. A.1).
+template <int K>
+__global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const uint64_t* __restrict__ keys, int64_t nnodes,
+                            const uint8_t* __restrict__ leaf, LevelTab lt, const double* __restrict__ coef,
+                            double* __restrict__ out, int* __restrict__ bad) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const double x[3] = {xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]};
+    for (int j = 0; j <= lt.depth; ++j) {
+        const int64_t side = (int64_t)1 << j;
+        int64_t l[3];
+        double u[3];
+        for (int d = 0; d < 3; ++d) {
+            int64_t v = (int64_t)floor(x[d] * side);
+            v = v < 0 ? 0 : (v > side - 1 ? side - 1 : v);
+            l[d] = v;
+            u[d] = x[d] * side - v;
+        }
+        const int64_t node = find_sorted(keys, nnodes, make_key(j, l[0], l[1], l[2]));
+        if (node < 0) break;
+        if (!leaf[node]) continue;
+        double ph[3][K];
+        for (int d = 0; d < 3; ++d) {
+            const double t = 2.0 * u[d] - 1.0;
+            double p0 = 1.0, p1 = t;
+            ph[d][0] = 1.0;
+            if (K > 1) ph[d][1] = t;
+            for (int a = 2; a < K; ++a) {
+                const double p2 = ((2 * a - 1) * t * p1 - (a - 1) * p0) / a;
+                ph[d][a] = p2;
+                p0 = p1;
+                p1 = p2;
+            }
+            for (int a = 0; a < K; ++a) ph[d][a] *= sqrt(2.0 * a + 1.0);
+        }
+        int64_t brick;
+        int child;
+        node_to_brick(lt, j, node, &brick, &child);
+        const double* cb = coef + brick * (int64_t)(8 * K * K * K);
+        double s = 0.0;
+        for (int a = 0; a < K; ++a) {
+            double sa = 0.0;
+            for (int b = 0; b < K; ++b) {
+                double sb = 0.0;
+                for (int c = 0; c < K; ++c) sb += cb[brick_index(K, child, a, b, c)] * ph[2][c];
+                sa += sb * ph[1][b];
+            }
+            s += sa * ph[0][a];
+        }
+        out[p] = s * pow(2.0, 1.5 * j);
+        return;
+    }
+    atomicAdd(bad, 1);
+    out[p] = 0.0;
+}
+
+template <template <int> class Fn, class... Args>
+void dispatch_k(int k, Args&&... args) {
+    switch (k) {
+        case 1: Fn<1>::run(args...); break;
+        case 2: Fn<2>::run(args...); break;
+        case 3: Fn<3>::run(args...); break;
+        case 4: Fn<4>::run(args...); break;
+        case 5: Fn<5>::run(args...); break;
+        case 6: Fn<6>::run(args...); break;
+        case 7: Fn<7>::run(args...); break;
+        case 8: Fn<8>::run(args...); break;
+        default: fail(MWNS_EINVAL, "unsupported k");
+    }
+}
+
+template <int K>
+struct ProjectLaunch {
+    static void run(hipStream_t st, int64_t n, int j, int jmax, const uint64_t* keys, int nsrc, const double* src,
+                    double thr, const double* tab, double* s, uint8_t* ref, double* err) {
+        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, thr, tab, s, ref, err);
+    }
+};
+template <int K>
+struct CompressLaunch {
+    static void run(hipStream_t st, int64_t n, int j, const int64_t* pn, const int64_t* cb, const LevelTab& lt,
+                    const double* H, double* coef) {
+        compress_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, pn, cb, lt, H, coef);
+    }
+};
+template <int K>
+struct EvalLaunch {
+    static void run(hipStream_t st, int64_t n, const double* xyz, const uint64_t* keys, int64_t nn, const uint8_t* leaf,
+                    const LevelTab& lt, const double* coef, double* out, int* bad) {
+        eval_kernel<K><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, xyz, keys, nn, leaf, lt, coef, out, bad);
+    }
+};
+
+LevelTab level_tab(const mwns_tree* t) {
+    LevelTab lt{};
+    for (int j = 0; j <= t->depth; ++j) {
+        lt.node_off[j] = t->lev[j].node_off;
+        lt.brick_off[j] = t->lev[j].brick_off;
+    }
+    lt.depth = t->depth;
+    return lt;
+}
+
+}  // namespace
+
+// Levels, node offsets and bricks from sorted keys and leaf flags.  Every internal node must have
+// its 8 children and every non-root node a parent.
+void finalize_structure(mwns_tree* t) {
+    const int64_t N = (int64_t)t->keys.size();
+    if (N == 0 || t->keys[0] != make_key(0, 0, 0, 0)) fail(MWNS_EINVAL, "tree has no root");
+    t->nnodes = N;
+    t->depth = key_level(t->keys[N - 1]);
+    t->lev.assign(t->depth + 1, mwns_level{});
+    for (int64_t i = 0; i < N; ++i) {
+        if (i && t->keys[i] <= t->keys[i - 1]) fail(MWNS_EINVAL, "keys not strictly ascending");
+        int j = key_level(t->keys[i]);
+        if (t->lev[j].nnodes == 0) t->lev[j].node_off = i;
+        t->lev[j].nnodes++;
+    }
+    t->nleaves = 0;
+    for (int64_t i = 0; i < N; ++i) t->nleaves += t->leaf[i] ? 1 : 0;
+    t->brick_parent.assign(1, -1);
+    t->lev[0].brick_off = 0;
+    t->lev[0].nbricks = 1;
+    int64_t nb = 1;
+    for (int j = 1; j <= t->depth; ++j) {
+        mwns_level& L = t->lev[j];
+        if (L.nnodes == 0 || L.nnodes % 8) fail(MWNS_EINVAL, "incomplete sibling groups at level " + std::to_string(j));
+        L.brick_off = nb;
+        L.nbricks = L.nnodes / 8;
+        nb += L.nbricks;
+        const mwns_level& Lp = t->lev[j - 1];
+        int64_t b = 0;
+        for (int64_t i = Lp.node_off; i < Lp.node_off + Lp.nnodes; ++i) {
+            if (t->leaf[i]) continue;
+            int64_t pl[3];
+            key_coords(t->keys[i], pl);
+            for (int s = 0; s < 8; ++s) {
+                const int64_t ci = L.node_off + 8 * b + s;
+                if (b >= L.nbricks ||
+                    t->keys[ci] != make_key(j, 2 * pl[0] + (s & 1), 2 * pl[1] + ((s >> 1) & 1), 2 * pl[2] + (s >> 2)))
+                    fail(MWNS_EINVAL, "children of an internal node are missing at level " + std::to_string(j));
+            }
+            t->brick_parent.push_back(i);
+            ++b;
+        }
+        if (b != L.nbricks) fail(MWNS_EINVAL, "nodes without a parent at level " + std::to_string(j));
+    }
+    for (int64_t i = t->lev[t->depth].node_off; i < N; ++i)
+        if (!t->leaf[i]) fail(MWNS_EINVAL, "internal node at the deepest level");
+    t->nbricks = nb;
+}
+
+// Internal nodes bottom-up (the redundant tree, Sec. 2.2.1).
+void compress_tree(mwns_tree* t, const double* dH) {
+    mwns_ctx* ctx = t->ctx;
+    LevelTab lt = level_tab(t);
+    for (int j = t->depth - 1; j >= 0; --j) {
+        const mwns_level& L = t->lev[j + 1];
+        if (L.nbricks == 0) continue;
+        std::vector<int64_t> pn(L.nbricks), cb(L.nbricks);
+        for (int64_t b = 0; b < L.nbricks; ++b) {
+            pn[b] = t->brick_parent[L.brick_off + b];
+            cb[b] = L.brick_off + b;
+        }
+        DevArray<int64_t> dpn(ctx, pn.size()), dcb(ctx, cb.size());
+        dpn.upload(pn.data(), pn.size(), ctx->stream);
+        dcb.upload(cb.data(), cb.size(), ctx->stream);
+        dispatch_k<CompressLaunch>(t->k, ctx->stream, L.nbricks, j, dpn.p, dcb.p, lt, dH, t->coef.p);
+        MWNS_HIP(hipGetLastError());
+        MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    }
+}
+
+}  // namespace mwns
+
+using namespace mwns;
+
+namespace {
+
+void projection_tables(int k, std::vector<double>& tab) {
+    Quad q = gauss_legendre01(k);
+    tab.assign(3 * k * k + k, 0.0);
+    double v[64];
+    for (int i = 0; i < k; ++i) {
+        legendre_phi(k, q.x[i], v);
+        for (int a = 0; a < k; ++a) tab[a * k + i] = v[a] * q.w[i];          // P[a][i]
+        for (int s = 0; s < 2; ++s) {
+            legendre_phi(k, 0.5 * (s + q.x[i]), v);
+            for (int a = 0; a < k; ++a) tab[k * k + (s * k + i) * k + a] = v[a];   // Q[s*k+i][a]
+        }
+        tab[3 * k * k + i] = q.x[i];
+    }
+}
+
+double source_norm(int n, const double* xyz, const double* a, const double* c) {
+    // ||f||_2 over R^3 for unit-mass Gaussians (closed form of the Gaussian overlap integrals)
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < n; ++q) {
+            const double s = a[i] + a[q];
+            double d2 = 0.0;
+            for (int d = 0; d < 3; ++d) d2 += (xyz[3 * i + d] - xyz[3 * q + d]) * (xyz[3 * i + d] - xyz[3 * q + d]);
+            tot += c[i] * c[q] * std::pow(a[i] * a[q] / (M_PI * M_PI), 1.5) * std::pow(M_PI / s, 1.5) *
+                   std::exp(-a[i] * a[q] * d2 / s);
+        }
+    return std::sqrt(tot);
+}
+
+std::vector<uint64_t> children_of(const std::vector<uint64_t>& keys, const std::vector<uint8_t>& sel) {
+    std::vector<uint64_t> out;
+    for (size_t i = 0; i < keys.size(); ++i) {
+        if (!sel[i]) continue;
+        int64_t l[3];
+        key_coords(keys[i], l);
+        const int j = key_level(keys[i]) + 1;
+        for (int s = 0; s < 8; ++s) out.push_back(make_key(j, 2 * l[0] + (s & 1), 2 * l[1] + ((s >> 1) & 1), 2 * l[2] + (s >> 2)));
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int jmax, int n, const double* xyz,
+                                   const double* a, const double* c, mwns_tree** out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !out || !xyz || !a || !c) fail(MWNS_EINVAL, "NULL argument");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, 8]");
+    if (j0 < 0 || jmax < j0 || jmax > MAXLEV || !(eps > 0.0) || n < 1) fail(MWNS_EINVAL, "j0, jmax, eps or n out of range");
+    for (int i = 0; i < n; ++i)
+        if (!(a[i] > 0.0) || !std::isfinite(c[i]) || !std::isfinite(xyz[3 * i]) || !std::isfinite(xyz[3 * i + 1]) ||
+            !std::isfinite(xyz[3 * i + 2]))
+            fail(MWNS_EINVAL, "source terms must have a > 0 and finite centres and weights");
+    hipStream_t st = ctx->stream;
+    std::unique_ptr<mwns_tree> t(new mwns_tree);
+    t->ctx = ctx;
+    t->k = k;
+    const int k3 = k * k * k;
+    // source terms: x, y, z, a, c (a/pi)^{3/2}
+    std::vector<double> src(5 * n);
+    for (int i = 0; i < n; ++i) {
+        for (int d = 0; d < 3; ++d) src[5 * i + d] = xyz[3 * i + d];
+        src[5 * i + 3] = a[i];
+        src[5 * i + 4] = c[i] * std::pow(a[i] / M_PI, 1.5);
+    }
+    const double thr = eps * source_norm(n, xyz, a, c);
+    t->threshold = thr;
+    std::vector<double> tab;
+    projection_tables(k, tab);
+    DevArray<double> dsrc(ctx, src.size()), dtab(ctx, tab.size());
+    dsrc.upload(src.data(), src.size(), st);
+    dtab.upload(tab.data(), tab.size(), st);
+    // levels below j0: complete grids of internal nodes; level j0..: candidates (Alg. 1)
+    std::vector<std::vector<uint64_t>> lkeys;
+    std::vector<std::vector<uint8_t>> lleaf;
+    std::vector<DevArray<double>> lcoef;
+    std::vector<uint64_t> cand;
+    for (int j = 0; j < j0; ++j) {
+        const int64_t side = (int64_t)1 << j;
+        std::vector<uint64_t> kk;
+        for (int64_t x = 0; x < side; ++x)
+            for (int64_t y = 0; y < side; ++y)
+                for (int64_t z = 0; z < side; ++z) kk.push_back(make_key(j, x, y, z));
+        std::sort(kk.begin(), kk.end());
+        lkeys.push_back(kk);
+        lleaf.push_back(std::vector<uint8_t>(kk.size(), 0));
+        lcoef.emplace_back();
+    }
+    {
+        const int64_t side = (int64_t)1 << j0;
+        for (int64_t x = 0; x < side; ++x)
+            for (int64_t y = 0; y < side; ++y)
+                for (int64_t z = 0; z < side; ++z) cand.push_back(make_key(j0, x, y, z));
+        std::sort(cand.begin(), cand.end());
+    }
+    double min_margin = INFINITY;
+    for (int j = j0; !cand.empty(); ++j) {
+        const int64_t nc = (int64_t)cand.size();
+        DevArray<uint64_t> dk(ctx, nc);
+        DevArray<double> ds(ctx, (size_t)nc * k3), derr(ctx, nc);
+        DevArray<uint8_t> dref(ctx, nc);
+        dk.upload(cand.data(), nc, st);
+        dispatch_k<ProjectLaunch>(k, st, nc, j, jmax, dk.p, n, dsrc.p, thr, dtab.p, ds.p, dref.p, derr.p);
+        MWNS_HIP(hipGetLastError());
+        std::vector<uint8_t> ref(nc);
+        std::vector<double> err(nc);
+        dref.download(ref.data(), nc, st);
+        derr.download(err.data(), nc, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+        if (j < jmax)
+            for (int64_t i = 0; i < nc; ++i) min_margin = std::min(min_margin, std::fabs(err[i] - thr) / thr);
+        std::vector<uint8_t> lf(nc);
+        for (int64_t i = 0; i < nc; ++i) lf[i] = ref[i] ? 0 : 1;
+        lkeys.push_back(cand);
+        lleaf.push_back(lf);
+        lcoef.push_back(std::move(ds));
+        cand = children_of(lkeys.back(), ref);
+    }
+    t->min_margin = min_margin;
+    for (size_t j = 0; j < lkeys.size(); ++j) {
+        t->keys.insert(t->keys.end(), lkeys[j].begin(), lkeys[j].end());
+        t->leaf.insert(t->leaf.end(), lleaf[j].begin(), lleaf[j].end());
+    }
+    finalize_structure(t.get());
+    t->dkeys.reset(ctx, t->nnodes);
+    t->dleaf.reset(ctx, t->nnodes);
+    t->dkeys.upload(t->keys.data(), t->nnodes, st);
+    t->dleaf.upload(t->leaf.data(), t->nnodes, st);
+    t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
+    MWNS_HIP(hipMemsetAsync(t->coef.p, 0, t->coef.n * sizeof(double), st));
+    LevelTab lt = level_tab(t.get());
+    for (int j = j0; j <= t->depth; ++j) {
+        const int64_t nn = t->lev[j].nnodes;
+        DevArray<uint8_t> dl(ctx, nn);
+        dl.upload(t->leaf.data() + t->lev[j].node_off, nn, st);
+        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(k, j, nn, lcoef[j].p, dl.p, lt, t->coef.p);
+        MWNS_HIP(hipGetLastError());
+        MWNS_HIP(hipStreamSynchronize(st));
+    }
+    DevArray<double> dH = upload_filters(ctx, k);
+    compress_tree(t.get(), dH.p);
+    *out = t.release();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
+                                  mwns_tree** out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !out || !keys || !coeffs) fail(MWNS_EINVAL, "NULL argument");
+    if (k < 1 || k > KMAX || nleaves < 1) fail(MWNS_EINVAL, "k or nleaves out of range");
+    const int k3 = k * k * k;
+    std::vector<int64_t> order(nleaves);
+    std::iota(order.begin(), order.end(), 0);
+    for (int64_t i = 0; i < nleaves; ++i) {
+        const int j = key_level(keys[i]);
+        int64_t l[3];
+        key_coords(keys[i], l);
+        if (j > MAXLEV || make_key(j, l[0], l[1], l[2]) != keys[i]) fail(MWNS_EINVAL, "malformed key");
+        for (int d = 0; d < 3; ++d)
+            if (l[d] >= ((int64_t)1 << j)) fail(MWNS_EINVAL, "key outside the unit cube");
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return keys[x] < keys[y]; });
+    std::vector<uint64_t> all;
+    for (int64_t i = 0; i < nleaves; ++i) {
+        uint64_t key = keys[order[i]];
+        all.push_back(key);
+        int j = key_level(key);
+        int64_t l[3];
+        key_coords(key, l);
+        while (j > 0) {
+            --j;
+            for (int d = 0; d < 3; ++d) l[d] >>= 1;
+            all.push_back(make_key(j, l[0], l[1], l[2]));
+        }
+    }
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    std::unique_ptr<mwns_tree> t(new mwns_tree);
+    t->ctx = ctx;
+    t->k = k;
+    t->keys = all;
+    t->leaf.assign(all.size(), 0);
+    std::vector<int64_t> pos(nleaves);
+    for (int64_t i = 0; i < nleaves; ++i) {
+        const uint64_t key = keys[order[i]];
+        if (i && key == keys[order[i - 1]]) fail(MWNS_EINVAL, "duplicate leaf key");
+        pos[i] = std::lower_bound(all.begin(), all.end(), key) - all.begin();
+        t->leaf[pos[i]] = 1;
+    }
+    // a leaf may not have descendants: its successor in key order at the next level would be a child
+    for (int64_t i = 0; i < nleaves; ++i) {
+        int64_t l[3];
+        const int j = key_level(all[pos[i]]);
+        key_coords(all[pos[i]], l);
+        if (std::binary_search(all.begin(), all.end(), make_key(j + 1, 2 * l[0], 2 * l[1], 2 * l[2])) ||
+            std::binary_search(all.begin(), all.end(), make_key(j + 1, 2 * l[0] + 1, 2 * l[1] + 1, 2 * l[2] + 1)))
+            fail(MWNS_EINVAL, "leaves overlap");
+    }
+    finalize_structure(t.get());
+    hipStream_t st = ctx->stream;
+    t->dkeys.reset(ctx, t->nnodes);
+    t->dleaf.reset(ctx, t->nnodes);
+    t->dkeys.upload(t->keys.data(), t->nnodes, st);
+    t->dleaf.upload(t->leaf.data(), t->nnodes, st);
+    t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
+    std::vector<double> hb(t->coef.n, 0.0);
+    for (int64_t i = 0; i < nleaves; ++i) {
+        int64_t brick;
+        int child;
+        node_brick(t.get(), pos[i], &brick, &child);
+        const double* src = coeffs + order[i] * k3;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                for (int c = 0; c < k; ++c) {
+                    const int P = 2 * k;
+                    const int64_t e = ((int64_t)((child & 1) * k + a) * P + ((child >> 1) & 1) * k + b) * P +
+                                      ((child >> 2) & 1) * k + c;
+                    hb[brick * brick_elems(k) + e] = src[(a * k + b) * k + c];
+                }
+    }
+    t->coef.upload(hb.data(), hb.size(), st);
+    DevArray<double> dH = upload_filters(ctx, k);
+    compress_tree(t.get(), dH.p);
+    *out = t.release();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_tree_get_info(const mwns_tree* t, mwns_tree_info* info) {
+    MWNS_GUARD_BEGIN
+    if (!t || !info) fail(MWNS_EINVAL, "NULL argument");
+    info->k = t->k;
+    info->depth = t->depth;
+    info->nnodes = t->nnodes;
+    info->nleaves = t->nleaves;
+    info->threshold = t->threshold;
+    info->min_margin = t->min_margin;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_tree_export(mwns_ctx* ctx, const mwns_tree* t, int64_t* nnodes, uint64_t* keys, uint8_t* is_leaf,
+                             double* coeffs) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !t || !nnodes) fail(MWNS_EINVAL, "NULL argument");
+    if (!keys) { *nnodes = t->nnodes; return MWNS_OK; }
+    if (*nnodes < t->nnodes) {
+        *nnodes = t->nnodes;
+        fail(MWNS_ERANGE, "export buffers too small");
+    }
+    std::copy(t->keys.begin(), t->keys.end(), keys);
+    if (is_leaf) std::copy(t->leaf.begin(), t->leaf.end(), is_leaf);
+    if (coeffs) {
+        const int k = t->k, k3 = k * k * k;
+        std::vector<double> hb(t->coef.n);
+        t->coef.download(hb.data(), hb.size(), ctx->stream);
+        MWNS_HIP(hipStreamSynchronize(ctx->stream));
+        for (int64_t i = 0; i < t->nnodes; ++i) {
+            int64_t brick;
+            int child;
+            node_brick(t, i, &brick, &child);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    for (int c = 0; c < k; ++c) {
+                        const int P = 2 * k;
+                        const int64_t e = ((int64_t)((child & 1) * k + a) * P + ((child >> 1) & 1) * k + b) * P +
+                                          ((child >> 2) & 1) * k + c;
+                        coeffs[i * k3 + (a * k + b) * k + c] = hb[brick * brick_elems(k) + e];
+                    }
+        }
+    }
+    *nnodes = t->nnodes;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !t || (npts && (!xyz || !out)) || npts < 0) fail(MWNS_EINVAL, "NULL argument");
+    if (npts == 0) return MWNS_OK;
+    for (int64_t p = 0; p < 3 * npts; ++p)
+        if (!(xyz[p] >= 0.0 && xyz[p] <= 1.0)) fail(MWNS_EINVAL, "point outside the unit cube");
+    hipStream_t st = ctx->stream;
+    DevArray<double> dx(ctx, 3 * npts), dout(ctx, npts);
+    DevArray<int> dbad(ctx, 1);
+    dx.upload(xyz, 3 * npts, st);
+    MWNS_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), st));
+    LevelTab lt = level_tab(t);
+    dispatch_k<EvalLaunch>(t->k, st, npts, dx.p, t->dkeys.p, t->nnodes, t->dleaf.p, lt, t->coef.p, dout.p, dbad.p);
+    MWNS_HIP(hipGetLastError());
+    int bad = 0;
+    dout.download(out, npts, st);
+    dbad.download(&bad, 1, st);
+    MWNS_HIP(hipStreamSynchronize(st));
+    if (bad) fail(MWNS_ESTATE, "points without a leaf: the tree does not cover the cube");
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+void mwns_tree_destroy(mwns_tree* t) { delete t; }
+
+}  // extern "C"
