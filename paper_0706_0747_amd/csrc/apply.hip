@@ -46,10 +46,29 @@ struct Tpl {
     int dpart;             // 0: whole band (all children, +), 1: down band (internal children, -)
 };
 
-constexpr int AT = 256;            // threads per apply block
-constexpr int T2S_V1 = 272;        // LDS strides of the mode-2 result [v1][u2][u3]
+constexpr int AT = 256;            // threads per block of the transform kernels
+constexpr int CT = 512;            // threads per block of the contraction kernel (8 waves)
+constexpr int CW = CT / 64;
+constexpr int T2S_V1 = 272;        // LDS strides of the mode-2 result [v1][u2][u3] (conflict-free)
 constexpr int T2S_U2 = 16;
+constexpr int NMAX = 4;            // largest box extent per dimension of one job (the host splits boxes)
+constexpr int S3_V = 36;           // LDS stride of the staged mode-3 operand [L][v][u]
 
+// One level of the apply as seen by the contraction kernel.
+struct LevelDesc {
+    const double* Xr;        // real input bricks of the level (the level's own bricks)
+    const double* Xg;        // ghost input bricks
+    const int32_t* nbr;      // [brick][(2Lr+1)^3] input index, -1 outside the cube
+    const uint8_t* cmask;    // [brick] bit s set when child s is internal
+    const Tpl* tpl;          // jobs of the level
+    const double* Fj;        // F^{j;m,l} of the level [M][NLF][k][k]
+    double* out;             // output bricks of the level
+    int64_t nreal;
+    int Lr, valid, ntpl, pad;
+};
+
+// Masked super-block entry S^{m,L}[u][v]: F^{j;m,2L+su-sv}_{a b} when the fine displacement lies in
+// [mlo, mhi], else 0; u = su*K + a (output), v = sv*K + b (input); rows/columns >= 2K are padding.
 template <int K>
 __device__ inline double sop(const double* __restrict__ Fm, int L, int mlo, int mhi, int u, int v) {
     if (u >= 2 * K || v >= 2 * K) return 0.0;
@@ -59,70 +78,109 @@ __device__ inline double sop(const double* __restrict__ Fm, int L, int mlo, int 
     return Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
 }
 
-template <int K>
-__global__ void __launch_bounds__(AT) ns_apply_kernel(const double* __restrict__ Xr, int64_t nreal,
-                                                      const double* __restrict__ Xg, const int32_t* __restrict__ nbr, int Lr,
-                                                      const uint8_t* __restrict__ cmask, int valid,
-                                                      const Tpl* __restrict__ tpl, int ntpl,
-                                                      const double* __restrict__ Fj, const double* __restrict__ w,
-                                                      double* __restrict__ out) {
+template <int K, int TPW>
+__device__ inline void load_slices(const double* __restrict__ X, int wave, int g, int r, double (&x)[TPW][4]) {
     constexpr int D = 2 * K;
-    constexpr int TPW = (D + 3) / 4;
+    for (int t = 0; t < TPW; ++t) {
+        const int v1 = wave * TPW + t;
+        const double* xp = X + ((int64_t)v1 * D + r) * D + 4 * g;
+        if (v1 < D && r < D && 4 * g + 3 < D && (D % 4) == 0) {
+            const double2 p0 = *reinterpret_cast<const double2*>(xp);
+            const double2 p1 = *reinterpret_cast<const double2*>(xp + 2);
+            x[t][0] = p0.x; x[t][1] = p0.y; x[t][2] = p1.x; x[t][3] = p1.y;
+        } else {
+            for (int kk = 0; kk < 4; ++kk) x[t][kk] = (v1 < D && r < D && 4 * g + kk < D) ? xp[kk] : 0.0;
+        }
+    }
+}
+
+// One block per output brick, over all levels at once (order[] lists (level, brick) by decreasing cost).
+template <int K>
+__global__ void __launch_bounds__(CT) ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order,
+                                                      const double* __restrict__ w) {
+    constexpr int D = 2 * K;
+    constexpr int TPW = (D + CW - 1) / CW;
     constexpr int64_t E = (int64_t)D * D * D;
     __shared__ double T2s[16 * T2S_V1];
+    __shared__ double S3s[NMAX * 16 * S3_V];
+    __shared__ double S2s[NMAX * 256];
+    __shared__ double S1s[NMAX * 256];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-    const int64_t b = blockIdx.x;
+    const int2 job = order[blockIdx.x];
+    const LevelDesc lv = levels[job.x];
+    const int64_t b = job.y;
+    const int Lr = lv.Lr;
     const int NL = 2 * Lr + 1;
-    const int32_t* nb = nbr + b * NL * NL * NL;
+    const int32_t* nb = lv.nbr + b * NL * NL * NL;
+    const int cmb = lv.cmask[b];
     d4 YW[TPW], YD[TPW];
     for (int t = 0; t < TPW; ++t) {
         YW[t] = (d4){0.0, 0.0, 0.0, 0.0};
         YD[t] = (d4){0.0, 0.0, 0.0, 0.0};
     }
-    const int cmb = cmask[b];
-    for (int ti = 0; ti < ntpl; ++ti) {
-        const Tpl tp = tpl[ti];
+    for (int ti = 0; ti < lv.ntpl; ++ti) {
+        const Tpl tp = lv.tpl[ti];
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
+        const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
         for (int m = tp.m1; m <= tp.m2; ++m) {
-            const double* Fm = Fj + (int64_t)m * NLF * K * K;
+            const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
             const double cw = tp.dpart ? -w[m] : w[m];
+            // stage this term's masked super-blocks in LDS (layouts chosen for conflict-free reads)
+            __syncthreads();
+            for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
+                const int sb = e >> 8, u = (e >> 4) & 15, v = e & 15;
+                if (sb < n1) S1s[sb * 256 + v * 16 + u] = cw * sop<K>(Fm, tp.lo[0] + sb, tp.mlo[0], tp.mhi[0], u, v);
+                else if (sb < n1 + n2) {
+                    const int q = sb - n1;
+                    S2s[q * 256 + v * 16 + u] = sop<K>(Fm, tp.lo[1] + q, tp.mlo[1], tp.mhi[1], u, v);
+                } else {
+                    const int q = sb - n1 - n2;
+                    S3s[q * 16 * S3_V + v * S3_V + u] = sop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], u, v);
+                }
+            }
+            __syncthreads();
             for (int L1 = tp.lo[0]; L1 <= tp.hi[0]; ++L1) {
                 d4 T2[TPW];
                 for (int t = 0; t < TPW; ++t) T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
                 bool any1 = false;
                 for (int L2 = tp.lo[1]; L2 <= tp.hi[1]; ++L2) {
+                    const int32_t* row = nb + ((L1 + Lr) * NL + (L2 + Lr)) * NL + Lr;
+                    int L3 = tp.lo[2];
+                    while (L3 <= tp.hi[2] && row[L3] < 0) ++L3;
+                    if (L3 > tp.hi[2]) continue;
+                    any1 = true;
                     d4 T1[TPW];
                     for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                    bool any2 = false;
-                    for (int L3 = tp.lo[2]; L3 <= tp.hi[2]; ++L3) {
-                        const int idx = nb[((L1 + Lr) * NL + (L2 + Lr)) * NL + (L3 + Lr)];
-                        if (idx < 0) continue;
-                        any2 = true;
-                        const double* X = idx < nreal ? Xr + idx * E : Xg + (idx - nreal) * E;
-                        double s3[4];
-                        for (int kk = 0; kk < 4; ++kk) s3[kk] = sop<K>(Fm, L3, tp.mlo[2], tp.mhi[2], r, 4 * g + kk);
-                        for (int t = 0; t < TPW; ++t) {
-                            const int v1 = wave * TPW + t;
-                            if (v1 >= D) break;
-                            double x[4];
-                            const double* xp = X + ((int64_t)v1 * D + r) * D + 4 * g;
-                            if (r < D && 4 * g + 3 < D && (D % 4) == 0) {
-                                const double2 p0 = *reinterpret_cast<const double2*>(xp);
-                                const double2 p1 = *reinterpret_cast<const double2*>(xp + 2);
-                                x[0] = p0.x; x[1] = p0.y; x[2] = p1.x; x[3] = p1.y;
-                            } else {
-                                for (int kk = 0; kk < 4; ++kk) x[kk] = (r < D && 4 * g + kk < D) ? xp[kk] : 0.0;
-                            }
-                            for (int kk = 0; kk < 4; ++kk)
-                                T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk], s3[kk], T1[t], 0, 0, 0);
-                        }
+                    double xc[TPW][4];
+                    {
+                        const int idx = row[L3];
+                        load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, wave, g, r, xc);
                     }
-                    if (!any2) continue;
-                    any1 = true;
+                    while (L3 <= tp.hi[2]) {
+                        int Ln = L3 + 1;
+                        while (Ln <= tp.hi[2] && row[Ln] < 0) ++Ln;
+                        double xn[TPW][4];
+                        if (Ln <= tp.hi[2]) {
+                            const int idx = row[Ln];
+                            load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, wave, g, r, xn);
+                        }
+                        const double* s3p = S3s + (L3 - tp.lo[2]) * 16 * S3_V + r;
+                        double s3[4];
+                        for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
+                        for (int kk = 0; kk < 4; ++kk)
+                            for (int t = 0; t < TPW; ++t)
+                                if (wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[t][kk], s3[kk], T1[t], 0, 0, 0);
+                        if (Ln <= tp.hi[2])
+                            for (int t = 0; t < TPW; ++t)
+                                for (int kk = 0; kk < 4; ++kk) xc[t][kk] = xn[t][kk];
+                        L3 = Ln;
+                    }
+                    const double* s2p = S2s + (L2 - tp.lo[1]) * 256 + r;
                     double s2[4];
-                    for (int i = 0; i < 4; ++i) s2[i] = sop<K>(Fm, L2, tp.mlo[1], tp.mhi[1], r, 4 * i + g);
-                    for (int t = 0; t < TPW; ++t)
-                        for (int i = 0; i < 4; ++i) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
+                    for (int i = 0; i < 4; ++i)
+                        for (int t = 0; t < TPW; ++t)
+                            if (wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
                 }
                 if (!any1) continue;
                 for (int t = 0; t < TPW; ++t) {
@@ -131,13 +189,14 @@ __global__ void __launch_bounds__(AT) ns_apply_kernel(const double* __restrict__
                     for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
                 }
                 __syncthreads();
+                const double* s1p = S1s + (L1 - tp.lo[0]) * 256 + r;
                 double s1[4];
-                for (int kk = 0; kk < 4; ++kk) s1[kk] = cw * sop<K>(Fm, L1, tp.mlo[0], tp.mhi[0], r, 4 * kk + g);
-                for (int t = 0; t < TPW; ++t) {
-                    const int u2 = wave * TPW + t;
-                    if (u2 >= D) break;
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int v1 = 4 * kk + g;
+                for (int kk = 0; kk < 4; ++kk) s1[kk] = s1p[(4 * kk + g) * 16];
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int v1 = 4 * kk + g;
+                    for (int t = 0; t < TPW; ++t) {
+                        const int u2 = wave * TPW + t;
+                        if (u2 >= D) break;
                         const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
                         if (tp.dpart) YD[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YD[t], 0, 0, 0);
                         else YW[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YW[t], 0, 0, 0);
@@ -147,7 +206,7 @@ __global__ void __launch_bounds__(AT) ns_apply_kernel(const double* __restrict__
             }
         }
     }
-    double* ob = out + b * E;
+    double* ob = lv.out + b * E;
     for (int t = 0; t < TPW; ++t) {
         const int u2 = wave * TPW + t;
         if (u2 >= D) break;
@@ -155,7 +214,7 @@ __global__ void __launch_bounds__(AT) ns_apply_kernel(const double* __restrict__
             const int u1 = 4 * i + g, u3 = r;
             if (u1 >= D || u3 >= D) continue;
             const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
-            double v = ((valid >> child) & 1) ? YW[t][i] : 0.0;
+            double v = ((lv.valid >> child) & 1) ? YW[t][i] : 0.0;
             if ((cmb >> child) & 1) v += YD[t][i];
             ob[((int64_t)u1 * D + u2) * D + u3] = v;
         }
@@ -327,51 +386,69 @@ __global__ void __launch_bounds__(AT) assemble_kernel(int j, const int64_t* __re
     up_brick<K>(Ht, blk, coef + (brick_off + b) * (int64_t)P * P * P, true, tmp1, tmp2);
 }
 
-// Number of (node, l, m) triples with a non-zero coefficient, per output brick of level j.
+// Number of (node, l, m) triples with a non-zero coefficient, one thread per output node of
+// level j.  Coefficients are c_m = [m in R_j(L)] - [internal][m in R_{j+1}(l)]; per node
+//   sum_l |W(l) sym-diff D(l)| = sum_l |W(l)| + [internal] sum_{|l|<=3} (|D(l)| - 2 |W(l) & D(l)|),
+// and sum_l |W(l)| = 8 sum_L |R_j(L)| over coarse L with P - L inside the cube (each coarse L
+// carries the 8 children of P - L); at level 0 the only input is the root itself.
+__device__ inline int range_len(const int32_t* r) { return r[1] >= r[0] ? r[1] - r[0] + 1 : 0; }
+
 __global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ pkeys, const uint8_t* __restrict__ cmask,
                              int valid, const int32_t* __restrict__ Rj, const int32_t* __restrict__ Rj1,
                              unsigned long long* __restrict__ total) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nout) return;
-    int64_t p[3] = {0, 0, 0};
-    if (j > 0) key_coords(pkeys[b], p);
-    const int64_t side = (int64_t)1 << j;
-    unsigned long long cnt = 0;
-    for (int child = 0; child < 8; ++child) {
-        if (!((valid >> child) & 1)) continue;
-        const int internal = (cmask[b] >> child) & 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nout * 8) return;
+    const int64_t b = t >> 3;
+    const int child = (int)(t & 7);
+    if (!((valid >> child) & 1)) return;
+    const int internal = (cmask[b] >> child) & 1;
+    auto at = [](const int32_t* R, int x, int y, int z) {
+        return R + (((x + LP) * NLP + (y + LP)) * NLP + (z + LP)) * 2;
+    };
+    long long cnt = 0;
+    if (j == 0) {
+        const int32_t* w = at(Rj, 0, 0, 0);
+        cnt = range_len(w);
+        if (internal && Rj1) {
+            const int32_t* d = at(Rj1, 0, 0, 0);
+            const int ov = (range_len(w) && range_len(d)) ? max(0, min(w[1], d[1]) - max(w[0], d[0]) + 1) : 0;
+            cnt += range_len(d) - 2 * ov;
+        }
+        atomicAdd(total, (unsigned long long)cnt);
+        return;
+    }
+    int64_t p[3];
+    key_coords(pkeys[b], p);
+    const int64_t pside = (int64_t)1 << (j - 1), side = (int64_t)1 << j;
+    for (int x = -LP; x <= LP; ++x)
+        for (int y = -LP; y <= LP; ++y)
+            for (int z = -LP; z <= LP; ++z) {
+                const int64_t q[3] = {p[0] - x, p[1] - y, p[2] - z};
+                if (q[0] < 0 || q[0] >= pside || q[1] < 0 || q[1] >= pside || q[2] < 0 || q[2] >= pside) continue;
+                cnt += 8 * range_len(at(Rj, x, y, z));
+            }
+    if (internal && Rj1) {
         const int64_t o[3] = {2 * p[0] + (child & 1), 2 * p[1] + ((child >> 1) & 1), 2 * p[2] + (child >> 2)};
-        for (int e1 = -LF; e1 <= LF; ++e1)
-            for (int e2 = -LF; e2 <= LF; ++e2)
-                for (int e3 = -LF; e3 <= LF; ++e3) {
+        for (int e1 = -LP; e1 <= LP; ++e1)
+            for (int e2 = -LP; e2 <= LP; ++e2)
+                for (int e3 = -LP; e3 <= LP; ++e3) {
                     const int64_t q[3] = {o[0] - e1, o[1] - e2, o[2] - e3};
                     if (q[0] < 0 || q[0] >= side || q[1] < 0 || q[1] >= side || q[2] < 0 || q[2] >= side) continue;
-                    const int64_t L[3] = {(o[0] >> 1) - (q[0] >> 1), (o[1] >> 1) - (q[1] >> 1), (o[2] >> 1) - (q[2] >> 1)};
-                    int a1 = 0, b1 = -1, a2 = 0, b2 = -1;
-                    if (L[0] >= -LP && L[0] <= LP && L[1] >= -LP && L[1] <= LP && L[2] >= -LP && L[2] <= LP) {
-                        const int32_t* rr = Rj + (((L[0] + LP) * NLP + (L[1] + LP)) * NLP + (L[2] + LP)) * 2;
-                        a1 = rr[0];
-                        b1 = rr[1];
-                    }
-                    if (internal && Rj1 && e1 >= -LP && e1 <= LP && e2 >= -LP && e2 <= LP && e3 >= -LP && e3 <= LP) {
-                        const int32_t* rr = Rj1 + (((e1 + LP) * NLP + (e2 + LP)) * NLP + (e3 + LP)) * 2;
-                        a2 = rr[0];
-                        b2 = rr[1];
-                    }
-                    const int n1 = b1 >= a1 ? b1 - a1 + 1 : 0, n2 = b2 >= a2 ? b2 - a2 + 1 : 0;
-                    const int ov = (n1 && n2) ? max(0, min(b1, b2) - max(a1, a2) + 1) : 0;
-                    cnt += (unsigned long long)(n1 + n2 - 2 * ov);
+                    const int L[3] = {(int)((o[0] >> 1) - (q[0] >> 1)), (int)((o[1] >> 1) - (q[1] >> 1)),
+                                      (int)((o[2] >> 1) - (q[2] >> 1))};
+                    const int32_t* w = at(Rj, L[0], L[1], L[2]);   // |L_d| <= 2 here
+                    const int32_t* d = at(Rj1, e1, e2, e3);
+                    const int ov = (range_len(w) && range_len(d)) ? max(0, min(w[1], d[1]) - max(w[0], d[0]) + 1) : 0;
+                    cnt += range_len(d) - 2 * ov;
                 }
     }
-    atomicAdd(total, cnt);
+    atomicAdd(total, (unsigned long long)cnt);
 }
 
 template <int K>
 struct ApplyLaunch {
-    static void run(hipStream_t st, int64_t nout, const double* Xr, int64_t nreal, const double* Xg, const int32_t* nbr,
-                    int Lr, const uint8_t* cmask, int valid, const Tpl* tpl, int ntpl, const double* Fj, const double* w,
-                    double* out) {
-        ns_apply_kernel<K><<<(unsigned)nout, AT, 0, st>>>(Xr, nreal, Xg, nbr, Lr, cmask, valid, tpl, ntpl, Fj, w, out);
+    static void run(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, const double* w) {
+        ns_apply_kernel<K><<<(unsigned)nblocks, CT, 0, st>>>(levels, order, w);
     }
 };
 template <int K>
@@ -539,61 +616,81 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
     dHt.upload(Ht.data(), Ht.size(), st);
     const int depth = f->depth;
     const int64_t planrow = (int64_t)NLP3 * 2;
-    // ---- per level: templates, closure tables, ghost bricks
     struct LevelWork {
         std::vector<Tpl> tpl;
+        std::vector<uint8_t> cm;
+        std::vector<uint64_t> pk;
         int Lr = 0;
-        int64_t nout = 0, nghost = 0, nleafonly = 0;
+        int64_t nout = 0, nghost = 0, nleafonly = 0, miss_off = 0;
+        int valid = 0xff;
         DevArray<int32_t> nbr;
         DevArray<uint8_t> cmask;
         DevArray<Tpl> dtpl;
         DevArray<double> ghosts;
-        DevArray<uint64_t> pkeys;
-        int valid = 0xff;
+        DevArray<uint64_t> pkeys, gkeys;
     };
     std::vector<LevelWork> W(depth + 1);
     Timer tclos(st), tcon(st), tasm(st);
     tclos.start();
-    int64_t total_ghosts = 0;
+    // ---- jobs of every level: whole band from plan row j, down band from row j+1
+    int64_t miss_total = 0;
     for (int j = 0; j <= depth; ++j) {
         LevelWork& lw = W[j];
         const mwns_level& L = f->lev[j];
         lw.nout = L.nbricks;
+        std::vector<Tpl> raw;
         if (j == 0) {
             Tpl t{};
             for (int d = 0; d < 3; ++d) { t.lo[d] = t.hi[d] = 0; t.mlo[d] = -LF; t.mhi[d] = LF; }
             const int32_t* r0 = op->plan.data() + (((LP * NLP) + LP) * NLP + LP) * 2;
             t.m1 = r0[0];
             t.m2 = r0[1];
-            t.dpart = 0;
-            if (t.m2 >= t.m1) lw.tpl.push_back(t);
+            if (t.m2 >= t.m1) raw.push_back(t);
             lw.valid = 0x01;
         } else {
-            append_templates(op->plan.data() + (int64_t)j * planrow, false, lw.tpl);
+            append_templates(op->plan.data() + (int64_t)j * planrow, false, raw);
         }
-        if (j < depth && j + 1 <= op->max_level) append_templates(op->plan.data() + (int64_t)(j + 1) * planrow, true, lw.tpl);
+        if (j < depth && j + 1 <= op->max_level) append_templates(op->plan.data() + (int64_t)(j + 1) * planrow, true, raw);
+        for (const Tpl& t : raw) {   // split boxes so that every extent is <= NMAX
+            int cuts[3][8][2], nc[3];
+            for (int d = 0; d < 3; ++d) {
+                nc[d] = 0;
+                for (int a = t.lo[d]; a <= t.hi[d]; a += NMAX) {
+                    cuts[d][nc[d]][0] = a;
+                    cuts[d][nc[d]][1] = std::min(t.hi[d], a + NMAX - 1);
+                    ++nc[d];
+                }
+            }
+            for (int x = 0; x < nc[0]; ++x)
+                for (int y = 0; y < nc[1]; ++y)
+                    for (int z = 0; z < nc[2]; ++z) {
+                        Tpl q = t;
+                        q.lo[0] = cuts[0][x][0]; q.hi[0] = cuts[0][x][1];
+                        q.lo[1] = cuts[1][y][0]; q.hi[1] = cuts[1][y][1];
+                        q.lo[2] = cuts[2][z][0]; q.hi[2] = cuts[2][z][1];
+                        lw.tpl.push_back(q);
+                    }
+        }
         int Lr = 0;
         for (const Tpl& t : lw.tpl)
             for (int d = 0; d < 3; ++d) Lr = std::max(Lr, std::max(std::abs(t.lo[d]), std::abs(t.hi[d])));
         lw.Lr = Lr;
         const int NL = 2 * Lr + 1, NL3 = NL * NL * NL;
-        // internal-children masks
-        std::vector<uint8_t> cm(lw.nout, 0);
-        if (j == 0) cm[0] = f->leaf[0] ? 0 : 1;
+        lw.cm.assign(lw.nout, 0);
+        if (j == 0) lw.cm[0] = f->leaf[0] ? 0 : 1;
         else
             for (int64_t b = 0; b < lw.nout; ++b)
                 for (int s = 0; s < 8; ++s)
-                    if (!f->leaf[L.node_off + 8 * b + s]) cm[b] |= (uint8_t)(1 << s);
+                    if (!f->leaf[L.node_off + 8 * b + s]) lw.cm[b] |= (uint8_t)(1 << s);
+        for (int64_t b = 0; b < lw.nout; ++b) lw.nleafonly += lw.cm[b] == 0;
         lw.cmask.reset(ctx, lw.nout);
-        lw.cmask.upload(cm.data(), lw.nout, st);
+        lw.cmask.upload(lw.cm.data(), lw.nout, st);
         lw.nbr.reset(ctx, (size_t)lw.nout * NL3);
-        lw.nleafonly = 0;
-        for (int64_t b = 0; b < lw.nout; ++b) lw.nleafonly += cm[b] == 0;
         if (j > 0) {
-            std::vector<uint64_t> pk(lw.nout);
-            for (int64_t b = 0; b < lw.nout; ++b) pk[b] = f->keys[f->brick_parent[L.brick_off + b]];
+            lw.pk.resize(lw.nout);
+            for (int64_t b = 0; b < lw.nout; ++b) lw.pk[b] = f->keys[f->brick_parent[L.brick_off + b]];
             lw.pkeys.reset(ctx, lw.nout);
-            lw.pkeys.upload(pk.data(), lw.nout, st);
+            lw.pkeys.upload(lw.pk.data(), lw.nout, st);
         }
         if (lw.tpl.empty()) continue;
         if (j == 0) {
@@ -602,74 +699,132 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
             lw.nbr.upload(nb.data(), NL3, st);
             continue;
         }
-        DevArray<uint64_t> miss(ctx, (size_t)lw.nout * NL3);
-        const int64_t n = lw.nout * NL3;
-        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(lw.nout, j - 1, lw.pkeys.p, Lr, lw.nbr.p, miss.p);
+        lw.miss_off = miss_total;
+        miss_total += lw.nout * NL3;
+    }
+    // ---- neighbour closure: all levels, one host round trip for the missing-key sets
+    DevArray<uint64_t> miss(ctx, std::max<int64_t>(1, miss_total));
+    for (int j = 1; j <= depth; ++j) {
+        LevelWork& lw = W[j];
+        if (lw.tpl.empty()) continue;
+        const int NL = 2 * lw.Lr + 1;
+        const int64_t n = lw.nout * NL * NL * NL;
+        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(lw.nout, j - 1, lw.pkeys.p, lw.Lr, lw.nbr.p,
+                                                                    miss.p + lw.miss_off);
         MWNS_HIP(hipGetLastError());
-        std::vector<uint64_t> hm(n);
-        miss.download(hm.data(), n, st);
-        MWNS_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<uint64_t> hm(miss_total);
+    miss.download(hm.data(), miss_total, st);
+    MWNS_HIP(hipStreamSynchronize(st));
+    int64_t total_ghosts = 0;
+    for (int j = 1; j <= depth; ++j) {
+        LevelWork& lw = W[j];
+        if (lw.tpl.empty()) continue;
+        const int NL = 2 * lw.Lr + 1;
+        const int64_t n = lw.nout * NL * NL * NL;
         std::vector<uint64_t> gk;
-        for (uint64_t v : hm)
-            if (v != ~0ull) gk.push_back(v);
+        for (int64_t i = 0; i < n; ++i)
+            if (hm[lw.miss_off + i] != ~0ull) gk.push_back(hm[lw.miss_off + i]);
         std::sort(gk.begin(), gk.end());
         gk.erase(std::unique(gk.begin(), gk.end()), gk.end());
         lw.nghost = (int64_t)gk.size();
         total_ghosts += lw.nghost;
-        if (lw.nghost) {
-            DevArray<uint64_t> dgk(ctx, gk.size());
-            dgk.upload(gk.data(), gk.size(), st);
-            closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, miss.p, dgk.p, lw.nghost, lw.nout, lw.nbr.p);
-            MWNS_HIP(hipGetLastError());
-            lw.ghosts.reset(ctx, (size_t)lw.nghost * E);
-            dispatch_k<GhostLaunch>(k, st, lw.nghost, j - 1, dgk.p, f->dkeys.p, f->nnodes, lt, f->coef.p, dHt.p, lw.ghosts.p);
-            MWNS_HIP(hipGetLastError());
-            MWNS_HIP(hipStreamSynchronize(st));
-        }
+        if (!lw.nghost) continue;
+        lw.gkeys.reset(ctx, gk.size());
+        lw.gkeys.upload(gk.data(), gk.size(), st);
+        closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, miss.p + lw.miss_off, lw.gkeys.p, lw.nghost,
+                                                                         lw.nout, lw.nbr.p);
+        MWNS_HIP(hipGetLastError());
+        lw.ghosts.reset(ctx, (size_t)lw.nghost * E);
+        dispatch_k<GhostLaunch>(k, st, lw.nghost, j - 1, lw.gkeys.p, f->dkeys.p, f->nnodes, lt, f->coef.p, dHt.p,
+                                lw.ghosts.p);
+        MWNS_HIP(hipGetLastError());
     }
     tclos.stop();
-    // ---- contractions
-    tcon.start();
+    // ---- contractions: one launch over every output brick of every level, costliest first
+    std::vector<LevelDesc> descs(depth + 1);
+    std::vector<std::pair<double, int2>> cost;
     int64_t jobs = 0;
     double flops = 0.0;
     for (int j = 0; j <= depth; ++j) {
         LevelWork& lw = W[j];
         double* outj = out->coef.p + f->lev[j].brick_off * E;
+        LevelDesc& d = descs[j];
+        d = LevelDesc{};
+        d.out = outj;
         if (lw.tpl.empty()) {
             MWNS_HIP(hipMemsetAsync(outj, 0, lw.nout * E * sizeof(double), st));
             continue;
         }
         lw.dtpl.reset(ctx, lw.tpl.size());
         lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), st);
-        const double* Xr = f->coef.p + f->lev[j].brick_off * E;
-        const double* Fj = op->F.p + (int64_t)j * op->M * NLF * k * k;
-        dispatch_k<ApplyLaunch>(k, st, lw.nout, Xr, lw.nout, lw.ghosts.p, lw.nbr.p, lw.Lr, lw.cmask.p, lw.valid,
-                                lw.dtpl.p, (int)lw.tpl.size(), Fj, op->dw.p, outj);
-        MWNS_HIP(hipGetLastError());
-        for (const Tpl& t : lw.tpl) {
-            const double n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
-            const double D2 = 2.0 * k;
-            const int64_t nb = t.dpart ? lw.nout - lw.nleafonly : lw.nout;
-            jobs += nb * (t.m2 - t.m1 + 1);
-            flops += (double)nb * (t.m2 - t.m1 + 1) * 2.0 * D2 * D2 * D2 * D2 * (n1 * n2 * n3 + n1 * n2 + n1);
+        d.Xr = f->coef.p + f->lev[j].brick_off * E;
+        d.Xg = lw.ghosts.p;
+        d.nbr = lw.nbr.p;
+        d.cmask = lw.cmask.p;
+        d.tpl = lw.dtpl.p;
+        d.Fj = op->F.p + (int64_t)j * op->M * NLF * k * k;
+        d.nreal = lw.nout;
+        d.Lr = lw.Lr;
+        d.valid = lw.valid;
+        d.ntpl = (int)lw.tpl.size();
+        const int64_t pside = j > 0 ? ((int64_t)1 << (j - 1)) : 1;
+        for (int64_t b = 0; b < lw.nout; ++b) {
+            int64_t p[3] = {0, 0, 0};
+            if (j > 0) key_coords(lw.pk[b], p);
+            double c = 0.0;
+            for (const Tpl& t : lw.tpl) {
+                if (t.dpart && lw.cm[b] == 0) continue;
+                double nin[3];
+                for (int dd = 0; dd < 3; ++dd) {
+                    int cnt = 0;
+                    for (int Lx = t.lo[dd]; Lx <= t.hi[dd]; ++Lx) cnt += (p[dd] - Lx >= 0 && p[dd] - Lx < pside);
+                    nin[dd] = cnt;
+                }
+                const double nt = t.m2 - t.m1 + 1;
+                c += nt * (nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0]);
+                const double D2 = 2.0 * k;
+                const double n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
+                (void)n2;
+                (void)n3;
+                (void)n1;
+                jobs += (int64_t)nt;
+                flops += nt * 2.0 * D2 * D2 * D2 * D2 * (nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0]);
+            }
+            cost.push_back({c, make_int2(j, (int)b)});
         }
     }
+    std::stable_sort(cost.begin(), cost.end(), [](const std::pair<double, int2>& a, const std::pair<double, int2>& b) {
+        return a.first > b.first;
+    });
+    std::vector<int2> order(cost.size());
+    for (size_t i = 0; i < cost.size(); ++i) order[i] = cost[i].second;
+    DevArray<LevelDesc> ddesc(ctx, descs.size());
+    ddesc.upload(descs.data(), descs.size(), st);
+    DevArray<int2> dorder(ctx, std::max<size_t>(1, order.size()));
+    dorder.upload(order.data(), order.size(), st);
+    tcon.start();
+    if (!order.empty()) {
+        dispatch_k<ApplyLaunch>(k, st, (int64_t)order.size(), ddesc.p, dorder.p, op->dw.p);
+        MWNS_HIP(hipGetLastError());
+    }
     tcon.stop();
-    // ---- assembly
+    // ---- assembly (eq. g_assemble), level by level on the stream
     tasm.start();
+    std::vector<DevArray<int64_t>> apb(depth + 1);
+    std::vector<DevArray<int>> apc(depth + 1);
     if (!(mode & MWNS_NO_ASSEMBLY)) {
         for (int j = 1; j <= depth; ++j) {
             const mwns_level& L = f->lev[j];
             std::vector<int64_t> pb(L.nbricks);
             std::vector<int> pc(L.nbricks);
             for (int64_t b = 0; b < L.nbricks; ++b) node_brick(f, f->brick_parent[L.brick_off + b], &pb[b], &pc[b]);
-            DevArray<int64_t> dpb(ctx, pb.size());
-            DevArray<int> dpc(ctx, pc.size());
-            dpb.upload(pb.data(), pb.size(), st);
-            dpc.upload(pc.data(), pc.size(), st);
-            dispatch_k<AssembleLaunch>(k, st, L.nbricks, j, dpb.p, dpc.p, L.brick_off, dHt.p, out->coef.p);
+            apb[j].reset(ctx, pb.size());
+            apc[j].reset(ctx, pc.size());
+            apb[j].upload(pb.data(), pb.size(), st);
+            apc[j].upload(pc.data(), pc.size(), st);
+            dispatch_k<AssembleLaunch>(k, st, L.nbricks, j, apb[j].p, apc[j].p, L.brick_off, dHt.p, out->coef.p);
             MWNS_HIP(hipGetLastError());
-            MWNS_HIP(hipStreamSynchronize(st));
         }
     }
     tasm.stop();
@@ -682,8 +837,8 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
         for (int j = 0; j <= depth; ++j) {
             const LevelWork& lw = W[j];
             const int32_t* Rj1 = (j + 1 <= op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
-            count_kernel<<<(unsigned)((lw.nout + 63) / 64), 64, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
-                                                                         dplan.p + (int64_t)j * planrow, Rj1, tot.p);
+            count_kernel<<<(unsigned)((lw.nout * 8 + 255) / 256), 256, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
+                                                                                dplan.p + (int64_t)j * planrow, Rj1, tot.p);
             MWNS_HIP(hipGetLastError());
         }
         unsigned long long c = 0;
@@ -697,6 +852,8 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
         s.ms_contract = tcon.ms();
         s.ms_assemble = tasm.ms();
         *stats = s;
+    } else {
+        MWNS_HIP(hipStreamSynchronize(st));
     }
     *g = out.release();
     return MWNS_OK;

@@ -89,7 +89,10 @@ def test_apply_matches_oracle(M, ctx, case):
     gt2, st2 = M.mwns_apply(ctx, op, f)
     _, _, gg = M.mwns_tree_export(ctx, gt2)
     assert np.linalg.norm(gg - g) <= 1e-12 * np.linalg.norm(g)
-    assert st2["contractions"] > 0 and st2["useful_flops"] > 0
+    assert st2["useful_flops"] > 0
+    # the device's contraction count equals the count of non-zero coefficients from the plan
+    import bench
+    assert st2["contractions"] == bench._count_contractions(oo.R, ot, np.arange(ot.keys.size))
 
 
 def test_apply_is_deterministic(M, ctx):
@@ -114,3 +117,127 @@ def test_eval_matches_oracle(M, ctx):
     v = M.mwns_tree_eval(ctx, f, P)
     ref = T.evaluate(ot, P)
     assert np.abs(v - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_c2_full_size_sampled(M, ctx):
+    """The benchmark workload (Poisson, k=8, eps=1e-6, 50 Gaussians) at full size: tree bit-exact,
+    and g at sampled leaves (and their ancestor chains) within 1e-12 of the oracle."""
+    from oracle import apply as A
+    w = workloads.c2()
+    ot = _oracle_tree(w)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    keys, leaf, coef = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(keys, ot.keys) and np.array_equal(leaf, ot.leaf)
+    assert np.abs(coef - ot.coef).max() <= 1e-13 * np.abs(ot.coef).max()
+    tau, wt = _fit(w, ot.depth)
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, oo.R)
+    g, st = M.mwns_apply(ctx, op, f)
+    _, _, gg = M.mwns_tree_export(ctx, g)
+    rng = np.random.Generator(np.random.PCG64(31))
+    leaves = np.nonzero(ot.leaf)[0]
+    sample = list(rng.choice(leaves, 48, replace=False))
+    deepest = np.nonzero(ot.level == ot.depth)[0]
+    sample += [leaves[0], leaves[-1], deepest[0], deepest[-1]]          # cube corners and deepest boxes
+    from oracle.tree import make_keys
+    chain = set()
+    for i in sample:
+        j, l = int(ot.level[i]), ot.l[i]
+        for lev in range(j + 1):
+            chain.add(int(ot.index(make_keys(np.array([lev]), *(l[None, :] >> (j - lev)).T))[0]))
+    chain = np.array(sorted(chain))
+    gh = dict(zip(chain, A.apply_modified(oo, ot, chain)))
+    ref = np.stack([A.assemble_chain(ot, i, lambda n: gh[n]) for i in sample])
+    got = gg[sample]
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 7])
+def test_odd_and_small_orders(M, ctx, k):
+    """Orders whose 2k is not a multiple of 4 take the element-wise load path of the kernel."""
+    from oracle import apply as A
+    w = workloads.small_adaptive(4, k=k, eps=1e-3 if k > 2 else 1e-2, jmax=4)
+    ot = _oracle_tree(w)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    keys, leaf, _ = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(keys, ot.keys)
+    tau, wt = _fit(w, ot.depth)
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, oo.R)
+    ref = A.assemble(ot, A.apply_modified(oo, ot))
+    _, _, gg = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f)[0])
+    assert np.linalg.norm(gg - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("j0,jmax", [(0, 0), (0, 3), (2, 2)])
+def test_coarse_start_and_uniform_trees(M, ctx, j0, jmax):
+    """Root-only tree, refinement from the root, and a uniform tree (no refinement test)."""
+    from oracle import apply as A
+    w = workloads.small_adaptive(6, k=4, eps=1e-3, jmax=jmax)
+    w["j0"] = j0
+    ot = _oracle_tree(w)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, j0, jmax, w.xyz, w.a, w.c)
+    keys, leaf, coef = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(keys, ot.keys) and np.array_equal(leaf, ot.leaf)
+    tau, wt = _fit(w, max(ot.depth, 1))
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, oo.R)
+    ref = A.assemble(ot, A.apply_modified(oo, ot))
+    _, _, gg = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f)[0])
+    assert np.linalg.norm(gg - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_tree_from_leaves_full_plan_random_coefficients(M, ctx):
+    """Imported leaves (random blocks on an adaptive structure) with screening off: every term on
+    every coarse displacement, against the oracle."""
+    from oracle import apply as A
+    from oracle import tree as T
+    w = workloads.small_adaptive(9, k=4, eps=1e-3, jmax=4)
+    ot0 = _oracle_tree(w)
+    lf = np.nonzero(ot0.leaf)[0]
+    rng = np.random.Generator(np.random.PCG64(5))
+    coef = rng.normal(size=(lf.size, 4, 4, 4))
+    perm = rng.permutation(lf.size)                       # any leaf order is accepted
+    ot = T.redundant_tree(4, ot0.keys[lf], coef)
+    f = M.mwns_tree_from_leaves(ctx, 4, ot0.keys[lf][perm], coef[perm])
+    keys, leaf, fc = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(keys, ot.keys) and np.abs(fc - ot.coef).max() <= 1e-13 * np.abs(ot.coef).max()
+    tau, wt = _fit(w, ot.depth)
+    R = A.full_plan(tau.size, ot.depth)
+    oo = A.Operator(4, tau, wt, w.eps, ot.depth, R=R)
+    op = M.mwns_op_create(ctx, 4, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, R)
+    ref = A.assemble(ot, A.apply_modified(oo, ot))
+    _, _, gg = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f)[0])
+    assert np.linalg.norm(gg - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_error_paths(M, ctx):
+    from paper_0706_0747_amd import _lib
+    w = workloads.small_adaptive(4, k=4, eps=1e-3, jmax=3)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = M.mwns_fit_kernel(0.0, 1.0, 1e-3, 1e-3, 1.8)
+    cases = [
+        lambda: M.mwns_op_create(ctx, 9, tau, wt, 1e-3, 3),                      # k beyond the kernels
+        lambda: M.mwns_op_create(ctx, 4, -tau, wt, 1e-3, 3),                     # tau <= 0
+        lambda: M.mwns_apply(ctx, M.mwns_op_create(ctx, 4, tau, wt, 1e-3, depth - 1), f),   # max_level < depth
+        lambda: M.mwns_apply(ctx, M.mwns_op_create(ctx, 5, tau, wt, 1e-3, depth), f),       # k mismatch
+        lambda: M.mwns_tree_eval(ctx, f, [[0.5, 0.5, 1.5]]),                      # outside the cube
+        lambda: M.mwns_project_gaussians(ctx, 4, 1e-3, 3, 2, w.xyz, w.a, w.c),  # jmax < j0
+        lambda: M.mwns_project_gaussians(ctx, 4, 1e-3, 0, 3, w.xyz, -w.a, w.c), # a <= 0
+        lambda: M.mwns_tree_from_leaves(ctx, 4, np.array([0], dtype=np.uint64) | np.uint64(1 << 57),
+                                        np.zeros((1, 4, 4, 4))),                 # one child only: no tiling
+    ]
+    for c in cases:
+        with pytest.raises(M.MwnsError) as e:
+            c()
+        assert e.value.status == _lib.MWNS_EINVAL, str(e.value)
+    op = M.mwns_op_create(ctx, 4, tau, wt, 1e-3, depth)
+    bad = M.mwns_op_plan_export(op).copy()
+    bad[1, 3, 3, 3] = (0, tau.size + 5)
+    with pytest.raises(M.MwnsError):
+        M.mwns_op_plan_import(op, bad)
