@@ -78,34 +78,52 @@ __device__ inline double sop(const double* __restrict__ Fm, int L, int mlo, int 
     return Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
 }
 
-template <int K, int TPW>
-__device__ inline void load_slices(const double* __restrict__ X, int wave, int g, int r, double (&x)[TPW][4]) {
+// Byte offset of lane (g, r)'s four consecutive doubles X[v1][r][4g..4g+3] in a brick; rows,
+// slices and column groups outside the 2K extent get an offset past the buffer (loads return 0).
+template <int K>
+__device__ inline uint32_t slice_offset(int v1, int g, int r) {
     constexpr int D = 2 * K;
+    if (v1 >= D || r >= D || 4 * g >= D) return 0x40000000u;
+    return (uint32_t)((((v1 * D) + r) * D + 4 * g) * 8);
+}
+
+template <int K, int TPW>
+__device__ inline void load_slices(const double* __restrict__ X, const uint32_t (&off)[TPW], double (&x)[TPW][4]) {
+    constexpr int D = 2 * K;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, D * D * D * 8, 0x00020000);
+    typedef double dv2 __attribute__((ext_vector_type(2)));
     for (int t = 0; t < TPW; ++t) {
-        const int v1 = wave * TPW + t;
-        const double* xp = X + ((int64_t)v1 * D + r) * D + 4 * g;
-        if (v1 < D && r < D && 4 * g + 3 < D && (D % 4) == 0) {
-            const double2 p0 = *reinterpret_cast<const double2*>(xp);
-            const double2 p1 = *reinterpret_cast<const double2*>(xp + 2);
-            x[t][0] = p0.x; x[t][1] = p0.y; x[t][2] = p1.x; x[t][3] = p1.y;
+        if constexpr (D % 4 == 0) {
+            const dv2 a = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t], 0, 0));
+            const dv2 b = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t] + 16, 0, 0));
+            x[t][0] = a.x; x[t][1] = a.y; x[t][2] = b.x; x[t][3] = b.y;
         } else {
-            for (int kk = 0; kk < 4; ++kk) x[t][kk] = (v1 < D && r < D && 4 * g + kk < D) ? xp[kk] : 0.0;
+            // a 4-column group may cross the end of a row: load the valid columns one by one
+            const uint32_t o = off[t];
+            const int col = (int)((o / 8) % D);
+            for (int kk = 0; kk < 4; ++kk) {
+                const uint32_t ok = (o < 0x40000000u && col + kk < D) ? o + 8 * kk : 0x40000000u;
+                x[t][kk] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, ok, 0, 0));
+            }
         }
     }
 }
 
 // One block per output brick, over all levels at once (order[] lists (level, brick) by decreasing cost).
 template <int K>
-__global__ void __launch_bounds__(CT) ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order,
+__global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4, 4))) ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order,
                                                       const double* __restrict__ w) {
     constexpr int D = 2 * K;
     constexpr int TPW = (D + CW - 1) / CW;
+    constexpr bool FULL = (CW * TPW == D);     // every wave owns TPW real slices (2k = 16)
     constexpr int64_t E = (int64_t)D * D * D;
     __shared__ double T2s[16 * T2S_V1];
     __shared__ double S3s[NMAX * 16 * S3_V];
     __shared__ double S2s[NMAX * 256];
     __shared__ double S1s[NMAX * 256];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    // wave index and every neighbour index are uniform per wave: keep them in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const int2 job = order[blockIdx.x];
     const LevelDesc lv = levels[job.x];
     const int64_t b = job.y;
@@ -113,10 +131,11 @@ __global__ void __launch_bounds__(CT) ns_apply_kernel(const LevelDesc* __restric
     const int NL = 2 * Lr + 1;
     const int32_t* nb = lv.nbr + b * NL * NL * NL;
     const int cmb = lv.cmask[b];
-    d4 YW[TPW], YD[TPW];
+    d4 Y[TPW];
+    uint32_t xoff[TPW];
     for (int t = 0; t < TPW; ++t) {
-        YW[t] = (d4){0.0, 0.0, 0.0, 0.0};
-        YD[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        xoff[t] = slice_offset<K>(wave * TPW + t, g, r);
     }
     for (int ti = 0; ti < lv.ntpl; ++ti) {
         const Tpl tp = lv.tpl[ti];
@@ -146,60 +165,57 @@ __global__ void __launch_bounds__(CT) ns_apply_kernel(const LevelDesc* __restric
                 for (int L2 = tp.lo[1]; L2 <= tp.hi[1]; ++L2) {
                     const int32_t* row = nb + ((L1 + Lr) * NL + (L2 + Lr)) * NL + Lr;
                     int L3 = tp.lo[2];
-                    while (L3 <= tp.hi[2] && row[L3] < 0) ++L3;
+                    while (L3 <= tp.hi[2] && __builtin_amdgcn_readfirstlane(row[L3]) < 0) ++L3;
                     if (L3 > tp.hi[2]) continue;
                     any1 = true;
                     d4 T1[TPW];
                     for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                    double xc[TPW][4];
-                    {
-                        const int idx = row[L3];
-                        load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, wave, g, r, xc);
-                    }
-                    while (L3 <= tp.hi[2]) {
-                        int Ln = L3 + 1;
-                        while (Ln <= tp.hi[2] && row[Ln] < 0) ++Ln;
-                        double xn[TPW][4];
-                        if (Ln <= tp.hi[2]) {
-                            const int idx = row[Ln];
-                            load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, wave, g, r, xn);
-                        }
+                    for (; L3 <= tp.hi[2]; ++L3) {
+                        const int idx = __builtin_amdgcn_readfirstlane(row[L3]);
+                        if (idx < 0) continue;
+                        double xc[TPW][4];
+                        load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, xoff, xc);
                         const double* s3p = S3s + (L3 - tp.lo[2]) * 16 * S3_V + r;
                         double s3[4];
                         for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
                         for (int kk = 0; kk < 4; ++kk)
                             for (int t = 0; t < TPW; ++t)
-                                if (wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[t][kk], s3[kk], T1[t], 0, 0, 0);
-                        if (Ln <= tp.hi[2])
-                            for (int t = 0; t < TPW; ++t)
-                                for (int kk = 0; kk < 4; ++kk) xc[t][kk] = xn[t][kk];
-                        L3 = Ln;
+                                if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[t][kk], s3[kk], T1[t], 0, 0, 0);
                     }
                     const double* s2p = S2s + (L2 - tp.lo[1]) * 256 + r;
                     double s2[4];
                     for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
                     for (int i = 0; i < 4; ++i)
                         for (int t = 0; t < TPW; ++t)
-                            if (wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
                 }
                 if (!any1) continue;
                 for (int t = 0; t < TPW; ++t) {
                     const int v1 = wave * TPW + t;
-                    if (v1 >= D) break;
+                    if (!FULL && v1 >= D) break;
                     for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
                 }
                 __syncthreads();
                 const double* s1p = S1s + (L1 - tp.lo[0]) * 256 + r;
                 double s1[4];
                 for (int kk = 0; kk < 4; ++kk) s1[kk] = s1p[(4 * kk + g) * 16];
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int v1 = 4 * kk + g;
-                    for (int t = 0; t < TPW; ++t) {
-                        const int u2 = wave * TPW + t;
-                        if (u2 >= D) break;
+                for (int t = 0; t < TPW; ++t) {
+                    const int u2 = wave * TPW + t;
+                    if (!FULL && u2 >= D) break;
+                    // the down band reaches only internal children: accumulate it apart, add it masked
+                    d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int v1 = 4 * kk + g;
                         const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
-                        if (tp.dpart) YD[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YD[t], 0, 0, 0);
-                        else YW[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, YW[t], 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, acc, 0, 0, 0);
+                    }
+                    if (tp.dpart) {
+                        for (int i = 0; i < 4; ++i) {
+                            const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
+                            if ((cmb >> child) & 1) Y[t][i] += acc[i];
+                        }
+                    } else {
+                        Y[t] = acc;
                     }
                 }
                 __syncthreads();
@@ -214,9 +230,7 @@ __global__ void __launch_bounds__(CT) ns_apply_kernel(const LevelDesc* __restric
             const int u1 = 4 * i + g, u3 = r;
             if (u1 >= D || u3 >= D) continue;
             const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
-            double v = ((lv.valid >> child) & 1) ? YW[t][i] : 0.0;
-            if ((cmb >> child) & 1) v += YD[t][i];
-            ob[((int64_t)u1 * D + u2) * D + u3] = v;
+            ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][i] : 0.0;
         }
     }
 }
