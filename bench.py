@@ -29,7 +29,22 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain elementwise kernel that reads and writes 256 MiB each: the counters it produces scale
+    FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = 32 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "elementwise copy", "bytes_read": n * 8, "bytes_written": n * 8}))
 
 
 def step(M, ctx, w, pts):
@@ -103,6 +118,9 @@ def _count_contractions(R, tr, idx):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)

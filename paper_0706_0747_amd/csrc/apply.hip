@@ -808,11 +808,40 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
             cost.push_back({c, make_int2(j, (int)b)});
         }
     }
-    std::stable_sort(cost.begin(), cost.end(), [](const std::pair<double, int2>& a, const std::pair<double, int2>& b) {
-        return a.first > b.first;
-    });
-    std::vector<int2> order(cost.size());
-    for (size_t i = 0; i < cost.size(); ++i) order[i] = cost[i].second;
+    // Launch order.  Workgroups are dealt round-robin to the 8 XCDs, each with its own L2, and the
+    // input sibling groups of neighbouring output bricks overlap: so levels go costliest first,
+    // each level is cut into 8 contiguous Morton ranges of equal length, and block 8i + x takes
+    // the i-th brick of range x, keeping every XCD on one compact region of the tree at a time.
+    std::vector<int2> order;
+    order.reserve(cost.size());
+    {
+        std::vector<std::pair<double, int>> lev_cost;   // (cost per brick, level)
+        size_t pos = 0;
+        std::vector<size_t> lev_begin(depth + 2, 0);
+        for (int j = 0; j <= depth; ++j) {
+            lev_begin[j] = pos;
+            double c = 0.0;
+            size_t n = 0;
+            while (pos < cost.size() && cost[pos].second.x == j) { c += cost[pos].first; ++pos; ++n; }
+            if (n) lev_cost.push_back({c / n, j});
+        }
+        lev_begin[depth + 1] = pos;
+        std::stable_sort(lev_cost.begin(), lev_cost.end(),
+                         [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+        constexpr int NXCD = 8;
+        for (const auto& lc : lev_cost) {
+            const int j = lc.second;
+            const size_t b0 = lev_begin[j];
+            size_t n = 0;
+            while (b0 + n < cost.size() && cost[b0 + n].second.x == j) ++n;
+            const size_t per = (n + NXCD - 1) / NXCD;
+            for (size_t i = 0; i < per; ++i)
+                for (int x = 0; x < NXCD; ++x) {
+                    const size_t idx = x * per + i;
+                    if (idx < n) order.push_back(cost[b0 + idx].second);
+                }
+        }
+    }
     DevArray<LevelDesc> ddesc(ctx, descs.size());
     ddesc.upload(descs.data(), descs.size(), st);
     DevArray<int2> dorder(ctx, std::max<size_t>(1, order.size()));

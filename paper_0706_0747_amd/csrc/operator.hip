@@ -118,48 +118,62 @@ __global__ void combine_kernel(int k, int M, int nlev, const double* __restrict_
     F[idx] = ldexp(s, -j);
 }
 
-// Frobenius norms of the super-blocks for scales 1..nlev-1, |L| = 0..LP; nf0[m] = ||F^{0;m,0}||_F.
-__global__ void norms_kernel(int k, int M, int nlev, const double* __restrict__ F, const double* __restrict__ H,
-                             double* __restrict__ norms /* [nlev][M][LP+1][3] */, double* __restrict__ nf0) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nL = LP + 1;
+// Frobenius norms of the super-blocks for scales 1..nlev-1, |L| = 0..LP: one 64-lane block per
+// (j, m, L), lane (a, b) owns entry (a, b) of each of the four k x k sub-blocks; U is formed as
+// H^{so T} (F^{j-1;m,L} H^{si}).  Block 0 of the grid also writes nf0[m] = ||F^{0;m,0}||_F.
+__global__ void __launch_bounds__(64) norms_kernel(int k, int M, int nlev, const double* __restrict__ F,
+                                                   const double* __restrict__ H, double* __restrict__ norms,
+                                                   double* __restrict__ nf0) {
     const int kk = k * k;
-    if (idx < M) {
-        const double* f = F + ((int64_t)idx * NLF + LF) * kk;
-        double s = 0.0;
-        for (int i = 0; i < kk; ++i) s += f[i] * f[i];
-        nf0[idx] = sqrt(s);
-    }
-    if (idx >= (nlev - 1) * M * nL) return;
-    const int L = idx % nL;
-    const int m = (idx / nL) % M;
-    const int j = 1 + idx / (nL * M);
-    const double* Fj = F + ((int64_t)j * M + m) * NLF * kk;
-    const double* Fc = F + ((int64_t)(j - 1) * M + m) * NLF * kk + (L + LF) * kk;
-    const double* Hs[2] = {H, H + kk};
-    double sF = 0.0, sU = 0.0, sD = 0.0;
-    for (int so = 0; so < 2; ++so)
-        for (int si = 0; si < 2; ++si) {
-            const int l = 2 * L + so - si;
-            const double* fb = Fj + (l + LF) * kk;
-            for (int a = 0; a < k; ++a)
-                for (int b = 0; b < k; ++b) {
-                    double u = 0.0;   // (H^so^T F^{j-1;L} H^si)_ab
-                    for (int p = 0; p < k; ++p) {
-                        double t = 0.0;
-                        for (int q = 0; q < k; ++q) t += Fc[p * k + q] * Hs[si][q * k + b];
-                        u += Hs[so][p * k + a] * t;
-                    }
-                    const double f = fb[a * k + b];
-                    sF += f * f;
-                    sU += u * u;
-                    sD += (f - u) * (f - u);
-                }
+    const int nL = LP + 1;
+    const int lane = threadIdx.x;
+    __shared__ double Hs[2 * KMAX * KMAX], Fc[KMAX * KMAX], T[2][KMAX * KMAX], red[3][64];
+    if (blockIdx.x == (unsigned)((nlev - 1) * M * nL)) {    // the extra last block: nf0
+        for (int m = lane; m < M; m += 64) {
+            const double* f = F + ((int64_t)m * NLF + LF) * kk;
+            double s = 0.0;
+            for (int i = 0; i < kk; ++i) s += f[i] * f[i];
+            nf0[m] = sqrt(s);
         }
-    double* o = norms + (((int64_t)j * M + m) * nL + L) * 3;
-    o[0] = sqrt(sF);
-    o[1] = sqrt(sU);
-    o[2] = sqrt(sD);
+        return;
+    }
+    const int L = blockIdx.x % nL;
+    const int m = (blockIdx.x / nL) % M;
+    const int j = 1 + blockIdx.x / (nL * M);
+    const double* Fj = F + ((int64_t)j * M + m) * NLF * kk;
+    const double* Fcg = F + ((int64_t)(j - 1) * M + m) * NLF * kk + (L + LF) * kk;
+    for (int e = lane; e < 2 * kk; e += 64) Hs[e] = H[e];
+    for (int e = lane; e < kk; e += 64) Fc[e] = Fcg[e];
+    __syncthreads();
+    const int a = lane / k, b = lane % k;
+    const bool act = lane < kk;
+    if (act)
+        for (int si = 0; si < 2; ++si) {            // T[si][a][b] = sum_q F[a][q] H^si[q][b]
+            double t = 0.0;
+            for (int q = 0; q < k; ++q) t += Fc[a * k + q] * Hs[si * kk + q * k + b];
+            T[si][a * k + b] = t;
+        }
+    __syncthreads();
+    double sF = 0.0, sU = 0.0, sD = 0.0;
+    if (act)
+        for (int so = 0; so < 2; ++so)
+            for (int si = 0; si < 2; ++si) {
+                double u = 0.0;                     // (H^so^T F^{j-1;L} H^si)_ab
+                for (int p = 0; p < k; ++p) u += Hs[so * kk + p * k + a] * T[si][p * k + b];
+                const double f = Fj[(2 * L + so - si + LF) * kk + a * k + b];
+                sF += f * f;
+                sU += u * u;
+                sD += (f - u) * (f - u);
+            }
+    red[0][lane] = sF;
+    red[1][lane] = sU;
+    red[2][lane] = sD;
+    __syncthreads();
+    if (lane < 3) {
+        double s = 0.0;
+        for (int i = 0; i < 64; ++i) s += red[lane][i];
+        norms[(((int64_t)j * M + m) * nL + L) * 3 + lane] = sqrt(s);
+    }
 }
 
 // One thread per (scale j >= 1, canonical class (c0 <= c1 <= c2)): term range.
@@ -272,8 +286,7 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     DevArray<double> dH = upload_filters(ctx, k);
     const int nL = LP + 1;
     DevArray<double> norms(ctx, (size_t)nlev * M * nL * 3), nf0(ctx, M);
-    const int nth = std::max(M, (nlev - 1) * M * nL);
-    norms_kernel<<<(nth + 127) / 128, 128, 0, st>>>(k, M, nlev, op->F.p, dH.p, norms.p, nf0.p);
+    norms_kernel<<<(nlev - 1) * M * nL + 1, 64, 0, st>>>(k, M, nlev, op->F.p, dH.p, norms.p, nf0.p);
     MWNS_HIP(hipGetLastError());
     std::vector<int32_t> ranges(std::max(1, (nlev - 1) * 20) * 2);
     if (nlev > 1) {

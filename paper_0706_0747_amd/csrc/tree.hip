@@ -48,13 +48,15 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
                                                      double thr, const double* __restrict__ tab, double* __restrict__ s_out,
                                                      uint8_t* __restrict__ refine, double* __restrict__ err_out) {
     constexpr int K3 = K * K * K;
+    constexpr int P2 = 2 * K;
     constexpr int NQ = 3 * K;                // 1-D points: K own nodes, then 2K children nodes
-    constexpr int NP = 9 * K3;               // own nodes + (2K)^3 children nodes
+    constexpr int NC = 8 * K3;               // children grid (2K)^3, points 0..NC-1
+    constexpr int NP = 9 * K3;               // then the box's own K^3 nodes
     constexpr int PER = (NP + PT - 1) / PT;
-    __shared__ double E[CH][3][NQ];
-    __shared__ double fv[NP];
-    __shared__ double t1[4 * K3];
-    __shared__ double t2[8 * K3];
+    __shared__ double E[CH][3][NQ];          // E[i][0][q] already carries the source weight
+    __shared__ double fown[K3];
+    __shared__ double t1[2 * K3];
+    __shared__ double t2[6 * K3];
     __shared__ double red[PT];
     // tab: P[a][i] = phi_a(x_i) w_i (K*K), Q[q][a] = phi_a((s + x_i)/2), q = s*K + i (2K*K), gx[K]
     const double* P = tab;
@@ -65,7 +67,21 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     key_coords(keys[box], l);
     const double h = ldexp(1.0, -j);
     double acc[PER];
-    for (int r = 0; r < PER; ++r) acc[r] = 0.0;
+    int qq[PER][3];
+    for (int r = 0; r < PER; ++r) {
+        acc[r] = 0.0;
+        const int pt = threadIdx.x + r * PT;
+        if (pt < NC) {
+            qq[r][0] = K + pt / (P2 * P2);
+            qq[r][1] = K + (pt / P2) % P2;
+            qq[r][2] = K + pt % P2;
+        } else {
+            const int o = pt - NC;
+            qq[r][0] = o / (K * K);
+            qq[r][1] = (o / K) % K;
+            qq[r][2] = o % K;
+        }
+    }
     for (int c0 = 0; c0 < nsrc; c0 += CH) {
         const int nc = min(CH, nsrc - c0);
         for (int e = threadIdx.x; e < nc * 3 * NQ; e += PT) {
@@ -74,97 +90,90 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
             double x;
             if (q < K) x = h * (l[d] + gx[q]);
             else {
-                const int s = (q - K) / K, p = (q - K) % K;
-                x = 0.5 * h * (2 * l[d] + s + gx[p]);
+                const int sg = (q - K) / K, pp = (q - K) % K;
+                x = 0.5 * h * (2 * l[d] + sg + gx[pp]);
             }
             const double dx = x - sp[d];
-            E[i][d][q] = exp(-sp[3] * dx * dx);
+            const double ev = exp(-sp[3] * dx * dx);
+            E[i][d][q] = d == 0 ? sp[4] * ev : ev;
         }
         __syncthreads();
         for (int r = 0; r < PER; ++r) {
             const int pt = threadIdx.x + r * PT;
             if (pt >= NP) break;
-            int q0, q1, q2;
-            if (pt < K3) {
-                q0 = pt / (K * K);
-                q1 = (pt / K) % K;
-                q2 = pt % K;
-            } else {
-                const int g = pt - K3, P2 = 2 * K;
-                q0 = K + g / (P2 * P2);
-                q1 = K + (g / P2) % P2;
-                q2 = K + g % P2;
-            }
             double a = acc[r];
-            for (int i = 0; i < nc; ++i) a += src[(int64_t)(c0 + i) * 5 + 4] * E[i][0][q0] * E[i][1][q1] * E[i][2][q2];
+            for (int i = 0; i < nc; ++i) a += E[i][0][qq[r][0]] * E[i][1][qq[r][1]] * E[i][2][qq[r][2]];
             acc[r] = a;
         }
         __syncthreads();
     }
     for (int r = 0; r < PER; ++r) {
         const int pt = threadIdx.x + r * PT;
-        if (pt < NP) fv[pt] = acc[r];
+        if (pt >= NC && pt < NP) fown[pt - NC] = acc[r];
     }
     __syncthreads();
     // s = 2^{-3j/2} (P (x) P (x) P) f_own, contracting the last index first
     const double nc3 = pow(2.0, -1.5 * j);
+    double* ta = t1;
+    double* s_l = t1 + K3;
     for (int e = threadIdx.x; e < K3; e += PT) {
         const int i1 = e / (K * K), i2 = (e / K) % K, a3 = e % K;
-        double s = 0.0;
-        for (int i3 = 0; i3 < K; ++i3) s += P[a3 * K + i3] * fv[(i1 * K + i2) * K + i3];
-        t1[e] = s;
+        double sm = 0.0;
+        for (int i3 = 0; i3 < K; ++i3) sm += P[a3 * K + i3] * fown[(i1 * K + i2) * K + i3];
+        ta[e] = sm;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < K3; e += PT) {
         const int i1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
-        double s = 0.0;
-        for (int i2 = 0; i2 < K; ++i2) s += P[a2 * K + i2] * t1[(i1 * K + i2) * K + a3];
-        t2[e] = s;
+        double sm = 0.0;
+        for (int i2 = 0; i2 < K; ++i2) sm += P[a2 * K + i2] * ta[(i1 * K + i2) * K + a3];
+        t2[e] = sm;
     }
     __syncthreads();
     double* sb = s_out + (int64_t)box * K3;
     for (int e = threadIdx.x; e < K3; e += PT) {
         const int a1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
-        double s = 0.0;
-        for (int i1 = 0; i1 < K; ++i1) s += P[a1 * K + i1] * t2[(i1 * K + a2) * K + a3];
-        s *= nc3;
-        sb[e] = s;
-        t1[e] = s;   // keep s for the interpolation
+        double sm = 0.0;
+        for (int i1 = 0; i1 < K; ++i1) sm += P[a1 * K + i1] * t2[(i1 * K + a2) * K + a3];
+        sm *= nc3;
+        sb[e] = sm;
+        s_l[e] = sm;   // keep s for the interpolation
     }
     __syncthreads();
     double emax = 0.0;
     if (j < jmax) {
-        // f~ on the (2K)^3 children grid = 2^{3j/2} (Q (x) Q (x) Q) s
-        constexpr int P2 = 2 * K;
+        // f~ on the (2K)^3 children grid = 2^{3j/2} (Q (x) Q (x) Q) s; compared with the values each
+        // thread holds for the same grid points
         const double ni = pow(2.0, 1.5 * j);
         double* u1 = t2;                     // [a1][a2][q3]   K*K*2K
         for (int e = threadIdx.x; e < K * K * P2; e += PT) {
             const int a1 = e / (K * P2), a2 = (e / P2) % K, q3 = e % P2;
-            double s = 0.0;
-            for (int a3 = 0; a3 < K; ++a3) s += Q[q3 * K + a3] * t1[(a1 * K + a2) * K + a3];
-            u1[e] = s;
+            double sm = 0.0;
+            for (int a3 = 0; a3 < K; ++a3) sm += Q[q3 * K + a3] * s_l[(a1 * K + a2) * K + a3];
+            u1[e] = sm;
         }
         __syncthreads();
         double* u2 = t2 + 2 * K3;            // [a1][q2][q3] K*2K*2K
         for (int e = threadIdx.x; e < K * P2 * P2; e += PT) {
             const int a1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
-            double s = 0.0;
-            for (int a2 = 0; a2 < K; ++a2) s += Q[q2 * K + a2] * u1[(a1 * K + a2) * P2 + q3];
-            u2[e] = s;
+            double sm = 0.0;
+            for (int a2 = 0; a2 < K; ++a2) sm += Q[q2 * K + a2] * u1[(a1 * K + a2) * P2 + q3];
+            u2[e] = sm;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < P2 * P2 * P2; e += PT) {
+        for (int r = 0; r < PER; ++r) {
+            const int e = threadIdx.x + r * PT;
+            if (e >= NC) break;
             const int q1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
-            double s = 0.0;
-            for (int a1 = 0; a1 < K; ++a1) s += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
-            const double d = fabs(fv[K3 + e] - ni * s);
-            emax = fmax(emax, d);
+            double sm = 0.0;
+            for (int a1 = 0; a1 < K; ++a1) sm += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
+            emax = fmax(emax, fabs(acc[r] - ni * sm));
         }
     }
     red[threadIdx.x] = emax;
     __syncthreads();
-    for (int s = PT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    for (int sh = PT / 2; sh > 0; sh >>= 1) {
+        if (threadIdx.x < sh) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + sh]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
