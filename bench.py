@@ -29,6 +29,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
+    ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
@@ -130,6 +131,7 @@ def main():
     w = workloads.c2()
     pts = workloads.points(10000)
     ctx = M.Context(0)
+    M.mwns_ctx_set_variant(ctx, w.k, args.variant)
     for _ in range(args.warmup):
         step(M, ctx, w, pts)
     torch.cuda.synchronize()
@@ -169,6 +171,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "ns_apply_kernel<8> (all levels of one apply)",
+                     "variant": M.mwns_ctx_get_variant(ctx, w.k),
                      "flops_per_apply": st["useful_flops"]},
     }
     if not args.no_cpu_baseline:

@@ -76,6 +76,14 @@ size_t mwns_ctx_bytes_in_use(const mwns_ctx* ctx);
 /* Thread-local text for the last non-OK status returned on this thread ("" if none). */
 const char* mwns_last_error(void);
 
+/* Tile variant of the contraction kernel used by this context for basis order k: an index in
+ * [0, mwns_num_variants()) (waves per workgroup, prefetch depth, waves per SIMD), or -1 for the
+ * library's default.  Variants differ in speed only; every variant computes the same result
+ * bit for bit.  mwns_tune_apply picks one by timing.  Errors: EINVAL (k or variant out of range). */
+int mwns_num_variants(void);
+mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant);
+mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* variant);
+
 /* -------------------------------------------------------------- (1) fit */
 
 /* Exponents tau_m and weights w_m of sum_m w_m exp(-tau_m r^2) approximating `scale` times the

@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import MWNS_F64, MWNS_NO_ASSEMBLY, MwnsError, check, lib
 
-__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "mwns_ctx_create",
+__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
+           "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
            "mwns_tree_get_info", "mwns_apply", "mwns_tree_eval", "LIB_PATH"]
@@ -108,6 +109,20 @@ class Tree:
 
 def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):
     return Context(device, use_torch, byte_budget)
+
+
+def mwns_num_variants():
+    return lib.mwns_num_variants()
+
+
+def mwns_ctx_set_variant(ctx, k, variant):
+    check(lib.mwns_ctx_set_variant(ctx.h, k, variant), "mwns_ctx_set_variant")
+
+
+def mwns_ctx_get_variant(ctx, k):
+    v = ctypes.c_int(0)
+    check(lib.mwns_ctx_get_variant(ctx.h, k, ctypes.byref(v)), "mwns_ctx_get_variant")
+    return v.value
 
 
 def mwns_fit_kernel(mu, alpha, eps, delta, R, scale=1.0, cap=4096):

@@ -9,7 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmwns.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libmwns.so is not built (run `python -m paper_0706_0747_amd.build`); "
+    raise ImportError("libmwns.so is not built (run `python paper_0706_0747_amd/build.py`); "
                       "there is no fallback for the MI355X kernels")
 
 lib = ctypes.CDLL(LIB_PATH)
@@ -46,6 +46,9 @@ SIGNATURES = {
     "mwns_ctx_synchronize": (c_int, [c_vp]),
     "mwns_ctx_bytes_in_use": (c_size, [c_vp]),
     "mwns_last_error": (ctypes.c_char_p, []),
+    "mwns_num_variants": (c_int, []),
+    "mwns_ctx_set_variant": (c_int, [c_vp, c_int, c_int]),
+    "mwns_ctx_get_variant": (c_int, [c_vp, c_int, P(c_int)]),
     "mwns_fit_kernel": (c_int, [c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_int, P(c_int), c_vp, c_vp]),
     "mwns_op_create": (c_int, [c_vp, c_int, c_int, c_vp, c_vp, c_dbl, c_int, P(OpOpts), P(c_vp)]),
     "mwns_op_plan_export": (c_int, [c_vp, c_vp, P(c_size)]),

@@ -1,6 +1,6 @@
 """Build libmwns.so (hand-written HIP for gfx950) in-tree with hipcc.
 
-    python -m paper_0706_0747_amd.build        # or build_library() from Python
+    python paper_0706_0747_amd/build.py        # or build_library() from Python
 """
 import concurrent.futures
 import os

@@ -47,8 +47,6 @@ struct Tpl {
 };
 
 constexpr int AT = 256;            // threads per block of the transform kernels
-constexpr int CT = 512;            // threads per block of the contraction kernel (8 waves)
-constexpr int CW = CT / 64;
 constexpr int T2S_V1 = 272;        // LDS strides of the mode-2 result [v1][u2][u3] (conflict-free)
 constexpr int T2S_U2 = 16;
 constexpr int NMAX = 4;            // largest box extent per dimension of one job (the host splits boxes)
@@ -88,9 +86,10 @@ __device__ inline uint32_t slice_offset(int v1, int g, int r) {
 }
 
 template <int K, int TPW>
-__device__ inline void load_slices(const double* __restrict__ X, const uint32_t (&off)[TPW], double (&x)[TPW][4]) {
+__device__ inline void load_slices(const double* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], double (&x)[TPW][4]) {
     constexpr int D = 2 * K;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, D * D * D * 8, 0x00020000);
+    // nbytes = 0 turns every load into an out-of-range one that returns zeros without touching memory
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, nbytes, 0x00020000);
     typedef double dv2 __attribute__((ext_vector_type(2)));
     for (int t = 0; t < TPW; ++t) {
         if constexpr (D % 4 == 0) {
@@ -109,18 +108,30 @@ __device__ inline void load_slices(const double* __restrict__ X, const uint32_t 
     }
 }
 
-// One block per output brick, over all levels at once (order[] lists (level, brick) by decreasing cost).
-template <int K>
-__global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4, 4))) ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order,
-                                                      const double* __restrict__ w) {
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
+// vector-memory loads, so prefetched input slices stay in flight across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// One block per output brick, over all levels at once (order[] lists (level, brick)).  CW waves
+// per block, each owning TPW input slices; PF steps of input slices are prefetched into registers.
+// For every job the in-cube cells of its box are first compacted into an LDS list (ascending L1,
+// L2, L3), so the term loop and the cell loop fuse into one stream of steps whose input bricks
+// are known PF steps ahead (the same list repeats for every term of the job).
+template <int K, int CW, int PF, int WPE>
+__global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, const double* __restrict__ w) {
+    constexpr int CT = 64 * CW;
     constexpr int D = 2 * K;
     constexpr int TPW = (D + CW - 1) / CW;
-    constexpr bool FULL = (CW * TPW == D);     // every wave owns TPW real slices (2k = 16)
+    constexpr bool FULL = (CW * TPW == D);     // every wave owns TPW real slices
     constexpr int64_t E = (int64_t)D * D * D;
+    constexpr int NB = PF + 1;
     __shared__ double T2s[16 * T2S_V1];
     __shared__ double S3s[NMAX * 16 * S3_V];
     __shared__ double S2s[NMAX * 256];
     __shared__ double S1s[NMAX * 256];
+    __shared__ int2 steps[NMAX * NMAX * NMAX];
+    __shared__ int nsteps_s;
     // wave index and every neighbour index are uniform per wave: keep them in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
@@ -141,84 +152,130 @@ __global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4, 4)))
         const Tpl tp = lv.tpl[ti];
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
         const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
-        for (int m = tp.m1; m <= tp.m2; ++m) {
-            const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
-            const double cw = tp.dpart ? -w[m] : w[m];
-            // stage this term's masked super-blocks in LDS (layouts chosen for conflict-free reads)
-            __syncthreads();
-            for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
-                const int sb = e >> 8, u = (e >> 4) & 15, v = e & 15;
-                if (sb < n1) S1s[sb * 256 + v * 16 + u] = cw * sop<K>(Fm, tp.lo[0] + sb, tp.mlo[0], tp.mhi[0], u, v);
-                else if (sb < n1 + n2) {
-                    const int q = sb - n1;
-                    S2s[q * 256 + v * 16 + u] = sop<K>(Fm, tp.lo[1] + q, tp.mlo[1], tp.mhi[1], u, v);
-                } else {
-                    const int q = sb - n1 - n2;
-                    S3s[q * 16 * S3_V + v * S3_V + u] = sop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], u, v);
-                }
+        // compact list of the box's in-cube cells: (input index, q1 << 4 | q2 << 2 | q3)
+        lds_barrier();
+        if (threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            int idx = -1, q1 = 0, q2 = 0, q3 = 0;
+            if (t < n1 * n2 * n3) {
+                q1 = t / (n2 * n3);
+                q2 = (t / n3) % n2;
+                q3 = t % n3;
+                idx = nb[((tp.lo[0] + q1 + Lr) * NL + (tp.lo[1] + q2 + Lr)) * NL + tp.lo[2] + q3 + Lr];
             }
-            __syncthreads();
-            for (int L1 = tp.lo[0]; L1 <= tp.hi[0]; ++L1) {
-                d4 T2[TPW];
-                for (int t = 0; t < TPW; ++t) T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                bool any1 = false;
-                for (int L2 = tp.lo[1]; L2 <= tp.hi[1]; ++L2) {
-                    const int32_t* row = nb + ((L1 + Lr) * NL + (L2 + Lr)) * NL + Lr;
-                    int L3 = tp.lo[2];
-                    while (L3 <= tp.hi[2] && __builtin_amdgcn_readfirstlane(row[L3]) < 0) ++L3;
-                    if (L3 > tp.hi[2]) continue;
-                    any1 = true;
-                    d4 T1[TPW];
-                    for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                    for (; L3 <= tp.hi[2]; ++L3) {
-                        const int idx = __builtin_amdgcn_readfirstlane(row[L3]);
-                        if (idx < 0) continue;
-                        double xc[TPW][4];
-                        load_slices<K, TPW>(idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E, xoff, xc);
-                        const double* s3p = S3s + (L3 - tp.lo[2]) * 16 * S3_V + r;
-                        double s3[4];
-                        for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
-                        for (int kk = 0; kk < 4; ++kk)
-                            for (int t = 0; t < TPW; ++t)
-                                if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[t][kk], s3[kk], T1[t], 0, 0, 0);
+            const unsigned long long in = __ballot(idx >= 0);
+            if (idx >= 0) steps[__popcll(in & ((1ull << t) - 1ull))] = make_int2(idx, (q1 << 4) | (q2 << 2) | q3);
+            if (t == 0) nsteps_s = __popcll(in);
+        }
+        lds_barrier();
+        const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
+        if (ns == 0) continue;
+        const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
+        auto brick = [&](int si) -> const double* {
+            const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
+            return idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E;
+        };
+        // Loads are issued unconditionally (past the end with nbytes = 0) so that the compiler's
+        // wait counts see one load group per step on every path.
+        double xb[NB][TPW][4];
+        int pf = 0;   // cell of the next prefetch
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const bool live = u < total;
+            load_slices<K, TPW>(brick(pf), live ? (int)(E * 8) : 0, xoff, xb[u]);
+            if (live && ++pf == ns) pf = 0;
+        }
+        int m = tp.m1, si = 0;
+        d4 T1[TPW], T2[TPW];
+        for (int t = 0; t < TPW; ++t) T1[t] = T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < total; s0 += NB) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (s0 + u >= total) break;
+                if (si == 0) {
+                    // stage this term's masked super-blocks in LDS (conflict-free reads; cw folded
+                    // into S1) before the next prefetch, so waiting for these loads does not wait
+                    // for it
+                    const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+                    const double cw = tp.dpart ? -w[m] : w[m];
+                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
+                        const int sb = e >> 8, v = (e >> 4) & 15, uu = e & 15;
+                        if (sb < n1) S1s[sb * 256 + v * 16 + uu] = cw * sop<K>(Fm, tp.lo[0] + sb, tp.mlo[0], tp.mhi[0], uu, v);
+                        else if (sb < n1 + n2) {
+                            const int q = sb - n1;
+                            S2s[q * 256 + v * 16 + uu] = sop<K>(Fm, tp.lo[1] + q, tp.mlo[1], tp.mhi[1], uu, v);
+                        } else {
+                            const int q = sb - n1 - n2;
+                            S3s[q * 16 * S3_V + v * S3_V + uu] = sop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], uu, v);
+                        }
                     }
-                    const double* s2p = S2s + (L2 - tp.lo[1]) * 256 + r;
+                    lds_barrier();
+                }
+                if (PF > 0) {
+                    const bool live = s0 + u + PF < total;
+                    load_slices<K, TPW>(brick(pf), live ? (int)(E * 8) : 0, xoff, xb[(u + PF) % NB]);
+                    if (live && ++pf == ns) pf = 0;
+                } else {
+                    load_slices<K, TPW>(brick(si), (int)(E * 8), xoff, xb[u]);
+                }
+                const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
+                const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
+                // mode 3: T1 += X x_3 S3^{L3}
+                {
+                    const double* s3p = S3s + (cell & 3) * 16 * S3_V + r;
+                    double s3[4];
+                    for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
+                    for (int kk = 0; kk < 4; ++kk)
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[u][t][kk], s3[kk], T1[t], 0, 0, 0);
+                }
+                if (next < 0 || (next >> 2) != (cell >> 2)) {
+                    // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
+                    const double* s2p = S2s + ((cell >> 2) & 3) * 256 + r;
                     double s2[4];
                     for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
                     for (int i = 0; i < 4; ++i)
                         for (int t = 0; t < TPW; ++t)
                             if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                    for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
                 }
-                if (!any1) continue;
-                for (int t = 0; t < TPW; ++t) {
-                    const int v1 = wave * TPW + t;
-                    if (!FULL && v1 >= D) break;
-                    for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
-                }
-                __syncthreads();
-                const double* s1p = S1s + (L1 - tp.lo[0]) * 256 + r;
-                double s1[4];
-                for (int kk = 0; kk < 4; ++kk) s1[kk] = s1p[(4 * kk + g) * 16];
-                for (int t = 0; t < TPW; ++t) {
-                    const int u2 = wave * TPW + t;
-                    if (!FULL && u2 >= D) break;
-                    // the down band reaches only internal children: accumulate it apart, add it masked
-                    d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int v1 = 4 * kk + g;
-                        const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, acc, 0, 0, 0);
+                if (next < 0 || (next >> 4) != (cell >> 4)) {
+                    // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
+                    for (int t = 0; t < TPW; ++t) {
+                        const int v1 = wave * TPW + t;
+                        if (!FULL && v1 >= D) break;
+                        for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
                     }
-                    if (tp.dpart) {
-                        for (int i = 0; i < 4; ++i) {
-                            const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
-                            if ((cmb >> child) & 1) Y[t][i] += acc[i];
+                    lds_barrier();
+                    const double* s1p = S1s + (cell >> 4) * 256 + r;
+                    double s1[4];
+                    for (int kk = 0; kk < 4; ++kk) s1[kk] = s1p[(4 * kk + g) * 16];
+                    for (int t = 0; t < TPW; ++t) {
+                        const int u2 = wave * TPW + t;
+                        if (!FULL && u2 >= D) break;
+                        // the down band reaches only internal children: accumulate it apart, add it masked
+                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const int v1 = 4 * kk + g;
+                            const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, acc, 0, 0, 0);
                         }
-                    } else {
-                        Y[t] = acc;
+                        if (tp.dpart) {
+                            for (int i = 0; i < 4; ++i) {
+                                const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
+                                if ((cmb >> child) & 1) Y[t][i] += acc[i];
+                            }
+                        } else {
+                            Y[t] = acc;
+                        }
                     }
+                    for (int t = 0; t < TPW; ++t) T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
+                    lds_barrier();
                 }
-                __syncthreads();
+                if (++si == ns) {
+                    si = 0;
+                    ++m;
+                }
             }
         }
     }
@@ -459,10 +516,32 @@ __global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ p
     atomicAdd(total, (unsigned long long)cnt);
 }
 
+// Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD).
+struct Variant {
+    int cw, pf, wpe;
+};
+constexpr Variant VARIANTS[] = {{8, 0, 4}, {8, 1, 2}, {8, 2, 2}, {16, 1, 4}, {16, 2, 4}, {16, 3, 4}};
+constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
+
+template <int K, int V>
+void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, const double* w) {
+    constexpr Variant v = VARIANTS[V];
+    ns_apply_kernel<K, v.cw, v.pf, v.wpe><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, w);
+}
+
 template <int K>
 struct ApplyLaunch {
-    static void run(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, const double* w) {
-        ns_apply_kernel<K><<<(unsigned)nblocks, CT, 0, st>>>(levels, order, w);
+    static void run(hipStream_t st, int variant, int64_t nblocks, const LevelDesc* levels, const int2* order,
+                    const double* w) {
+        switch (variant) {
+            case 0: launch_variant<K, 0>(st, nblocks, levels, order, w); break;
+            case 1: launch_variant<K, 1>(st, nblocks, levels, order, w); break;
+            case 2: launch_variant<K, 2>(st, nblocks, levels, order, w); break;
+            case 3: launch_variant<K, 3>(st, nblocks, levels, order, w); break;
+            case 4: launch_variant<K, 4>(st, nblocks, levels, order, w); break;
+            case 5: launch_variant<K, 5>(st, nblocks, levels, order, w); break;
+            default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
+        }
     }
 };
 template <int K>
@@ -479,6 +558,13 @@ struct AssembleLaunch {
         assemble_kernel<K><<<(unsigned)nb, AT, 0, st>>>(j, pb, pc, off, Ht, coef);
     }
 };
+
+constexpr int DEFAULT_VARIANT = 0;   // (8 waves, no prefetch, 4 waves per SIMD): fastest on the k = 8 Poisson workload
+
+int variant_for(const mwns_ctx* ctx, int k) {
+    const int v = ctx->variant[k];
+    return v >= 0 ? v : DEFAULT_VARIANT;
+}
 
 template <template <int> class Fn, class... Args>
 void dispatch_k(int k, Args&&... args) {
@@ -590,6 +676,27 @@ struct Timer {
 }  // namespace mwns
 
 using namespace mwns;
+
+extern "C" int mwns_num_variants(void) { return NVARIANTS; }
+
+extern "C" mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant) {
+    MWNS_GUARD_BEGIN
+    if (!ctx) fail(MWNS_EINVAL, "ctx is NULL");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
+    if (variant < -1 || variant >= NVARIANTS) fail(MWNS_EINVAL, "variant out of range");
+    ctx->variant[k] = variant;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* variant) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !variant) fail(MWNS_EINVAL, "NULL argument");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
+    *variant = ctx->variant[k];
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
 
 extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
                                   mwns_apply_stats* stats) {
@@ -848,7 +955,7 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
     dorder.upload(order.data(), order.size(), st);
     tcon.start();
     if (!order.empty()) {
-        dispatch_k<ApplyLaunch>(k, st, (int64_t)order.size(), ddesc.p, dorder.p, op->dw.p);
+        dispatch_k<ApplyLaunch>(k, st, variant_for(ctx, k), (int64_t)order.size(), ddesc.p, dorder.p, op->dw.p);
         MWNS_HIP(hipGetLastError());
     }
     tcon.stop();

@@ -106,6 +106,7 @@ struct mwns_ctx {
     void* user = nullptr;
     size_t budget = 0;
     size_t in_use = 0;
+    int variant[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};   // per basis order k
 };
 
 namespace mwns {

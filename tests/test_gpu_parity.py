@@ -106,6 +106,27 @@ def test_apply_is_deterministic(M, ctx):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["adaptive_k6", "adaptive_k8"])
+def test_tile_variants_bit_identical(M, case):
+    """Every contraction-kernel tile variant computes the same g bit for bit (variants change only
+    the wave count, prefetch depth and occupancy, not the order of the arithmetic)."""
+    w = CASES[case]()
+    c = M.Context(0)
+    f = M.mwns_project_gaussians(c, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    op = M.mwns_op_create(c, w.k, tau, wt, w.eps, depth)
+    outs = []
+    for v in range(M.mwns_num_variants()):
+        M.mwns_ctx_set_variant(c, w.k, v)
+        assert M.mwns_ctx_get_variant(c, w.k) == v
+        outs.append(M.mwns_tree_export(c, M.mwns_apply(c, op, f)[0])[2])
+    for v, o in enumerate(outs[1:], 1):
+        assert np.array_equal(o, outs[0]), "variant %d differs from variant 0" % v
+    with pytest.raises(M.MwnsError):
+        M.mwns_ctx_set_variant(c, w.k, M.mwns_num_variants())
+
+
 def test_eval_matches_oracle(M, ctx):
     from oracle import tree as T
     w = CASES["adaptive_k6"]()
