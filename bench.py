@@ -28,7 +28,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-vs-FP64 measurement")
+    ap.add_argument("--cpu-sample-nodes", type=int, default=15000)
     ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -48,6 +49,29 @@ def calibrate_copy():
     print(json.dumps({"calibration": "elementwise copy", "bytes_read": n * 8, "bytes_written": n * 8}))
 
 
+def traffic_from_profile():
+    """HBM bytes of one contraction-kernel launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), provided the summary was taken on the
+    current kernel source (same git blob id of apply.hip); otherwise None."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "ns_apply_kernel_poisson_k8_eps1e-6.md")
+    src = os.path.join(ROOT, "paper_0706_0747_amd", "csrc", "apply.hip")
+    try:
+        with open(prof) as fh:
+            text = fh.read()
+        with open(src, "rb") as fh:
+            data = fh.read()
+    except OSError:
+        return None
+    blob = hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
+    m1 = re.search(r"apply_hip_blob: ([0-9a-f]{40})", text)
+    m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    if not m1 or not m2 or m1.group(1) != blob:
+        return None
+    return float(m2.group(1))
+
+
 def step(M, ctx, w, pts):
     """One pass of the whole path; returns (g, stats, depth)."""
     f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
@@ -56,7 +80,40 @@ def step(M, ctx, w, pts):
     op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth)
     g, stats = M.mwns_apply(ctx, op, f)
     vals = M.mwns_tree_eval(ctx, g, pts)
-    return g, stats, depth, vals
+    return g, stats, depth, vals, f, op
+
+
+def leaf_norm(leaf, coef):
+    import numpy as np
+    return math.sqrt(float(np.sum(coef[leaf == 1] ** 2)))
+
+
+def mixed_measurement(M, ctx, w, f, op, g64, st64, reps):
+    """Apply-only wall time of the FP64 and the precision-routed apply on the same tree and
+    operator, the latter at tol = eps ||g_F64||; the measured relative L2 error against FP64."""
+    import torch
+    tol = w.eps * st64["g_norm"]
+    times = {}
+    for name, fn in (("fp64", lambda: M.mwns_apply(ctx, op, f, stats=False)),
+                     ("mixed", lambda: M.mwns_apply_mixed(ctx, op, f, tol, stats=False))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = 1e3 * (time.perf_counter() - t0) / reps
+    gm, stm = M.mwns_apply_mixed(ctx, op, f, tol)
+    _, leaf, a = M.mwns_tree_export(ctx, g64)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    err = leaf_norm(leaf, b - a)
+    return times["fp64"] / times["mixed"], {
+        "tol_rel": w.eps, "err_rel_measured": err / st64["g_norm"], "err_rel_bound": stm["err_bound"] / st64["g_norm"],
+        "apply_ms_fp64": times["fp64"], "apply_ms_mixed": times["mixed"],
+        "contract_ms_fp64": st64["ms_contract"], "contract_ms_mixed": stm["ms_contract"],
+        "class_flop_share": {c: stm["class_flops"][i] / stm["useful_flops"]
+                             for i, c in enumerate(("f64", "f32", "bf16c", "bf16"))},
+        "classes": "FP64 MFMA; FP32 MFMA; BF16 MFMA on hi/lo splits (4 partial products); BF16 MFMA"}
 
 
 def cpu_baseline(w, depth, nsample):
@@ -138,7 +195,7 @@ def main():
     t0 = time.perf_counter()
     stats_all = []
     for _ in range(args.steps):
-        g, stats, depth, _ = step(M, ctx, w, pts)
+        g, stats, depth, _, f, op = step(M, ctx, w, pts)
         stats_all.append(stats)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -168,12 +225,15 @@ def main():
         "apply_contractions_per_s": contr / ((st["ms_closure"] + st["ms_contract"] + st["ms_assemble"]) * 1e-3),
         "apply_ms": {"closure": st["ms_closure"], "contract": ms_con, "assemble": st["ms_assemble"]},
         "mixed_vs_fp64_speedup": None,
+        "mixed": None,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profile(),
                      "kernel": "ns_apply_kernel<8> (all levels of one apply)",
                      "variant": M.mwns_ctx_get_variant(ctx, w.k),
                      "flops_per_apply": st["useful_flops"]},
     }
+    if not args.no_mixed:
+        line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(M, ctx, w, f, op, g, st, args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, info["depth"], args.cpu_sample_nodes)
     print(json.dumps(line))

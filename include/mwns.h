@@ -183,6 +183,9 @@ typedef struct {
     double ms_closure;        /* device time of neighbour closure and interpolation */
     double ms_contract;       /* device time of the contraction kernels */
     double ms_assemble;       /* device time of the top-down assembly */
+    double err_bound;         /* a-priori bound on ||g - g_F64||_2 of the precision routing (0: all FP64) */
+    double g_norm;            /* ||g||_2 over [0,1]^3 (0 with MWNS_NO_ASSEMBLY) */
+    double class_flops[4];    /* useful_flops by precision class: FP64, FP32, BF16 compensated, BF16 */
 } mwns_apply_stats;
 
 /* g = T f with T given by `op` (its F tables and plan), in the modified ns-form (eq. apply_algo;
@@ -195,6 +198,30 @@ typedef struct {
  * stats may be NULL; filling it synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
 mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
                        mwns_apply_stats* stats);
+
+/* Precision classes of the mixed apply (bit mask of the reduced ones a call may use). */
+enum {
+    MWNS_CLASS_F32 = 1,       /* FP32 MFMA, FP32 inputs and accumulation */
+    MWNS_CLASS_BF16C = 2,     /* BF16 MFMA on hi/lo-split operands, all four partial products (compensated) */
+    MWNS_CLASS_BF16 = 4       /* BF16 MFMA, one operand of every mode product rounded to BF16 */
+};
+
+typedef struct {
+    double tol;               /* bound on ||g - g_F64||_2 the routing must keep (absolute; 0 = all FP64) */
+    int classes;              /* MWNS_CLASS_* bits allowed */
+} mwns_mixed_opts;
+
+/* g = T f as mwns_apply, with every (level, displacement box, term) contraction job routed to FP64
+ * or to one of the allowed reduced classes.  Not part of the paper's method: a system layer that
+ * keeps the result within opts->tol of the all-FP64 apply.  A job's contribution to g over its
+ * whole level is bounded by beta = |w_m| prod_d sum_{L_d in box} ||S_d^{m,L_d}||_F ||X_level||_2
+ * (S_d the masked 2k x 2k super-blocks, X_level every input sibling group of the level), and a
+ * class with unit rounding factor gamma computes it within gamma * beta; classes are chosen so
+ * that the sum of gamma * beta is at most tol (stats->err_bound), minimising modelled time.  The
+ * transforms, the interpolation, the assembly and the output accumulation stay FP64.  flags: 0 or
+ * MWNS_NO_ASSEMBLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM, EDEVICE. */
+mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts, int flags,
+                             mwns_tree** g, mwns_apply_stats* stats);
 
 /* ----------------------------------------------------------- (5) evaluate */
 

@@ -8,7 +8,8 @@ the HIP stream and, through the allocator callbacks, the device memory.
     tau, w = mwns_fit_kernel(mu, alpha, eps, delta, R)      # (1) fit
     op = mwns_op_create(ctx, k, tau, w, eps, max_level)     # (2) operator
     f = mwns_project_gaussians(ctx, k, eps, j0, jmax, xyz, a, c)   # (3) project
-    g, stats = mwns_apply(ctx, op, f)                       # (4) apply
+    g, stats = mwns_apply(ctx, op, f)                       # (4) apply (FP64)
+    g, stats = mwns_apply_mixed(ctx, op, f, tol)            #     or precision-routed, ||g - g_F64|| <= tol
     vals = mwns_tree_eval(ctx, g, pts)                      # (5) evaluate
 """
 import ctypes
@@ -16,9 +17,11 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import MWNS_F64, MWNS_NO_ASSEMBLY, MwnsError, check, lib
+from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, MWNS_NO_ASSEMBLY, MwnsError, check,
+                   lib)
 
-__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
+__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_CLASS_F32",
+           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
@@ -68,9 +71,9 @@ class Context:
     def bytes_in_use(self):
         return lib.mwns_ctx_bytes_in_use(self.h)
 
-    def close(self):
+    def close(self, _destroy=lib.mwns_ctx_destroy):
         if getattr(self, "h", None):
-            lib.mwns_ctx_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -85,9 +88,9 @@ class Operator:
     def threshold(self):
         return lib.mwns_op_threshold(self.h)
 
-    def close(self):
+    def close(self, _destroy=lib.mwns_op_destroy):
         if getattr(self, "h", None):
-            lib.mwns_op_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -98,9 +101,9 @@ class Tree:
     def __init__(self, ctx, h):
         self.ctx, self.h = ctx, h
 
-    def close(self):
+    def close(self, _destroy=lib.mwns_tree_destroy):
         if getattr(self, "h", None):
-            lib.mwns_tree_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -207,8 +210,26 @@ def mwns_apply(ctx, op, f, mode=MWNS_F64, stats=True):
     h = ctypes.c_void_p()
     st = _lib.ApplyStats()
     check(lib.mwns_apply(ctx.h, op.h, f.h, mode, ctypes.byref(h), ctypes.byref(st) if stats else None), "mwns_apply")
-    out = {fld: getattr(st, fld) for fld, _ in _lib.ApplyStats._fields_} if stats else None
-    return Tree(ctx, h), out
+    return Tree(ctx, h), (_stats_dict(st) if stats else None)
+
+
+def _stats_dict(st):
+    out = {}
+    for fld, _ in _lib.ApplyStats._fields_:
+        v = getattr(st, fld)
+        out[fld] = list(v) if fld == "class_flops" else v
+    return out
+
+
+def mwns_apply_mixed(ctx, op, f, tol, classes=MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16, flags=0, stats=True):
+    """g = T f with contractions routed to FP64 / FP32 / BF16 so that ||g - g_F64||_2 <= tol;
+    returns (g, stats dict or None)."""
+    h = ctypes.c_void_p()
+    st = _lib.ApplyStats()
+    opts = _lib.MixedOpts(float(tol), int(classes))
+    check(lib.mwns_apply_mixed(ctx.h, op.h, f.h, ctypes.byref(opts), flags, ctypes.byref(h),
+                               ctypes.byref(st) if stats else None), "mwns_apply_mixed")
+    return Tree(ctx, h), (_stats_dict(st) if stats else None)
 
 
 def mwns_tree_eval(ctx, tree, pts):

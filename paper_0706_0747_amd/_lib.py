@@ -5,6 +5,13 @@ library has not been built."""
 import ctypes
 import os
 
+try:
+    # The binding runs libmwns on the HIP runtime that PyTorch-ROCm loads (its streams and memory
+    # are torch's): import torch first so that the library binds to that runtime.
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmwns.so")
 
@@ -20,6 +27,7 @@ P = ctypes.POINTER
 MWNS_OK, MWNS_EINVAL, MWNS_ENOMEM, MWNS_EDEVICE, MWNS_ERANGE, MWNS_ESTATE = range(6)
 MWNS_F64 = 0
 MWNS_NO_ASSEMBLY = 1 << 8
+MWNS_CLASS_F32, MWNS_CLASS_BF16C, MWNS_CLASS_BF16 = 1, 2, 4
 STATUS_NAMES = {0: "MWNS_OK", 1: "MWNS_EINVAL", 2: "MWNS_ENOMEM", 3: "MWNS_EDEVICE", 4: "MWNS_ERANGE", 5: "MWNS_ESTATE"}
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_vp, c_size, c_vp)
@@ -37,7 +45,12 @@ class TreeInfo(ctypes.Structure):
 
 class ApplyStats(ctypes.Structure):
     _fields_ = [("contractions", c_i64), ("brick_jobs", c_i64), ("ghost_bricks", c_i64), ("useful_flops", c_dbl),
-                ("ms_closure", c_dbl), ("ms_contract", c_dbl), ("ms_assemble", c_dbl)]
+                ("ms_closure", c_dbl), ("ms_contract", c_dbl), ("ms_assemble", c_dbl), ("err_bound", c_dbl),
+                ("g_norm", c_dbl), ("class_flops", c_dbl * 4)]
+
+
+class MixedOpts(ctypes.Structure):
+    _fields_ = [("tol", c_dbl), ("classes", c_int)]
 
 
 SIGNATURES = {
@@ -62,6 +75,7 @@ SIGNATURES = {
     "mwns_tree_export": (c_int, [c_vp, c_vp, P(c_i64), c_vp, c_vp, c_vp]),
     "mwns_tree_destroy": (None, [c_vp]),
     "mwns_apply": (c_int, [c_vp, c_vp, c_vp, c_int, P(c_vp), P(ApplyStats)]),
+    "mwns_apply_mixed": (c_int, [c_vp, c_vp, c_vp, P(MixedOpts), c_int, P(c_vp), P(ApplyStats)]),
     "mwns_tree_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
 }
 

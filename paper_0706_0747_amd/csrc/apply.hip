@@ -44,18 +44,40 @@ struct Tpl {
     int mlo[3], mhi[3];    // fine displacement mask per dimension
     int m1, m2;            // inclusive term range
     int dpart;             // 0: whole band (all children, +), 1: down band (internal children, -)
+    int prec;              // precision class of the job's terms (PREC_*)
 };
 
+// Precision classes of a job.  Every class accumulates into the FP64 output; the reduced ones
+// take their inputs from FP32 or split-BF16 copies of the input bricks and accumulate each
+// mode product in FP32.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16C = 2, PREC_BF16 = 3, NPREC = 4 };
+
 constexpr int AT = 256;            // threads per block of the transform kernels
-constexpr int T2S_V1 = 272;        // LDS strides of the mode-2 result [v1][u2][u3] (conflict-free)
+constexpr int T2S_V1 = 272;        // LDS strides of the FP64 mode-2 result [v1][u2][u3] (conflict-free)
 constexpr int T2S_U2 = 16;
+constexpr int T2F_V1 = 324;        // the same for the FP32 mode-2 result (64 distinct banks per access)
+constexpr int T2F_U2 = 20;
 constexpr int NMAX = 4;            // largest box extent per dimension of one job (the host splits boxes)
-constexpr int S3_V = 36;           // LDS stride of the staged mode-3 operand [L][v][u]
+constexpr int S3_V = 36;           // LDS stride of the staged FP64 mode-3 operand [L][v][u]
+constexpr int SF_V = 20;           // LDS stride of the staged FP32 operands [L][v][u]
+// LDS of the contraction kernel, in doubles: the FP64 layout is the largest of the classes.
+constexpr int SM_T2 = 16 * T2S_V1, SM_S3 = NMAX * 16 * S3_V, SM_S2 = NMAX * 256, SM_S1 = NMAX * 256;
+constexpr int SMEM_DOUBLES = SM_T2 + SM_S3 + SM_S2 + SM_S1;
+static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * SF_V / 2 <= SMEM_DOUBLES, "FP32 LDS layout");
+static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * 4 * 2 <= SMEM_DOUBLES, "BF16 LDS layout");
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // One level of the apply as seen by the contraction kernel.
 struct LevelDesc {
     const double* Xr;        // real input bricks of the level (the level's own bricks)
     const double* Xg;        // ghost input bricks
+    const float* Xr32;       // FP32 copies, rows padded to 16: [brick][v1][v2][16]  (or null)
+    const float* Xg32;
+    const u4* Xrb;           // split-BF16 copies: [brick][v1][v2][4 groups] of (4 hi, 4 lo)  (or null)
+    const u4* Xgb;
     const int32_t* nbr;      // [brick][(2Lr+1)^3] input index, -1 outside the cube
     const uint8_t* cmask;    // [brick] bit s set when child s is internal
     const Tpl* tpl;          // jobs of the level
@@ -85,8 +107,17 @@ __device__ inline uint32_t slice_offset(int v1, int g, int r) {
     return (uint32_t)((((v1 * D) + r) * D + 4 * g) * 8);
 }
 
+// Byte offset of lane (g, r)'s 16-byte group in the padded reduced-precision copies (FP32 or
+// split BF16; both hold 64 bytes per (v1, v2) row).
+template <int K>
+__device__ inline uint32_t slice_offset_lp(int v1, int g, int r) {
+    constexpr int D = 2 * K;
+    if (v1 >= D || r >= D) return 0x40000000u;
+    return (uint32_t)(((v1 * D) + r) * 64 + 16 * g);
+}
+
 template <int K, int TPW>
-__device__ inline void load_slices(const double* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], double (&x)[TPW][4]) {
+__device__ inline void load_slices(const double* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], d4 (&x)[TPW]) {
     constexpr int D = 2 * K;
     // nbytes = 0 turns every load into an out-of-range one that returns zeros without touching memory
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, nbytes, 0x00020000);
@@ -95,7 +126,7 @@ __device__ inline void load_slices(const double* __restrict__ X, int nbytes, con
         if constexpr (D % 4 == 0) {
             const dv2 a = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t], 0, 0));
             const dv2 b = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t] + 16, 0, 0));
-            x[t][0] = a.x; x[t][1] = a.y; x[t][2] = b.x; x[t][3] = b.y;
+            x[t] = (d4){a.x, a.y, b.x, b.y};
         } else {
             // a 4-column group may cross the end of a row: load the valid columns one by one
             const uint32_t o = off[t];
@@ -108,28 +139,286 @@ __device__ inline void load_slices(const double* __restrict__ X, int nbytes, con
     }
 }
 
+template <int TPW>
+__device__ inline void load_slices_lp(const void* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], u4 (&x)[TPW]) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, nbytes, 0x00020000);
+    for (int t = 0; t < TPW; ++t) x[t] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t], 0, 0));
+}
+
+// Split of four FP32 values into BF16 hi and lo parts (hi + lo carries 16 significant bits):
+// returns (hi0 hi1 | hi2 hi3 | lo0 lo1 | lo2 lo3) packed two per dword.
+__device__ inline u4 split4(f4 x) {
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    bf2 h01 = {(__bf16)x[0], (__bf16)x[1]}, h23 = {(__bf16)x[2], (__bf16)x[3]};
+    bf2 l01 = {(__bf16)(x[0] - (float)h01[0]), (__bf16)(x[1] - (float)h01[1])};
+    bf2 l23 = {(__bf16)(x[2] - (float)h23[0]), (__bf16)(x[3] - (float)h23[1])};
+    return (u4){__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23), __builtin_bit_cast(unsigned, l01),
+                __builtin_bit_cast(unsigned, l23)};
+}
+
+// A x B over 16 contraction slots per operand pair with split-BF16 operands a = (4 hi | 4 lo) and
+// b = (4 hi | 4 lo) of the same 4 contraction indices: the 16x16x32 BF16 MFMA sees the slots
+// (a_hi b_hi | a_lo b_hi) and, when compensated, (a_hi b_lo | a_lo b_lo): all four partial
+// products, exact in FP32, summed in FP32.  Uncompensated: (a_hi + a_lo) b_hi.
+template <bool COMP>
+__device__ inline f4 mfma_bf16x(u4 a, u4 b, f4 c) {
+    const bf8 A = __builtin_bit_cast(bf8, a);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf8, (u4){b[0], b[1], b[0], b[1]}), c, 0, 0, 0);
+    if constexpr (COMP) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf8, (u4){b[2], b[3], b[2], b[3]}), c, 0, 0, 0);
+    return c;
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
 // vector-memory loads, so prefetched input slices stay in flight across it.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Rows of the FP32 mode-1 operand: output row m of the MFMA tile holds u1 = perm_row(m), so that
+// register i of lane (g, r) holds u1 = 4i + g as in the FP64 layout of the output accumulators.
+__device__ inline int perm_row(int m) { return 4 * (m & 3) + (m >> 2); }
+
+template <int PREC>
+struct ClassTypes;
+template <>
+struct ClassTypes<PREC_F64> { using Acc = d4; using XV = d4; };
+template <int PREC>
+struct ClassTypes { using Acc = f4; using XV = u4; };
+
+// The terms of one job for one output brick (see the kernel below), in precision class PREC.
+template <int K, int CW, int PF, int PREC>
+__device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, const double* __restrict__ w, int ns,
+                                        const int2* steps, double* smem, int wave, int g, int r, int cmb,
+                                        d4 (&Y)[(2 * K + CW - 1) / CW]) {
+    constexpr int CT = 64 * CW;
+    constexpr int D = 2 * K;
+    constexpr int TPW = (D + CW - 1) / CW;
+    constexpr bool FULL = (CW * TPW == D);
+    constexpr int64_t E = (int64_t)D * D * D;
+    constexpr int64_t ELP = (int64_t)D * D * 64;   // bytes of a reduced-precision brick
+    constexpr int NB = PF + 1;
+    using Acc = typename ClassTypes<PREC>::Acc;
+    using XV = typename ClassTypes<PREC>::XV;
+    const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+    const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
+    // LDS carve-up of this class
+    double* T2s = smem;
+    double* S3s = smem + SM_T2;
+    double* S2s = S3s + SM_S3;
+    double* S1s = S2s + SM_S2;
+    float* T2f = reinterpret_cast<float*>(smem);
+    float* S3f = T2f + 16 * T2F_V1;
+    float* S2f = S3f + NMAX * 16 * SF_V;
+    float* S1f = S2f + NMAX * 16 * SF_V;
+    u4* S3b = reinterpret_cast<u4*>(T2f + 16 * T2F_V1);   // [L][u][4 groups] of (4 hi | 4 lo)
+    u4* S2b = S3b + NMAX * 64;
+    u4* S1b = S2b + NMAX * 64;
+    uint32_t xoff[TPW];
+    for (int t = 0; t < TPW; ++t)
+        xoff[t] = PREC == PREC_F64 ? slice_offset<K>(wave * TPW + t, g, r) : slice_offset_lp<K>(wave * TPW + t, g, r);
+    auto load = [&](int si, bool live, XV (&x)[TPW]) {
+        const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
+        const bool real = idx < lv.nreal;
+        const int64_t q = real ? idx : idx - lv.nreal;
+        if constexpr (PREC == PREC_F64) {
+            load_slices<K, TPW>((real ? lv.Xr : lv.Xg) + q * E, live ? (int)(E * 8) : 0, xoff, x);
+        } else if constexpr (PREC == PREC_F32) {
+            load_slices_lp<TPW>((const char*)(real ? lv.Xr32 : lv.Xg32) + q * ELP, live ? (int)ELP : 0, xoff, x);
+        } else {
+            load_slices_lp<TPW>((const char*)(real ? lv.Xrb : lv.Xgb) + q * ELP, live ? (int)ELP : 0, xoff, x);
+        }
+    };
+    XV xb[NB][TPW];
+    int pf = 0;   // cell of the next prefetch
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const bool live = u < total;
+        load(pf, live, xb[u]);
+        if (live && ++pf == ns) pf = 0;
+    }
+    int m = tp.m1, si = 0;
+    Acc T1[TPW], T2[TPW];
+    for (int t = 0; t < TPW; ++t) T1[t] = T2[t] = Acc{};
+    for (int s0 = 0; s0 < total; s0 += NB) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            if (s0 + u >= total) break;
+            if (si == 0) {
+                // stage this term's masked super-blocks in LDS (cw folded into S1), before the next
+                // prefetch so that waiting for these loads does not wait for it
+                const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+                const double cw = tp.dpart ? -w[m] : w[m];
+                if constexpr (PREC == PREC_F64 || PREC == PREC_F32) {
+                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
+                        const int sb = e >> 8, v = (e >> 4) & 15, uu = e & 15;
+                        int q, d;
+                        if (sb < n1) { q = sb; d = 0; }
+                        else if (sb < n1 + n2) { q = sb - n1; d = 1; }
+                        else { q = sb - n1 - n2; d = 2; }
+                        const double val = (d == 0 ? cw : 1.0) * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v);
+                        if constexpr (PREC == PREC_F64) {
+                            double* dst = d == 0 ? S1s + q * 256 + v * 16 : d == 1 ? S2s + q * 256 + v * 16 : S3s + q * 16 * S3_V + v * S3_V;
+                            dst[uu] = val;
+                        } else {
+                            float* dst = (d == 0 ? S1f : d == 1 ? S2f : S3f) + (q * 16 + v) * SF_V;
+                            dst[uu] = (float)val;
+                        }
+                    }
+                } else {
+                    // split BF16: one thread per (super-block, row u, group of 4 contraction indices)
+                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 64; e += CT) {
+                        const int sb = e >> 6, uu = (e >> 2) & 15, gg = e & 3;
+                        int q, d;
+                        if (sb < n1) { q = sb; d = 0; }
+                        else if (sb < n1 + n2) { q = sb - n1; d = 1; }
+                        else { q = sb - n1 - n2; d = 2; }
+                        const double sc = d == 0 ? cw : 1.0;
+                        f4 v4;
+                        for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, 4 * gg + c));
+                        (d == 0 ? S1b : d == 1 ? S2b : S3b)[(q * 16 + uu) * 4 + gg] = split4(v4);
+                    }
+                }
+                lds_barrier();
+            }
+            if (PF > 0) {
+                const bool live = s0 + u + PF < total;
+                load(pf, live, xb[(u + PF) % NB]);
+                if (live && ++pf == ns) pf = 0;
+            } else {
+                load(si, true, xb[u]);
+            }
+            const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
+            const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
+            const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
+            // mode 3: T1 += X x_3 S3^{L3}
+            if constexpr (PREC == PREC_F64) {
+                const double* s3p = S3s + q3 * 16 * S3_V + r;
+                double s3[4];
+                for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
+                for (int kk = 0; kk < 4; ++kk)
+                    for (int t = 0; t < TPW; ++t)
+                        if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[u][t][kk], s3[kk], T1[t], 0, 0, 0);
+            } else if constexpr (PREC == PREC_F32) {
+                const float* s3p = S3f + q3 * 16 * SF_V + r;
+                float s3[4];
+                for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * SF_V];
+                // reinterpret the whole vector: a bit_cast of one subscripted vector element is
+                // miscompiled (it reads element 0 whatever the subscript)
+                f4 xf[TPW];
+                for (int t = 0; t < TPW; ++t) xf[t] = __builtin_bit_cast(f4, xb[u][t]);
+                for (int kk = 0; kk < 4; ++kk)
+                    for (int t = 0; t < TPW; ++t)
+                        if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xf[t][kk], s3[kk], T1[t], 0, 0, 0);
+            } else {
+                const u4 s3 = S3b[(q3 * 16 + r) * 4 + g];
+                for (int t = 0; t < TPW; ++t)
+                    if (FULL || wave * TPW + t < D) T1[t] = mfma_bf16x<PREC == PREC_BF16C>(xb[u][t], s3, T1[t]);
+            }
+            if (next < 0 || (next >> 2) != (cell >> 2)) {
+                // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
+                if constexpr (PREC == PREC_F64) {
+                    const double* s2p = S2s + q2 * 256 + r;
+                    double s2[4];
+                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
+                    for (int i = 0; i < 4; ++i)
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                } else if constexpr (PREC == PREC_F32) {
+                    const float* s2p = S2f + q2 * 16 * SF_V + r;
+                    float s2[4];
+                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * g + i) * SF_V];
+                    for (int i = 0; i < 4; ++i)
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2[i], T1[t][i], T2[t], 0, 0, 0);
+                } else {
+                    const u4 s2 = S2b[(q2 * 16 + r) * 4 + g];
+                    for (int t = 0; t < TPW; ++t)
+                        if (FULL || wave * TPW + t < D) T2[t] = mfma_bf16x<PREC == PREC_BF16C>(s2, split4(T1[t]), T2[t]);
+                }
+                for (int t = 0; t < TPW; ++t) T1[t] = Acc{};
+            }
+            if (next < 0 || (next >> 4) != (cell >> 4)) {
+                // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
+                for (int t = 0; t < TPW; ++t) {
+                    const int v1 = wave * TPW + t;
+                    if (!FULL && v1 >= D) break;
+                    for (int i = 0; i < 4; ++i) {
+                        if constexpr (PREC == PREC_F64) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
+                        else T2f[v1 * T2F_V1 + (4 * g + i) * T2F_U2 + r] = T2[t][i];
+                    }
+                }
+                lds_barrier();
+                for (int t = 0; t < TPW; ++t) {
+                    const int u2 = wave * TPW + t;
+                    if (!FULL && u2 >= D) break;
+                    d4 add;
+                    if constexpr (PREC == PREC_F64) {
+                        const double* s1p = S1s + q1 * 256 + r;
+                        // the down band reaches only internal children: accumulate it apart, add it masked
+                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const int v1 = 4 * kk + g;
+                            const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1p[(4 * kk + g) * 16], bv, acc, 0, 0, 0);
+                        }
+                        if (!tp.dpart) { Y[t] = acc; continue; }
+                        add = acc;
+                    } else {
+                        f4 acc = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (PREC == PREC_F32) {
+                            const float* s1p = S1f + q1 * 16 * SF_V + perm_row(r);
+                            for (int kk = 0; kk < 4; ++kk) {
+                                const int v1 = 4 * g + kk;
+                                const float bv = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(s1p[v1 * SF_V], bv, acc, 0, 0, 0);
+                            }
+                        } else {
+                            f4 bv;
+                            for (int j = 0; j < 4; ++j) {
+                                const int v1 = 4 * g + j;
+                                bv[j] = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
+                            }
+                            acc = mfma_bf16x<PREC == PREC_BF16C>(S1b[(q1 * 16 + perm_row(r)) * 4 + g], split4(bv), acc);
+                        }
+                        add = (d4){(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+                        if (!tp.dpart) { Y[t] += add; continue; }
+                    }
+                    for (int i = 0; i < 4; ++i) {
+                        const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
+                        if ((cmb >> child) & 1) Y[t][i] += add[i];
+                    }
+                }
+                for (int t = 0; t < TPW; ++t) T2[t] = Acc{};
+                lds_barrier();
+            }
+            if (++si == ns) {
+                si = 0;
+                ++m;
+            }
+        }
+    }
+}
 
 // One block per output brick, over all levels at once (order[] lists (level, brick)).  CW waves
 // per block, each owning TPW input slices; PF steps of input slices are prefetched into registers.
 // For every job the in-cube cells of its box are first compacted into an LDS list (ascending L1,
 // L2, L3), so the term loop and the cell loop fuse into one stream of steps whose input bricks
 // are known PF steps ahead (the same list repeats for every term of the job).
+//
+// MFMA mapping of the FP64 class (v_mfma_f64_16x16x4: A[m][k] in lane m+16k, B[k][n] in lane
+// n+16k, D[4i+g][n] in lane 16g+n, register i): wave w owns the input slices v1 in {w*TPW..}: mode 3
+// (contract v3, A = X slice with K index 4g+kk loaded as 4 consecutive doubles, B = S3), mode 2
+// straight from the mode-3 accumulators (their register i holds contraction index 4i+g), an LDS
+// transpose, then mode 1 into the per-wave output tiles.  The FP32 class (v_mfma_f32_16x16x4,
+// D[4g+i][n]) follows the same chain with the contraction slots permuted to match; the BF16
+// classes (v_mfma_f32_16x16x32_bf16, lane 16g+n holding K slots 8g..8g+7) give every lane the 4
+// contraction indices 4g..4g+3 as (4 hi | 4 lo) halves, which is exactly what the FP32 mode-3
+// accumulators of the lane hold, so mode 2 again needs no data movement.
 template <int K, int CW, int PF, int WPE>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, const double* __restrict__ w) {
-    constexpr int CT = 64 * CW;
     constexpr int D = 2 * K;
     constexpr int TPW = (D + CW - 1) / CW;
-    constexpr bool FULL = (CW * TPW == D);     // every wave owns TPW real slices
     constexpr int64_t E = (int64_t)D * D * D;
-    constexpr int NB = PF + 1;
-    __shared__ double T2s[16 * T2S_V1];
-    __shared__ double S3s[NMAX * 16 * S3_V];
-    __shared__ double S2s[NMAX * 256];
-    __shared__ double S1s[NMAX * 256];
+    __shared__ double smem[SMEM_DOUBLES];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s;
     // wave index and every neighbour index are uniform per wave: keep them in scalar registers
@@ -143,11 +432,7 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
     const int32_t* nb = lv.nbr + b * NL * NL * NL;
     const int cmb = lv.cmask[b];
     d4 Y[TPW];
-    uint32_t xoff[TPW];
-    for (int t = 0; t < TPW; ++t) {
-        Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
-        xoff[t] = slice_offset<K>(wave * TPW + t, g, r);
-    }
+    for (int t = 0; t < TPW; ++t) Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
     for (int ti = 0; ti < lv.ntpl; ++ti) {
         const Tpl tp = lv.tpl[ti];
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
@@ -170,113 +455,11 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
         lds_barrier();
         const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
         if (ns == 0) continue;
-        const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
-        auto brick = [&](int si) -> const double* {
-            const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
-            return idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E;
-        };
-        // Loads are issued unconditionally (past the end with nbytes = 0) so that the compiler's
-        // wait counts see one load group per step on every path.
-        double xb[NB][TPW][4];
-        int pf = 0;   // cell of the next prefetch
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const bool live = u < total;
-            load_slices<K, TPW>(brick(pf), live ? (int)(E * 8) : 0, xoff, xb[u]);
-            if (live && ++pf == ns) pf = 0;
-        }
-        int m = tp.m1, si = 0;
-        d4 T1[TPW], T2[TPW];
-        for (int t = 0; t < TPW; ++t) T1[t] = T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
-        for (int s0 = 0; s0 < total; s0 += NB) {
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                if (s0 + u >= total) break;
-                if (si == 0) {
-                    // stage this term's masked super-blocks in LDS (conflict-free reads; cw folded
-                    // into S1) before the next prefetch, so waiting for these loads does not wait
-                    // for it
-                    const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
-                    const double cw = tp.dpart ? -w[m] : w[m];
-                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
-                        const int sb = e >> 8, v = (e >> 4) & 15, uu = e & 15;
-                        if (sb < n1) S1s[sb * 256 + v * 16 + uu] = cw * sop<K>(Fm, tp.lo[0] + sb, tp.mlo[0], tp.mhi[0], uu, v);
-                        else if (sb < n1 + n2) {
-                            const int q = sb - n1;
-                            S2s[q * 256 + v * 16 + uu] = sop<K>(Fm, tp.lo[1] + q, tp.mlo[1], tp.mhi[1], uu, v);
-                        } else {
-                            const int q = sb - n1 - n2;
-                            S3s[q * 16 * S3_V + v * S3_V + uu] = sop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], uu, v);
-                        }
-                    }
-                    lds_barrier();
-                }
-                if (PF > 0) {
-                    const bool live = s0 + u + PF < total;
-                    load_slices<K, TPW>(brick(pf), live ? (int)(E * 8) : 0, xoff, xb[(u + PF) % NB]);
-                    if (live && ++pf == ns) pf = 0;
-                } else {
-                    load_slices<K, TPW>(brick(si), (int)(E * 8), xoff, xb[u]);
-                }
-                const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
-                const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
-                // mode 3: T1 += X x_3 S3^{L3}
-                {
-                    const double* s3p = S3s + (cell & 3) * 16 * S3_V + r;
-                    double s3[4];
-                    for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
-                    for (int kk = 0; kk < 4; ++kk)
-                        for (int t = 0; t < TPW; ++t)
-                            if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[u][t][kk], s3[kk], T1[t], 0, 0, 0);
-                }
-                if (next < 0 || (next >> 2) != (cell >> 2)) {
-                    // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
-                    const double* s2p = S2s + ((cell >> 2) & 3) * 256 + r;
-                    double s2[4];
-                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
-                    for (int i = 0; i < 4; ++i)
-                        for (int t = 0; t < TPW; ++t)
-                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
-                    for (int t = 0; t < TPW; ++t) T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                }
-                if (next < 0 || (next >> 4) != (cell >> 4)) {
-                    // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
-                    for (int t = 0; t < TPW; ++t) {
-                        const int v1 = wave * TPW + t;
-                        if (!FULL && v1 >= D) break;
-                        for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
-                    }
-                    lds_barrier();
-                    const double* s1p = S1s + (cell >> 4) * 256 + r;
-                    double s1[4];
-                    for (int kk = 0; kk < 4; ++kk) s1[kk] = s1p[(4 * kk + g) * 16];
-                    for (int t = 0; t < TPW; ++t) {
-                        const int u2 = wave * TPW + t;
-                        if (!FULL && u2 >= D) break;
-                        // the down band reaches only internal children: accumulate it apart, add it masked
-                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
-                        for (int kk = 0; kk < 4; ++kk) {
-                            const int v1 = 4 * kk + g;
-                            const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
-                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[kk], bv, acc, 0, 0, 0);
-                        }
-                        if (tp.dpart) {
-                            for (int i = 0; i < 4; ++i) {
-                                const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
-                                if ((cmb >> child) & 1) Y[t][i] += acc[i];
-                            }
-                        } else {
-                            Y[t] = acc;
-                        }
-                    }
-                    for (int t = 0; t < TPW; ++t) T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
-                    lds_barrier();
-                }
-                if (++si == ns) {
-                    si = 0;
-                    ++m;
-                }
-            }
+        switch (__builtin_amdgcn_readfirstlane(tp.prec)) {
+            case PREC_F64: run_job<K, CW, PF, PREC_F64>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
+            case PREC_F32: run_job<K, CW, PF, PREC_F32>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
+            case PREC_BF16C: run_job<K, CW, PF, PREC_BF16C>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
+            default: run_job<K, CW, PF, PREC_BF16>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
         }
     }
     double* ob = lv.out + b * E;
@@ -290,6 +473,40 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
             ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][i] : 0.0;
         }
     }
+}
+
+// Reduced-precision copies of input bricks: one thread per (brick, v1, v2, group of 4 columns)
+// writes 16 bytes -- four FP32 values (F32) or their split BF16 (hi | lo) (BF16); columns at or
+// beyond 2K are zero.
+template <int K, bool BF>
+__global__ void convert_kernel(int64_t nbricks, const double* __restrict__ X, u4* __restrict__ out) {
+    constexpr int D = 2 * K;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbricks * D * D * 4) return;
+    const int gg = (int)(i & 3);
+    const int64_t row = i >> 2;     // (brick, v1, v2)
+    const double* x = X + row * D;
+    f4 v;
+    for (int c = 0; c < 4; ++c) v[c] = 4 * gg + c < D ? (float)x[4 * gg + c] : 0.f;
+    out[i] = BF ? split4(v) : __builtin_bit_cast(u4, v);
+}
+
+// Sum of squares of every brick element of one level (real and ghost inputs): one 256-thread
+// block per brick, reduced in LDS and added to *acc.
+template <int K>
+__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ X, double* __restrict__ acc) {
+    constexpr int E = 8 * K * K * K;
+    __shared__ double red[256];
+    const double* x = X + (int64_t)blockIdx.x * E;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < E; e += 256) s += x[e] * x[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(acc, red[0]);
 }
 
 // ---------------------------------------------------------------- closure
@@ -581,6 +798,111 @@ void dispatch_k(int k, Args&&... args) {
     }
 }
 
+template <int K>
+struct SumsqLaunch {
+    static void run(hipStream_t st, int64_t nb, const double* X, double* acc) {
+        if (nb > 0) sumsq_kernel<K><<<(unsigned)nb, 256, 0, st>>>(X, acc);
+    }
+};
+template <int K>
+struct ConvertLaunch {
+    static void run(hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
+        const int64_t n = nb * 2 * K * 2 * K * 4;
+        if (n == 0) return;
+        if (bf) convert_kernel<K, true><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
+        else convert_kernel<K, false><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
+    }
+};
+
+// Sum of squares of the coefficients of the leaves among the 8 children of every brick of one
+// level (level 0: only child 0, the root): one 256-thread block per brick.
+template <int K>
+__global__ void __launch_bounds__(256) leafsq_kernel(int64_t node_off, int nchild, const uint8_t* __restrict__ leaf,
+                                                     const double* __restrict__ coef, double* __restrict__ acc) {
+    constexpr int P = 2 * K, K3 = K * K * K;
+    __shared__ double red[256];
+    const double* brick = coef + (int64_t)blockIdx.x * P * P * P;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < nchild * K3; e += 256) {
+        const int child = e / K3, q = e % K3;
+        if (!leaf[node_off + (int64_t)blockIdx.x * 8 + child]) continue;
+        const int a = q / (K * K), bb = (q / K) % K, c = q % K;
+        const double x = brick[(((child & 1) * K + a) * P + ((child >> 1) & 1) * K + bb) * P + (child >> 2) * K + c];
+        s += x * x;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(acc, red[0]);
+}
+template <int K>
+struct LeafsqLaunch {
+    static void run(hipStream_t st, int64_t nb, int64_t node_off, int nchild, const uint8_t* leaf, const double* coef,
+                    double* acc) {
+        if (nb > 0) leafsq_kernel<K><<<(unsigned)nb, 256, 0, st>>>(node_off, nchild, leaf, coef, acc);
+    }
+};
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- precision routing
+// Rounding-error factors of the classes: a three-mode chain whose every mode has relative
+// operand errors a (matrix) and b (input) and an FP32 accumulation over at most 16 * NMAX products
+// computes (|S1| (x) |S2| (x) |S3|) |X| up to the factor ((1 + a + b + n u32)^3 - 1).
+constexpr double U32 = 0x1p-24, UBF = 0x1p-8, USPLIT = 0x1p-16;
+constexpr double cube_minus_one(double d) { return (1.0 + d) * (1.0 + d) * (1.0 + d) - 1.0; }
+constexpr double NACC = 16.0 * NMAX * U32;
+constexpr double GAMMA[NPREC] = {0.0, cube_minus_one(2.0 * U32 + NACC), cube_minus_one(2.0 * (USPLIT + U32) + NACC),
+                                 cube_minus_one(UBF + USPLIT + 2.0 * U32 + NACC)};
+// Relative time per unit of work, for the routing objective only.
+constexpr double COST[NPREC] = {1.0, 0.6, 0.3, 0.2};
+
+struct RouteItem {
+    int j, t, m, cls;
+    double beta, work;
+};
+
+// Chooses a class for every (level, job, term) minimising the modelled time subject to
+// sum gamma_class * beta <= tol (Lagrangian relaxation, bisection on the multiplier); beta bounds
+// the FP64 contribution of the item over its whole level:
+//   || sum_b sum_{L in box} (S1 (x) S2 (x) S3) X_{b-L} || <= |w_m| prod_d sum_{L_d} ||S_d^{m,L_d}||_F ||X_level||,
+// each input brick feeding one output brick per displacement.  Returns the bound reached.
+double route(std::vector<RouteItem>& items, double tol, int allowed) {
+    auto eval = [&](double lam, bool commit) {
+        double err = 0.0;
+        for (RouteItem& it : items) {
+            int best = PREC_F64;
+            double bv = it.work * COST[PREC_F64];
+            for (int p = 1; p < NPREC; ++p) {
+                if (!((allowed >> (p - 1)) & 1)) continue;
+                const double v = it.work * COST[p] + lam * GAMMA[p] * it.beta;
+                if (v < bv) { bv = v; best = p; }
+            }
+            err += GAMMA[best] * it.beta;
+            if (commit) it.cls = best;
+        }
+        return err;
+    };
+    if (!(tol > 0.0) || items.empty()) {
+        for (RouteItem& it : items) it.cls = PREC_F64;
+        return 0.0;
+    }
+    double lo = -60.0, hi = 80.0;     // log10 of the multiplier; at 10^80 every item is FP64
+    if (eval(std::pow(10.0, lo), false) <= tol) return eval(std::pow(10.0, lo), true);
+    for (int it = 0; it < 100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (eval(std::pow(10.0, mid), false) <= tol) hi = mid;
+        else lo = mid;
+    }
+    return eval(std::pow(10.0, hi), true);
+}
+
 // Coarsest per-dimension partition of [-LP, LP] on which a plan row is constant; returns cells.
 std::vector<std::array<int, 2>> segments(const int32_t* row, int d) {
     auto slice_equal = [&](int t) {   // plan slices at coordinate t and t+1 along dimension d
@@ -698,11 +1020,12 @@ extern "C" mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* var
     MWNS_GUARD_END
 }
 
-extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
-                                  mwns_apply_stats* stats) {
-    MWNS_GUARD_BEGIN
+namespace {
+
+// The apply behind both entry points; mixed == nullptr is the all-FP64 apply.
+void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, const mwns_mixed_opts* mixed,
+                mwns_tree** g, mwns_apply_stats* stats) {
     if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
-    if ((mode & 0xff) != MWNS_F64) fail(MWNS_EINVAL, "unsupported precision mode");
     if (op->k != f->k) fail(MWNS_EINVAL, "operator and tree have different k");
     if (op->max_level < f->depth) fail(MWNS_EINVAL, "operator max_level is below the tree depth");
     const int k = f->k;
@@ -861,12 +1184,107 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
                                 lw.ghosts.p);
         MWNS_HIP(hipGetLastError());
     }
+    // ---- precision routing (mixed apply): per-level input norms, classes, reduced-precision inputs
+    double err_bound = 0.0;
+    std::vector<DevArray<u4>> xr32(depth + 1), xg32(depth + 1), xrb(depth + 1), xgb(depth + 1);
+    if (mixed) {
+        DevArray<double> lsq(ctx, depth + 1);
+        fill_kernel<<<1, 64, 0, st>>>(lsq.p, depth + 1, 0.0);
+        for (int j = 0; j <= depth; ++j) {
+            const LevelWork& lw = W[j];
+            if (lw.tpl.empty()) continue;
+            dispatch_k<SumsqLaunch>(k, st, lw.nout, f->coef.p + f->lev[j].brick_off * E, lsq.p + j);
+            dispatch_k<SumsqLaunch>(k, st, lw.nghost, lw.ghosts.p, lsq.p + j);
+        }
+        MWNS_HIP(hipGetLastError());
+        std::vector<double> hsq(depth + 1);
+        lsq.download(hsq.data(), depth + 1, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+        std::vector<RouteItem> items;
+        const int M = op->M;
+        for (int j = 0; j <= depth; ++j) {
+            const LevelWork& lw = W[j];
+            const double xn = std::sqrt(hsq[j]);
+            int64_t ninternal = 0;
+            for (int64_t b = 0; b < lw.nout; ++b) ninternal += lw.cm[b] != 0;
+            for (int t = 0; t < (int)lw.tpl.size(); ++t) {
+                const Tpl& tp = lw.tpl[t];
+                const double nb = tp.dpart ? (double)ninternal : (double)lw.nout;
+                const double n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+                for (int m = tp.m1; m <= tp.m2; ++m) {
+                    const double* fr = op->fro.data() + ((int64_t)j * M + m) * NLF;
+                    double beta = std::fabs(op->w[m]) * xn;
+                    for (int d = 0; d < 3; ++d) {
+                        double a = 0.0;
+                        for (int L = tp.lo[d]; L <= tp.hi[d]; ++L) {
+                            double s2 = 0.0;
+                            for (int su = 0; su < 2; ++su)
+                                for (int sv = 0; sv < 2; ++sv) {
+                                    const int l = 2 * L + su - sv;
+                                    if (l >= tp.mlo[d] && l <= tp.mhi[d]) s2 += fr[l + LF] * fr[l + LF];
+                                }
+                            a += std::sqrt(s2);
+                        }
+                        beta *= a;
+                    }
+                    items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1)});
+                }
+            }
+        }
+        err_bound = route(items, mixed->tol, mixed->classes);
+        // split every job into runs of terms of one class
+        size_t pos = 0;
+        for (int j = 0; j <= depth; ++j) {
+            LevelWork& lw = W[j];
+            std::vector<Tpl> split;
+            for (int t = 0; t < (int)lw.tpl.size(); ++t) {
+                Tpl cur = lw.tpl[t];
+                for (int m = lw.tpl[t].m1; m <= lw.tpl[t].m2; ++m, ++pos) {
+                    const int c = items[pos].cls;
+                    if (m == lw.tpl[t].m1) { cur.m1 = m; cur.prec = c; }
+                    else if (c != cur.prec) {
+                        cur.m2 = m - 1;
+                        split.push_back(cur);
+                        cur.m1 = m;
+                        cur.prec = c;
+                    }
+                    cur.m2 = m;
+                }
+                split.push_back(cur);
+            }
+            lw.tpl.swap(split);
+            bool need32 = false, needbf = false;
+            for (const Tpl& t : lw.tpl) {
+                need32 = need32 || t.prec == PREC_F32;
+                needbf = needbf || t.prec == PREC_BF16C || t.prec == PREC_BF16;
+            }
+            const int64_t units = (int64_t)4 * 2 * k * 2 * k;     // 16-byte units per brick
+            const double* xr = f->coef.p + f->lev[j].brick_off * E;
+            if (need32) {
+                xr32[j].reset(ctx, (size_t)lw.nout * units);
+                dispatch_k<ConvertLaunch>(k, st, lw.nout, xr, xr32[j].p, false);
+                if (lw.nghost) {
+                    xg32[j].reset(ctx, (size_t)lw.nghost * units);
+                    dispatch_k<ConvertLaunch>(k, st, lw.nghost, lw.ghosts.p, xg32[j].p, false);
+                }
+            }
+            if (needbf) {
+                xrb[j].reset(ctx, (size_t)lw.nout * units);
+                dispatch_k<ConvertLaunch>(k, st, lw.nout, xr, xrb[j].p, true);
+                if (lw.nghost) {
+                    xgb[j].reset(ctx, (size_t)lw.nghost * units);
+                    dispatch_k<ConvertLaunch>(k, st, lw.nghost, lw.ghosts.p, xgb[j].p, true);
+                }
+            }
+            MWNS_HIP(hipGetLastError());
+        }
+    }
     tclos.stop();
     // ---- contractions: one launch over every output brick of every level, costliest first
     std::vector<LevelDesc> descs(depth + 1);
     std::vector<std::pair<double, int2>> cost;
     int64_t jobs = 0;
-    double flops = 0.0;
+    double flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j <= depth; ++j) {
         LevelWork& lw = W[j];
         double* outj = out->coef.p + f->lev[j].brick_off * E;
@@ -881,6 +1299,10 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
         lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), st);
         d.Xr = f->coef.p + f->lev[j].brick_off * E;
         d.Xg = lw.ghosts.p;
+        d.Xr32 = reinterpret_cast<const float*>(xr32[j].p);
+        d.Xg32 = reinterpret_cast<const float*>(xg32[j].p);
+        d.Xrb = xrb[j].p;
+        d.Xgb = xgb[j].p;
         d.nbr = lw.nbr.p;
         d.cmask = lw.cmask.p;
         d.tpl = lw.dtpl.p;
@@ -902,15 +1324,15 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
                     for (int Lx = t.lo[dd]; Lx <= t.hi[dd]; ++Lx) cnt += (p[dd] - Lx >= 0 && p[dd] - Lx < pside);
                     nin[dd] = cnt;
                 }
+                if (nin[0] * nin[1] * nin[2] == 0) continue;     // the box lies outside the cube
                 const double nt = t.m2 - t.m1 + 1;
-                c += nt * (nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0]);
+                const double steps = nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0];
+                c += nt * steps * COST[t.prec];
                 const double D2 = 2.0 * k;
-                const double n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
-                (void)n2;
-                (void)n3;
-                (void)n1;
                 jobs += (int64_t)nt;
-                flops += nt * 2.0 * D2 * D2 * D2 * D2 * (nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0]);
+                const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
+                flops += fl;
+                class_flops[t.prec] += fl;
             }
             cost.push_back({c, make_int2(j, (int)b)});
         }
@@ -991,8 +1413,18 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
                                                                                 dplan.p + (int64_t)j * planrow, Rj1, tot.p);
             MWNS_HIP(hipGetLastError());
         }
+        // ||g||_2: the leaves' scaling functions are orthonormal with disjoint supports
+        DevArray<double> gsq(ctx, 1);
+        fill_kernel<<<1, 64, 0, st>>>(gsq.p, 1, 0.0);
+        if (!(mode & MWNS_NO_ASSEMBLY))
+            for (int j = 0; j <= depth; ++j)
+                dispatch_k<LeafsqLaunch>(k, st, f->lev[j].nbricks, f->lev[j].node_off, j == 0 ? 1 : 8, f->dleaf.p,
+                                         out->coef.p + f->lev[j].brick_off * E, gsq.p);
+        MWNS_HIP(hipGetLastError());
         unsigned long long c = 0;
+        double g2 = 0.0;
         tot.download(&c, 1, st);
+        gsq.download(&g2, 1, st);
         MWNS_HIP(hipStreamSynchronize(st));
         s.contractions = (int64_t)c;
         s.brick_jobs = jobs;
@@ -1001,11 +1433,35 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
         s.ms_closure = tclos.ms();
         s.ms_contract = tcon.ms();
         s.ms_assemble = tasm.ms();
+        s.err_bound = err_bound;
+        s.g_norm = std::sqrt(g2);
+        for (int p = 0; p < NPREC; ++p) s.class_flops[p] = class_flops[p];
         *stats = s;
     } else {
         MWNS_HIP(hipStreamSynchronize(st));
     }
     *g = out.release();
+}
+
+}  // namespace
+
+extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
+                                  mwns_apply_stats* stats) {
+    MWNS_GUARD_BEGIN
+    if ((mode & 0xff) != MWNS_F64 || (mode & ~(0xff | MWNS_NO_ASSEMBLY))) fail(MWNS_EINVAL, "unsupported mode");
+    apply_impl(ctx, op, f, mode, nullptr, g, stats);
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts,
+                                        int flags, mwns_tree** g, mwns_apply_stats* stats) {
+    MWNS_GUARD_BEGIN
+    if (!opts) fail(MWNS_EINVAL, "opts is NULL");
+    if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) fail(MWNS_EINVAL, "tol must be finite and >= 0");
+    if (opts->classes & ~(MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16)) fail(MWNS_EINVAL, "unknown precision class");
+    if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
+    apply_impl(ctx, op, f, flags, opts, g, stats);
     return MWNS_OK;
     MWNS_GUARD_END
 }

@@ -154,6 +154,7 @@ struct mwns_op {
     mwns::DevArray<double> F;        // [max_level+1][M][NLF][k][k]
     mwns::DevArray<double> dw;       // [M]
     std::vector<int32_t> plan;       // [max_level+1][NLP^3][2]
+    std::vector<double> fro;         // [max_level+1][M][NLF] Frobenius norms of the blocks F^{j;m,l}
 };
 
 struct mwns_level {

@@ -176,6 +176,17 @@ __global__ void __launch_bounds__(64) norms_kernel(int k, int M, int nlev, const
     }
 }
 
+// Frobenius norm of every block F^{j;m,l}, one thread per (j, m, l); used to bound the rounding
+// error of reduced-precision contractions.
+__global__ void fro_kernel(int k, int64_t n, const double* __restrict__ F, double* __restrict__ fro) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* f = F + i * k * k;
+    double s = 0.0;
+    for (int e = 0; e < k * k; ++e) s += f[e] * f[e];
+    fro[i] = sqrt(s);
+}
+
 // One thread per (scale j >= 1, canonical class (c0 <= c1 <= c2)): term range.
 __global__ void plan_kernel(int M, int nlev, double eps, const double* __restrict__ w, const double* __restrict__ norms,
                             const double* __restrict__ nf0, int32_t* __restrict__ ranges /* [nlev][20][2] */) {
@@ -297,6 +308,15 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     }
     std::vector<double> hnf0(M);
     nf0.download(hnf0.data(), M, st);
+    {
+        const int64_t nb = (int64_t)nlev * M * NLF;
+        DevArray<double> dfro(ctx, nb);
+        fro_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(k, nb, op->F.p, dfro.p);
+        MWNS_HIP(hipGetLastError());
+        op->fro.resize(nb);
+        dfro.download(op->fro.data(), nb, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+    }
     MWNS_HIP(hipStreamSynchronize(st));
     double theta = 0.0;
     for (int m = 0; m < M; ++m) theta += w[m] * hnf0[m] * hnf0[m] * hnf0[m];
