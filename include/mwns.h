@@ -167,6 +167,11 @@ mwns_status mwns_tree_get_info(const mwns_tree* t, mwns_tree_info* info);
 mwns_status mwns_tree_export(mwns_ctx* ctx, const mwns_tree* t, int64_t* nnodes, uint64_t* keys, uint8_t* is_leaf,
                              double* coeffs);
 void mwns_tree_destroy(mwns_tree* t);
+/* Replace the leaf coefficients of t in place (structure unchanged): coeffs[nleaves][k][k][k]
+ * (host) in canonical leaf order (ascending key among the leaves, as mwns_tree_export lists
+ * them); the internal nodes are recomputed by two-scale decomposition (App. A.3,
+ * eq. decomp_scaling).  Errors: EINVAL, EDEVICE. */
+mwns_status mwns_tree_set_leaves(mwns_ctx* ctx, mwns_tree* t, const double* coeffs);
 
 /* ------------------------------------------------------------- (4) apply */
 
@@ -222,6 +227,36 @@ typedef struct {
  * MWNS_NO_ASSEMBLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM, EDEVICE. */
 mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts, int flags,
                              mwns_tree** g, mwns_apply_stats* stats);
+
+/* Batched apply: g_i = T_i f_i for n (operator, tree) pairs, trees of any size, as one
+ * persistent contraction launch per basis order present (workgroups stay resident and pull
+ * output sibling groups of every tree from 8 per-XCD work queues, costliest first), with one
+ * host round trip for the neighbour closure of the whole batch.  mixed: NULL for FP64, or n
+ * routing options (tree i is routed with mixed[i], as mwns_apply_mixed).  gs[n] receives the
+ * output handles (NULL on error).  stats (may be NULL) sums the counts over the batch; err_bound
+ * is the largest per-tree bound and g_norm the root of the summed squares.  Results equal the
+ * single applies bit for bit.  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
+                             const mwns_mixed_opts* mixed, int flags, mwns_tree** gs, mwns_apply_stats* stats);
+
+/* A reusable batched apply.  mwns_plan_create does everything that depends only on the trees'
+ * structure and the operators -- jobs, neighbour closure, interpolation sites, routing (from
+ * the inputs' norms at creation), launch orders, every buffer -- and captures the value phase
+ * (interpolated inputs, reduced-precision copies, contractions, assembly) once as a hipGraph.
+ * mwns_plan_execute replays it on the context's stream for the current coefficients of the input
+ * trees (update them in place with mwns_tree_set_leaves); it allocates nothing and does not
+ * synchronise.  The plan borrows ops and fs (keep them alive and unchanged in structure) and owns
+ * its n outputs: mwns_plan_output returns a borrowed handle, valid until mwns_plan_destroy and
+ * overwritten by every execute.  For routed plans the error bound holds while every level's input
+ * norm stays at most its value at creation.  mwns_plan_stats synchronises.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+typedef struct mwns_plan mwns_plan;
+mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
+                             const mwns_mixed_opts* mixed, int flags, mwns_plan** out);
+mwns_status mwns_plan_execute(mwns_plan* plan);
+mwns_status mwns_plan_output(const mwns_plan* plan, int i, const mwns_tree** g);
+mwns_status mwns_plan_stats(const mwns_plan* plan, mwns_apply_stats* stats);
+void mwns_plan_destroy(mwns_plan* plan);
 
 /* ----------------------------------------------------------- (5) evaluate */
 

@@ -21,7 +21,8 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
                    lib)
 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_CLASS_F32",
-           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
+           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
+           "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
@@ -108,6 +109,96 @@ class Tree:
 
     def __del__(self):
         self.close()
+
+
+class BorrowedTree:
+    """A tree handle owned by something else (a plan's output): never destroyed from here."""
+
+    def __init__(self, ctx, h, owner):
+        self.ctx, self.h, self._owner = ctx, h, owner
+
+    def close(self):
+        pass
+
+
+class Plan:
+    """mwns_plan: a batched apply captured once as a hipGraph and replayed by execute()."""
+
+    def __init__(self, ctx, h, n, keep):
+        self.ctx, self.h, self.n, self._keep = ctx, h, n, keep
+
+    def execute(self):
+        check(lib.mwns_plan_execute(self.h), "mwns_plan_execute")
+
+    def output(self, i):
+        g = ctypes.c_void_p()
+        check(lib.mwns_plan_output(self.h, i, ctypes.byref(g)), "mwns_plan_output")
+        return BorrowedTree(self.ctx, g, self)
+
+    def stats(self):
+        st = _lib.ApplyStats()
+        check(lib.mwns_plan_stats(self.h, ctypes.byref(st)), "mwns_plan_stats")
+        return _stats_dict(st)
+
+    def close(self, _destroy=lib.mwns_plan_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _handles(objs):
+    arr = (ctypes.c_void_p * len(objs))()
+    for i, o in enumerate(objs):
+        arr[i] = o.h.value if isinstance(o.h, ctypes.c_void_p) else o.h
+    return arr
+
+
+def _mixed_array(mixed, n):
+    if mixed is None:
+        return None
+    if isinstance(mixed, (int, float)):
+        mixed = [mixed] * n
+    arr = (_lib.MixedOpts * n)()
+    for i, m in enumerate(mixed):
+        tol, classes = (m, MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16) if isinstance(m, (int, float)) else m
+        arr[i] = _lib.MixedOpts(float(tol), int(classes))
+    return arr
+
+
+def mwns_apply_batch(ctx, ops, fs, mixed=None, flags=0, stats=True):
+    """Batched apply of the pairs (ops[i], fs[i]) in one persistent launch per basis order.
+    mixed: None (FP64), a tol for every tree, or a list of tol or (tol, classes) per tree.
+    Returns (list of Trees, aggregated stats or None)."""
+    n = len(ops)
+    if len(fs) != n:
+        raise ValueError("ops and fs differ in length")
+    gs = (ctypes.c_void_p * n)()
+    st = _lib.ApplyStats()
+    mx = _mixed_array(mixed, n)
+    check(lib.mwns_apply_batch(ctx.h, n, _handles(ops), _handles(fs), mx, flags, gs,
+                               ctypes.byref(st) if stats else None), "mwns_apply_batch")
+    return [Tree(ctx, ctypes.c_void_p(gs[i])) for i in range(n)], (_stats_dict(st) if stats else None)
+
+
+def mwns_plan_create(ctx, ops, fs, mixed=None, flags=0):
+    n = len(ops)
+    if len(fs) != n:
+        raise ValueError("ops and fs differ in length")
+    h = ctypes.c_void_p()
+    mx = _mixed_array(mixed, n)
+    check(lib.mwns_plan_create(ctx.h, n, _handles(ops), _handles(fs), mx, flags, ctypes.byref(h)), "mwns_plan_create")
+    return Plan(ctx, h, n, (list(ops), list(fs)))
+
+
+def mwns_tree_set_leaves(ctx, tree, coeffs):
+    """Replace the leaf coefficients (canonical leaf order, [nleaves, k, k, k]) in place."""
+    info = mwns_tree_get_info(tree)
+    k = info["k"]
+    coeffs = _f64(coeffs, (info["nleaves"], k, k, k))
+    check(lib.mwns_tree_set_leaves(ctx.h, tree.h, coeffs.ctypes.data), "mwns_tree_set_leaves")
 
 
 def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):

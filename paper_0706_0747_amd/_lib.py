@@ -76,6 +76,13 @@ SIGNATURES = {
     "mwns_tree_destroy": (None, [c_vp]),
     "mwns_apply": (c_int, [c_vp, c_vp, c_vp, c_int, P(c_vp), P(ApplyStats)]),
     "mwns_apply_mixed": (c_int, [c_vp, c_vp, c_vp, P(MixedOpts), c_int, P(c_vp), P(ApplyStats)]),
+    "mwns_apply_batch": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, P(ApplyStats)]),
+    "mwns_plan_create": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_int, P(c_vp)]),
+    "mwns_plan_execute": (c_int, [c_vp]),
+    "mwns_plan_output": (c_int, [c_vp, c_int, P(c_vp)]),
+    "mwns_plan_stats": (c_int, [c_vp, P(ApplyStats)]),
+    "mwns_plan_destroy": (None, [c_vp]),
+    "mwns_tree_set_leaves": (c_int, [c_vp, c_vp, c_vp]),
     "mwns_tree_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
 }
 

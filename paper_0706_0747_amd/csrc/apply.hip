@@ -25,7 +25,7 @@
 #include <cmath>
 #include <memory>
 
-#include "mwns_internal.h"
+#include "contract.h"
 
 namespace mwns {
 
@@ -38,476 +38,7 @@ struct LevelTab2 {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-
-struct Tpl {
-    int lo[3], hi[3];      // coarse displacement box
-    int mlo[3], mhi[3];    // fine displacement mask per dimension
-    int m1, m2;            // inclusive term range
-    int dpart;             // 0: whole band (all children, +), 1: down band (internal children, -)
-    int prec;              // precision class of the job's terms (PREC_*)
-};
-
-// Precision classes of a job.  Every class accumulates into the FP64 output; the reduced ones
-// take their inputs from FP32 or split-BF16 copies of the input bricks and accumulate each
-// mode product in FP32.
-enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16C = 2, PREC_BF16 = 3, NPREC = 4 };
-
 constexpr int AT = 256;            // threads per block of the transform kernels
-constexpr int T2S_V1 = 272;        // LDS strides of the FP64 mode-2 result [v1][u2][u3] (conflict-free)
-constexpr int T2S_U2 = 16;
-constexpr int T2F_V1 = 324;        // the same for the FP32 mode-2 result (64 distinct banks per access)
-constexpr int T2F_U2 = 20;
-constexpr int NMAX = 4;            // largest box extent per dimension of one job (the host splits boxes)
-constexpr int S3_V = 36;           // LDS stride of the staged FP64 mode-3 operand [L][v][u]
-constexpr int SF_V = 20;           // LDS stride of the staged FP32 operands [L][v][u]
-// LDS of the contraction kernel, in doubles: the FP64 layout is the largest of the classes.
-constexpr int SM_T2 = 16 * T2S_V1, SM_S3 = NMAX * 16 * S3_V, SM_S2 = NMAX * 256, SM_S1 = NMAX * 256;
-constexpr int SMEM_DOUBLES = SM_T2 + SM_S3 + SM_S2 + SM_S1;
-static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * SF_V / 2 <= SMEM_DOUBLES, "FP32 LDS layout");
-static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * 4 * 2 <= SMEM_DOUBLES, "BF16 LDS layout");
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// One level of the apply as seen by the contraction kernel.
-struct LevelDesc {
-    const double* Xr;        // real input bricks of the level (the level's own bricks)
-    const double* Xg;        // ghost input bricks
-    const float* Xr32;       // FP32 copies, rows padded to 16: [brick][v1][v2][16]  (or null)
-    const float* Xg32;
-    const u4* Xrb;           // split-BF16 copies: [brick][v1][v2][4 groups] of (4 hi, 4 lo)  (or null)
-    const u4* Xgb;
-    const int32_t* nbr;      // [brick][(2Lr+1)^3] input index, -1 outside the cube
-    const uint8_t* cmask;    // [brick] bit s set when child s is internal
-    const Tpl* tpl;          // jobs of the level
-    const double* Fj;        // F^{j;m,l} of the level [M][NLF][k][k]
-    double* out;             // output bricks of the level
-    int64_t nreal;
-    int Lr, valid, ntpl, pad;
-};
-
-// Masked super-block entry S^{m,L}[u][v]: F^{j;m,2L+su-sv}_{a b} when the fine displacement lies in
-// [mlo, mhi], else 0; u = su*K + a (output), v = sv*K + b (input); rows/columns >= 2K are padding.
-template <int K>
-__device__ inline double sop(const double* __restrict__ Fm, int L, int mlo, int mhi, int u, int v) {
-    if (u >= 2 * K || v >= 2 * K) return 0.0;
-    const int su = u >= K, sv = v >= K;
-    const int l = 2 * L + su - sv;
-    if (l < mlo || l > mhi) return 0.0;
-    return Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
-}
-
-// Byte offset of lane (g, r)'s four consecutive doubles X[v1][r][4g..4g+3] in a brick; rows,
-// slices and column groups outside the 2K extent get an offset past the buffer (loads return 0).
-template <int K>
-__device__ inline uint32_t slice_offset(int v1, int g, int r) {
-    constexpr int D = 2 * K;
-    if (v1 >= D || r >= D || 4 * g >= D) return 0x40000000u;
-    return (uint32_t)((((v1 * D) + r) * D + 4 * g) * 8);
-}
-
-// Byte offset of lane (g, r)'s 16-byte group in the padded reduced-precision copies (FP32 or
-// split BF16; both hold 64 bytes per (v1, v2) row).
-template <int K>
-__device__ inline uint32_t slice_offset_lp(int v1, int g, int r) {
-    constexpr int D = 2 * K;
-    if (v1 >= D || r >= D) return 0x40000000u;
-    return (uint32_t)(((v1 * D) + r) * 64 + 16 * g);
-}
-
-template <int K, int TPW>
-__device__ inline void load_slices(const double* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], d4 (&x)[TPW]) {
-    constexpr int D = 2 * K;
-    // nbytes = 0 turns every load into an out-of-range one that returns zeros without touching memory
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, nbytes, 0x00020000);
-    typedef double dv2 __attribute__((ext_vector_type(2)));
-    for (int t = 0; t < TPW; ++t) {
-        if constexpr (D % 4 == 0) {
-            const dv2 a = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t], 0, 0));
-            const dv2 b = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t] + 16, 0, 0));
-            x[t] = (d4){a.x, a.y, b.x, b.y};
-        } else {
-            // a 4-column group may cross the end of a row: load the valid columns one by one
-            const uint32_t o = off[t];
-            const int col = (int)((o / 8) % D);
-            for (int kk = 0; kk < 4; ++kk) {
-                const uint32_t ok = (o < 0x40000000u && col + kk < D) ? o + 8 * kk : 0x40000000u;
-                x[t][kk] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, ok, 0, 0));
-            }
-        }
-    }
-}
-
-template <int TPW>
-__device__ inline void load_slices_lp(const void* __restrict__ X, int nbytes, const uint32_t (&off)[TPW], u4 (&x)[TPW]) {
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, nbytes, 0x00020000);
-    for (int t = 0; t < TPW; ++t) x[t] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(rs, off[t], 0, 0));
-}
-
-// Split of four FP32 values into BF16 hi and lo parts (hi + lo carries 16 significant bits):
-// returns (hi0 hi1 | hi2 hi3 | lo0 lo1 | lo2 lo3) packed two per dword.
-__device__ inline u4 split4(f4 x) {
-    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-    bf2 h01 = {(__bf16)x[0], (__bf16)x[1]}, h23 = {(__bf16)x[2], (__bf16)x[3]};
-    bf2 l01 = {(__bf16)(x[0] - (float)h01[0]), (__bf16)(x[1] - (float)h01[1])};
-    bf2 l23 = {(__bf16)(x[2] - (float)h23[0]), (__bf16)(x[3] - (float)h23[1])};
-    return (u4){__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23), __builtin_bit_cast(unsigned, l01),
-                __builtin_bit_cast(unsigned, l23)};
-}
-
-// A x B over 16 contraction slots per operand pair with split-BF16 operands a = (4 hi | 4 lo) and
-// b = (4 hi | 4 lo) of the same 4 contraction indices: the 16x16x32 BF16 MFMA sees the slots
-// (a_hi b_hi | a_lo b_hi) and, when compensated, (a_hi b_lo | a_lo b_lo): all four partial
-// products, exact in FP32, summed in FP32.  Uncompensated: (a_hi + a_lo) b_hi.
-template <bool COMP>
-__device__ inline f4 mfma_bf16x(u4 a, u4 b, f4 c) {
-    const bf8 A = __builtin_bit_cast(bf8, a);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf8, (u4){b[0], b[1], b[0], b[1]}), c, 0, 0, 0);
-    if constexpr (COMP) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf8, (u4){b[2], b[3], b[2], b[3]}), c, 0, 0, 0);
-    return c;
-}
-
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
-// vector-memory loads, so prefetched input slices stay in flight across it.
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// Rows of the FP32 mode-1 operand: output row m of the MFMA tile holds u1 = perm_row(m), so that
-// register i of lane (g, r) holds u1 = 4i + g as in the FP64 layout of the output accumulators.
-__device__ inline int perm_row(int m) { return 4 * (m & 3) + (m >> 2); }
-
-template <int PREC>
-struct ClassTypes;
-template <>
-struct ClassTypes<PREC_F64> { using Acc = d4; using XV = d4; };
-template <int PREC>
-struct ClassTypes { using Acc = f4; using XV = u4; };
-
-// The terms of one job for one output brick (see the kernel below), in precision class PREC.
-template <int K, int CW, int PF, int PREC>
-__device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, const double* __restrict__ w, int ns,
-                                        const int2* steps, double* smem, int wave, int g, int r, int cmb,
-                                        d4 (&Y)[(2 * K + CW - 1) / CW]) {
-    constexpr int CT = 64 * CW;
-    constexpr int D = 2 * K;
-    constexpr int TPW = (D + CW - 1) / CW;
-    constexpr bool FULL = (CW * TPW == D);
-    constexpr int64_t E = (int64_t)D * D * D;
-    constexpr int64_t ELP = (int64_t)D * D * 64;   // bytes of a reduced-precision brick
-    constexpr int NB = PF + 1;
-    using Acc = typename ClassTypes<PREC>::Acc;
-    using XV = typename ClassTypes<PREC>::XV;
-    const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
-    const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
-    // LDS carve-up of this class
-    double* T2s = smem;
-    double* S3s = smem + SM_T2;
-    double* S2s = S3s + SM_S3;
-    double* S1s = S2s + SM_S2;
-    float* T2f = reinterpret_cast<float*>(smem);
-    float* S3f = T2f + 16 * T2F_V1;
-    float* S2f = S3f + NMAX * 16 * SF_V;
-    float* S1f = S2f + NMAX * 16 * SF_V;
-    u4* S3b = reinterpret_cast<u4*>(T2f + 16 * T2F_V1);   // [L][u][4 groups] of (4 hi | 4 lo)
-    u4* S2b = S3b + NMAX * 64;
-    u4* S1b = S2b + NMAX * 64;
-    uint32_t xoff[TPW];
-    for (int t = 0; t < TPW; ++t)
-        xoff[t] = PREC == PREC_F64 ? slice_offset<K>(wave * TPW + t, g, r) : slice_offset_lp<K>(wave * TPW + t, g, r);
-    auto load = [&](int si, bool live, XV (&x)[TPW]) {
-        const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
-        const bool real = idx < lv.nreal;
-        const int64_t q = real ? idx : idx - lv.nreal;
-        if constexpr (PREC == PREC_F64) {
-            load_slices<K, TPW>((real ? lv.Xr : lv.Xg) + q * E, live ? (int)(E * 8) : 0, xoff, x);
-        } else if constexpr (PREC == PREC_F32) {
-            load_slices_lp<TPW>((const char*)(real ? lv.Xr32 : lv.Xg32) + q * ELP, live ? (int)ELP : 0, xoff, x);
-        } else {
-            load_slices_lp<TPW>((const char*)(real ? lv.Xrb : lv.Xgb) + q * ELP, live ? (int)ELP : 0, xoff, x);
-        }
-    };
-    XV xb[NB][TPW];
-    int pf = 0;   // cell of the next prefetch
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        const bool live = u < total;
-        load(pf, live, xb[u]);
-        if (live && ++pf == ns) pf = 0;
-    }
-    int m = tp.m1, si = 0;
-    Acc T1[TPW], T2[TPW];
-    for (int t = 0; t < TPW; ++t) T1[t] = T2[t] = Acc{};
-    for (int s0 = 0; s0 < total; s0 += NB) {
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            if (s0 + u >= total) break;
-            if (si == 0) {
-                // stage this term's masked super-blocks in LDS (cw folded into S1), before the next
-                // prefetch so that waiting for these loads does not wait for it
-                const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
-                const double cw = tp.dpart ? -w[m] : w[m];
-                if constexpr (PREC == PREC_F64 || PREC == PREC_F32) {
-                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 256; e += CT) {
-                        const int sb = e >> 8, v = (e >> 4) & 15, uu = e & 15;
-                        int q, d;
-                        if (sb < n1) { q = sb; d = 0; }
-                        else if (sb < n1 + n2) { q = sb - n1; d = 1; }
-                        else { q = sb - n1 - n2; d = 2; }
-                        const double val = (d == 0 ? cw : 1.0) * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v);
-                        if constexpr (PREC == PREC_F64) {
-                            double* dst = d == 0 ? S1s + q * 256 + v * 16 : d == 1 ? S2s + q * 256 + v * 16 : S3s + q * 16 * S3_V + v * S3_V;
-                            dst[uu] = val;
-                        } else {
-                            float* dst = (d == 0 ? S1f : d == 1 ? S2f : S3f) + (q * 16 + v) * SF_V;
-                            dst[uu] = (float)val;
-                        }
-                    }
-                } else {
-                    // split BF16: one thread per (super-block, row u, group of 4 contraction indices)
-                    for (int e = threadIdx.x; e < (n1 + n2 + n3) * 64; e += CT) {
-                        const int sb = e >> 6, uu = (e >> 2) & 15, gg = e & 3;
-                        int q, d;
-                        if (sb < n1) { q = sb; d = 0; }
-                        else if (sb < n1 + n2) { q = sb - n1; d = 1; }
-                        else { q = sb - n1 - n2; d = 2; }
-                        const double sc = d == 0 ? cw : 1.0;
-                        f4 v4;
-                        for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, 4 * gg + c));
-                        (d == 0 ? S1b : d == 1 ? S2b : S3b)[(q * 16 + uu) * 4 + gg] = split4(v4);
-                    }
-                }
-                lds_barrier();
-            }
-            if (PF > 0) {
-                const bool live = s0 + u + PF < total;
-                load(pf, live, xb[(u + PF) % NB]);
-                if (live && ++pf == ns) pf = 0;
-            } else {
-                load(si, true, xb[u]);
-            }
-            const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
-            const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
-            const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
-            // mode 3: T1 += X x_3 S3^{L3}
-            if constexpr (PREC == PREC_F64) {
-                const double* s3p = S3s + q3 * 16 * S3_V + r;
-                double s3[4];
-                for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
-                for (int kk = 0; kk < 4; ++kk)
-                    for (int t = 0; t < TPW; ++t)
-                        if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[u][t][kk], s3[kk], T1[t], 0, 0, 0);
-            } else if constexpr (PREC == PREC_F32) {
-                const float* s3p = S3f + q3 * 16 * SF_V + r;
-                float s3[4];
-                for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * SF_V];
-                // reinterpret the whole vector: a bit_cast of one subscripted vector element is
-                // miscompiled (it reads element 0 whatever the subscript)
-                f4 xf[TPW];
-                for (int t = 0; t < TPW; ++t) xf[t] = __builtin_bit_cast(f4, xb[u][t]);
-                for (int kk = 0; kk < 4; ++kk)
-                    for (int t = 0; t < TPW; ++t)
-                        if (FULL || wave * TPW + t < D) T1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xf[t][kk], s3[kk], T1[t], 0, 0, 0);
-            } else {
-                const u4 s3 = S3b[(q3 * 16 + r) * 4 + g];
-                for (int t = 0; t < TPW; ++t)
-                    if (FULL || wave * TPW + t < D) T1[t] = mfma_bf16x<PREC == PREC_BF16C>(xb[u][t], s3, T1[t]);
-            }
-            if (next < 0 || (next >> 2) != (cell >> 2)) {
-                // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
-                if constexpr (PREC == PREC_F64) {
-                    const double* s2p = S2s + q2 * 256 + r;
-                    double s2[4];
-                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
-                    for (int i = 0; i < 4; ++i)
-                        for (int t = 0; t < TPW; ++t)
-                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], T2[t], 0, 0, 0);
-                } else if constexpr (PREC == PREC_F32) {
-                    const float* s2p = S2f + q2 * 16 * SF_V + r;
-                    float s2[4];
-                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * g + i) * SF_V];
-                    for (int i = 0; i < 4; ++i)
-                        for (int t = 0; t < TPW; ++t)
-                            if (FULL || wave * TPW + t < D) T2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2[i], T1[t][i], T2[t], 0, 0, 0);
-                } else {
-                    const u4 s2 = S2b[(q2 * 16 + r) * 4 + g];
-                    for (int t = 0; t < TPW; ++t)
-                        if (FULL || wave * TPW + t < D) T2[t] = mfma_bf16x<PREC == PREC_BF16C>(s2, split4(T1[t]), T2[t]);
-                }
-                for (int t = 0; t < TPW; ++t) T1[t] = Acc{};
-            }
-            if (next < 0 || (next >> 4) != (cell >> 4)) {
-                // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
-                for (int t = 0; t < TPW; ++t) {
-                    const int v1 = wave * TPW + t;
-                    if (!FULL && v1 >= D) break;
-                    for (int i = 0; i < 4; ++i) {
-                        if constexpr (PREC == PREC_F64) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[t][i];
-                        else T2f[v1 * T2F_V1 + (4 * g + i) * T2F_U2 + r] = T2[t][i];
-                    }
-                }
-                lds_barrier();
-                for (int t = 0; t < TPW; ++t) {
-                    const int u2 = wave * TPW + t;
-                    if (!FULL && u2 >= D) break;
-                    d4 add;
-                    if constexpr (PREC == PREC_F64) {
-                        const double* s1p = S1s + q1 * 256 + r;
-                        // the down band reaches only internal children: accumulate it apart, add it masked
-                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
-                        for (int kk = 0; kk < 4; ++kk) {
-                            const int v1 = 4 * kk + g;
-                            const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
-                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1p[(4 * kk + g) * 16], bv, acc, 0, 0, 0);
-                        }
-                        if (!tp.dpart) { Y[t] = acc; continue; }
-                        add = acc;
-                    } else {
-                        f4 acc = {0.f, 0.f, 0.f, 0.f};
-                        if constexpr (PREC == PREC_F32) {
-                            const float* s1p = S1f + q1 * 16 * SF_V + perm_row(r);
-                            for (int kk = 0; kk < 4; ++kk) {
-                                const int v1 = 4 * g + kk;
-                                const float bv = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(s1p[v1 * SF_V], bv, acc, 0, 0, 0);
-                            }
-                        } else {
-                            f4 bv;
-                            for (int j = 0; j < 4; ++j) {
-                                const int v1 = 4 * g + j;
-                                bv[j] = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
-                            }
-                            acc = mfma_bf16x<PREC == PREC_BF16C>(S1b[(q1 * 16 + perm_row(r)) * 4 + g], split4(bv), acc);
-                        }
-                        add = (d4){(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
-                        if (!tp.dpart) { Y[t] += add; continue; }
-                    }
-                    for (int i = 0; i < 4; ++i) {
-                        const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
-                        if ((cmb >> child) & 1) Y[t][i] += add[i];
-                    }
-                }
-                for (int t = 0; t < TPW; ++t) T2[t] = Acc{};
-                lds_barrier();
-            }
-            if (++si == ns) {
-                si = 0;
-                ++m;
-            }
-        }
-    }
-}
-
-// One block per output brick, over all levels at once (order[] lists (level, brick)).  CW waves
-// per block, each owning TPW input slices; PF steps of input slices are prefetched into registers.
-// For every job the in-cube cells of its box are first compacted into an LDS list (ascending L1,
-// L2, L3), so the term loop and the cell loop fuse into one stream of steps whose input bricks
-// are known PF steps ahead (the same list repeats for every term of the job).
-//
-// MFMA mapping of the FP64 class (v_mfma_f64_16x16x4: A[m][k] in lane m+16k, B[k][n] in lane
-// n+16k, D[4i+g][n] in lane 16g+n, register i): wave w owns the input slices v1 in {w*TPW..}: mode 3
-// (contract v3, A = X slice with K index 4g+kk loaded as 4 consecutive doubles, B = S3), mode 2
-// straight from the mode-3 accumulators (their register i holds contraction index 4i+g), an LDS
-// transpose, then mode 1 into the per-wave output tiles.  The FP32 class (v_mfma_f32_16x16x4,
-// D[4g+i][n]) follows the same chain with the contraction slots permuted to match; the BF16
-// classes (v_mfma_f32_16x16x32_bf16, lane 16g+n holding K slots 8g..8g+7) give every lane the 4
-// contraction indices 4g..4g+3 as (4 hi | 4 lo) halves, which is exactly what the FP32 mode-3
-// accumulators of the lane hold, so mode 2 again needs no data movement.
-template <int K, int CW, int PF, int WPE>
-__global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, const double* __restrict__ w) {
-    constexpr int D = 2 * K;
-    constexpr int TPW = (D + CW - 1) / CW;
-    constexpr int64_t E = (int64_t)D * D * D;
-    __shared__ double smem[SMEM_DOUBLES];
-    __shared__ int2 steps[NMAX * NMAX * NMAX];
-    __shared__ int nsteps_s;
-    // wave index and every neighbour index are uniform per wave: keep them in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-    const int2 job = order[blockIdx.x];
-    const LevelDesc lv = levels[job.x];
-    const int64_t b = job.y;
-    const int Lr = lv.Lr;
-    const int NL = 2 * Lr + 1;
-    const int32_t* nb = lv.nbr + b * NL * NL * NL;
-    const int cmb = lv.cmask[b];
-    d4 Y[TPW];
-    for (int t = 0; t < TPW; ++t) Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
-    for (int ti = 0; ti < lv.ntpl; ++ti) {
-        const Tpl tp = lv.tpl[ti];
-        if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
-        const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
-        // compact list of the box's in-cube cells: (input index, q1 << 4 | q2 << 2 | q3)
-        lds_barrier();
-        if (threadIdx.x < 64) {
-            const int t = threadIdx.x;
-            int idx = -1, q1 = 0, q2 = 0, q3 = 0;
-            if (t < n1 * n2 * n3) {
-                q1 = t / (n2 * n3);
-                q2 = (t / n3) % n2;
-                q3 = t % n3;
-                idx = nb[((tp.lo[0] + q1 + Lr) * NL + (tp.lo[1] + q2 + Lr)) * NL + tp.lo[2] + q3 + Lr];
-            }
-            const unsigned long long in = __ballot(idx >= 0);
-            if (idx >= 0) steps[__popcll(in & ((1ull << t) - 1ull))] = make_int2(idx, (q1 << 4) | (q2 << 2) | q3);
-            if (t == 0) nsteps_s = __popcll(in);
-        }
-        lds_barrier();
-        const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
-        if (ns == 0) continue;
-        switch (__builtin_amdgcn_readfirstlane(tp.prec)) {
-            case PREC_F64: run_job<K, CW, PF, PREC_F64>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            case PREC_F32: run_job<K, CW, PF, PREC_F32>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            case PREC_BF16C: run_job<K, CW, PF, PREC_BF16C>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            default: run_job<K, CW, PF, PREC_BF16>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-        }
-    }
-    double* ob = lv.out + b * E;
-    for (int t = 0; t < TPW; ++t) {
-        const int u2 = wave * TPW + t;
-        if (u2 >= D) break;
-        for (int i = 0; i < 4; ++i) {
-            const int u1 = 4 * i + g, u3 = r;
-            if (u1 >= D || u3 >= D) continue;
-            const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
-            ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][i] : 0.0;
-        }
-    }
-}
-
-// Reduced-precision copies of input bricks: one thread per (brick, v1, v2, group of 4 columns)
-// writes 16 bytes -- four FP32 values (F32) or their split BF16 (hi | lo) (BF16); columns at or
-// beyond 2K are zero.
-template <int K, bool BF>
-__global__ void convert_kernel(int64_t nbricks, const double* __restrict__ X, u4* __restrict__ out) {
-    constexpr int D = 2 * K;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nbricks * D * D * 4) return;
-    const int gg = (int)(i & 3);
-    const int64_t row = i >> 2;     // (brick, v1, v2)
-    const double* x = X + row * D;
-    f4 v;
-    for (int c = 0; c < 4; ++c) v[c] = 4 * gg + c < D ? (float)x[4 * gg + c] : 0.f;
-    out[i] = BF ? split4(v) : __builtin_bit_cast(u4, v);
-}
-
-// Sum of squares of every brick element of one level (real and ghost inputs): one 256-thread
-// block per brick, reduced in LDS and added to *acc.
-template <int K>
-__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ X, double* __restrict__ acc) {
-    constexpr int E = 8 * K * K * K;
-    __shared__ double red[256];
-    const double* x = X + (int64_t)blockIdx.x * E;
-    double s = 0.0;
-    for (int e = threadIdx.x; e < E; e += 256) s += x[e] * x[e];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(acc, red[0]);
-}
 
 // ---------------------------------------------------------------- closure
 // For every output brick of level j (parent P at level j-1) and L in [-Lr,Lr]^3: index of the
@@ -733,34 +264,6 @@ __global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ p
     atomicAdd(total, (unsigned long long)cnt);
 }
 
-// Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD).
-struct Variant {
-    int cw, pf, wpe;
-};
-constexpr Variant VARIANTS[] = {{8, 0, 4}, {8, 1, 2}, {8, 2, 2}, {16, 1, 4}, {16, 2, 4}, {16, 3, 4}};
-constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
-
-template <int K, int V>
-void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, const double* w) {
-    constexpr Variant v = VARIANTS[V];
-    ns_apply_kernel<K, v.cw, v.pf, v.wpe><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, w);
-}
-
-template <int K>
-struct ApplyLaunch {
-    static void run(hipStream_t st, int variant, int64_t nblocks, const LevelDesc* levels, const int2* order,
-                    const double* w) {
-        switch (variant) {
-            case 0: launch_variant<K, 0>(st, nblocks, levels, order, w); break;
-            case 1: launch_variant<K, 1>(st, nblocks, levels, order, w); break;
-            case 2: launch_variant<K, 2>(st, nblocks, levels, order, w); break;
-            case 3: launch_variant<K, 3>(st, nblocks, levels, order, w); break;
-            case 4: launch_variant<K, 4>(st, nblocks, levels, order, w); break;
-            case 5: launch_variant<K, 5>(st, nblocks, levels, order, w); break;
-            default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
-        }
-    }
-};
 template <int K>
 struct GhostLaunch {
     static void run(hipStream_t st, int64_t ng, int jm1, const uint64_t* gk, const uint64_t* keys, int64_t nn,
@@ -773,44 +276,6 @@ struct AssembleLaunch {
     static void run(hipStream_t st, int64_t nb, int j, const int64_t* pb, const int* pc, int64_t off, const double* Ht,
                     double* coef) {
         assemble_kernel<K><<<(unsigned)nb, AT, 0, st>>>(j, pb, pc, off, Ht, coef);
-    }
-};
-
-constexpr int DEFAULT_VARIANT = 0;   // (8 waves, no prefetch, 4 waves per SIMD): fastest on the k = 8 Poisson workload
-
-int variant_for(const mwns_ctx* ctx, int k) {
-    const int v = ctx->variant[k];
-    return v >= 0 ? v : DEFAULT_VARIANT;
-}
-
-template <template <int> class Fn, class... Args>
-void dispatch_k(int k, Args&&... args) {
-    switch (k) {
-        case 1: Fn<1>::run(args...); break;
-        case 2: Fn<2>::run(args...); break;
-        case 3: Fn<3>::run(args...); break;
-        case 4: Fn<4>::run(args...); break;
-        case 5: Fn<5>::run(args...); break;
-        case 6: Fn<6>::run(args...); break;
-        case 7: Fn<7>::run(args...); break;
-        case 8: Fn<8>::run(args...); break;
-        default: fail(MWNS_EINVAL, "unsupported k");
-    }
-}
-
-template <int K>
-struct SumsqLaunch {
-    static void run(hipStream_t st, int64_t nb, const double* X, double* acc) {
-        if (nb > 0) sumsq_kernel<K><<<(unsigned)nb, 256, 0, st>>>(X, acc);
-    }
-};
-template <int K>
-struct ConvertLaunch {
-    static void run(hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
-        const int64_t n = nb * 2 * K * 2 * K * 4;
-        if (n == 0) return;
-        if (bf) convert_kernel<K, true><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
-        else convert_kernel<K, false><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
     }
 };
 
@@ -999,39 +464,58 @@ struct Timer {
 
 using namespace mwns;
 
-extern "C" int mwns_num_variants(void) { return NVARIANTS; }
-
-extern "C" mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant) {
-    MWNS_GUARD_BEGIN
-    if (!ctx) fail(MWNS_EINVAL, "ctx is NULL");
-    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
-    if (variant < -1 || variant >= NVARIANTS) fail(MWNS_EINVAL, "variant out of range");
-    ctx->variant[k] = variant;
-    return MWNS_OK;
-    MWNS_GUARD_END
-}
-
-extern "C" mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* variant) {
-    MWNS_GUARD_BEGIN
-    if (!ctx || !variant) fail(MWNS_EINVAL, "NULL argument");
-    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
-    *variant = ctx->variant[k];
-    return MWNS_OK;
-    MWNS_GUARD_END
-}
-
 namespace {
 
-// The apply behind both entry points; mixed == nullptr is the all-FP64 apply.
-void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, const mwns_mixed_opts* mixed,
-                mwns_tree** g, mwns_apply_stats* stats) {
-    if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
+__global__ void zero_ints_kernel(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+struct LevelWork {
+    std::vector<Tpl> tpl;
+    std::vector<uint8_t> cm;
+    std::vector<uint64_t> pk;
+    int Lr = 0;
+    int64_t nout = 0, nghost = 0, miss_off = 0;
+    int valid = 0xff;
+    DevArray<int32_t> nbr;
+    DevArray<uint8_t> cmask;
+    DevArray<Tpl> dtpl;
+    DevArray<double> ghosts;
+    DevArray<uint64_t> pkeys, gkeys;
+    DevArray<u4> xr32, xg32, xrb, xgb;     // reduced-precision copies of the inputs (routed applies)
+    DevArray<int64_t> apb;                 // assembly: parent's brick of every brick of the level
+    DevArray<int> apc;                     //           parent's child slot in that brick
+};
+
+// One (operator, input tree) pair of an apply and everything its device work needs.
+struct TreeApply {
+    const mwns_op* op = nullptr;
+    const mwns_tree* f = nullptr;
+    std::unique_ptr<mwns_tree> out;
+    int k = 0, depth = 0;
+    std::vector<LevelWork> W;
+    DevArray<double> dHt;
+    LevelTab2 lt{};
+    int64_t miss_base = 0, miss_total = 0, total_ghosts = 0, jobs = 0;
+    double err_bound = 0.0, flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
+    size_t desc_base = 0;
+};
+
+// Validation, output skeleton, jobs of every level (whole band from plan row j, down band from
+// row j+1), child masks, parent keys, neighbour-table storage and assembly maps.
+void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
+    if (!op || !f) fail(MWNS_EINVAL, "NULL operator or tree");
+    if (op->ctx != ctx || f->ctx != ctx) fail(MWNS_EINVAL, "operator or tree belongs to another context");
     if (op->k != f->k) fail(MWNS_EINVAL, "operator and tree have different k");
     if (op->max_level < f->depth) fail(MWNS_EINVAL, "operator max_level is below the tree depth");
-    const int k = f->k;
+    a.op = op;
+    a.f = f;
+    const int k = a.k = f->k;
     const int64_t E = brick_elems(k);
     hipStream_t st = ctx->stream;
-    std::unique_ptr<mwns_tree> out(new mwns_tree);
+    a.out.reset(new mwns_tree);
+    mwns_tree* out = a.out.get();
     out->ctx = ctx;
     out->k = k;
     out->depth = f->depth;
@@ -1047,39 +531,23 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
     MWNS_HIP(hipMemcpyAsync(out->dkeys.p, f->dkeys.p, f->nnodes * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     MWNS_HIP(hipMemcpyAsync(out->dleaf.p, f->dleaf.p, f->nnodes, hipMemcpyDeviceToDevice, st));
     out->coef.reset(ctx, (size_t)f->nbricks * E);
-    LevelTab2 lt = level_tab2(f);
-    std::vector<double> Ht(2 * k * k);
+    a.lt = level_tab2(f);
     {
-        std::vector<double> H(2 * k * k);
+        std::vector<double> H(2 * k * k), Ht(2 * k * k);
         two_scale_filters(k, H.data(), H.data() + k * k);
         for (int s = 0; s < 2; ++s)
-            for (int a = 0; a < k; ++a)
-                for (int c = 0; c < k; ++c) Ht[s * k * k + c * k + a] = H[s * k * k + a * k + c];
+            for (int x = 0; x < k; ++x)
+                for (int c = 0; c < k; ++c) Ht[s * k * k + c * k + x] = H[s * k * k + x * k + c];
+        a.dHt.reset(ctx, Ht.size());
+        a.dHt.upload(Ht.data(), Ht.size(), st);
     }
-    DevArray<double> dHt(ctx, Ht.size());
-    dHt.upload(Ht.data(), Ht.size(), st);
-    const int depth = f->depth;
+    const int depth = a.depth = f->depth;
     const int64_t planrow = (int64_t)NLP3 * 2;
-    struct LevelWork {
-        std::vector<Tpl> tpl;
-        std::vector<uint8_t> cm;
-        std::vector<uint64_t> pk;
-        int Lr = 0;
-        int64_t nout = 0, nghost = 0, nleafonly = 0, miss_off = 0;
-        int valid = 0xff;
-        DevArray<int32_t> nbr;
-        DevArray<uint8_t> cmask;
-        DevArray<Tpl> dtpl;
-        DevArray<double> ghosts;
-        DevArray<uint64_t> pkeys, gkeys;
-    };
-    std::vector<LevelWork> W(depth + 1);
-    Timer tclos(st), tcon(st), tasm(st);
-    tclos.start();
-    // ---- jobs of every level: whole band from plan row j, down band from row j+1
-    int64_t miss_total = 0;
+    a.W.clear();
+    a.W.resize(depth + 1);
+    a.miss_total = 0;
     for (int j = 0; j <= depth; ++j) {
-        LevelWork& lw = W[j];
+        LevelWork& lw = a.W[j];
         const mwns_level& L = f->lev[j];
         lw.nout = L.nbricks;
         std::vector<Tpl> raw;
@@ -1099,9 +567,9 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
             int cuts[3][8][2], nc[3];
             for (int d = 0; d < 3; ++d) {
                 nc[d] = 0;
-                for (int a = t.lo[d]; a <= t.hi[d]; a += NMAX) {
-                    cuts[d][nc[d]][0] = a;
-                    cuts[d][nc[d]][1] = std::min(t.hi[d], a + NMAX - 1);
+                for (int x = t.lo[d]; x <= t.hi[d]; x += NMAX) {
+                    cuts[d][nc[d]][0] = x;
+                    cuts[d][nc[d]][1] = std::min(t.hi[d], x + NMAX - 1);
                     ++nc[d];
                 }
             }
@@ -1126,7 +594,6 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
             for (int64_t b = 0; b < lw.nout; ++b)
                 for (int s = 0; s < 8; ++s)
                     if (!f->leaf[L.node_off + 8 * b + s]) lw.cm[b] |= (uint8_t)(1 << s);
-        for (int64_t b = 0; b < lw.nout; ++b) lw.nleafonly += lw.cm[b] == 0;
         lw.cmask.reset(ctx, lw.nout);
         lw.cmask.upload(lw.cm.data(), lw.nout, st);
         lw.nbr.reset(ctx, (size_t)lw.nout * NL3);
@@ -1135,6 +602,13 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
             for (int64_t b = 0; b < lw.nout; ++b) lw.pk[b] = f->keys[f->brick_parent[L.brick_off + b]];
             lw.pkeys.reset(ctx, lw.nout);
             lw.pkeys.upload(lw.pk.data(), lw.nout, st);
+            std::vector<int64_t> pb(lw.nout);
+            std::vector<int> pc(lw.nout);
+            for (int64_t b = 0; b < lw.nout; ++b) node_brick(f, f->brick_parent[L.brick_off + b], &pb[b], &pc[b]);
+            lw.apb.reset(ctx, pb.size());
+            lw.apc.reset(ctx, pc.size());
+            lw.apb.upload(pb.data(), pb.size(), st);
+            lw.apc.upload(pc.data(), pc.size(), st);
         }
         if (lw.tpl.empty()) continue;
         if (j == 0) {
@@ -1143,185 +617,208 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
             lw.nbr.upload(nb.data(), NL3, st);
             continue;
         }
-        lw.miss_off = miss_total;
-        miss_total += lw.nout * NL3;
+        lw.miss_off = a.miss_total;
+        a.miss_total += lw.nout * NL3;
     }
-    // ---- neighbour closure: all levels, one host round trip for the missing-key sets
-    DevArray<uint64_t> miss(ctx, std::max<int64_t>(1, miss_total));
-    for (int j = 1; j <= depth; ++j) {
-        LevelWork& lw = W[j];
+}
+
+// Neighbour closure kernels of every level; missing parents' keys go to miss[miss_base + ...].
+void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
+    for (int j = 1; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
         if (lw.tpl.empty()) continue;
         const int NL = 2 * lw.Lr + 1;
         const int64_t n = lw.nout * NL * NL * NL;
-        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(lw.nout, j - 1, lw.pkeys.p, lw.Lr, lw.nbr.p,
-                                                                    miss.p + lw.miss_off);
+        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(lw.nout, j - 1, lw.pkeys.p, lw.Lr, lw.nbr.p,
+                                                                             miss + a.miss_base + lw.miss_off);
         MWNS_HIP(hipGetLastError());
     }
-    std::vector<uint64_t> hm(miss_total);
-    miss.download(hm.data(), miss_total, st);
-    MWNS_HIP(hipStreamSynchronize(st));
-    int64_t total_ghosts = 0;
-    for (int j = 1; j <= depth; ++j) {
-        LevelWork& lw = W[j];
+}
+
+// The distinct missing keys of every level become its ghost bricks (Alg. 3 Step 2): their
+// indices complete the neighbour tables and their storage is allocated.
+void discover_ghosts(mwns_ctx* ctx, TreeApply& a, const uint64_t* hmiss, uint64_t* dmiss) {
+    a.total_ghosts = 0;
+    for (int j = 1; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
         if (lw.tpl.empty()) continue;
         const int NL = 2 * lw.Lr + 1;
         const int64_t n = lw.nout * NL * NL * NL;
+        const uint64_t* hm = hmiss + a.miss_base + lw.miss_off;
         std::vector<uint64_t> gk;
         for (int64_t i = 0; i < n; ++i)
-            if (hm[lw.miss_off + i] != ~0ull) gk.push_back(hm[lw.miss_off + i]);
+            if (hm[i] != ~0ull) gk.push_back(hm[i]);
         std::sort(gk.begin(), gk.end());
         gk.erase(std::unique(gk.begin(), gk.end()), gk.end());
         lw.nghost = (int64_t)gk.size();
-        total_ghosts += lw.nghost;
+        a.total_ghosts += lw.nghost;
         if (!lw.nghost) continue;
         lw.gkeys.reset(ctx, gk.size());
-        lw.gkeys.upload(gk.data(), gk.size(), st);
-        closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, miss.p + lw.miss_off, lw.gkeys.p, lw.nghost,
-                                                                         lw.nout, lw.nbr.p);
+        lw.gkeys.upload(gk.data(), gk.size(), ctx->stream);
+        closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(
+            n, dmiss + a.miss_base + lw.miss_off, lw.gkeys.p, lw.nghost, lw.nout, lw.nbr.p);
         MWNS_HIP(hipGetLastError());
-        lw.ghosts.reset(ctx, (size_t)lw.nghost * E);
-        dispatch_k<GhostLaunch>(k, st, lw.nghost, j - 1, lw.gkeys.p, f->dkeys.p, f->nnodes, lt, f->coef.p, dHt.p,
-                                lw.ghosts.p);
+        lw.ghosts.reset(ctx, (size_t)lw.nghost * brick_elems(a.k));
+    }
+}
+
+// Ghost values: interpolation from the deepest existing ancestor (depends on f's coefficients).
+void launch_ghosts(mwns_ctx* ctx, TreeApply& a) {
+    for (int j = 1; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
+        if (lw.tpl.empty() || !lw.nghost) continue;
+        dispatch_k<GhostLaunch>(a.k, ctx->stream, lw.nghost, j - 1, lw.gkeys.p, a.f->dkeys.p, a.f->nnodes, a.lt,
+                                a.f->coef.p, a.dHt.p, lw.ghosts.p);
         MWNS_HIP(hipGetLastError());
     }
-    // ---- precision routing (mixed apply): per-level input norms, classes, reduced-precision inputs
-    double err_bound = 0.0;
-    std::vector<DevArray<u4>> xr32(depth + 1), xg32(depth + 1), xrb(depth + 1), xgb(depth + 1);
-    if (mixed) {
-        DevArray<double> lsq(ctx, depth + 1);
-        fill_kernel<<<1, 64, 0, st>>>(lsq.p, depth + 1, 0.0);
-        for (int j = 0; j <= depth; ++j) {
-            const LevelWork& lw = W[j];
-            if (lw.tpl.empty()) continue;
-            dispatch_k<SumsqLaunch>(k, st, lw.nout, f->coef.p + f->lev[j].brick_off * E, lsq.p + j);
-            dispatch_k<SumsqLaunch>(k, st, lw.nghost, lw.ghosts.p, lsq.p + j);
-        }
-        MWNS_HIP(hipGetLastError());
-        std::vector<double> hsq(depth + 1);
-        lsq.download(hsq.data(), depth + 1, st);
-        MWNS_HIP(hipStreamSynchronize(st));
-        std::vector<RouteItem> items;
-        const int M = op->M;
-        for (int j = 0; j <= depth; ++j) {
-            const LevelWork& lw = W[j];
-            const double xn = std::sqrt(hsq[j]);
-            int64_t ninternal = 0;
-            for (int64_t b = 0; b < lw.nout; ++b) ninternal += lw.cm[b] != 0;
-            for (int t = 0; t < (int)lw.tpl.size(); ++t) {
-                const Tpl& tp = lw.tpl[t];
-                const double nb = tp.dpart ? (double)ninternal : (double)lw.nout;
-                const double n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
-                for (int m = tp.m1; m <= tp.m2; ++m) {
-                    const double* fr = op->fro.data() + ((int64_t)j * M + m) * NLF;
-                    double beta = std::fabs(op->w[m]) * xn;
-                    for (int d = 0; d < 3; ++d) {
-                        double a = 0.0;
-                        for (int L = tp.lo[d]; L <= tp.hi[d]; ++L) {
-                            double s2 = 0.0;
-                            for (int su = 0; su < 2; ++su)
-                                for (int sv = 0; sv < 2; ++sv) {
-                                    const int l = 2 * L + su - sv;
-                                    if (l >= tp.mlo[d] && l <= tp.mhi[d]) s2 += fr[l + LF] * fr[l + LF];
-                                }
-                            a += std::sqrt(s2);
-                        }
-                        beta *= a;
+}
+
+// Routed apply: the sum of squares of every level's inputs (real and ghost) into lsq[0..depth].
+void launch_level_norms(mwns_ctx* ctx, TreeApply& a, double* lsq) {
+    const int64_t E = brick_elems(a.k);
+    for (int j = 0; j <= a.depth; ++j) {
+        const LevelWork& lw = a.W[j];
+        if (lw.tpl.empty()) continue;
+        launch_sumsq(a.k, ctx->stream, lw.nout, a.f->coef.p + a.f->lev[j].brick_off * E, lsq + j);
+        launch_sumsq(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lsq + j);
+    }
+    MWNS_HIP(hipGetLastError());
+}
+
+// Routed apply: classes of every (level, job, term) from the level norms, jobs split into runs of
+// one class, reduced-precision input copies allocated.
+void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed_opts& opts) {
+    const mwns_op* op = a.op;
+    std::vector<RouteItem> items;
+    const int M = op->M;
+    for (int j = 0; j <= a.depth; ++j) {
+        const LevelWork& lw = a.W[j];
+        const double xn = std::sqrt(lsq[j]);
+        int64_t ninternal = 0;
+        for (int64_t b = 0; b < lw.nout; ++b) ninternal += lw.cm[b] != 0;
+        for (int t = 0; t < (int)lw.tpl.size(); ++t) {
+            const Tpl& tp = lw.tpl[t];
+            const double nb = tp.dpart ? (double)ninternal : (double)lw.nout;
+            const double n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+            for (int m = tp.m1; m <= tp.m2; ++m) {
+                const double* fr = op->fro.data() + ((int64_t)j * M + m) * NLF;
+                double beta = std::fabs(op->w[m]) * xn;
+                for (int d = 0; d < 3; ++d) {
+                    double s = 0.0;
+                    for (int L = tp.lo[d]; L <= tp.hi[d]; ++L) {
+                        double s2 = 0.0;
+                        for (int su = 0; su < 2; ++su)
+                            for (int sv = 0; sv < 2; ++sv) {
+                                const int l = 2 * L + su - sv;
+                                if (l >= tp.mlo[d] && l <= tp.mhi[d]) s2 += fr[l + LF] * fr[l + LF];
+                            }
+                        s += std::sqrt(s2);
                     }
-                    items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1)});
+                    beta *= s;
                 }
+                items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1)});
             }
-        }
-        err_bound = route(items, mixed->tol, mixed->classes);
-        // split every job into runs of terms of one class
-        size_t pos = 0;
-        for (int j = 0; j <= depth; ++j) {
-            LevelWork& lw = W[j];
-            std::vector<Tpl> split;
-            for (int t = 0; t < (int)lw.tpl.size(); ++t) {
-                Tpl cur = lw.tpl[t];
-                for (int m = lw.tpl[t].m1; m <= lw.tpl[t].m2; ++m, ++pos) {
-                    const int c = items[pos].cls;
-                    if (m == lw.tpl[t].m1) { cur.m1 = m; cur.prec = c; }
-                    else if (c != cur.prec) {
-                        cur.m2 = m - 1;
-                        split.push_back(cur);
-                        cur.m1 = m;
-                        cur.prec = c;
-                    }
-                    cur.m2 = m;
-                }
-                split.push_back(cur);
-            }
-            lw.tpl.swap(split);
-            bool need32 = false, needbf = false;
-            for (const Tpl& t : lw.tpl) {
-                need32 = need32 || t.prec == PREC_F32;
-                needbf = needbf || t.prec == PREC_BF16C || t.prec == PREC_BF16;
-            }
-            const int64_t units = (int64_t)4 * 2 * k * 2 * k;     // 16-byte units per brick
-            const double* xr = f->coef.p + f->lev[j].brick_off * E;
-            if (need32) {
-                xr32[j].reset(ctx, (size_t)lw.nout * units);
-                dispatch_k<ConvertLaunch>(k, st, lw.nout, xr, xr32[j].p, false);
-                if (lw.nghost) {
-                    xg32[j].reset(ctx, (size_t)lw.nghost * units);
-                    dispatch_k<ConvertLaunch>(k, st, lw.nghost, lw.ghosts.p, xg32[j].p, false);
-                }
-            }
-            if (needbf) {
-                xrb[j].reset(ctx, (size_t)lw.nout * units);
-                dispatch_k<ConvertLaunch>(k, st, lw.nout, xr, xrb[j].p, true);
-                if (lw.nghost) {
-                    xgb[j].reset(ctx, (size_t)lw.nghost * units);
-                    dispatch_k<ConvertLaunch>(k, st, lw.nghost, lw.ghosts.p, xgb[j].p, true);
-                }
-            }
-            MWNS_HIP(hipGetLastError());
         }
     }
-    tclos.stop();
-    // ---- contractions: one launch over every output brick of every level, costliest first
-    std::vector<LevelDesc> descs(depth + 1);
-    std::vector<std::pair<double, int2>> cost;
-    int64_t jobs = 0;
-    double flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j <= depth; ++j) {
-        LevelWork& lw = W[j];
-        double* outj = out->coef.p + f->lev[j].brick_off * E;
-        LevelDesc& d = descs[j];
-        d = LevelDesc{};
-        d.out = outj;
+    a.err_bound = route(items, opts.tol, opts.classes);
+    size_t pos = 0;
+    for (int j = 0; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
+        std::vector<Tpl> split;
+        for (int t = 0; t < (int)lw.tpl.size(); ++t) {
+            Tpl cur = lw.tpl[t];
+            for (int m = lw.tpl[t].m1; m <= lw.tpl[t].m2; ++m, ++pos) {
+                const int c = items[pos].cls;
+                if (m == lw.tpl[t].m1) { cur.m1 = m; cur.prec = c; }
+                else if (c != cur.prec) {
+                    cur.m2 = m - 1;
+                    split.push_back(cur);
+                    cur.m1 = m;
+                    cur.prec = c;
+                }
+                cur.m2 = m;
+            }
+            split.push_back(cur);
+        }
+        lw.tpl.swap(split);
+        bool need32 = false, needbf = false;
+        for (const Tpl& t : lw.tpl) {
+            need32 = need32 || t.prec == PREC_F32;
+            needbf = needbf || t.prec == PREC_BF16C || t.prec == PREC_BF16;
+        }
+        const int64_t units = (int64_t)4 * 2 * a.k * 2 * a.k;     // 16-byte units per brick
+        if (need32) {
+            lw.xr32.reset(ctx, (size_t)lw.nout * units);
+            if (lw.nghost) lw.xg32.reset(ctx, (size_t)lw.nghost * units);
+        }
+        if (needbf) {
+            lw.xrb.reset(ctx, (size_t)lw.nout * units);
+            if (lw.nghost) lw.xgb.reset(ctx, (size_t)lw.nghost * units);
+        }
+    }
+}
+
+// Routed apply: fill the reduced-precision input copies.
+void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
+    const int64_t E = brick_elems(a.k);
+    for (int j = 0; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
+        const double* xr = a.f->coef.p + a.f->lev[j].brick_off * E;
+        if (lw.xr32.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xr32.p, false);
+        if (lw.xg32.p) launch_convert(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lw.xg32.p, false);
+        if (lw.xrb.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xrb.p, true);
+        if (lw.xgb.p) launch_convert(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lw.xgb.p, true);
+    }
+    MWNS_HIP(hipGetLastError());
+}
+
+// Level descriptors of the contraction kernel (appended to descs) and the cost of every output
+// brick (for the launch order): cost entries are (cost, (descriptor index, brick)).
+void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs, std::vector<std::pair<double, int2>>& cost) {
+    const int k = a.k;
+    const int64_t E = brick_elems(k);
+    a.desc_base = descs.size();
+    a.jobs = 0;
+    a.flops = 0.0;
+    for (int p = 0; p < NPREC; ++p) a.class_flops[p] = 0.0;
+    for (int j = 0; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
+        LevelDesc d{};
+        d.out = a.out->coef.p + a.f->lev[j].brick_off * E;
+        const int di = (int)descs.size();
         if (lw.tpl.empty()) {
-            MWNS_HIP(hipMemsetAsync(outj, 0, lw.nout * E * sizeof(double), st));
+            descs.push_back(d);
             continue;
         }
         lw.dtpl.reset(ctx, lw.tpl.size());
-        lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), st);
-        d.Xr = f->coef.p + f->lev[j].brick_off * E;
+        lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), ctx->stream);
+        d.Xr = a.f->coef.p + a.f->lev[j].brick_off * E;
         d.Xg = lw.ghosts.p;
-        d.Xr32 = reinterpret_cast<const float*>(xr32[j].p);
-        d.Xg32 = reinterpret_cast<const float*>(xg32[j].p);
-        d.Xrb = xrb[j].p;
-        d.Xgb = xgb[j].p;
+        d.Xr32 = reinterpret_cast<const float*>(lw.xr32.p);
+        d.Xg32 = reinterpret_cast<const float*>(lw.xg32.p);
+        d.Xrb = lw.xrb.p;
+        d.Xgb = lw.xgb.p;
         d.nbr = lw.nbr.p;
         d.cmask = lw.cmask.p;
         d.tpl = lw.dtpl.p;
-        d.Fj = op->F.p + (int64_t)j * op->M * NLF * k * k;
+        d.Fj = a.op->F.p + (int64_t)j * a.op->M * NLF * k * k;
+        d.w = a.op->dw.p;
         d.nreal = lw.nout;
         d.Lr = lw.Lr;
         d.valid = lw.valid;
         d.ntpl = (int)lw.tpl.size();
+        descs.push_back(d);
         const int64_t pside = j > 0 ? ((int64_t)1 << (j - 1)) : 1;
         for (int64_t b = 0; b < lw.nout; ++b) {
-            int64_t p[3] = {0, 0, 0};
-            if (j > 0) key_coords(lw.pk[b], p);
+            int64_t pp[3] = {0, 0, 0};
+            if (j > 0) key_coords(lw.pk[b], pp);
             double c = 0.0;
             for (const Tpl& t : lw.tpl) {
                 if (t.dpart && lw.cm[b] == 0) continue;
                 double nin[3];
                 for (int dd = 0; dd < 3; ++dd) {
                     int cnt = 0;
-                    for (int Lx = t.lo[dd]; Lx <= t.hi[dd]; ++Lx) cnt += (p[dd] - Lx >= 0 && p[dd] - Lx < pside);
+                    for (int Lx = t.lo[dd]; Lx <= t.hi[dd]; ++Lx) cnt += (pp[dd] - Lx >= 0 && pp[dd] - Lx < pside);
                     nin[dd] = cnt;
                 }
                 if (nin[0] * nin[1] * nin[2] == 0) continue;     // the box lies outside the cube
@@ -1329,118 +826,284 @@ void apply_impl(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, 
                 const double steps = nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0];
                 c += nt * steps * COST[t.prec];
                 const double D2 = 2.0 * k;
-                jobs += (int64_t)nt;
+                a.jobs += (int64_t)nt;
                 const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
-                flops += fl;
-                class_flops[t.prec] += fl;
+                a.flops += fl;
+                a.class_flops[t.prec] += fl;
             }
-            cost.push_back({c, make_int2(j, (int)b)});
+            cost.push_back({c, make_int2(di, (int)b)});
         }
     }
-    // Launch order.  Workgroups are dealt round-robin to the 8 XCDs, each with its own L2, and the
-    // input sibling groups of neighbouring output bricks overlap: so levels go costliest first,
-    // each level is cut into 8 contiguous Morton ranges of equal length, and block 8i + x takes
-    // the i-th brick of range x, keeping every XCD on one compact region of the tree at a time.
-    std::vector<int2> order;
-    order.reserve(cost.size());
-    {
-        std::vector<std::pair<double, int>> lev_cost;   // (cost per brick, level)
-        size_t pos = 0;
-        std::vector<size_t> lev_begin(depth + 2, 0);
-        for (int j = 0; j <= depth; ++j) {
-            lev_begin[j] = pos;
-            double c = 0.0;
-            size_t n = 0;
-            while (pos < cost.size() && cost[pos].second.x == j) { c += cost[pos].first; ++pos; ++n; }
-            if (n) lev_cost.push_back({c / n, j});
-        }
-        lev_begin[depth + 1] = pos;
-        std::stable_sort(lev_cost.begin(), lev_cost.end(),
-                         [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
-        constexpr int NXCD = 8;
-        for (const auto& lc : lev_cost) {
-            const int j = lc.second;
-            const size_t b0 = lev_begin[j];
-            size_t n = 0;
-            while (b0 + n < cost.size() && cost[b0 + n].second.x == j) ++n;
-            const size_t per = (n + NXCD - 1) / NXCD;
-            for (size_t i = 0; i < per; ++i)
-                for (int x = 0; x < NXCD; ++x) {
-                    const size_t idx = x * per + i;
-                    if (idx < n) order.push_back(cost[b0 + idx].second);
-                }
-        }
+}
+
+// Outputs of levels without jobs are zero (a kernel, so that the sequence can be captured).
+void launch_zero_outputs(mwns_ctx* ctx, TreeApply& a) {
+    const int64_t E = brick_elems(a.k);
+    for (int j = 0; j <= a.depth; ++j) {
+        const LevelWork& lw = a.W[j];
+        if (!lw.tpl.empty() || lw.nout == 0) continue;
+        const int64_t n = lw.nout * E;
+        fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(a.out->coef.p + a.f->lev[j].brick_off * E, n, 0.0);
     }
-    DevArray<LevelDesc> ddesc(ctx, descs.size());
-    ddesc.upload(descs.data(), descs.size(), st);
-    DevArray<int2> dorder(ctx, std::max<size_t>(1, order.size()));
-    dorder.upload(order.data(), order.size(), st);
-    tcon.start();
-    if (!order.empty()) {
-        dispatch_k<ApplyLaunch>(k, st, variant_for(ctx, k), (int64_t)order.size(), ddesc.p, dorder.p, op->dw.p);
+    MWNS_HIP(hipGetLastError());
+}
+
+// Assembly (eq. g_assemble), level by level.
+void launch_assembly(mwns_ctx* ctx, TreeApply& a) {
+    for (int j = 1; j <= a.depth; ++j) {
+        const mwns_level& L = a.f->lev[j];
+        dispatch_k<AssembleLaunch>(a.k, ctx->stream, L.nbricks, j, a.W[j].apb.p, a.W[j].apc.p, L.brick_off, a.dHt.p,
+                                   a.out->coef.p);
         MWNS_HIP(hipGetLastError());
     }
-    tcon.stop();
-    // ---- assembly (eq. g_assemble), level by level on the stream
-    tasm.start();
-    std::vector<DevArray<int64_t>> apb(depth + 1);
-    std::vector<DevArray<int>> apc(depth + 1);
-    if (!(mode & MWNS_NO_ASSEMBLY)) {
-        for (int j = 1; j <= depth; ++j) {
-            const mwns_level& L = f->lev[j];
-            std::vector<int64_t> pb(L.nbricks);
-            std::vector<int> pc(L.nbricks);
-            for (int64_t b = 0; b < L.nbricks; ++b) node_brick(f, f->brick_parent[L.brick_off + b], &pb[b], &pc[b]);
-            apb[j].reset(ctx, pb.size());
-            apc[j].reset(ctx, pc.size());
-            apb[j].upload(pb.data(), pb.size(), st);
-            apc[j].upload(pc.data(), pc.size(), st);
-            dispatch_k<AssembleLaunch>(k, st, L.nbricks, j, apb[j].p, apc[j].p, L.brick_off, dHt.p, out->coef.p);
-            MWNS_HIP(hipGetLastError());
+}
+
+// Launch order.  Workgroups are dealt round-robin to the 8 XCDs, each with its own L2, and the
+// input sibling groups of neighbouring output bricks overlap: so (tree, level) groups go costliest
+// per brick first, each group is cut into 8 contiguous Morton ranges of equal length, and XCD x
+// takes range x of every group.  For the one-workgroup-per-brick launch the ranges are
+// interleaved (position 8i + x holds the i-th brick of range x); for the persistent launch they
+// are concatenated into 8 queues (queue x = every group's range x, costliest group first).
+void make_order(const std::vector<std::pair<double, int2>>& cost, bool persistent, std::vector<int2>& order,
+                std::vector<int>& queues) {
+    std::vector<std::pair<size_t, size_t>> groups;   // [begin, end) of each descriptor's bricks in cost
+    std::vector<double> per;                         // cost per brick of each group
+    for (size_t pos = 0; pos < cost.size();) {
+        size_t e = pos;
+        double c = 0.0;
+        while (e < cost.size() && cost[e].second.x == cost[pos].second.x) c += cost[e++].first;
+        groups.push_back({pos, e});
+        per.push_back(c / (double)(e - pos));
+        pos = e;
+    }
+    std::vector<size_t> gi(groups.size());
+    for (size_t i = 0; i < gi.size(); ++i) gi[i] = i;
+    std::stable_sort(gi.begin(), gi.end(), [&](size_t x, size_t y) { return per[x] > per[y]; });
+    order.clear();
+    order.reserve(cost.size());
+    queues.assign(QUEUE_INTS, 0);
+    if (!persistent) {
+        for (size_t g : gi) {
+            const size_t b0 = groups[g].first, n = groups[g].second - b0;
+            const size_t step = (n + NXCD - 1) / NXCD;
+            for (size_t i = 0; i < step; ++i)
+                for (int x = 0; x < NXCD; ++x)
+                    if (x * step + i < n) order.push_back(cost[b0 + x * step + i].second);
+        }
+        return;
+    }
+    for (int x = 0; x < NXCD; ++x) {
+        queues[NXCD + x] = (int)order.size();
+        for (size_t g : gi) {
+            const size_t b0 = groups[g].first, n = groups[g].second - b0;
+            const size_t step = (n + NXCD - 1) / NXCD;
+            for (size_t i = x * step; i < std::min(n, (x + 1) * step); ++i) order.push_back(cost[b0 + i].second);
+        }
+        queues[2 * NXCD + x] = (int)order.size();
+    }
+}
+
+// Device contraction count and ||g|| of one apply into s (synchronises).
+void collect_stats(mwns_ctx* ctx, TreeApply& a, int mode, mwns_apply_stats& s) {
+    hipStream_t st = ctx->stream;
+    const int64_t planrow = (int64_t)NLP3 * 2;
+    const int64_t E = brick_elems(a.k);
+    DevArray<unsigned long long> tot(ctx, 1);
+    DevArray<double> gsq(ctx, 1);
+    fill_kernel<<<1, 64, 0, st>>>(gsq.p, 1, 0.0);
+    zero_ints_kernel<<<1, 64, 0, st>>>(reinterpret_cast<int*>(tot.p), 2);
+    DevArray<int32_t> dplan(ctx, a.op->plan.size());
+    dplan.upload(a.op->plan.data(), a.op->plan.size(), st);
+    for (int j = 0; j <= a.depth; ++j) {
+        const LevelWork& lw = a.W[j];
+        const int32_t* Rj1 = (j + 1 <= a.op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
+        count_kernel<<<(unsigned)((lw.nout * 8 + 255) / 256), 256, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
+                                                                            dplan.p + (int64_t)j * planrow, Rj1, tot.p);
+    }
+    // ||g||_2: the leaves' scaling functions are orthonormal with disjoint supports
+    if (!(mode & MWNS_NO_ASSEMBLY))
+        for (int j = 0; j <= a.depth; ++j)
+            dispatch_k<LeafsqLaunch>(a.k, st, a.f->lev[j].nbricks, a.f->lev[j].node_off, j == 0 ? 1 : 8, a.f->dleaf.p,
+                                     a.out->coef.p + a.f->lev[j].brick_off * E, gsq.p);
+    MWNS_HIP(hipGetLastError());
+    unsigned long long c = 0;
+    double g2 = 0.0;
+    tot.download(&c, 1, st);
+    gsq.download(&g2, 1, st);
+    MWNS_HIP(hipStreamSynchronize(st));
+    s.contractions += (int64_t)c;
+    s.brick_jobs += a.jobs;
+    s.ghost_bricks += a.total_ghosts;
+    s.useful_flops += a.flops;
+    s.err_bound = std::max(s.err_bound, a.err_bound);
+    s.g_norm = std::sqrt(s.g_norm * s.g_norm + g2);
+    for (int p = 0; p < NPREC; ++p) s.class_flops[p] += a.class_flops[p];
+}
+
+// Everything before the value phase: structure, closure (one host round trip for the whole
+// batch), ghost discovery and, for routed applies, the level norms and classes (a second round
+// trip).  Ghost values and converted inputs are computed here too when `values` is set.
+void prepare(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& trees, const mwns_op* const* ops,
+             const mwns_tree* const* fs, const mwns_mixed_opts* mixed, bool values, DevArray<uint64_t>& miss) {
+    hipStream_t st = ctx->stream;
+    const int n = (int)trees.size();
+    int64_t miss_total = 0;
+    for (int i = 0; i < n; ++i) {
+        setup(ctx, *trees[i], ops[i], fs[i]);
+        trees[i]->miss_base = miss_total;
+        miss_total += trees[i]->miss_total;
+    }
+    miss.reset(ctx, std::max<int64_t>(1, miss_total));
+    for (auto& a : trees) launch_closure(ctx, *a, miss.p);
+    std::vector<uint64_t> hm(miss_total);
+    miss.download(hm.data(), miss_total, st);
+    MWNS_HIP(hipStreamSynchronize(st));
+    for (auto& a : trees) discover_ghosts(ctx, *a, hm.data(), miss.p);
+    if (mixed) {
+        // routing needs the ghosts' values for the level norms
+        size_t nl = 0;
+        for (auto& a : trees) nl += a->depth + 1;
+        DevArray<double> lsq(ctx, nl);
+        fill_kernel<<<(unsigned)((nl + 63) / 64), 64, 0, st>>>(lsq.p, (int64_t)nl, 0.0);
+        size_t off = 0;
+        for (auto& a : trees) {
+            launch_ghosts(ctx, *a);
+            launch_level_norms(ctx, *a, lsq.p + off);
+            off += a->depth + 1;
+        }
+        std::vector<double> hl(nl);
+        lsq.download(hl.data(), nl, st);
+        MWNS_HIP(hipStreamSynchronize(st));
+        off = 0;
+        for (int i = 0; i < n; ++i) {
+            route_tree(ctx, *trees[i], hl.data() + off, mixed[i]);
+            off += trees[i]->depth + 1;
+        }
+        if (values)
+            for (auto& a : trees) launch_convert_inputs(ctx, *a);
+    } else if (values) {
+        for (auto& a : trees) launch_ghosts(ctx, *a);
+    }
+}
+
+// Descriptors and launch orders of a batch, one contraction launch per basis order k.
+struct Launches {
+    std::vector<LevelDesc> descs;
+    DevArray<LevelDesc> ddesc;
+    struct Group {
+        int k = 0, variant = 0;
+        int64_t nblocks = 0;
+        std::vector<int2> order;
+        std::vector<int> queue_init;
+        DevArray<int2> dorder;
+        DevArray<int> dqueue;
+    };
+    std::vector<Group> groups;
+};
+
+void build_launches(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& trees, bool persistent, Launches& Lz) {
+    std::vector<int> ks;
+    for (auto& a : trees)
+        if (std::find(ks.begin(), ks.end(), a->k) == ks.end()) ks.push_back(a->k);
+    std::vector<std::vector<std::pair<double, int2>>> costs(ks.size());
+    for (auto& a : trees) {
+        const size_t gi = std::find(ks.begin(), ks.end(), a->k) - ks.begin();
+        build_descs(ctx, *a, Lz.descs, costs[gi]);
+    }
+    Lz.ddesc.reset(ctx, std::max<size_t>(1, Lz.descs.size()));
+    Lz.ddesc.upload(Lz.descs.data(), Lz.descs.size(), ctx->stream);
+    Lz.groups.resize(ks.size());
+    for (size_t gi = 0; gi < ks.size(); ++gi) {
+        auto& g = Lz.groups[gi];
+        g.k = ks[gi];
+        g.variant = variant_for(ctx, g.k);
+        make_order(costs[gi], persistent, g.order, g.queue_init);
+        g.dorder.reset(ctx, std::max<size_t>(1, g.order.size()));
+        g.dorder.upload(g.order.data(), g.order.size(), ctx->stream);
+        if (persistent) {
+            g.dqueue.reset(ctx, QUEUE_INTS);
+            g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
+            g.nblocks = std::min<int64_t>((int64_t)g.order.size(), resident_blocks(g.k, g.variant, ctx->device));
+        } else {
+            g.nblocks = (int64_t)g.order.size();
         }
     }
+}
+
+void launch_contractions(mwns_ctx* ctx, Launches& Lz) {
+    for (auto& g : Lz.groups) {
+        if (g.order.empty()) continue;
+        if (g.dqueue.p) zero_ints_kernel<<<1, 64, 0, ctx->stream>>>(g.dqueue.p, NXCD);
+        launch_contract(g.k, g.variant, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
+        MWNS_HIP(hipGetLastError());
+    }
+}
+
+// Batched apply of n (operator, tree) pairs; mixed: NULL (FP64) or n routing options.
+void apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
+                 const mwns_mixed_opts* mixed, int mode, bool persistent, mwns_tree** gs, mwns_apply_stats* stats) {
+    if (!ctx || !ops || !fs || !gs || n < 1) fail(MWNS_EINVAL, "NULL argument or empty batch");
+    hipStream_t st = ctx->stream;
+    std::vector<std::unique_ptr<TreeApply>> trees;
+    for (int i = 0; i < n; ++i) trees.emplace_back(new TreeApply);
+    Timer tclos(st), tcon(st), tasm(st);
+    tclos.start();
+    DevArray<uint64_t> miss;     // read by the closure kernels until the stream passes them
+    prepare(ctx, trees, ops, fs, mixed, true, miss);
+    Launches Lz;
+    build_launches(ctx, trees, persistent, Lz);
+    for (auto& a : trees) launch_zero_outputs(ctx, *a);
+    tclos.stop();
+    tcon.start();
+    launch_contractions(ctx, Lz);
+    tcon.stop();
+    tasm.start();
+    if (!(mode & MWNS_NO_ASSEMBLY))
+        for (auto& a : trees) launch_assembly(ctx, *a);
     tasm.stop();
     if (stats) {
         mwns_apply_stats s{};
-        DevArray<unsigned long long> tot(ctx, 1);
-        MWNS_HIP(hipMemsetAsync(tot.p, 0, sizeof(unsigned long long), st));
-        DevArray<int32_t> dplan(ctx, op->plan.size());
-        dplan.upload(op->plan.data(), op->plan.size(), st);
-        for (int j = 0; j <= depth; ++j) {
-            const LevelWork& lw = W[j];
-            const int32_t* Rj1 = (j + 1 <= op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
-            count_kernel<<<(unsigned)((lw.nout * 8 + 255) / 256), 256, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
-                                                                                dplan.p + (int64_t)j * planrow, Rj1, tot.p);
-            MWNS_HIP(hipGetLastError());
-        }
-        // ||g||_2: the leaves' scaling functions are orthonormal with disjoint supports
-        DevArray<double> gsq(ctx, 1);
-        fill_kernel<<<1, 64, 0, st>>>(gsq.p, 1, 0.0);
-        if (!(mode & MWNS_NO_ASSEMBLY))
-            for (int j = 0; j <= depth; ++j)
-                dispatch_k<LeafsqLaunch>(k, st, f->lev[j].nbricks, f->lev[j].node_off, j == 0 ? 1 : 8, f->dleaf.p,
-                                         out->coef.p + f->lev[j].brick_off * E, gsq.p);
-        MWNS_HIP(hipGetLastError());
-        unsigned long long c = 0;
-        double g2 = 0.0;
-        tot.download(&c, 1, st);
-        gsq.download(&g2, 1, st);
-        MWNS_HIP(hipStreamSynchronize(st));
-        s.contractions = (int64_t)c;
-        s.brick_jobs = jobs;
-        s.ghost_bricks = total_ghosts;
-        s.useful_flops = flops;
+        for (auto& a : trees) collect_stats(ctx, *a, mode, s);
         s.ms_closure = tclos.ms();
         s.ms_contract = tcon.ms();
         s.ms_assemble = tasm.ms();
-        s.err_bound = err_bound;
-        s.g_norm = std::sqrt(g2);
-        for (int p = 0; p < NPREC; ++p) s.class_flops[p] = class_flops[p];
         *stats = s;
     } else {
         MWNS_HIP(hipStreamSynchronize(st));
     }
-    *g = out.release();
+    for (int i = 0; i < n; ++i) gs[i] = trees[i]->out.release();
+}
+
+}  // namespace
+
+// A reusable apply: structure, closure, ghost keys, routing and buffers fixed at creation; the
+// value phase (ghost values, input copies, contractions, assembly) captured once as a hipGraph.
+struct mwns_plan {
+    mwns_ctx* ctx = nullptr;
+    int mode = 0;
+    std::vector<std::unique_ptr<TreeApply>> trees;
+    Launches launches;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~mwns_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+void record_values(mwns_plan* pl, hipStream_t st) {
+    mwns_ctx tmp = *pl->ctx;      // the same device and allocator, launches on st
+    tmp.stream = st;
+    for (auto& a : pl->trees) {
+        launch_ghosts(&tmp, *a);
+        launch_convert_inputs(&tmp, *a);
+        launch_zero_outputs(&tmp, *a);
+    }
+    launch_contractions(&tmp, pl->launches);
+    if (!(pl->mode & MWNS_NO_ASSEMBLY))
+        for (auto& a : pl->trees) launch_assembly(&tmp, *a);
 }
 
 }  // namespace
@@ -1449,19 +1112,110 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
                                   mwns_apply_stats* stats) {
     MWNS_GUARD_BEGIN
     if ((mode & 0xff) != MWNS_F64 || (mode & ~(0xff | MWNS_NO_ASSEMBLY))) fail(MWNS_EINVAL, "unsupported mode");
-    apply_impl(ctx, op, f, mode, nullptr, g, stats);
+    if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
+    apply_batch(ctx, 1, &op, &f, nullptr, mode, false, g, stats);
     return MWNS_OK;
     MWNS_GUARD_END
 }
+
+namespace {
+void check_mixed(const mwns_mixed_opts* opts) {
+    if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) fail(MWNS_EINVAL, "tol must be finite and >= 0");
+    if (opts->classes & ~(MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16)) fail(MWNS_EINVAL, "unknown precision class");
+}
+}  // namespace
 
 extern "C" mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts,
                                         int flags, mwns_tree** g, mwns_apply_stats* stats) {
     MWNS_GUARD_BEGIN
     if (!opts) fail(MWNS_EINVAL, "opts is NULL");
-    if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) fail(MWNS_EINVAL, "tol must be finite and >= 0");
-    if (opts->classes & ~(MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16)) fail(MWNS_EINVAL, "unknown precision class");
+    check_mixed(opts);
     if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
-    apply_impl(ctx, op, f, flags, opts, g, stats);
+    if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
+    apply_batch(ctx, 1, &op, &f, opts, flags, false, g, stats);
     return MWNS_OK;
     MWNS_GUARD_END
 }
+
+extern "C" mwns_status mwns_apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
+                                        const mwns_mixed_opts* mixed, int flags, mwns_tree** gs, mwns_apply_stats* stats) {
+    MWNS_GUARD_BEGIN
+    if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
+    if (mixed)
+        for (int i = 0; i < n; ++i) check_mixed(mixed + i);
+    if (gs)
+        for (int i = 0; i < n; ++i) gs[i] = nullptr;
+    apply_batch(ctx, n, ops, fs, mixed, flags, true, gs, stats);
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
+                                        const mwns_mixed_opts* mixed, int flags, mwns_plan** out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !ops || !fs || !out || n < 1) fail(MWNS_EINVAL, "NULL argument or empty batch");
+    if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
+    if (mixed)
+        for (int i = 0; i < n; ++i) check_mixed(mixed + i);
+    std::unique_ptr<mwns_plan> pl(new mwns_plan);
+    pl->ctx = ctx;
+    pl->mode = flags;
+    for (int i = 0; i < n; ++i) pl->trees.emplace_back(new TreeApply);
+    {
+        DevArray<uint64_t> miss;
+        prepare(ctx, pl->trees, ops, fs, mixed, false, miss);
+        build_launches(ctx, pl->trees, true, pl->launches);
+        MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    // capture the value phase on a private stream (default priority) and instantiate it
+    hipStream_t cap;
+    MWNS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        try {
+            record_values(pl.get(), cap);
+        } catch (...) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(cap, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            (void)hipStreamDestroy(cap);
+            throw;
+        }
+        e = hipStreamEndCapture(cap, &pl->graph);
+    }
+    (void)hipStreamDestroy(cap);
+    check_hip(e, "capturing the apply graph");
+    MWNS_HIP(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    *out = pl.release();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_plan_execute(mwns_plan* pl) {
+    MWNS_GUARD_BEGIN
+    if (!pl) fail(MWNS_EINVAL, "plan is NULL");
+    MWNS_HIP(hipGraphLaunch(pl->exec, pl->ctx->stream));
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_plan_output(const mwns_plan* pl, int i, const mwns_tree** g) {
+    MWNS_GUARD_BEGIN
+    if (!pl || !g) fail(MWNS_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int)pl->trees.size()) fail(MWNS_EINVAL, "output index out of range");
+    *g = pl->trees[i]->out.get();
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" mwns_status mwns_plan_stats(const mwns_plan* pl, mwns_apply_stats* stats) {
+    MWNS_GUARD_BEGIN
+    if (!pl || !stats) fail(MWNS_EINVAL, "NULL argument");
+    mwns_apply_stats s{};
+    for (auto& a : pl->trees) collect_stats(pl->ctx, *a, pl->mode, s);
+    *stats = s;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+extern "C" void mwns_plan_destroy(mwns_plan* pl) { delete pl; }

@@ -1,0 +1,81 @@
+// Declarations shared by the contraction kernel (contract.hip) and the apply driver (apply.hip).
+// Internal to libmwns.
+#pragma once
+#include "mwns_internal.h"
+
+namespace mwns {
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// One contraction job of a level: a box of coarse displacements, a fine-displacement mask, a
+// term range and the band it belongs to.
+struct Tpl {
+    int lo[3], hi[3];      // coarse displacement box
+    int mlo[3], mhi[3];    // fine displacement mask per dimension
+    int m1, m2;            // inclusive term range
+    int dpart;             // 0: whole band (all children, +), 1: down band (internal children, -)
+    int prec;              // precision class of the job's terms (PREC_*)
+};
+
+// Precision classes of a job.  Every class accumulates into the FP64 output; the reduced ones
+// take their inputs from FP32 or split-BF16 copies of the input bricks and accumulate each
+// mode product in FP32.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16C = 2, PREC_BF16 = 3, NPREC = 4 };
+
+constexpr int NMAX = 4;            // largest box extent per dimension of one job (the driver splits boxes)
+
+// One level of one apply as seen by the contraction kernel.
+struct LevelDesc {
+    const double* Xr;        // real input bricks of the level (the level's own bricks)
+    const double* Xg;        // ghost input bricks
+    const float* Xr32;       // FP32 copies, rows padded to 16: [brick][v1][v2][16]  (or null)
+    const float* Xg32;
+    const u4* Xrb;           // split-BF16 copies: [brick][v1][v2][4 groups] of (4 hi, 4 lo)  (or null)
+    const u4* Xgb;
+    const int32_t* nbr;      // [brick][(2Lr+1)^3] input index, -1 outside the cube
+    const uint8_t* cmask;    // [brick] bit s set when child s is internal
+    const Tpl* tpl;          // jobs of the level
+    const double* Fj;        // F^{j;m,l} of the level [M][NLF][k][k]
+    const double* w;         // weights w_m of the operator
+    double* out;             // output bricks of the level
+    int64_t nreal;
+    int Lr, valid, ntpl, pad;
+};
+
+constexpr int NXCD = 8;            // XCDs of the MI355X; workgroup b is dispatched to XCD b % 8
+
+// Work queues of the persistent launch: counters[8] | begin[8] | end[8] (ints).  Queue x holds
+// the positions [begin[x], end[x]) of the order array; counters start at zero.
+constexpr int QUEUE_INTS = 3 * NXCD;
+
+template <template <int> class Fn, class... Args>
+void dispatch_k(int k, Args&&... args) {
+    switch (k) {
+        case 1: Fn<1>::run(args...); break;
+        case 2: Fn<2>::run(args...); break;
+        case 3: Fn<3>::run(args...); break;
+        case 4: Fn<4>::run(args...); break;
+        case 5: Fn<5>::run(args...); break;
+        case 6: Fn<6>::run(args...); break;
+        case 7: Fn<7>::run(args...); break;
+        case 8: Fn<8>::run(args...); break;
+        default: fail(MWNS_EINVAL, "unsupported k");
+    }
+}
+
+int num_variants();
+int variant_for(const mwns_ctx* ctx, int k);
+
+// Contraction of every listed (level, brick) job.  queues == nullptr: workgroup b takes order[b]
+// (nblocks = number of jobs); otherwise nblocks resident workgroups pull positions from the 8
+// per-XCD queues (their own XCD's first, then the others') until all are drained.
+void launch_contract(int k, int variant, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
+                     int* queues);
+// Workgroups of the variant that fit on the device at once (for the persistent launch).
+int64_t resident_blocks(int k, int variant, int device);
+// FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
+void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
+// *acc += sum of squares of nb bricks.
+void launch_sumsq(int k, hipStream_t st, int64_t nb, const double* X, double* acc);
+
+}  // namespace mwns

@@ -661,6 +661,35 @@ mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const u
     MWNS_GUARD_END
 }
 
+mwns_status mwns_tree_set_leaves(mwns_ctx* ctx, mwns_tree* t, const double* coeffs) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !t || !coeffs) fail(MWNS_EINVAL, "NULL argument");
+    if (t->ctx != ctx) fail(MWNS_EINVAL, "tree belongs to another context");
+    const int k = t->k, k3 = k * k * k, P = 2 * k;
+    std::vector<double> hb(t->coef.n, 0.0);
+    int64_t li = 0;
+    for (int64_t i = 0; i < t->nnodes; ++i) {
+        if (!t->leaf[i]) continue;
+        int64_t brick;
+        int child;
+        node_brick(t, i, &brick, &child);
+        const double* src = coeffs + li++ * k3;
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                for (int c = 0; c < k; ++c) {
+                    const int64_t e = ((int64_t)((child & 1) * k + a) * P + ((child >> 1) & 1) * k + b) * P +
+                                      ((child >> 2) & 1) * k + c;
+                    hb[brick * brick_elems(k) + e] = src[(a * k + b) * k + c];
+                }
+    }
+    t->coef.upload(hb.data(), hb.size(), ctx->stream);
+    DevArray<double> dH = upload_filters(ctx, k);
+    compress_tree(t, dH.p);
+    MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
 mwns_status mwns_tree_get_info(const mwns_tree* t, mwns_tree_info* info) {
     MWNS_GUARD_BEGIN
     if (!t || !info) fail(MWNS_EINVAL, "NULL argument");
