@@ -772,9 +772,12 @@ void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
     MWNS_HIP(hipGetLastError());
 }
 
-// Level descriptors of the contraction kernel (appended to descs) and the cost of every output
-// brick (for the launch order): cost entries are (cost, (descriptor index, brick)).
-void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs, std::vector<std::pair<double, int2>>& cost) {
+// Level descriptors of the contraction kernel (appended to descs) and, per precision class, the
+// cost of every output brick with jobs of that class (for the launch orders): entries are
+// (cost, (descriptor index, brick)).  The FP64 list holds every brick, since its launch writes
+// every output brick.
+void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
+                 std::vector<std::pair<double, int2>> (&cost)[NPREC]) {
     const int k = a.k;
     const int64_t E = brick_elems(k);
     a.desc_base = descs.size();
@@ -812,7 +815,7 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs, std
         for (int64_t b = 0; b < lw.nout; ++b) {
             int64_t pp[3] = {0, 0, 0};
             if (j > 0) key_coords(lw.pk[b], pp);
-            double c = 0.0;
+            double c[NPREC] = {0.0, 0.0, 0.0, 0.0};
             for (const Tpl& t : lw.tpl) {
                 if (t.dpart && lw.cm[b] == 0) continue;
                 double nin[3];
@@ -824,14 +827,15 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs, std
                 if (nin[0] * nin[1] * nin[2] == 0) continue;     // the box lies outside the cube
                 const double nt = t.m2 - t.m1 + 1;
                 const double steps = nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0];
-                c += nt * steps * COST[t.prec];
+                c[t.prec] += nt * steps;
                 const double D2 = 2.0 * k;
                 a.jobs += (int64_t)nt;
                 const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
             }
-            cost.push_back({c, make_int2(di, (int)b)});
+            for (int p = 0; p < NPREC; ++p)
+                if (p == PREC_F64 || c[p] > 0.0) cost[p].push_back({c[p], make_int2(di, (int)b)});
         }
     }
 }
@@ -991,7 +995,7 @@ struct Launches {
     std::vector<LevelDesc> descs;
     DevArray<LevelDesc> ddesc;
     struct Group {
-        int k = 0, variant = 0;
+        int k = 0, variant = 0, prec = PREC_F64;
         int64_t nblocks = 0;
         std::vector<int2> order;
         std::vector<int> queue_init;
@@ -1005,36 +1009,43 @@ void build_launches(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& tree
     std::vector<int> ks;
     for (auto& a : trees)
         if (std::find(ks.begin(), ks.end(), a->k) == ks.end()) ks.push_back(a->k);
-    std::vector<std::vector<std::pair<double, int2>>> costs(ks.size());
+    std::vector<std::array<std::vector<std::pair<double, int2>>, NPREC>> costs(ks.size());
     for (auto& a : trees) {
         const size_t gi = std::find(ks.begin(), ks.end(), a->k) - ks.begin();
-        build_descs(ctx, *a, Lz.descs, costs[gi]);
+        std::vector<std::pair<double, int2>> c[NPREC];
+        build_descs(ctx, *a, Lz.descs, c);
+        for (int p = 0; p < NPREC; ++p) costs[gi][p].insert(costs[gi][p].end(), c[p].begin(), c[p].end());
     }
     Lz.ddesc.reset(ctx, std::max<size_t>(1, Lz.descs.size()));
     Lz.ddesc.upload(Lz.descs.data(), Lz.descs.size(), ctx->stream);
-    Lz.groups.resize(ks.size());
-    for (size_t gi = 0; gi < ks.size(); ++gi) {
-        auto& g = Lz.groups[gi];
-        g.k = ks[gi];
-        g.variant = variant_for(ctx, g.k);
-        make_order(costs[gi], persistent, g.order, g.queue_init);
-        g.dorder.reset(ctx, std::max<size_t>(1, g.order.size()));
-        g.dorder.upload(g.order.data(), g.order.size(), ctx->stream);
-        if (persistent) {
-            g.dqueue.reset(ctx, QUEUE_INTS);
-            g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
-            g.nblocks = std::min<int64_t>((int64_t)g.order.size(), resident_blocks(g.k, g.variant, ctx->device));
-        } else {
-            g.nblocks = (int64_t)g.order.size();
+    Lz.groups.clear();
+    for (size_t gi = 0; gi < ks.size(); ++gi)
+        for (int p = 0; p < NPREC; ++p) {     // FP64 first: its launch writes every output brick
+            if (costs[gi][p].empty()) continue;
+            Lz.groups.emplace_back();
+            auto& g = Lz.groups.back();
+            g.k = ks[gi];
+            g.prec = p;
+            g.variant = variant_for(ctx, g.k);
+            make_order(costs[gi][p], persistent, g.order, g.queue_init);
+            g.dorder.reset(ctx, std::max<size_t>(1, g.order.size()));
+            g.dorder.upload(g.order.data(), g.order.size(), ctx->stream);
+            if (persistent) {
+                g.dqueue.reset(ctx, QUEUE_INTS);
+                g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
+                g.nblocks = std::min<int64_t>((int64_t)g.order.size(), resident_blocks(g.k, g.variant, g.prec, ctx->device));
+            } else {
+                g.nblocks = (int64_t)g.order.size();
+            }
         }
-    }
 }
 
 void launch_contractions(mwns_ctx* ctx, Launches& Lz) {
     for (auto& g : Lz.groups) {
         if (g.order.empty()) continue;
         if (g.dqueue.p) zero_ints_kernel<<<1, 64, 0, ctx->stream>>>(g.dqueue.p, NXCD);
-        launch_contract(g.k, g.variant, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
+        launch_contract(g.k, g.variant, g.prec, g.prec != PREC_F64, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p,
+                        g.dqueue.p);
         MWNS_HIP(hipGetLastError());
     }
 }

@@ -66,13 +66,15 @@ void dispatch_k(int k, Args&&... args) {
 int num_variants();
 int variant_for(const mwns_ctx* ctx, int k);
 
-// Contraction of every listed (level, brick) job.  queues == nullptr: workgroup b takes order[b]
-// (nblocks = number of jobs); otherwise nblocks resident workgroups pull positions from the 8
-// per-XCD queues (their own XCD's first, then the others') until all are drained.
-void launch_contract(int k, int variant, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
-                     int* queues);
-// Workgroups of the variant that fit on the device at once (for the persistent launch).
-int64_t resident_blocks(int k, int variant, int device);
+// The jobs of precision class prec of every listed (level, brick).  queues == nullptr: workgroup
+// b takes order[b] (nblocks = number of listed bricks); otherwise nblocks resident workgroups pull
+// positions from the 8 per-XCD queues (their own XCD's first, then the others') until all are
+// drained.  accumulate: add to the output brick instead of overwriting it.  The tile variant
+// applies to the FP64 class; the reduced classes run in the default shape.
+void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t st, int64_t nblocks,
+                     const LevelDesc* levels, const int2* order, int* queues);
+// Workgroups of that kernel that fit on the device at once (for the persistent launch).
+int64_t resident_blocks(int k, int variant, int prec, int device);
 // FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
 // *acc += sum of squares of nb bricks.

@@ -10,6 +10,7 @@
 //     Y += c w_m sum_{L1} S^{L1} x_1 [ sum_{L2} S^{L2} x_2 [ sum_{L3} S^{L3} x_3 X_{P-L} ] ].
 // 2k <= 16 is padded to one 16 x 16 MFMA tile per dimension.
 #include <algorithm>
+#include <type_traits>
 
 #include "contract.h"
 
@@ -358,9 +359,9 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
 // classes (v_mfma_f32_16x16x32_bf16, lane 16g+n holding K slots 8g..8g+7) give every lane the 4
 // contraction indices 4g..4g+3 as (4 hi | 4 lo) halves, which is exactly what the FP32 mode-3
 // accumulators of the lane hold, so mode 2 again needs no data movement.
-template <int K, int CW, int PF>
-__device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ levels, int2 job, double* smem, int2* steps,
-                                               int* nsteps) {
+template <int K, int CW, int PF, int PREC>
+__device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ levels, int2 job, int accumulate, double* smem,
+                                               int2* steps, int* nsteps) {
     constexpr int D = 2 * K;
     constexpr int TPW = (D + CW - 1) / CW;
     constexpr int64_t E = (int64_t)D * D * D;
@@ -375,10 +376,21 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
     const int NL = 2 * Lr + 1;
     const int32_t* nb = lv.nbr + b * NL * NL * NL;
     const int cmb = lv.cmask[b];
+    double* ob = lv.out + b * E;
+    // this launch's class adds to what the launches of the other classes wrote (accumulate)
     d4 Y[TPW];
-    for (int t = 0; t < TPW; ++t) Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < TPW; ++t) {
+        Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        const int u2 = wave * TPW + t;
+        if (!accumulate || u2 >= D) continue;
+        for (int i = 0; i < 4; ++i) {
+            const int u1 = 4 * i + g, u3 = r;
+            if (u1 < D && u3 < D) Y[t][i] = ob[((int64_t)u1 * D + u2) * D + u3];
+        }
+    }
     for (int ti = 0; ti < lv.ntpl; ++ti) {
         const Tpl tp = lv.tpl[ti];
+        if (tp.prec != PREC) continue;          // another launch's class
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
         const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
         // compact list of the box's in-cube cells: (input index, q1 << 4 | q2 << 2 | q3)
@@ -399,14 +411,8 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
         lds_barrier();
         const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
         if (ns == 0) continue;
-        switch (__builtin_amdgcn_readfirstlane(tp.prec)) {
-            case PREC_F64: run_job<K, CW, PF, PREC_F64>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            case PREC_F32: run_job<K, CW, PF, PREC_F32>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            case PREC_BF16C: run_job<K, CW, PF, PREC_BF16C>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-            default: run_job<K, CW, PF, PREC_BF16>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y); break;
-        }
+        run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
     }
-    double* ob = lv.out + b * E;
     for (int t = 0; t < TPW; ++t) {
         const int u2 = wave * TPW + t;
         if (u2 >= D) break;
@@ -419,14 +425,18 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
     }
 }
 
-template <int K, int CW, int PF, int WPE>
+// One launch per precision class PREC: it runs the jobs of that class only (each class's chain
+// alone keeps the register count low) and, with accumulate set, adds to the output the launches
+// of the other classes wrote.
+template <int K, int CW, int PF, int WPE, int PREC>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
+ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues,
+                int accumulate) {
     __shared__ double smem[SMEM_DOUBLES];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
-        contract_brick<K, CW, PF>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        contract_brick<K, CW, PF, PREC>(levels, order[blockIdx.x], accumulate, smem, steps, &nsteps_s);
         return;
     }
     // persistent: pull positions from this XCD's queue, then from the others; every workgroup
@@ -451,7 +461,7 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0) break;
-        contract_brick<K, CW, PF>(levels, order[pos], smem, steps, &nsteps_s);
+        contract_brick<K, CW, PF, PREC>(levels, order[pos], accumulate, smem, steps, &nsteps_s);
     }
 }
 
@@ -497,46 +507,46 @@ constexpr Variant VARIANTS[] = {{8, 0, 4}, {8, 1, 2}, {8, 2, 2}, {16, 1, 4}, {16
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 constexpr int DEFAULT_VARIANT = 0;   // (8 waves, no prefetch, 4 waves per SIMD): fastest on the k = 8 Poisson workload
 
-template <int K, int V>
-void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
+template <int K, int V, int PREC>
+void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues, int acc) {
     constexpr Variant v = VARIANTS[V];
-    ns_apply_kernel<K, v.cw, v.pf, v.wpe><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, queues);
+    ns_apply_kernel<K, v.cw, v.pf, v.wpe, PREC><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, queues, acc);
 }
 
-template <int K, int V>
+template <int K, int V, int PREC>
 int64_t resident_variant(int device) {
     constexpr Variant v = VARIANTS[V];
     int per_cu = 0, ncu = 0;
-    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_kernel<K, v.cw, v.pf, v.wpe>, 64 * v.cw, 0));
+    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_kernel<K, v.cw, v.pf, v.wpe, PREC>, 64 * v.cw, 0));
     MWNS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     return (int64_t)std::max(1, per_cu) * ncu;
 }
 
+// The FP64 class exists in every tile variant; the reduced classes in the default shape only.
 template <int K>
 struct ApplyLaunch {
-    static void run(hipStream_t st, int variant, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
-        switch (variant) {
-            case 0: launch_variant<K, 0>(st, nblocks, levels, order, queues); break;
-            case 1: launch_variant<K, 1>(st, nblocks, levels, order, queues); break;
-            case 2: launch_variant<K, 2>(st, nblocks, levels, order, queues); break;
-            case 3: launch_variant<K, 3>(st, nblocks, levels, order, queues); break;
-            case 4: launch_variant<K, 4>(st, nblocks, levels, order, queues); break;
-            case 5: launch_variant<K, 5>(st, nblocks, levels, order, queues); break;
-            default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
+    static void run(hipStream_t st, int variant, int prec, int acc, int64_t nblocks, const LevelDesc* levels,
+                    const int2* order, int* queues, int64_t* resident, int device) {
+        auto go = [&](auto vt, auto pt) {
+            constexpr int V = decltype(vt)::value, PR = decltype(pt)::value;
+            if (resident) *resident = resident_variant<K, V, PR>(device);
+            else launch_variant<K, V, PR>(st, nblocks, levels, order, queues, acc);
+        };
+        using I0 = std::integral_constant<int, 0>;
+        switch (prec) {
+            case PREC_F32: go(I0{}, std::integral_constant<int, PREC_F32>{}); return;
+            case PREC_BF16C: go(I0{}, std::integral_constant<int, PREC_BF16C>{}); return;
+            case PREC_BF16: go(I0{}, std::integral_constant<int, PREC_BF16>{}); return;
+            default: break;
         }
-    }
-};
-
-template <int K>
-struct ResidentQuery {
-    static void run(int variant, int device, int64_t* out) {
+        using F = std::integral_constant<int, PREC_F64>;
         switch (variant) {
-            case 0: *out = resident_variant<K, 0>(device); break;
-            case 1: *out = resident_variant<K, 1>(device); break;
-            case 2: *out = resident_variant<K, 2>(device); break;
-            case 3: *out = resident_variant<K, 3>(device); break;
-            case 4: *out = resident_variant<K, 4>(device); break;
-            case 5: *out = resident_variant<K, 5>(device); break;
+            case 0: go(I0{}, F{}); break;
+            case 1: go(std::integral_constant<int, 1>{}, F{}); break;
+            case 2: go(std::integral_constant<int, 2>{}, F{}); break;
+            case 3: go(std::integral_constant<int, 3>{}, F{}); break;
+            case 4: go(std::integral_constant<int, 4>{}, F{}); break;
+            case 5: go(std::integral_constant<int, 5>{}, F{}); break;
             default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
         }
     }
@@ -567,15 +577,16 @@ int variant_for(const mwns_ctx* ctx, int k) {
     return v >= 0 ? v : DEFAULT_VARIANT;
 }
 
-void launch_contract(int k, int variant, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
-                     int* queues) {
+void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t st, int64_t nblocks,
+                     const LevelDesc* levels, const int2* order, int* queues) {
     if (nblocks <= 0) return;
-    dispatch_k<ApplyLaunch>(k, st, variant, nblocks, levels, order, queues);
+    dispatch_k<ApplyLaunch>(k, st, variant, prec, accumulate ? 1 : 0, nblocks, levels, order, queues, (int64_t*)nullptr, 0);
 }
 
-int64_t resident_blocks(int k, int variant, int device) {
+int64_t resident_blocks(int k, int variant, int prec, int device) {
     int64_t n = 0;
-    dispatch_k<ResidentQuery>(k, variant, device, &n);
+    dispatch_k<ApplyLaunch>(k, (hipStream_t) nullptr, variant, prec, 0, (int64_t)0, (const LevelDesc*)nullptr,
+                            (const int2*)nullptr, (int*)nullptr, &n, device);
     return n;
 }
 
