@@ -5,9 +5,12 @@ A step is one pass of the whole path on the Poisson workload with k = 8, eps = 1
 plan, device), adaptive projection to a redundant tree (device), the apply (neighbour closure,
 FP64-MFMA contractions, assembly; device) and evaluation at 1e4 points.  The printed JSON line
 reports NS-apply block-contractions per second of step time, the roofline of the contraction
-kernel (FP64 MFMA) and the CPU oracle timed on a bounded sample of the same apply.
+kernel (FP64 MFMA) and the CPU oracle timed on a bounded sample of the same apply.  Beside it:
+the precision-routed apply against the FP64 one on the same tree at tol = eps ||g|| ("mixed"),
+and the batch of uneven seeded solves applied one by one, as one persistent batched launch and
+as replays of a captured plan ("batch").
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mixed] [--no-batch]
 """
 import argparse
 import json
@@ -29,6 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-vs-FP64 measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-apply measurement")
     ap.add_argument("--cpu-sample-nodes", type=int, default=15000)
     ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -114,6 +118,49 @@ def mixed_measurement(M, ctx, w, f, op, g64, st64, reps):
         "class_flop_share": {c: stm["class_flops"][i] / stm["useful_flops"]
                              for i, c in enumerate(("f64", "f32", "bf16c", "bf16"))},
         "classes": "FP64 MFMA; FP32 MFMA; BF16 MFMA on hi/lo splits (4 partial products); BF16 MFMA"}
+
+
+def batch_measurement(M, ctx, reps, nmembers=64):
+    """The batch of uneven solves (seeded members of mixed kernels, k and eps; members with k > 8
+    are left out): total contractions per second for sequential single applies, one batched
+    persistent apply, and replays of the captured apply plan."""
+    import torch
+    members = [workloads_member(i) for i in range(nmembers)]
+    kept = [w for w in members if w.k <= 8]
+    ops, fs = [], []
+    for w in kept:
+        f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+        depth = M.mwns_tree_get_info(f)["depth"]
+        tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+        ops.append(M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth))
+        fs.append(f)
+    _, st = M.mwns_apply_batch(ctx, ops, fs)
+    plan = M.mwns_plan_create(ctx, ops, fs)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    ms_seq = timed(lambda: [M.mwns_apply(ctx, op, f, stats=False) for op, f in zip(ops, fs)])
+    ms_batch = timed(lambda: M.mwns_apply_batch(ctx, ops, fs, stats=False))
+    ms_plan = timed(plan.execute)
+    plan.close()
+    nodes = sum(M.mwns_tree_get_info(f)["nnodes"] for f in fs)
+    c = st["contractions"]
+    return {"members": len(kept), "members_skipped_k_gt_8": len(members) - len(kept), "nodes": int(nodes),
+            "contractions": int(c), "ms_sequential": ms_seq, "ms_batch": ms_batch, "ms_plan_replay": ms_plan,
+            "contractions_per_s_sequential": c / (ms_seq * 1e-3), "contractions_per_s_batch": c / (ms_batch * 1e-3),
+            "contractions_per_s_plan": c / (ms_plan * 1e-3)}
+
+
+def workloads_member(i):
+    import workloads
+    return workloads.c4_member(i)
 
 
 def cpu_baseline(w, depth, nsample):
@@ -234,6 +281,8 @@ def main():
     }
     if not args.no_mixed:
         line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(M, ctx, w, f, op, g, st, args.steps)
+    if not args.no_batch:
+        line["batch"] = batch_measurement(M, ctx, args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, info["depth"], args.cpu_sample_nodes)
     print(json.dumps(line))

@@ -82,6 +82,7 @@ const char* mwns_last_error(void);
  * bit for bit.  mwns_tune_apply picks one by timing.  Errors: EINVAL (k or variant out of range). */
 int mwns_num_variants(void);
 mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant);
+/* The variant in use for order k (the library's default when none was set). */
 mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* variant);
 
 /* -------------------------------------------------------------- (1) fit */
@@ -251,6 +252,12 @@ mwns_status mwns_apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, co
  * norm stays at most its value at creation.  mwns_plan_stats synchronises.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 typedef struct mwns_plan mwns_plan;
+/* Autotuner: times the FP64 contraction launch of the apply of f by op in every tile variant
+ * (one warm-up and `reps` timed launches each, HIP events on the context's stream), stores the
+ * fastest as the context's variant for f's k and returns it in *best; times_ms (NULL or
+ * mwns_num_variants() doubles) receives the average launch time of each variant.  Synchronises.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_tune_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int reps, int* best, double* times_ms);
 mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
                              const mwns_mixed_opts* mixed, int flags, mwns_plan** out);
 mwns_status mwns_plan_execute(mwns_plan* plan);

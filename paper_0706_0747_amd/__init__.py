@@ -22,7 +22,8 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
-           "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
+           "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
+           "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
@@ -44,6 +45,7 @@ class Context:
 
     def __init__(self, device=0, use_torch=True, byte_budget=0):
         self._keep = []
+        self.device = device
         stream = None
         alloc = _lib.ALLOC_FN()
         free = _lib.FREE_FN()
@@ -199,6 +201,43 @@ def mwns_tree_set_leaves(ctx, tree, coeffs):
     k = info["k"]
     coeffs = _f64(coeffs, (info["nleaves"], k, k, k))
     check(lib.mwns_tree_set_leaves(ctx.h, tree.h, coeffs.ctypes.data), "mwns_tree_set_leaves")
+
+
+def mwns_tune_apply(ctx, op, f, reps=3):
+    """Times every tile variant on this apply, selects the fastest for f's k; returns (best, ms[])."""
+    best = ctypes.c_int(0)
+    t = np.zeros(mwns_num_variants())
+    check(lib.mwns_tune_apply(ctx.h, op.h, f.h, reps, ctypes.byref(best), t.ctypes.data), "mwns_tune_apply")
+    return best.value, t
+
+
+def autotune(ctx, op, f, cache_path=None, reps=3):
+    """Tile variant for f's k: read from the JSON cache at cache_path (keyed by device and k) when
+    present, else measured with mwns_tune_apply and written there.  The choice is set on ctx."""
+    import json
+    import os
+    import torch
+    k = mwns_tree_get_info(f)["k"]
+    key = "%s/k%d" % (torch.cuda.get_device_name(ctx_device(ctx)), k)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache and 0 <= int(cache[key]) < mwns_num_variants():
+        mwns_ctx_set_variant(ctx, k, int(cache[key]))
+        return int(cache[key])
+    best, _ = mwns_tune_apply(ctx, op, f, reps)
+    if cache_path:
+        cache[key] = best
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return best
+
+
+def ctx_device(ctx):
+    return ctx.device
 
 
 def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):

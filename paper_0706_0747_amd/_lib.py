@@ -83,6 +83,7 @@ SIGNATURES = {
     "mwns_plan_stats": (c_int, [c_vp, P(ApplyStats)]),
     "mwns_plan_destroy": (None, [c_vp]),
     "mwns_tree_set_leaves": (c_int, [c_vp, c_vp, c_vp]),
+    "mwns_tune_apply": (c_int, [c_vp, c_vp, c_vp, c_int, P(c_int), c_vp]),
     "mwns_tree_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
 }
 

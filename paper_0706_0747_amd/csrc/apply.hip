@@ -1230,3 +1230,36 @@ extern "C" mwns_status mwns_plan_stats(const mwns_plan* pl, mwns_apply_stats* st
 }
 
 extern "C" void mwns_plan_destroy(mwns_plan* pl) { delete pl; }
+
+extern "C" mwns_status mwns_tune_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int reps, int* best,
+                                       double* times_ms) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !op || !f || !best) fail(MWNS_EINVAL, "NULL argument");
+    if (reps < 1) fail(MWNS_EINVAL, "reps must be >= 1");
+    std::vector<std::unique_ptr<TreeApply>> trees;
+    trees.emplace_back(new TreeApply);
+    DevArray<uint64_t> miss;
+    prepare(ctx, trees, &op, &f, nullptr, true, miss);
+    Launches Lz;
+    build_launches(ctx, trees, false, Lz);
+    launch_zero_outputs(ctx, *trees[0]);
+    const int nv = num_variants();
+    std::vector<double> t(nv, 0.0);
+    Timer tm(ctx->stream);
+    for (int v = 0; v < nv; ++v) {
+        for (auto& g : Lz.groups) g.variant = v;
+        launch_contractions(ctx, Lz);     // warm-up
+        tm.start();
+        for (int r = 0; r < reps; ++r) launch_contractions(ctx, Lz);
+        tm.stop();
+        t[v] = tm.ms() / reps;
+    }
+    int b = 0;
+    for (int v = 1; v < nv; ++v)
+        if (t[v] < t[b]) b = v;
+    ctx->variant[f->k] = b;
+    *best = b;
+    if (times_ms) std::copy(t.begin(), t.end(), times_ms);
+    return MWNS_OK;
+    MWNS_GUARD_END
+}

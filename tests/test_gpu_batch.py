@@ -117,3 +117,19 @@ def test_plan_replays_match_applies(M, ctx, routed):
     st = plan.stats()
     assert st["contractions"] > 0
     plan.close()
+
+
+def test_autotuner_picks_a_variant_and_caches_it(M, tmp_path):
+    """mwns_tune_apply times every tile variant and sets the fastest; the apply after tuning is
+    bit-identical to the default one; autotune() reuses the cached choice."""
+    c = M.Context(0)
+    w, f, op = _member(M, c, MEMBERS[1])
+    ref = M.mwns_tree_export(c, M.mwns_apply(c, op, f)[0])[2]
+    best, times = M.mwns_tune_apply(c, op, f, reps=2)
+    assert 0 <= best < M.mwns_num_variants() and np.all(times > 0.0)
+    assert best == int(np.argmin(times)) and M.mwns_ctx_get_variant(c, w.k) == best
+    assert np.array_equal(M.mwns_tree_export(c, M.mwns_apply(c, op, f)[0])[2], ref)
+    path = str(tmp_path / "tiles.json")
+    v1 = M.autotune(c, op, f, cache_path=path, reps=1)
+    M.mwns_ctx_set_variant(c, w.k, (v1 + 1) % M.mwns_num_variants())
+    assert M.autotune(c, op, f, cache_path=path) == v1 and M.mwns_ctx_get_variant(c, w.k) == v1
