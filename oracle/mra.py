@@ -93,6 +93,12 @@ def crosscorr_coeffs(k):
     Pm = crosscorr(k, u - 1.0)                            # Phi^- at u-1 in [-1,0)
     Cp = np.einsum("i,iab,in->abn", w, Pp, basis)
     Cm = np.einsum("i,iab,in->abn", w, Pm, basis)
+    # Phi^+-_ab has degree a+b+1 on each half (App. A.4): the coefficients of higher degrees are
+    # exactly zero (the quadrature leaves ~1e-15 there, which the large high-degree Gaussian
+    # moments of narrow terms would amplify)
+    a, b, n = np.meshgrid(np.arange(k), np.arange(k), np.arange(2 * k), indexing="ij")
+    Cp[n > a + b + 1] = 0.0
+    Cm[n > a + b + 1] = 0.0
     return Cp, Cm
 
 

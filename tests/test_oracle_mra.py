@@ -136,6 +136,34 @@ def test_F_block_against_direct_2d_quadrature(k, j, tau, l):
     assert np.abs(F - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
 
 
+def _G_adjacent(beta, l):
+    """int_0^1 int_0^1 exp(-beta (u + l - v)^2) du dv for l = 0, 1 (the constant basis pair), by the
+    triangular density of u - v: closed forms through erf."""
+    from scipy.special import erf
+    sb = np.sqrt(beta)
+    if l == 0:
+        return np.sqrt(np.pi / beta) * erf(sb) - (1.0 - np.exp(-beta)) / beta
+    return ((1.0 - np.exp(-beta)) / (2.0 * beta) + np.sqrt(np.pi / beta) * (erf(2.0 * sb) - erf(sb))
+            - (np.exp(-beta) - np.exp(-4.0 * beta)) / (2.0 * beta))
+
+
+@pytest.mark.parametrize("k", [6, 8, 9, 10])
+@pytest.mark.parametrize("j,tau", [(0, 1e3), (2, 1e4), (0, 1e6), (1, 7.1e8), (0, 1e10)])
+def test_F_constant_pair_closed_form(k, j, tau):
+    """F^{j;l}_00 = 2^-j G(tau/4^j, l) with G the closed form of the double integral of the Gaussian
+    over two unit boxes at distance l (eq. KernelFactor with phi_0 = 1): to 1e-14 relative on the
+    diagonal block also for very narrow Gaussians, where every high-degree moment of Phi is large,
+    and to 1e-14 of that diagonal entry (the term's scale) for the neighbour; F^{j;0}_10 = 0 by the
+    reflection x -> 1 - x."""
+    beta = tau / 4.0 ** j
+    F0 = mra.F_block(k, j, tau, 0)
+    ref0 = _G_adjacent(beta, 0) / 2.0 ** j
+    assert abs(F0[0, 0] - ref0) <= 1e-14 * ref0, (F0[0, 0], ref0)
+    F1 = mra.F_block(k, j, tau, 1)
+    assert abs(F1[0, 0] - _G_adjacent(beta, 1) / 2.0 ** j) <= 1e-14 * ref0
+    assert abs(F0[1, 0]) <= 1e-15 * abs(F0[0, 0])
+
+
 @pytest.mark.parametrize("k", [6, 8])
 def test_F_symmetry_and_limits(k):
     D = np.diag((-1.0) ** np.arange(k))
