@@ -13,6 +13,8 @@ Readings ("Readings of the paper"):
     zero-detail reconstruction s^{j+1}_{2l+s} = H^(s)^T s^j.
   * In F^{j;m,l} the displacement is l = l_out - l_in and the row index a is the output degree.
 """
+import functools
+
 import numpy as np
 
 __all__ = ["gauss_legendre01", "phi", "two_scale_filters", "crosscorr",
@@ -80,25 +82,99 @@ def crosscorr(k, x):
     return out
 
 
+def _shifted_legendre(n):
+    """Integer coefficients (ascending powers of x) of P_n(2x - 1) = sum_i (-1)^(n+i) C(n,i) C(n+i,i) x^i."""
+    from math import comb
+    return [(-1) ** (n + i) * comb(n, i) * comb(n + i, i) for i in range(n + 1)]
+
+
+def _poly_mul(p, q):
+    out = [0] * (len(p) + len(q) - 1)
+    for i, a in enumerate(p):
+        for j, b in enumerate(q):
+            out[i + j] += a * b
+    return out
+
+
+def _poly_shift(p, c):
+    """Coefficients of p(x + c) for rational c."""
+    from math import comb
+    out = [0] * len(p)
+    for i, a in enumerate(p):
+        for j in range(i + 1):
+            out[j] += a * comb(i, j) * c ** (i - j)
+    return out
+
+
+def _cross_rational(a, b, plus):
+    """Rational coefficients (ascending powers of x) of Q_ab with Phi_ab = sqrt((2a+1)(2b+1)) Q_ab:
+        plus : Q(x) = int_0^{1-x} P~_a(x+y) P~_b(y) dy            (x in [0,1])
+        minus: Q(x) = int_{-x}^{1} P~_a(x+y) P~_b(y) dy           (x in [-1,0])
+    with P~_n(t) = P_n(2t-1) (App. A.4, eqs. CrossCor, crosscor.01).  The integrand is expanded as
+    a polynomial in (x, y), integrated in y exactly and the bounds substituted."""
+    from fractions import Fraction
+    pa, pb = _shifted_legendre(a), _shifted_legendre(b)
+    # P~_a(x + y) = sum_i pa_i (x+y)^i = sum_{r,s} c_rs x^r y^s
+    from math import comb
+    terms = {}
+    for i, ca in enumerate(pa):
+        for r in range(i + 1):
+            for sy, cb in enumerate(pb):
+                key = (r, i - r + sy)
+                terms[key] = terms.get(key, 0) + ca * comb(i, r) * cb
+    # int y^s dy = y^(s+1)/(s+1) between the bounds; bounds are polynomials in x
+    lo = [Fraction(0)] if plus else [Fraction(0), Fraction(-1)]          # 0  or  -x
+    hi = [Fraction(1), Fraction(-1)] if plus else [Fraction(1)]          # 1-x or 1
+    out = [Fraction(0)] * (a + b + 2)
+    for (r, sy), c in terms.items():
+        ph = [Fraction(1)]
+        pl = [Fraction(1)]
+        for _ in range(sy + 1):
+            ph = _poly_mul(ph, hi)
+            pl = _poly_mul(pl, lo)
+        diff = [(ph[i] if i < len(ph) else 0) - (pl[i] if i < len(pl) else 0) for i in range(max(len(ph), len(pl)))]
+        for i, d in enumerate(diff):
+            if d:
+                out[r + i] += Fraction(c) * d / (sy + 1)
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _crosscorr_coeffs_cached(k):
+    return _crosscorr_coeffs_exact(k)
+
+
 def crosscorr_coeffs(k):
-    """Exact expansion of Phi^+ and Phi^- in Legendre scaling functions of degree < 2k
-    (they are polynomials of degree a+b+1 <= 2k-1 on each half, App. A.4):
+    """Cp, Cm of _crosscorr_coeffs_exact (cached per k; fresh copies)."""
+    Cp, Cm = _crosscorr_coeffs_cached(k)
+    return Cp.copy(), Cm.copy()
+
+
+def _crosscorr_coeffs_exact(k):
+    """Expansion of Phi^+ and Phi^- in Legendre scaling functions of degree < 2k (App. A.4: they
+    are polynomials of degree a+b+1 <= 2k-1 on each half):
         Phi^+_ab(x)  = sum_n Cp[a,b,n] phi_n(x)     on [0,1]
         Phi^-_ab(x)  = sum_n Cm[a,b,n] phi_n(x+1)   on [-1,0]
-    The coefficients are inner products with phi_n computed by the 2k-point rule (exact for
-    degree <= 4k-1) from values given by crosscorr()."""
-    u, w = gauss_legendre01(2 * k)
-    basis = phi(2 * k, u)                                 # (2k nodes, 2k)
-    Pp = crosscorr(k, u)                                  # Phi^+ at u in [0,1]
-    Pm = crosscorr(k, u - 1.0)                            # Phi^- at u-1 in [-1,0)
-    Cp = np.einsum("i,iab,in->abn", w, Pp, basis)
-    Cm = np.einsum("i,iab,in->abn", w, Pm, basis)
-    # Phi^+-_ab has degree a+b+1 on each half (App. A.4): the coefficients of higher degrees are
-    # exactly zero (the quadrature leaves ~1e-15 there, which the large high-degree Gaussian
-    # moments of narrow terms would amplify)
-    a, b, n = np.meshgrid(np.arange(k), np.arange(k), np.arange(2 * k), indexing="ij")
-    Cp[n > a + b + 1] = 0.0
-    Cm[n > a + b + 1] = 0.0
+    computed in exact rational arithmetic (Phi_ab = sqrt((2a+1)(2b+1)) Q_ab, phi_n =
+    sqrt(2n+1) P~_n, int_0^1 x^i dx = 1/(i+1)); only the final square-root factor is rounded, so
+    coefficients of degree above a+b+1 are exactly zero and the others carry no quadrature noise
+    (narrow Gaussian terms weight every coefficient with moments far larger than the block)."""
+    from fractions import Fraction
+    Cp = np.zeros((k, k, 2 * k))
+    Cm = np.zeros((k, k, 2 * k))
+    pl = [_shifted_legendre(n) for n in range(2 * k)]
+    for a in range(k):
+        for b in range(k):
+            qp = _cross_rational(a, b, True)
+            qm = _poly_shift(_cross_rational(a, b, False), Fraction(-1))   # as a polynomial in z = x + 1
+            for n in range(min(a + b + 2, 2 * k)):
+                prod_p = _poly_mul(qp, pl[n])
+                prod_m = _poly_mul(qm, pl[n])
+                ip = sum(Fraction(c) / (i + 1) for i, c in enumerate(prod_p))
+                im = sum(Fraction(c) / (i + 1) for i, c in enumerate(prod_m))
+                sc = np.sqrt(float((2 * a + 1) * (2 * b + 1) * (2 * n + 1)))
+                Cp[a, b, n] = float(ip) * sc
+                Cm[a, b, n] = float(im) * sc
     return Cp, Cm
 
 

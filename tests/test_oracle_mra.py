@@ -136,6 +136,20 @@ def test_F_block_against_direct_2d_quadrature(k, j, tau, l):
     assert np.abs(F - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("k", [2, 6, 10])
+def test_crosscorr_coefficients_reproduce_phi(k):
+    """The exact rational expansion of Phi^+- (App. A.4) reproduces Phi_ab(x) evaluated by the
+    independent Gauss-Legendre integration in crosscorr(), on both halves; coefficients above
+    degree a+b+1 are exactly zero."""
+    Cp, Cm = mra.crosscorr_coeffs(k)
+    x = np.linspace(0.003, 0.997, 11)
+    basis = mra.phi(2 * k, x)
+    assert np.abs(np.einsum("abn,in->iab", Cp, basis) - mra.crosscorr(k, x)).max() < 1e-14
+    assert np.abs(np.einsum("abn,in->iab", Cm, basis) - mra.crosscorr(k, x - 1.0)).max() < 1e-14
+    a, b, n = np.meshgrid(np.arange(k), np.arange(k), np.arange(2 * k), indexing="ij")
+    assert np.all(Cp[n > a + b + 1] == 0.0) and np.all(Cm[n > a + b + 1] == 0.0)
+
+
 def _G_adjacent(beta, l):
     """int_0^1 int_0^1 exp(-beta (u + l - v)^2) du dv for l = 0, 1 (the constant basis pair), by the
     triangular density of u - v: closed forms through erf."""
