@@ -23,7 +23,9 @@
  *  - All device work of a context is ordered on the context's stream.  Calls that return host
  *    data synchronise that stream before returning.  A context is not thread-safe: use one
  *    context per host thread.
- *  - Orders and sizes: 1 <= k <= 8 (basis order = number of Legendre polynomials per dimension);
+ *  - Orders and sizes: 1 <= k <= 10 (basis order = number of Legendre polynomials per dimension;
+ *    k <= 8 runs on the one-tile contraction kernel with every precision class and tile variant,
+ *    9 <= k <= 10 on the two-tile kernel in FP64 only, whose routed applies keep every job FP64);
  *    tree levels 0..19.  Coefficient blocks are [a][b][c] with a the x degree, b the y degree and
  *    c the z degree (c fastest).  Keys are level << 57 | morton(lx, ly, lz) with the x bit lowest
  *    in each bit triple; a tree's canonical node order is ascending key.

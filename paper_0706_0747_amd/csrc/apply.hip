@@ -720,7 +720,8 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             }
         }
     }
-    a.err_bound = route(items, opts.tol, opts.classes);
+    // orders above 8 have no reduced-precision kernels: every job stays FP64
+    a.err_bound = route(items, opts.tol, a.k > KNARROW ? 0 : opts.classes);
     size_t pos = 0;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
@@ -833,6 +834,10 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
+            }
+            if (k > KNARROW) {    // two-tile kernel: one job per column half of the brick
+                for (int half = 0; half < 2; ++half) cost[PREC_F64].push_back({c[PREC_F64], make_int2(di, (int)(2 * b + half))});
+                continue;
             }
             for (int p = 0; p < NPREC; ++p)
                 if (p == PREC_F64 || c[p] > 0.0) cost[p].push_back({c[p], make_int2(di, (int)b)});
@@ -1033,7 +1038,9 @@ void build_launches(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& tree
             if (persistent) {
                 g.dqueue.reset(ctx, QUEUE_INTS);
                 g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
-                g.nblocks = std::min<int64_t>((int64_t)g.order.size(), resident_blocks(g.k, g.variant, g.prec, ctx->device));
+                const int64_t res = g.k > KNARROW ? resident_blocks_wide(g.k, ctx->device)
+                                                  : resident_blocks(g.k, g.variant, g.prec, ctx->device);
+                g.nblocks = std::min<int64_t>((int64_t)g.order.size(), res);
             } else {
                 g.nblocks = (int64_t)g.order.size();
             }
@@ -1044,8 +1051,10 @@ void launch_contractions(mwns_ctx* ctx, Launches& Lz) {
     for (auto& g : Lz.groups) {
         if (g.order.empty()) continue;
         if (g.dqueue.p) zero_ints_kernel<<<1, 64, 0, ctx->stream>>>(g.dqueue.p, NXCD);
-        launch_contract(g.k, g.variant, g.prec, g.prec != PREC_F64, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p,
-                        g.dqueue.p);
+        if (g.k > KNARROW) launch_contract_wide(g.k, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
+        else
+            launch_contract(g.k, g.variant, g.prec, g.prec != PREC_F64, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p,
+                            g.dqueue.p);
         MWNS_HIP(hipGetLastError());
     }
 }

@@ -59,6 +59,8 @@ void dispatch_k(int k, Args&&... args) {
         case 6: Fn<6>::run(args...); break;
         case 7: Fn<7>::run(args...); break;
         case 8: Fn<8>::run(args...); break;
+        case 9: Fn<9>::run(args...); break;
+        case 10: Fn<10>::run(args...); break;
         default: fail(MWNS_EINVAL, "unsupported k");
     }
 }
@@ -75,6 +77,10 @@ void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t 
                      const LevelDesc* levels, const int2* order, int* queues);
 // Workgroups of that kernel that fit on the device at once (for the persistent launch).
 int64_t resident_blocks(int k, int variant, int prec, int device);
+// The two-tile kernel for KNARROW < k <= KMAX (FP64 only): order[] entries are (level
+// descriptor, 2 * brick + column half), each half a separate workgroup job.
+void launch_contract_wide(int k, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues);
+int64_t resident_blocks_wide(int k, int device);
 // FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
 // *acc += sum of squares of nb bricks.

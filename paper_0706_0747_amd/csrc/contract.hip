@@ -574,24 +574,39 @@ int num_variants() { return NVARIANTS; }
 
 int variant_for(const mwns_ctx* ctx, int k) {
     const int v = ctx->variant[k];
-    return v >= 0 ? v : DEFAULT_VARIANT;
+    return k > KNARROW ? 0 : (v >= 0 ? v : DEFAULT_VARIANT);
+}
+
+template <template <int> class Fn, class... Args>
+void dispatch_narrow(int k, Args&&... args) {
+    switch (k) {
+        case 1: Fn<1>::run(args...); break;
+        case 2: Fn<2>::run(args...); break;
+        case 3: Fn<3>::run(args...); break;
+        case 4: Fn<4>::run(args...); break;
+        case 5: Fn<5>::run(args...); break;
+        case 6: Fn<6>::run(args...); break;
+        case 7: Fn<7>::run(args...); break;
+        case 8: Fn<8>::run(args...); break;
+        default: fail(MWNS_EINVAL, "the one-tile contraction kernel takes k <= 8");
+    }
 }
 
 void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t st, int64_t nblocks,
                      const LevelDesc* levels, const int2* order, int* queues) {
     if (nblocks <= 0) return;
-    dispatch_k<ApplyLaunch>(k, st, variant, prec, accumulate ? 1 : 0, nblocks, levels, order, queues, (int64_t*)nullptr, 0);
+    dispatch_narrow<ApplyLaunch>(k, st, variant, prec, accumulate ? 1 : 0, nblocks, levels, order, queues, (int64_t*)nullptr, 0);
 }
 
 int64_t resident_blocks(int k, int variant, int prec, int device) {
     int64_t n = 0;
-    dispatch_k<ApplyLaunch>(k, (hipStream_t) nullptr, variant, prec, 0, (int64_t)0, (const LevelDesc*)nullptr,
+    dispatch_narrow<ApplyLaunch>(k, (hipStream_t) nullptr, variant, prec, 0, (int64_t)0, (const LevelDesc*)nullptr,
                             (const int2*)nullptr, (int*)nullptr, &n, device);
     return n;
 }
 
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
-    dispatch_k<ConvertLaunch>(k, st, nb, X, out, bf);
+    dispatch_narrow<ConvertLaunch>(k, st, nb, X, out, bf);
 }
 
 void launch_sumsq(int k, hipStream_t st, int64_t nb, const double* X, double* acc) {
@@ -609,6 +624,7 @@ extern "C" mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant) {
     if (!ctx) fail(MWNS_EINVAL, "ctx is NULL");
     if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
     if (variant < -1 || variant >= NVARIANTS) fail(MWNS_EINVAL, "variant out of range");
+    if (k > KNARROW && variant > 0) fail(MWNS_EINVAL, "orders above 8 have a single tile shape (variant 0)");
     ctx->variant[k] = variant;
     return MWNS_OK;
     MWNS_GUARD_END

@@ -1,0 +1,304 @@
+// The contraction kernel of the apply for 8 < k <= 10 (2k in (16, 20]), FP64 MFMA.
+//
+// Same method as contract.hip (sibling-group bricks, 2k x 2k super-blocks S^{j;m,L} per
+// dimension, the nested-loop factorisation of Sec. 5 over boxes of coarse displacements, the
+// coefficient rule c_m = [m in R_j(L)] - [b internal][m in R_{j+1}(l)]), with every dimension of
+// the brick covered by two 16-wide MFMA tiles: v_mfma_f64_16x16x4 (A[m][k] in lane m+16k, B[k][n]
+// in lane n+16k, D[4i+g][n] in lane 16g+n, register i).  A workgroup computes one half of the
+// output columns u3 (16c .. 16c+15) of one output brick; 10 waves own two input slices v1 each.
+//   mode 3, per slice and row tile a (v2 = 16a + r): contraction over v3 in five K-steps
+//     (v3 = 4g + s for s < 4 from four consecutive doubles, then v3 = 16 + g);
+//   mode 2, per row tile b of u2, straight from the mode-3 accumulators: tile a = 0 register i
+//     holds v2 = 4i + g, tile a = 1 register 0 holds v2 = 16 + g -- again five K-steps;
+//   mode 1 through an LDS transpose of the mode-2 result, five K-steps over v1.
+#include <algorithm>
+
+#include "contract.h"
+
+namespace mwns {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int WCW = 10;            // waves per workgroup
+constexpr int WCT = 64 * WCW;
+constexpr int WS3_V = 36;          // LDS stride of the staged mode-3 operand [L][v3][u3 of this half]
+constexpr int WSA_V = 48;          // LDS stride of the staged mode-2 / mode-1 operands [L][v][u < 32]
+
+template <int K>
+struct Wide {
+    static constexpr int D = 2 * K;
+    static constexpr int TPW = (D + WCW - 1) / WCW;
+    static constexpr int T2_V1 = D * 16 + 16;     // LDS stride of the mode-2 result [v1][u2][16]
+    static constexpr int SM_T2 = D * T2_V1;
+    static constexpr int SM_S3 = NMAX * D * WS3_V;
+    static constexpr int SM_SA = NMAX * D * WSA_V;
+    static constexpr int SMEM = SM_T2 + SM_S3 + 2 * SM_SA;
+    static_assert(D > 16 && D <= 20, "two tiles per dimension with the fifth K-step covering 16..19");
+};
+
+// Masked super-block entry S^{m,L}[u][v] (rows: output u = su*K + a; columns: input v); zero
+// outside the 2K extent and outside the fine-displacement mask [mlo, mhi].
+template <int K>
+__device__ inline double wsop(const double* __restrict__ Fm, int L, int mlo, int mhi, int u, int v) {
+    if (u >= 2 * K || v >= 2 * K) return 0.0;
+    const int su = u >= K, sv = v >= K;
+    const int l = 2 * L + su - sv;
+    if (l < mlo || l > mhi) return 0.0;
+    return Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
+}
+
+__device__ inline void wlds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int K>
+__device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict__ levels, int2 job, double* smem,
+                                                    int2* steps, int* nsteps) {
+    using W = Wide<K>;
+    constexpr int D = W::D, TPW = W::TPW;
+    constexpr bool FULL = (WCW * TPW == D);
+    constexpr int64_t E = (int64_t)D * D * D;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const LevelDesc lv = levels[job.x];
+    const int64_t b = job.y >> 1;
+    const int c = job.y & 1;                        // output columns u3 = 16c + r
+    const double* __restrict__ w = lv.w;
+    const int Lr = lv.Lr;
+    const int NL = 2 * Lr + 1;
+    const int32_t* nb = lv.nbr + b * NL * NL * NL;
+    const int cmb = lv.cmask[b];
+    double* T2s = smem;
+    double* S3s = smem + W::SM_T2;
+    double* S2s = S3s + W::SM_S3;
+    double* S1s = S2s + W::SM_SA;
+    // byte offsets of lane (g, r)'s loads in a brick: four doubles X[v1][16a + r][4g..4g+3] and
+    // one double X[v1][16a + r][16 + g]; invalid ones point past the buffer (the load returns 0)
+    uint32_t off4[TPW][2], off1[TPW][2];
+    for (int t = 0; t < TPW; ++t)
+        for (int a = 0; a < 2; ++a) {
+            const int v1 = wave * TPW + t, v2 = 16 * a + r;
+            const bool ok = v1 < D && v2 < D;
+            off4[t][a] = ok ? (uint32_t)(((v1 * D + v2) * D + 4 * g) * 8) : 0x40000000u;
+            off1[t][a] = ok && 16 + g < D ? (uint32_t)(((v1 * D + v2) * D + 16 + g) * 8) : 0x40000000u;
+        }
+    d4 Y[TPW][2];
+    for (int t = 0; t < TPW; ++t) Y[t][0] = Y[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int ti = 0; ti < lv.ntpl; ++ti) {
+        const Tpl tp = lv.tpl[ti];
+        if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
+        const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+        wlds_barrier();
+        if (threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            int idx = -1, q1 = 0, q2 = 0, q3 = 0;
+            if (t < n1 * n2 * n3) {
+                q1 = t / (n2 * n3);
+                q2 = (t / n3) % n2;
+                q3 = t % n3;
+                idx = nb[((tp.lo[0] + q1 + Lr) * NL + (tp.lo[1] + q2 + Lr)) * NL + tp.lo[2] + q3 + Lr];
+            }
+            const unsigned long long in = __ballot(idx >= 0);
+            if (idx >= 0) steps[__popcll(in & ((1ull << t) - 1ull))] = make_int2(idx, (q1 << 4) | (q2 << 2) | q3);
+            if (t == 0) *nsteps = __popcll(in);
+        }
+        wlds_barrier();
+        const int ns = __builtin_amdgcn_readfirstlane(*nsteps);
+        if (ns == 0) continue;
+        const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
+        int m = tp.m1, si = 0;
+        d4 T1[TPW][2], T2[TPW][2];
+        for (int t = 0; t < TPW; ++t) T1[t][0] = T1[t][1] = T2[t][0] = T2[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < total; ++s) {
+            if (si == 0) {
+                // stage this term's masked super-blocks (cw folded into S1): S1, S2 as [L][v][u < 32],
+                // S3 as [L][v3][u3 of this half]
+                const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+                const double cw = tp.dpart ? -w[m] : w[m];
+                const int nA = (n1 + n2) * D * 32, nS3 = n3 * D * 16;
+                for (int e = threadIdx.x; e < nA + nS3; e += WCT) {
+                    if (e < nA) {
+                        const int u = e & 31, v = (e >> 5) % D, sb = (e >> 5) / D;
+                        if (sb < n1) S1s[(sb * D + v) * WSA_V + u] = cw * wsop<K>(Fm, tp.lo[0] + sb, tp.mlo[0], tp.mhi[0], u, v);
+                        else {
+                            const int q = sb - n1;
+                            S2s[(q * D + v) * WSA_V + u] = wsop<K>(Fm, tp.lo[1] + q, tp.mlo[1], tp.mhi[1], u, v);
+                        }
+                    } else {
+                        const int e3 = e - nA;
+                        const int ul = e3 & 15, v = (e3 >> 4) % D, q = (e3 >> 4) / D;
+                        S3s[(q * D + v) * WS3_V + ul] = wsop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], 16 * c + ul, v);
+                    }
+                }
+                wlds_barrier();
+            }
+            const int2 st = steps[si];
+            const int idx = __builtin_amdgcn_readfirstlane(st.x);
+            const int cell = __builtin_amdgcn_readfirstlane(st.y);
+            const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
+            const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
+            const double* X = idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)(E * 8), 0x00020000);
+            // mode 3: T1 += X x_3 S3^{L3}
+            {
+                double s3[5];
+                for (int kk = 0; kk < 4; ++kk) s3[kk] = S3s[(q3 * D + 4 * g + kk) * WS3_V + r];
+                s3[4] = 16 + g < D ? S3s[(q3 * D + 16 + g) * WS3_V + r] : 0.0;
+                typedef double dv2 __attribute__((ext_vector_type(2)));
+                for (int t = 0; t < TPW; ++t) {
+                    if (!FULL && wave * TPW + t >= D) break;
+                    for (int a = 0; a < 2; ++a) {
+                        const dv2 x01 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a], 0, 0));
+                        const dv2 x23 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a] + 16, 0, 0));
+                        const double x4 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off1[t][a], 0, 0));
+                        d4 acc = T1[t][a];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x01.x, s3[0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x01.y, s3[1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x23.x, s3[2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x23.y, s3[3], acc, 0, 0, 0);
+                        T1[t][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(x4, s3[4], acc, 0, 0, 0);
+                    }
+                }
+            }
+            if (next < 0 || (next >> 2) != (cell >> 2)) {
+                // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
+                for (int bt = 0; bt < 2; ++bt) {
+                    double s2[5];
+                    for (int i = 0; i < 4; ++i) s2[i] = S2s[(q2 * D + 4 * i + g) * WSA_V + 16 * bt + r];
+                    s2[4] = 16 + g < D ? S2s[(q2 * D + 16 + g) * WSA_V + 16 * bt + r] : 0.0;
+                    for (int t = 0; t < TPW; ++t) {
+                        if (!FULL && wave * TPW + t >= D) break;
+                        d4 acc = T2[t][bt];
+                        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][0][i], acc, 0, 0, 0);
+                        T2[t][bt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[4], T1[t][1][0], acc, 0, 0, 0);
+                    }
+                }
+                for (int t = 0; t < TPW; ++t) T1[t][0] = T1[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+            }
+            if (next < 0 || (next >> 4) != (cell >> 4)) {
+                // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
+                for (int t = 0; t < TPW; ++t) {
+                    const int v1 = wave * TPW + t;
+                    if (!FULL && v1 >= D) break;
+                    for (int bt = 0; bt < 2; ++bt)
+                        for (int i = 0; i < 4; ++i) {
+                            const int u2 = 16 * bt + 4 * i + g;
+                            if (u2 < D) T2s[v1 * W::T2_V1 + u2 * 16 + r] = T2[t][bt][i];
+                        }
+                }
+                wlds_barrier();
+                for (int t = 0; t < TPW; ++t) {
+                    const int u2 = wave * TPW + t;
+                    if (!FULL && u2 >= D) break;
+                    double bv[5];
+                    for (int kk = 0; kk < 4; ++kk) bv[kk] = T2s[(4 * kk + g) * W::T2_V1 + u2 * 16 + r];
+                    bv[4] = 16 + g < D ? T2s[(16 + g) * W::T2_V1 + u2 * 16 + r] : 0.0;
+                    for (int bt = 0; bt < 2; ++bt) {
+                        // the down band reaches only internal children: accumulate it apart, add it masked
+                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t][bt];
+                        for (int kk = 0; kk < 4; ++kk)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + 16 * bt + r], bv[kk], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + 16 * bt + r] : 0.0,
+                                                                   bv[4], acc, 0, 0, 0);
+                        if (tp.dpart) {
+                            for (int i = 0; i < 4; ++i) {
+                                const int u1 = 16 * bt + 4 * i + g, u3 = 16 * c + r;
+                                const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+                                if ((cmb >> child) & 1) Y[t][bt][i] += acc[i];
+                            }
+                        } else {
+                            Y[t][bt] = acc;
+                        }
+                    }
+                }
+                for (int t = 0; t < TPW; ++t) T2[t][0] = T2[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+                wlds_barrier();
+            }
+            if (++si == ns) {
+                si = 0;
+                ++m;
+            }
+        }
+    }
+    double* ob = lv.out + b * E;
+    const int u3 = 16 * c + r;
+    for (int t = 0; t < TPW; ++t) {
+        const int u2 = wave * TPW + t;
+        if (u2 >= D || u3 >= D) break;
+        for (int bt = 0; bt < 2; ++bt)
+            for (int i = 0; i < 4; ++i) {
+                const int u1 = 16 * bt + 4 * i + g;
+                if (u1 >= D) continue;
+                const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+                ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][bt][i] : 0.0;
+            }
+    }
+}
+
+// order[] entries are (level descriptor, 2 * brick + column half).  queues: as the one-tile kernel.
+template <int K>
+__global__ void __launch_bounds__(WCT) __attribute__((amdgpu_waves_per_eu(3, 3)))
+ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
+    __shared__ double smem[Wide<K>::SMEM];
+    __shared__ int2 steps[NMAX * NMAX * NMAX];
+    __shared__ int nsteps_s, pos_s;
+    if (!queues) {
+        contract_brick_wide<K>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        return;
+    }
+    const int x0 = blockIdx.x % NXCD;
+    int tried = 0;   // meaningful in thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int pos = -1;
+            while (tried < NXCD) {
+                const int q = (x0 + tried) % NXCD;
+                const int i = atomicAdd(&queues[q], 1);
+                if (queues[NXCD + q] + i < queues[2 * NXCD + q]) {
+                    pos = queues[NXCD + q] + i;
+                    break;
+                }
+                ++tried;
+            }
+            pos_s = pos;
+        }
+        __syncthreads();
+        const int pos = pos_s;
+        __syncthreads();
+        if (pos < 0) break;
+        contract_brick_wide<K>(levels, order[pos], smem, steps, &nsteps_s);
+    }
+}
+
+template <int K>
+void launch_wide_k(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
+    ns_apply_wide_kernel<K><<<(unsigned)nblocks, WCT, 0, st>>>(levels, order, queues);
+}
+
+template <int K>
+int64_t resident_wide_k(int device) {
+    int per_cu = 0, ncu = 0;
+    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_wide_kernel<K>, WCT, 0));
+    MWNS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+    return (int64_t)std::max(1, per_cu) * ncu;
+}
+
+}  // namespace
+
+void launch_contract_wide(int k, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
+    if (nblocks <= 0) return;
+    switch (k) {
+        case 9: launch_wide_k<9>(st, nblocks, levels, order, queues); break;
+        case 10: launch_wide_k<10>(st, nblocks, levels, order, queues); break;
+        default: fail(MWNS_EINVAL, "the two-tile contraction kernel takes 8 < k <= 10");
+    }
+}
+
+int64_t resident_blocks_wide(int k, int device) {
+    switch (k) {
+        case 9: return resident_wide_k<9>(device);
+        case 10: return resident_wide_k<10>(device);
+        default: fail(MWNS_EINVAL, "the two-tile contraction kernel takes 8 < k <= 10");
+    }
+}
+
+}  // namespace mwns

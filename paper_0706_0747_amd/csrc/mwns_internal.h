@@ -11,7 +11,8 @@
 
 namespace mwns {
 
-constexpr int KMAX = 8;          // largest basis order handled by the brick kernels (2k <= 16)
+constexpr int KMAX = 10;         // largest basis order (2k <= 16: one MFMA tile per dimension; above: two)
+constexpr int KNARROW = 8;       // largest order of the one-tile contraction kernel
 constexpr int LF = 7;            // 1-D blocks are tabulated for l = -LF..LF
 constexpr int NLF = 2 * LF + 1;
 constexpr int LP = 3;            // the plan covers coarse displacements |L_d| <= LP

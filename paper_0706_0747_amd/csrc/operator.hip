@@ -119,7 +119,7 @@ __global__ void combine_kernel(int k, int M, int nlev, const double* __restrict_
 }
 
 // Frobenius norms of the super-blocks for scales 1..nlev-1, |L| = 0..LP: one 64-lane block per
-// (j, m, L), lane (a, b) owns entry (a, b) of each of the four k x k sub-blocks; U is formed as
+// (j, m, L), lane e owns entries e, e+64, .. of each of the four k x k sub-blocks; U is formed as
 // H^{so T} (F^{j-1;m,L} H^{si}).  Block 0 of the grid also writes nf0[m] = ||F^{0;m,0}||_F.
 __global__ void __launch_bounds__(64) norms_kernel(int k, int M, int nlev, const double* __restrict__ F,
                                                    const double* __restrict__ H, double* __restrict__ norms,
@@ -145,17 +145,19 @@ __global__ void __launch_bounds__(64) norms_kernel(int k, int M, int nlev, const
     for (int e = lane; e < 2 * kk; e += 64) Hs[e] = H[e];
     for (int e = lane; e < kk; e += 64) Fc[e] = Fcg[e];
     __syncthreads();
-    const int a = lane / k, b = lane % k;
-    const bool act = lane < kk;
-    if (act)
+    // lane owns the entries (a, b) = divmod(e, k) for e = lane, lane + 64, ... (one entry for k <= 8)
+    for (int e = lane; e < kk; e += 64) {
+        const int a = e / k, b = e % k;
         for (int si = 0; si < 2; ++si) {            // T[si][a][b] = sum_q F[a][q] H^si[q][b]
             double t = 0.0;
             for (int q = 0; q < k; ++q) t += Fc[a * k + q] * Hs[si * kk + q * k + b];
             T[si][a * k + b] = t;
         }
+    }
     __syncthreads();
     double sF = 0.0, sU = 0.0, sD = 0.0;
-    if (act)
+    for (int e = lane; e < kk; e += 64) {
+        const int a = e / k, b = e % k;
         for (int so = 0; so < 2; ++so)
             for (int si = 0; si < 2; ++si) {
                 double u = 0.0;                     // (H^so^T F^{j-1;L} H^si)_ab
@@ -165,6 +167,7 @@ __global__ void __launch_bounds__(64) norms_kernel(int k, int M, int nlev, const
                 sU += u * u;
                 sD += (f - u) * (f - u);
             }
+    }
     red[0][lane] = sF;
     red[1][lane] = sU;
     red[2][lane] = sD;
@@ -258,7 +261,7 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
                            const mwns_op_opts* opts, mwns_op** out) {
     MWNS_GUARD_BEGIN
     if (!ctx || !out || !tau || !w) fail(MWNS_EINVAL, "NULL argument");
-    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, 8]");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, " + std::to_string(KMAX) + "]");
     if (M < 1 || max_level < 0 || max_level > MAXLEV || !(eps > 0.0)) fail(MWNS_EINVAL, "M, max_level or eps out of range");
     for (int m = 0; m < M; ++m)
         if (!(tau[m] > 0.0) || !(w[m] >= 0.0) || !std::isfinite(tau[m]) || !std::isfinite(w[m]))

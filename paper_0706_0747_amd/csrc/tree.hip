@@ -317,6 +317,8 @@ void dispatch_k(int k, Args&&... args) {
         case 6: Fn<6>::run(args...); break;
         case 7: Fn<7>::run(args...); break;
         case 8: Fn<8>::run(args...); break;
+        case 9: Fn<9>::run(args...); break;
+        case 10: Fn<10>::run(args...); break;
         default: fail(MWNS_EINVAL, "unsupported k");
     }
 }
@@ -479,7 +481,7 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
                                    const double* a, const double* c, mwns_tree** out) {
     MWNS_GUARD_BEGIN
     if (!ctx || !out || !xyz || !a || !c) fail(MWNS_EINVAL, "NULL argument");
-    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, 8]");
+    if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k must be in [1, " + std::to_string(KMAX) + "]");
     if (j0 < 0 || jmax < j0 || jmax > MAXLEV || !(eps > 0.0) || n < 1) fail(MWNS_EINVAL, "j0, jmax, eps or n out of range");
     for (int i = 0; i < n; ++i)
         if (!(a[i] > 0.0) || !std::isfinite(c[i]) || !std::isfinite(xyz[3 * i]) || !std::isfinite(xyz[3 * i + 1]) ||

@@ -243,7 +243,7 @@ def test_error_paths(M, ctx):
     depth = M.mwns_tree_get_info(f)["depth"]
     tau, wt = M.mwns_fit_kernel(0.0, 1.0, 1e-3, 1e-3, 1.8)
     cases = [
-        lambda: M.mwns_op_create(ctx, 9, tau, wt, 1e-3, 3),                      # k beyond the kernels
+        lambda: M.mwns_op_create(ctx, 11, tau, wt, 1e-3, 3),                     # k beyond the kernels
         lambda: M.mwns_op_create(ctx, 4, -tau, wt, 1e-3, 3),                     # tau <= 0
         lambda: M.mwns_apply(ctx, M.mwns_op_create(ctx, 4, tau, wt, 1e-3, depth - 1), f),   # max_level < depth
         lambda: M.mwns_apply(ctx, M.mwns_op_create(ctx, 5, tau, wt, 1e-3, depth), f),       # k mismatch
