@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-apply measurement")
     ap.add_argument("--cpu-sample-nodes", type=int, default=15000)
     ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: Poisson k=8 eps=1e-6 (the reported configuration); c3: Yukawa k=10 eps=1e-8")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
@@ -53,14 +55,19 @@ def calibrate_copy():
     print(json.dumps({"calibration": "elementwise copy", "bytes_read": n * 8, "bytes_written": n * 8}))
 
 
-def traffic_from_profile():
+PROFILES = {"c2": ("ns_apply_kernel_poisson_k8_eps1e-6.md", "contract.hip"),
+            "c3": ("ns_apply_wide_kernel_yukawa_k10_eps1e-8.md", "contract_wide.hip")}
+
+
+def traffic_from_profile(workload):
     """HBM bytes of one contraction-kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), provided the summary was taken on the
-    current kernel source (same git blob id of apply.hip); otherwise None."""
+    current kernel source (same git blob id of the kernel's file); otherwise None."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "ns_apply_kernel_poisson_k8_eps1e-6.md")
-    src = os.path.join(ROOT, "paper_0706_0747_amd", "csrc", "apply.hip")
+    name, kernel_src = PROFILES[workload]
+    prof = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_0706_0747_amd", "csrc", kernel_src)
     try:
         with open(prof) as fh:
             text = fh.read()
@@ -69,7 +76,7 @@ def traffic_from_profile():
     except OSError:
         return None
     blob = hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
-    m1 = re.search(r"apply_hip_blob: ([0-9a-f]{40})", text)
+    m1 = re.search(r"kernel_source_blob: ([0-9a-f]{40})", text)
     m2 = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
     if not m1 or not m2 or m1.group(1) != blob:
         return None
@@ -232,7 +239,7 @@ def main():
     import torch
     import paper_0706_0747_amd as M
     import workloads
-    w = workloads.c2()
+    w = workloads.c2() if args.workload == "c2" else workloads.c3()
     pts = workloads.points(10000)
     ctx = M.Context(0)
     M.mwns_ctx_set_variant(ctx, w.k, args.variant)
@@ -265,7 +272,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "kernel": "poisson 1/(4 pi r)", "k": w.k, "eps": w.eps,
+        "config": {"workload": w.name,
+                   "kernel": "poisson 1/(4 pi r)" if w.mu == 0.0 else "yukawa exp(-mu r)/(4 pi r), mu=%.4f" % w.mu,
+                   "k": w.k, "eps": w.eps,
                    "sources": int(w.a.size), "seed": w.seed, "leaves": int(info["nleaves"]),
                    "nodes": int(info["nnodes"]), "depth": int(info["depth"]), "eval_points": int(pts.shape[0])},
         "contractions_per_step": int(contr),
@@ -274,12 +283,14 @@ def main():
         "mixed_vs_fp64_speedup": None,
         "mixed": None,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profile(),
-                     "kernel": "ns_apply_kernel<8> (all levels of one apply)",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profile(args.workload),
+                     "traffic_unit": "bytes per launch",
+                     "kernel": ("ns_apply_kernel<8> (all levels of one apply)" if w.k <= 8 else
+                                "ns_apply_wide_kernel<%d> (all levels of one apply)" % w.k),
                      "variant": M.mwns_ctx_get_variant(ctx, w.k),
                      "flops_per_apply": st["useful_flops"]},
     }
-    if not args.no_mixed:
+    if not args.no_mixed and w.k <= 8:
         line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(M, ctx, w, f, op, g, st, args.steps)
     if not args.no_batch:
         line["batch"] = batch_measurement(M, ctx, args.steps)
