@@ -70,6 +70,14 @@ __global__ void closure_kernel(int64_t nout, int jm1, const uint64_t* __restrict
     miss[idx] = key;
 }
 
+// The missing keys (entries != ~0) of one apply's closure, appended to out (order immaterial).
+__global__ void compact_miss_kernel(int64_t n, const uint64_t* __restrict__ miss, uint64_t* __restrict__ out,
+                                    unsigned int* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || miss[i] == ~0ull) return;
+    out[atomicAdd(count, 1u)] = miss[i];
+}
+
 __global__ void closure_fill_kernel(int64_t n, const uint64_t* __restrict__ miss, const uint64_t* __restrict__ gkeys,
                                     int64_t ng, int64_t nreal, int32_t* __restrict__ nbr) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,24 +220,43 @@ __global__ void __launch_bounds__(AT) assemble_kernel(int j, const int64_t* __re
 // carries the 8 children of P - L); at level 0 the only input is the root itself.
 __device__ inline int range_len(const int32_t* r) { return r[1] >= r[0] ? r[1] - r[0] + 1 : 0; }
 
-__global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ pkeys, const uint8_t* __restrict__ cmask,
-                             int valid, const int32_t* __restrict__ Rj, const int32_t* __restrict__ Rj1,
+// One level of the count (all levels go in one launch).
+struct CountLevel {
+    const uint64_t* pkeys;
+    const uint8_t* cmask;
+    const int32_t* Rj;
+    const int32_t* Rj1;      // null when the operator has no row j+1
+    int64_t first;           // first work item of the level: items are (brick, child, slab)
+    int64_t nout;
+    int j, valid;
+};
+
+// One thread per (output node, x-slab of the displacements): slab x in [-LP, LP] takes L_1 = x
+// of the whole band and e_1 = x of the down band.
+__global__ void count_kernel(const CountLevel* __restrict__ lv, int nlev, int64_t nitems,
                              unsigned long long* __restrict__ total) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nout * 8) return;
-    const int64_t b = t >> 3;
-    const int child = (int)(t & 7);
-    if (!((valid >> child) & 1)) return;
-    const int internal = (cmask[b] >> child) & 1;
+    if (t >= nitems) return;
+    int li = 0;
+    while (li + 1 < nlev && lv[li + 1].first <= t) ++li;
+    const CountLevel c = lv[li];
+    const int64_t r = t - c.first;
+    const int64_t b = r / (8 * NLP);
+    const int child = (int)((r / NLP) % 8);
+    const int x = (int)(r % NLP) - LP;
+    if (!((c.valid >> child) & 1)) return;
+    const int j = c.j;
+    const int internal = (c.cmask[b] >> child) & 1;
     auto at = [](const int32_t* R, int x, int y, int z) {
         return R + (((x + LP) * NLP + (y + LP)) * NLP + (z + LP)) * 2;
     };
     long long cnt = 0;
     if (j == 0) {
-        const int32_t* w = at(Rj, 0, 0, 0);
+        if (x != 0) return;
+        const int32_t* w = at(c.Rj, 0, 0, 0);
         cnt = range_len(w);
-        if (internal && Rj1) {
-            const int32_t* d = at(Rj1, 0, 0, 0);
+        if (internal && c.Rj1) {
+            const int32_t* d = at(c.Rj1, 0, 0, 0);
             const int ov = (range_len(w) && range_len(d)) ? max(0, min(w[1], d[1]) - max(w[0], d[0]) + 1) : 0;
             cnt += range_len(d) - 2 * ov;
         }
@@ -237,31 +264,33 @@ __global__ void count_kernel(int64_t nout, int j, const uint64_t* __restrict__ p
         return;
     }
     int64_t p[3];
-    key_coords(pkeys[b], p);
+    key_coords(c.pkeys[b], p);
     const int64_t pside = (int64_t)1 << (j - 1), side = (int64_t)1 << j;
-    for (int x = -LP; x <= LP; ++x)
+    if (p[0] - x >= 0 && p[0] - x < pside)
         for (int y = -LP; y <= LP; ++y)
             for (int z = -LP; z <= LP; ++z) {
-                const int64_t q[3] = {p[0] - x, p[1] - y, p[2] - z};
-                if (q[0] < 0 || q[0] >= pside || q[1] < 0 || q[1] >= pside || q[2] < 0 || q[2] >= pside) continue;
-                cnt += 8 * range_len(at(Rj, x, y, z));
+                const int64_t q1 = p[1] - y, q2 = p[2] - z;
+                if (q1 < 0 || q1 >= pside || q2 < 0 || q2 >= pside) continue;
+                cnt += 8 * range_len(at(c.Rj, x, y, z));
             }
-    if (internal && Rj1) {
+    if (internal && c.Rj1) {
         const int64_t o[3] = {2 * p[0] + (child & 1), 2 * p[1] + ((child >> 1) & 1), 2 * p[2] + (child >> 2)};
-        for (int e1 = -LP; e1 <= LP; ++e1)
+        const int e1 = x;
+        const int64_t q0 = o[0] - e1;
+        if (q0 >= 0 && q0 < side)
             for (int e2 = -LP; e2 <= LP; ++e2)
                 for (int e3 = -LP; e3 <= LP; ++e3) {
-                    const int64_t q[3] = {o[0] - e1, o[1] - e2, o[2] - e3};
-                    if (q[0] < 0 || q[0] >= side || q[1] < 0 || q[1] >= side || q[2] < 0 || q[2] >= side) continue;
+                    const int64_t q[3] = {q0, o[1] - e2, o[2] - e3};
+                    if (q[1] < 0 || q[1] >= side || q[2] < 0 || q[2] >= side) continue;
                     const int L[3] = {(int)((o[0] >> 1) - (q[0] >> 1)), (int)((o[1] >> 1) - (q[1] >> 1)),
                                       (int)((o[2] >> 1) - (q[2] >> 1))};
-                    const int32_t* w = at(Rj, L[0], L[1], L[2]);   // |L_d| <= 2 here
-                    const int32_t* d = at(Rj1, e1, e2, e3);
+                    const int32_t* w = at(c.Rj, L[0], L[1], L[2]);   // |L_d| <= 2 here
+                    const int32_t* d = at(c.Rj1, e1, e2, e3);
                     const int ov = (range_len(w) && range_len(d)) ? max(0, min(w[1], d[1]) - max(w[0], d[0]) + 1) : 0;
                     cnt += range_len(d) - 2 * ov;
                 }
     }
-    atomicAdd(total, (unsigned long long)cnt);
+    if (cnt) atomicAdd(total, (unsigned long long)cnt);
 }
 
 template <int K>
@@ -637,24 +666,24 @@ void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
 
 // The distinct missing keys of every level become its ghost bricks (Alg. 3 Step 2): their
 // indices complete the neighbour tables and their storage is allocated.
-void discover_ghosts(mwns_ctx* ctx, TreeApply& a, const uint64_t* hmiss, uint64_t* dmiss) {
+void discover_ghosts(mwns_ctx* ctx, TreeApply& a, std::vector<uint64_t>& keys, uint64_t* dmiss) {
     a.total_ghosts = 0;
+    // a missing parent key of level j-1 belongs to the closure of output level j
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    size_t pos = 0;
     for (int j = 1; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
+        const size_t b0 = pos;
+        while (pos < keys.size() && key_level(keys[pos]) == j - 1) ++pos;
         if (lw.tpl.empty()) continue;
         const int NL = 2 * lw.Lr + 1;
         const int64_t n = lw.nout * NL * NL * NL;
-        const uint64_t* hm = hmiss + a.miss_base + lw.miss_off;
-        std::vector<uint64_t> gk;
-        for (int64_t i = 0; i < n; ++i)
-            if (hm[i] != ~0ull) gk.push_back(hm[i]);
-        std::sort(gk.begin(), gk.end());
-        gk.erase(std::unique(gk.begin(), gk.end()), gk.end());
-        lw.nghost = (int64_t)gk.size();
+        lw.nghost = (int64_t)(pos - b0);
         a.total_ghosts += lw.nghost;
         if (!lw.nghost) continue;
-        lw.gkeys.reset(ctx, gk.size());
-        lw.gkeys.upload(gk.data(), gk.size(), ctx->stream);
+        lw.gkeys.reset(ctx, lw.nghost);
+        lw.gkeys.upload(keys.data() + b0, lw.nghost, ctx->stream);
         closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(
             n, dmiss + a.miss_base + lw.miss_off, lw.gkeys.p, lw.nghost, lw.nout, lw.nbr.p);
         MWNS_HIP(hipGetLastError());
@@ -819,12 +848,10 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
             double c[NPREC] = {0.0, 0.0, 0.0, 0.0};
             for (const Tpl& t : lw.tpl) {
                 if (t.dpart && lw.cm[b] == 0) continue;
-                double nin[3];
-                for (int dd = 0; dd < 3; ++dd) {
-                    int cnt = 0;
-                    for (int Lx = t.lo[dd]; Lx <= t.hi[dd]; ++Lx) cnt += (pp[dd] - Lx >= 0 && pp[dd] - Lx < pside);
-                    nin[dd] = cnt;
-                }
+                double nin[3];     // displacements L of the box with P - L inside the cube
+                for (int dd = 0; dd < 3; ++dd)
+                    nin[dd] = (double)std::max<int64_t>(
+                        0, std::min<int64_t>(t.hi[dd], pp[dd]) - std::max<int64_t>(t.lo[dd], pp[dd] - pside + 1) + 1);
                 if (nin[0] * nin[1] * nin[2] == 0) continue;     // the box lies outside the cube
                 const double nt = t.m2 - t.m1 + 1;
                 const double steps = nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0];
@@ -923,12 +950,25 @@ void collect_stats(mwns_ctx* ctx, TreeApply& a, int mode, mwns_apply_stats& s) {
     zero_ints_kernel<<<1, 64, 0, st>>>(reinterpret_cast<int*>(tot.p), 2);
     DevArray<int32_t> dplan(ctx, a.op->plan.size());
     dplan.upload(a.op->plan.data(), a.op->plan.size(), st);
+    std::vector<CountLevel> cl;
+    int64_t nitems = 0;
     for (int j = 0; j <= a.depth; ++j) {
         const LevelWork& lw = a.W[j];
-        const int32_t* Rj1 = (j + 1 <= a.op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
-        count_kernel<<<(unsigned)((lw.nout * 8 + 255) / 256), 256, 0, st>>>(lw.nout, j, lw.pkeys.p, lw.cmask.p, lw.valid,
-                                                                            dplan.p + (int64_t)j * planrow, Rj1, tot.p);
+        CountLevel c{};
+        c.pkeys = lw.pkeys.p;
+        c.cmask = lw.cmask.p;
+        c.Rj = dplan.p + (int64_t)j * planrow;
+        c.Rj1 = (j + 1 <= a.op->max_level) ? dplan.p + (int64_t)(j + 1) * planrow : nullptr;
+        c.first = nitems;
+        c.nout = lw.nout;
+        c.j = j;
+        c.valid = lw.valid;
+        cl.push_back(c);
+        nitems += lw.nout * 8 * NLP;
     }
+    DevArray<CountLevel> dcl(ctx, cl.size());
+    dcl.upload(cl.data(), cl.size(), st);
+    count_kernel<<<(unsigned)((nitems + 255) / 256), 256, 0, st>>>(dcl.p, (int)cl.size(), nitems, tot.p);
     // ||g||_2: the leaves' scaling functions are orthonormal with disjoint supports
     if (!(mode & MWNS_NO_ASSEMBLY))
         for (int j = 0; j <= a.depth; ++j)
@@ -964,10 +1004,29 @@ void prepare(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& trees, cons
     }
     miss.reset(ctx, std::max<int64_t>(1, miss_total));
     for (auto& a : trees) launch_closure(ctx, *a, miss.p);
-    std::vector<uint64_t> hm(miss_total);
-    miss.download(hm.data(), miss_total, st);
+    // only the missing keys travel to the host: compact them per tree on the device
+    const int nt = (int)trees.size();
+    DevArray<uint64_t> comp(ctx, std::max<int64_t>(1, miss_total));
+    DevArray<unsigned int> cnt(ctx, nt);
+    zero_ints_kernel<<<(nt + 63) / 64, 64, 0, st>>>(reinterpret_cast<int*>(cnt.p), nt);
+    for (int i = 0; i < nt; ++i) {
+        const TreeApply& a = *trees[i];
+        if (a.miss_total)
+            compact_miss_kernel<<<(unsigned)((a.miss_total + 255) / 256), 256, 0, st>>>(
+                a.miss_total, miss.p + a.miss_base, comp.p + a.miss_base, cnt.p + i);
+    }
+    MWNS_HIP(hipGetLastError());
+    std::vector<unsigned int> hc(nt);
+    cnt.download(hc.data(), nt, st);
     MWNS_HIP(hipStreamSynchronize(st));
-    for (auto& a : trees) discover_ghosts(ctx, *a, hm.data(), miss.p);
+    std::vector<std::vector<uint64_t>> keys(nt);
+    for (int i = 0; i < nt; ++i) {
+        keys[i].resize(hc[i]);
+        if (hc[i]) MWNS_HIP(hipMemcpyAsync(keys[i].data(), comp.p + trees[i]->miss_base, hc[i] * sizeof(uint64_t),
+                                          hipMemcpyDeviceToHost, st));
+    }
+    MWNS_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nt; ++i) discover_ghosts(ctx, *trees[i], keys[i], miss.p);
     if (mixed) {
         // routing needs the ghosts' values for the level norms
         size_t nl = 0;

@@ -52,7 +52,11 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     constexpr int NQ = 3 * K;                // 1-D points: K own nodes, then 2K children nodes
     constexpr int NC = 8 * K3;               // children grid (2K)^3, points 0..NC-1
     constexpr int NP = 9 * K3;               // then the box's own K^3 nodes
-    constexpr int PER = (NP + PT - 1) / PT;
+    constexpr int NPAIR = P2 * P2;           // (y, z) pairs of the children grid
+    constexpr int PPT = (NPAIR + PT - 1) / PT;
+    static_assert(K * K <= PT, "one thread per (y, z) pair of the own grid");
+    (void)NC;
+    (void)NP;
     __shared__ double E[CH][3][NQ];          // E[i][0][q] already carries the source weight
     __shared__ double fown[K3];
     __shared__ double t1[2 * K3];
@@ -66,22 +70,14 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     int64_t l[3];
     key_coords(keys[box], l);
     const double h = ldexp(1.0, -j);
-    double acc[PER];
-    int qq[PER][3];
-    for (int r = 0; r < PER; ++r) {
-        acc[r] = 0.0;
-        const int pt = threadIdx.x + r * PT;
-        if (pt < NC) {
-            qq[r][0] = K + pt / (P2 * P2);
-            qq[r][1] = K + (pt / P2) % P2;
-            qq[r][2] = K + pt % P2;
-        } else {
-            const int o = pt - NC;
-            qq[r][0] = o / (K * K);
-            qq[r][1] = (o / K) % K;
-            qq[r][2] = o % K;
-        }
-    }
+    // The source is separable per term, f = sum_i w_i e_i(x) e_i(y) e_i(z): a thread owns (y, z)
+    // pairs and sweeps x, reading e_i(y), e_i(z) once per term and e_i(x) as LDS broadcasts.
+    // Every value is still accumulated as sum_i (e_i(x) e_i(y)) e_i(z) in term order.
+    double accc[PPT][P2];                    // children grid: [pair][x]
+    double acco[K];                          // own grid, pair threadIdx.x < K*K: [x]
+    for (int p = 0; p < PPT; ++p)
+        for (int q = 0; q < P2; ++q) accc[p][q] = 0.0;
+    for (int q = 0; q < K; ++q) acco[q] = 0.0;
     for (int c0 = 0; c0 < nsrc; c0 += CH) {
         const int nc = min(CH, nsrc - c0);
         for (int e = threadIdx.x; e < nc * 3 * NQ; e += PT) {
@@ -98,19 +94,26 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
             E[i][d][q] = d == 0 ? sp[4] * ev : ev;
         }
         __syncthreads();
-        for (int r = 0; r < PER; ++r) {
-            const int pt = threadIdx.x + r * PT;
-            if (pt >= NP) break;
-            double a = acc[r];
-            for (int i = 0; i < nc; ++i) a += E[i][0][qq[r][0]] * E[i][1][qq[r][1]] * E[i][2][qq[r][2]];
-            acc[r] = a;
+        for (int p = 0; p < PPT; ++p) {
+            const int pr = threadIdx.x + p * PT;
+            if (pr >= NPAIR) break;
+            const int qy = K + pr / P2, qz = K + pr % P2;
+            for (int i = 0; i < nc; ++i) {
+                const double ey = E[i][1][qy], ez = E[i][2][qz];
+                for (int q = 0; q < P2; ++q) accc[p][q] += E[i][0][K + q] * ey * ez;
+            }
+        }
+        if (threadIdx.x < K * K) {
+            const int oy = threadIdx.x / K, oz = threadIdx.x % K;
+            for (int i = 0; i < nc; ++i) {
+                const double ey = E[i][1][oy], ez = E[i][2][oz];
+                for (int q = 0; q < K; ++q) acco[q] += E[i][0][q] * ey * ez;
+            }
         }
         __syncthreads();
     }
-    for (int r = 0; r < PER; ++r) {
-        const int pt = threadIdx.x + r * PT;
-        if (pt >= NC && pt < NP) fown[pt - NC] = acc[r];
-    }
+    if (threadIdx.x < K * K)
+        for (int q = 0; q < K; ++q) fown[q * K * K + threadIdx.x] = acco[q];
     __syncthreads();
     // s = 2^{-3j/2} (P (x) P (x) P) f_own, contracting the last index first
     const double nc3 = pow(2.0, -1.5 * j);
@@ -161,13 +164,15 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
             u2[e] = sm;
         }
         __syncthreads();
-        for (int r = 0; r < PER; ++r) {
-            const int e = threadIdx.x + r * PT;
-            if (e >= NC) break;
-            const int q1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
-            double sm = 0.0;
-            for (int a1 = 0; a1 < K; ++a1) sm += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
-            emax = fmax(emax, fabs(acc[r] - ni * sm));
+        for (int p = 0; p < PPT; ++p) {
+            const int pr = threadIdx.x + p * PT;
+            if (pr >= NPAIR) break;
+            const int q2 = pr / P2, q3 = pr % P2;
+            for (int q1 = 0; q1 < P2; ++q1) {
+                double sm = 0.0;
+                for (int a1 = 0; a1 < K; ++a1) sm += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
+                emax = fmax(emax, fabs(accc[p][q1] - ni * sm));
+            }
         }
     }
     red[threadIdx.x] = emax;
@@ -565,13 +570,14 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
     MWNS_HIP(hipMemsetAsync(t->coef.p, 0, t->coef.n * sizeof(double), st));
     LevelTab lt = level_tab(t.get());
+    std::vector<DevArray<uint8_t>> dls(t->depth + 1);
     for (int j = j0; j <= t->depth; ++j) {
         const int64_t nn = t->lev[j].nnodes;
-        DevArray<uint8_t> dl(ctx, nn);
-        dl.upload(t->leaf.data() + t->lev[j].node_off, nn, st);
-        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(k, j, nn, lcoef[j].p, dl.p, lt, t->coef.p);
+        dls[j].reset(ctx, nn);
+        dls[j].upload(t->leaf.data() + t->lev[j].node_off, nn, st);
+        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(k, j, nn, lcoef[j].p, dls[j].p, lt,
+                                                                                  t->coef.p);
         MWNS_HIP(hipGetLastError());
-        MWNS_HIP(hipStreamSynchronize(st));
     }
     DevArray<double> dH = upload_filters(ctx, k);
     compress_tree(t.get(), dH.p);
