@@ -73,8 +73,14 @@ mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_
 void mwns_ctx_destroy(mwns_ctx* ctx);
 /* Block until all work on the context's stream has completed.  Errors: EDEVICE. */
 mwns_status mwns_ctx_synchronize(mwns_ctx* ctx);
-/* Device bytes currently held by the context (handles included). */
+/* Device bytes in live blocks of the context (handles included). */
 size_t mwns_ctx_bytes_in_use(const mwns_ctx* ctx);
+/* Freed device blocks are kept by the context and reused by later calls on its stream (sizes in
+ * classes of a quarter octave); these count against byte_budget and are released when an
+ * allocation would exceed it, by mwns_ctx_release_cache (which synchronises) and by
+ * mwns_ctx_destroy.  bytes_cached reports their total. */
+size_t mwns_ctx_bytes_cached(const mwns_ctx* ctx);
+mwns_status mwns_ctx_release_cache(mwns_ctx* ctx);
 /* Thread-local text for the last non-OK status returned on this thread ("" if none). */
 const char* mwns_last_error(void);
 

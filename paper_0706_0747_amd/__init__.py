@@ -59,7 +59,10 @@ class Context:
                 return torch.cuda.caching_allocator_alloc(int(nbytes), device, s)
 
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except (AttributeError, TypeError):
+                    pass            # interpreter shutdown: torch is already gone
 
             alloc = _lib.ALLOC_FN(_alloc)
             free = _lib.FREE_FN(_free)
@@ -73,6 +76,12 @@ class Context:
 
     def bytes_in_use(self):
         return lib.mwns_ctx_bytes_in_use(self.h)
+
+    def bytes_cached(self):
+        return lib.mwns_ctx_bytes_cached(self.h)
+
+    def release_cache(self):
+        check(lib.mwns_ctx_release_cache(self.h), "mwns_ctx_release_cache")
 
     def close(self, _destroy=lib.mwns_ctx_destroy):
         if getattr(self, "h", None):

@@ -58,6 +58,8 @@ SIGNATURES = {
     "mwns_ctx_destroy": (None, [c_vp]),
     "mwns_ctx_synchronize": (c_int, [c_vp]),
     "mwns_ctx_bytes_in_use": (c_size, [c_vp]),
+    "mwns_ctx_bytes_cached": (c_size, [c_vp]),
+    "mwns_ctx_release_cache": (c_int, [c_vp]),
     "mwns_last_error": (ctypes.c_char_p, []),
     "mwns_num_variants": (c_int, []),
     "mwns_ctx_set_variant": (c_int, [c_vp, c_int, c_int]),

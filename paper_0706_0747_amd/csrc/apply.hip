@@ -500,6 +500,35 @@ __global__ void zero_ints_kernel(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// A device pointer into an arena (owned elsewhere).
+template <class T>
+struct DevView {
+    T* p = nullptr;
+};
+
+// Small host arrays of one phase gathered into one device block with a single copy (each
+// separate hipMemcpyAsync from pageable memory costs tens of microseconds).  Views receive their
+// device addresses at commit; the host copy stays alive with the arena.
+struct UploadArena {
+    std::vector<char> host;
+    std::vector<std::pair<size_t, void**>> fix;
+    DevArray<char> dev;
+    template <class T>
+    void add(const T* data, size_t n, DevView<T>& view) {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + n * sizeof(T));
+        if (n) std::memcpy(host.data() + off, data, n * sizeof(T));
+        fix.push_back({off, reinterpret_cast<void**>(&view.p)});
+    }
+    void commit(mwns_ctx* ctx) {
+        if (host.empty()) return;
+        dev.reset(ctx, host.size());
+        dev.upload(host.data(), host.size(), ctx->stream);
+        for (auto& f : fix) *f.second = dev.p + f.first;
+        fix.clear();
+    }
+};
+
 struct LevelWork {
     std::vector<Tpl> tpl;
     std::vector<uint8_t> cm;
@@ -508,13 +537,13 @@ struct LevelWork {
     int64_t nout = 0, nghost = 0, miss_off = 0;
     int valid = 0xff;
     DevArray<int32_t> nbr;
-    DevArray<uint8_t> cmask;
-    DevArray<Tpl> dtpl;
+    DevView<uint8_t> cmask;
+    DevView<Tpl> dtpl;
     DevArray<double> ghosts;
-    DevArray<uint64_t> pkeys, gkeys;
+    DevView<uint64_t> pkeys, gkeys;
     DevArray<u4> xr32, xg32, xrb, xgb;     // reduced-precision copies of the inputs (routed applies)
-    DevArray<int64_t> apb;                 // assembly: parent's brick of every brick of the level
-    DevArray<int> apc;                     //           parent's child slot in that brick
+    DevView<int64_t> apb;                  // assembly: parent's brick of every brick of the level
+    DevView<int> apc;                      //           parent's child slot in that brick
 };
 
 // One (operator, input tree) pair of an apply and everything its device work needs.
@@ -524,7 +553,8 @@ struct TreeApply {
     std::unique_ptr<mwns_tree> out;
     int k = 0, depth = 0;
     std::vector<LevelWork> W;
-    DevArray<double> dHt;
+    DevView<double> dHt;
+    UploadArena setup_arena, ghost_arena, desc_arena;
     LevelTab2 lt{};
     int64_t miss_base = 0, miss_total = 0, total_ghosts = 0, jobs = 0;
     double err_bound = 0.0, flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
@@ -567,8 +597,7 @@ void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
         for (int s = 0; s < 2; ++s)
             for (int x = 0; x < k; ++x)
                 for (int c = 0; c < k; ++c) Ht[s * k * k + c * k + x] = H[s * k * k + x * k + c];
-        a.dHt.reset(ctx, Ht.size());
-        a.dHt.upload(Ht.data(), Ht.size(), st);
+        a.setup_arena.add(Ht.data(), Ht.size(), a.dHt);
     }
     const int depth = a.depth = f->depth;
     const int64_t planrow = (int64_t)NLP3 * 2;
@@ -623,21 +652,17 @@ void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
             for (int64_t b = 0; b < lw.nout; ++b)
                 for (int s = 0; s < 8; ++s)
                     if (!f->leaf[L.node_off + 8 * b + s]) lw.cm[b] |= (uint8_t)(1 << s);
-        lw.cmask.reset(ctx, lw.nout);
-        lw.cmask.upload(lw.cm.data(), lw.nout, st);
+        a.setup_arena.add(lw.cm.data(), lw.nout, lw.cmask);
         lw.nbr.reset(ctx, (size_t)lw.nout * NL3);
         if (j > 0) {
             lw.pk.resize(lw.nout);
             for (int64_t b = 0; b < lw.nout; ++b) lw.pk[b] = f->keys[f->brick_parent[L.brick_off + b]];
-            lw.pkeys.reset(ctx, lw.nout);
-            lw.pkeys.upload(lw.pk.data(), lw.nout, st);
+            a.setup_arena.add(lw.pk.data(), lw.nout, lw.pkeys);
             std::vector<int64_t> pb(lw.nout);
             std::vector<int> pc(lw.nout);
             for (int64_t b = 0; b < lw.nout; ++b) node_brick(f, f->brick_parent[L.brick_off + b], &pb[b], &pc[b]);
-            lw.apb.reset(ctx, pb.size());
-            lw.apc.reset(ctx, pc.size());
-            lw.apb.upload(pb.data(), pb.size(), st);
-            lw.apc.upload(pc.data(), pc.size(), st);
+            a.setup_arena.add(pb.data(), pb.size(), lw.apb);
+            a.setup_arena.add(pc.data(), pc.size(), lw.apc);
         }
         if (lw.tpl.empty()) continue;
         if (j == 0) {
@@ -649,6 +674,7 @@ void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
         lw.miss_off = a.miss_total;
         a.miss_total += lw.nout * NL3;
     }
+    a.setup_arena.commit(ctx);
 }
 
 // Neighbour closure kernels of every level; missing parents' keys go to miss[miss_base + ...].
@@ -677,13 +703,16 @@ void discover_ghosts(mwns_ctx* ctx, TreeApply& a, std::vector<uint64_t>& keys, u
         const size_t b0 = pos;
         while (pos < keys.size() && key_level(keys[pos]) == j - 1) ++pos;
         if (lw.tpl.empty()) continue;
-        const int NL = 2 * lw.Lr + 1;
-        const int64_t n = lw.nout * NL * NL * NL;
         lw.nghost = (int64_t)(pos - b0);
         a.total_ghosts += lw.nghost;
-        if (!lw.nghost) continue;
-        lw.gkeys.reset(ctx, lw.nghost);
-        lw.gkeys.upload(keys.data() + b0, lw.nghost, ctx->stream);
+        if (lw.nghost) a.ghost_arena.add(keys.data() + b0, lw.nghost, lw.gkeys);
+    }
+    a.ghost_arena.commit(ctx);
+    for (int j = 1; j <= a.depth; ++j) {
+        LevelWork& lw = a.W[j];
+        if (lw.tpl.empty() || !lw.nghost) continue;
+        const int NL = 2 * lw.Lr + 1;
+        const int64_t n = lw.nout * NL * NL * NL;
         closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(
             n, dmiss + a.miss_base + lw.miss_off, lw.gkeys.p, lw.nghost, lw.nout, lw.nbr.p);
         MWNS_HIP(hipGetLastError());
@@ -810,6 +839,9 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                  std::vector<std::pair<double, int2>> (&cost)[NPREC]) {
     const int k = a.k;
     const int64_t E = brick_elems(k);
+    for (int j = 0; j <= a.depth; ++j)
+        if (!a.W[j].tpl.empty()) a.desc_arena.add(a.W[j].tpl.data(), a.W[j].tpl.size(), a.W[j].dtpl);
+    a.desc_arena.commit(ctx);
     a.desc_base = descs.size();
     a.jobs = 0;
     a.flops = 0.0;
@@ -823,8 +855,7 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
             descs.push_back(d);
             continue;
         }
-        lw.dtpl.reset(ctx, lw.tpl.size());
-        lw.dtpl.upload(lw.tpl.data(), lw.tpl.size(), ctx->stream);
+
         d.Xr = a.f->coef.p + a.f->lev[j].brick_off * E;
         d.Xg = lw.ghosts.p;
         d.Xr32 = reinterpret_cast<const float*>(lw.xr32.p);

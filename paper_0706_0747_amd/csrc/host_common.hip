@@ -19,28 +19,66 @@ void check_hip(hipError_t e, const char* what) {
     if (e != hipSuccess) fail(MWNS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device blocks are kept after they are freed and reused for later requests of the same size
+// class (four classes per power of two, so at most 25% is wasted).  All of a context's work is
+// ordered on its stream, so a block freed by earlier work is free for later work on that stream.
+// Reuse spares the allocator (for the Python binding, a callback into torch) on every apply.
+size_t size_class(size_t bytes) {
+    if (bytes <= 256) return 256;
+    int e = 63 - __builtin_clzll((unsigned long long)(bytes - 1));      // 2^e < bytes <= 2^(e+1)
+    const size_t step = (size_t)1 << (e - 1);                          // quarter octave
+    return (bytes + step - 1) / step * step;
+}
+
+void release_cache(mwns_ctx* ctx) {
+    for (auto& c : ctx->cache) {
+        if (ctx->free_fn) ctx->free_fn(c.second, ctx->user);
+        else (void)hipFree(c.second);
+        ctx->in_use -= c.first;
+    }
+    ctx->cache.clear();
+    ctx->cached = 0;
+}
+
 void* dalloc(mwns_ctx* ctx, size_t bytes) {
     if (bytes == 0) return nullptr;
-    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
-        fail(MWNS_ENOMEM, "context byte budget exceeded (" + std::to_string(ctx->in_use + bytes) + " > " +
+    const size_t cls = size_class(bytes);
+    for (size_t i = ctx->cache.size(); i-- > 0;)
+        if (ctx->cache[i].first == cls) {
+            void* p = ctx->cache[i].second;
+            ctx->cache.erase(ctx->cache.begin() + (std::ptrdiff_t)i);
+            ctx->cached -= cls;
+            return p;
+        }
+    if (ctx->budget && ctx->in_use + cls > ctx->budget) release_cache(ctx);
+    if (ctx->budget && ctx->in_use + cls > ctx->budget)
+        fail(MWNS_ENOMEM, "context byte budget exceeded (" + std::to_string(ctx->in_use + cls) + " > " +
                               std::to_string(ctx->budget) + ")");
     void* p = nullptr;
     if (ctx->alloc) {
-        p = ctx->alloc(bytes, ctx->user);
-        if (!p) fail(MWNS_ENOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        p = ctx->alloc(cls, ctx->user);
+        if (!p) {
+            release_cache(ctx);
+            p = ctx->alloc(cls, ctx->user);
+        }
+        if (!p) fail(MWNS_ENOMEM, "device allocator returned NULL for " + std::to_string(cls) + " bytes");
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess || !p) fail(MWNS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        hipError_t e = hipMalloc(&p, cls);
+        if (e != hipSuccess || !p) {
+            release_cache(ctx);
+            e = hipMalloc(&p, cls);
+        }
+        if (e != hipSuccess || !p) fail(MWNS_ENOMEM, "hipMalloc of " + std::to_string(cls) + " bytes failed");
     }
-    ctx->in_use += bytes;
+    ctx->in_use += cls;
     return p;
 }
 
 void dfree(mwns_ctx* ctx, void* p, size_t bytes) {
     if (!p) return;
-    if (ctx->free_fn) ctx->free_fn(p, ctx->user);
-    else (void)hipFree(p);
-    ctx->in_use -= bytes;
+    const size_t cls = size_class(bytes);
+    ctx->cache.push_back({cls, p});
+    ctx->cached += cls;
 }
 
 // n-point Gauss-Legendre rule on [0,1]: nodes are the roots of P_n(2x-1) (App. A.1), found by
@@ -188,7 +226,21 @@ mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_
     MWNS_GUARD_END
 }
 
-void mwns_ctx_destroy(mwns_ctx* ctx) { delete ctx; }
+void mwns_ctx_destroy(mwns_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    release_cache(ctx);
+    delete ctx;
+}
+
+mwns_status mwns_ctx_release_cache(mwns_ctx* ctx) {
+    MWNS_GUARD_BEGIN
+    if (!ctx) fail(MWNS_EINVAL, "ctx is NULL");
+    MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    release_cache(ctx);
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
 
 mwns_status mwns_ctx_synchronize(mwns_ctx* ctx) {
     MWNS_GUARD_BEGIN
@@ -198,6 +250,7 @@ mwns_status mwns_ctx_synchronize(mwns_ctx* ctx) {
     MWNS_GUARD_END
 }
 
-size_t mwns_ctx_bytes_in_use(const mwns_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+size_t mwns_ctx_bytes_in_use(const mwns_ctx* ctx) { return ctx ? ctx->in_use - ctx->cached : 0; }
+size_t mwns_ctx_bytes_cached(const mwns_ctx* ctx) { return ctx ? ctx->cached : 0; }
 
 }  // extern "C"

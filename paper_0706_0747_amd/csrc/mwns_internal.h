@@ -106,13 +106,16 @@ struct mwns_ctx {
     mwns_free_fn free_fn = nullptr;
     void* user = nullptr;
     size_t budget = 0;
-    size_t in_use = 0;
+    size_t in_use = 0;                                  // bytes held: live blocks and the cache
+    size_t cached = 0;                                  // bytes of freed blocks kept for reuse
+    std::vector<std::pair<size_t, void*>> cache;        // (size class, block), most recent last
     int variant[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};   // per basis order k
 };
 
 namespace mwns {
 void* dalloc(mwns_ctx* ctx, size_t bytes);
 void dfree(mwns_ctx* ctx, void* p, size_t bytes);
+void release_cache(mwns_ctx* ctx);
 template <class T>
 struct DevArray {
     mwns_ctx* ctx = nullptr;

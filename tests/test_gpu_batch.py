@@ -133,3 +133,21 @@ def test_autotuner_picks_a_variant_and_caches_it(M, tmp_path):
     v1 = M.autotune(c, op, f, cache_path=path, reps=1)
     M.mwns_ctx_set_variant(c, w.k, (v1 + 1) % M.mwns_num_variants())
     assert M.autotune(c, op, f, cache_path=path) == v1 and M.mwns_ctx_get_variant(c, w.k) == v1
+
+
+def test_device_block_cache_reuse(M):
+    """Freed device blocks stay with the context and serve the next apply (results unchanged);
+    release_cache hands them back."""
+    c = M.Context(0)
+    w, f, op = _member(M, c, MEMBERS[1])
+    g, _ = M.mwns_apply(c, op, f)
+    ref = M.mwns_tree_export(c, g)[2]
+    g.close()
+    cached = c.bytes_cached()
+    assert cached > 0
+    live = c.bytes_in_use()
+    g2, _ = M.mwns_apply(c, op, f)
+    assert np.array_equal(M.mwns_tree_export(c, g2)[2], ref)
+    assert c.bytes_cached() <= cached and c.bytes_in_use() >= live
+    c.release_cache()
+    assert c.bytes_cached() == 0
