@@ -28,8 +28,25 @@ constexpr int SF_V = 20;           // LDS stride of the staged FP32 operands [L]
 // LDS of the contraction kernel, in doubles: the FP64 layout is the largest of the classes.
 constexpr int SM_T2 = 16 * T2S_V1, SM_S3 = NMAX * 16 * S3_V, SM_S2 = NMAX * 256, SM_S1 = NMAX * 256;
 constexpr int SMEM_DOUBLES = SM_T2 + SM_S3 + SM_S2 + SM_S1;
-static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * SF_V / 2 <= SMEM_DOUBLES, "FP32 LDS layout");
-static_assert(16 * T2F_V1 / 2 + 3 * NMAX * 16 * 4 * 2 <= SMEM_DOUBLES, "BF16 LDS layout");
+// The reduced classes run GT terms of a job per pass over its cells (one input load, one step
+// bookkeeping and one staging barrier for all of them); their LDS holds the FP32 mode-2 result
+// once and the staged super-blocks of every term of the group.
+template <int PREC, int K = 8>
+struct LpShape {
+    static constexpr bool BF = PREC != PREC_F32;
+    // terms per pass: as many as the 128-register budget of two workgroups per CU holds unspilled
+    static constexpr int GT = BF ? 2 : (K == 8 ? 2 : 1);
+    static constexpr int TERM_BYTES = BF ? 3 * NMAX * 64 * 16 : 3 * NMAX * 16 * SF_V * 4;  // S1, S2, S3 of a term
+    static constexpr int T2_BYTES = 16 * T2F_V1 * 4;
+    static constexpr int SMEM = (T2_BYTES + GT * TERM_BYTES + 7) / 8;                  // doubles
+};
+template <int PREC, int K>
+constexpr int smem_doubles() {
+    if constexpr (PREC == PREC_F64) return SMEM_DOUBLES;
+    else return LpShape<PREC, K>::SMEM;
+}
+static_assert(smem_doubles<PREC_F32, 8>() * 8 <= 80 * 1024 && smem_doubles<PREC_BF16C, 8>() * 8 <= 80 * 1024,
+              "two workgroups per CU");
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -344,6 +361,173 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
     }
 }
 
+// The terms of one job for one output brick in a reduced class, GT terms per pass: every step
+// loads the input slices once and feeds them to the GT terms' chains (FP32 or split-BF16; see
+// run_job for the operand layouts); mode 1 goes through the LDS transpose term by term.
+template <int K, int CW, int PREC>
+__device__ __forceinline__ void run_job_lp(const LevelDesc& lv, const Tpl& tp, const double* __restrict__ w, int ns,
+                                           const int2* steps, double* smem, int wave, int g, int r, int cmb,
+                                           d4 (&Y)[(2 * K + CW - 1) / CW]) {
+    using S = LpShape<PREC, K>;
+    constexpr int GT = S::GT;
+    constexpr bool BF = S::BF;
+    constexpr int CT = 64 * CW;
+    constexpr int D = 2 * K;
+    constexpr int TPW = (D + CW - 1) / CW;
+    constexpr bool FULL = (CW * TPW == D);
+    constexpr int64_t ELP = (int64_t)D * D * 64;   // bytes of a reduced-precision brick
+    const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+    float* T2f = reinterpret_cast<float*>(smem);
+    char* sbase = reinterpret_cast<char*>(smem) + S::T2_BYTES;
+    // staged operands of term gi of the pass
+    auto S3f = [&](int gi) { return reinterpret_cast<float*>(sbase + gi * S::TERM_BYTES); };
+    auto S2f = [&](int gi) { return S3f(gi) + NMAX * 16 * SF_V; };
+    auto S1f = [&](int gi) { return S2f(gi) + NMAX * 16 * SF_V; };
+    auto S3b = [&](int gi) { return reinterpret_cast<u4*>(sbase + gi * S::TERM_BYTES); };
+    auto S2b = [&](int gi) { return S3b(gi) + NMAX * 64; };
+    auto S1b = [&](int gi) { return S2b(gi) + NMAX * 64; };
+    uint32_t xoff[TPW];
+    for (int t = 0; t < TPW; ++t) xoff[t] = slice_offset_lp<K>(wave * TPW + t, g, r);
+    for (int m0 = tp.m1; m0 <= tp.m2; m0 += GT) {
+        const int gn = __builtin_amdgcn_readfirstlane(min(GT, tp.m2 - m0 + 1));
+        // stage the super-blocks of the pass's terms (the previous pass ended with a barrier)
+        if constexpr (!BF) {
+            const int per = (n1 + n2 + n3) * 256;
+            for (int e = threadIdx.x; e < gn * per; e += CT) {
+                const int gi = e / per, ee = e % per;
+                const int sb = ee >> 8, v = (ee >> 4) & 15, uu = ee & 15;
+                const int m = m0 + gi;
+                const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+                int q, d;
+                if (sb < n1) { q = sb; d = 0; }
+                else if (sb < n1 + n2) { q = sb - n1; d = 1; }
+                else { q = sb - n1 - n2; d = 2; }
+                const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
+                float* dst = (d == 0 ? S1f(gi) : d == 1 ? S2f(gi) : S3f(gi)) + (q * 16 + v) * SF_V;
+                dst[uu] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v));
+            }
+        } else {
+            const int per = (n1 + n2 + n3) * 64;
+            for (int e = threadIdx.x; e < gn * per; e += CT) {
+                const int gi = e / per, ee = e % per;
+                const int sb = ee >> 6, uu = (ee >> 2) & 15, gg = ee & 3;
+                const int m = m0 + gi;
+                const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+                int q, d;
+                if (sb < n1) { q = sb; d = 0; }
+                else if (sb < n1 + n2) { q = sb - n1; d = 1; }
+                else { q = sb - n1 - n2; d = 2; }
+                const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
+                f4 v4;
+                for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, 4 * gg + c));
+                (d == 0 ? S1b(gi) : d == 1 ? S2b(gi) : S3b(gi))[(q * 16 + uu) * 4 + gg] = split4(v4);
+            }
+        }
+        lds_barrier();
+        f4 T1[GT][TPW], T2[GT][TPW];
+        for (int gi = 0; gi < GT; ++gi)
+            for (int t = 0; t < TPW; ++t) T1[gi][t] = T2[gi][t] = (f4){0.f, 0.f, 0.f, 0.f};
+        for (int si = 0; si < ns; ++si) {
+            const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
+            const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
+            const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
+            const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
+            const bool real = idx < lv.nreal;
+            const int64_t qi = real ? idx : idx - lv.nreal;
+            const void* X = BF ? (const void*)((const char*)(real ? lv.Xrb : lv.Xgb) + qi * ELP)
+                               : (const void*)((const char*)(real ? lv.Xr32 : lv.Xg32) + qi * ELP);
+            u4 xb[TPW];
+            load_slices_lp<TPW>(X, (int)ELP, xoff, xb);
+            // mode 3 for every term of the pass
+            if constexpr (!BF) {
+                f4 xf[TPW];
+                for (int t = 0; t < TPW; ++t) xf[t] = __builtin_bit_cast(f4, xb[t]);
+                for (int gi = 0; gi < GT; ++gi) {
+                    if (gi >= gn) break;
+                    const float* s3p = S3f(gi) + q3 * 16 * SF_V + r;
+                    float s3[4];
+                    for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * SF_V];
+                    for (int kk = 0; kk < 4; ++kk)
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D)
+                                T1[gi][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xf[t][kk], s3[kk], T1[gi][t], 0, 0, 0);
+                }
+            } else {
+                for (int gi = 0; gi < GT; ++gi) {
+                    if (gi >= gn) break;
+                    const u4 s3 = S3b(gi)[(q3 * 16 + r) * 4 + g];
+                    for (int t = 0; t < TPW; ++t)
+                        if (FULL || wave * TPW + t < D) T1[gi][t] = mfma_bf16x<PREC == PREC_BF16C>(xb[t], s3, T1[gi][t]);
+                }
+            }
+            if (next < 0 || (next >> 2) != (cell >> 2)) {
+                // end of an (L1, L2) row -- mode 2 for every term
+                for (int gi = 0; gi < GT; ++gi) {
+                    if (gi >= gn) break;
+                    if constexpr (!BF) {
+                        const float* s2p = S2f(gi) + q2 * 16 * SF_V + r;
+                        float s2[4];
+                        for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * g + i) * SF_V];
+                        for (int i = 0; i < 4; ++i)
+                            for (int t = 0; t < TPW; ++t)
+                                if (FULL || wave * TPW + t < D)
+                                    T2[gi][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2[i], T1[gi][t][i], T2[gi][t], 0, 0, 0);
+                    } else {
+                        const u4 s2 = S2b(gi)[(q2 * 16 + r) * 4 + g];
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D)
+                                T2[gi][t] = mfma_bf16x<PREC == PREC_BF16C>(s2, split4(T1[gi][t]), T2[gi][t]);
+                    }
+                    for (int t = 0; t < TPW; ++t) T1[gi][t] = (f4){0.f, 0.f, 0.f, 0.f};
+                }
+            }
+            if (next < 0 || (next >> 4) != (cell >> 4)) {
+                // end of an L1 plane -- mode 1, term by term through the one LDS transpose buffer
+                for (int gi = 0; gi < GT; ++gi) {
+                    if (gi >= gn) break;
+                    for (int t = 0; t < TPW; ++t) {
+                        const int v1 = wave * TPW + t;
+                        if (!FULL && v1 >= D) break;
+                        for (int i = 0; i < 4; ++i) T2f[v1 * T2F_V1 + (4 * g + i) * T2F_U2 + r] = T2[gi][t][i];
+                    }
+                    lds_barrier();
+                    for (int t = 0; t < TPW; ++t) {
+                        const int u2 = wave * TPW + t;
+                        if (!FULL && u2 >= D) break;
+                        f4 acc = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (!BF) {
+                            const float* s1p = S1f(gi) + q1 * 16 * SF_V + perm_row(r);
+                            for (int kk = 0; kk < 4; ++kk) {
+                                const int v1 = 4 * g + kk;
+                                const float bv = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(s1p[v1 * SF_V], bv, acc, 0, 0, 0);
+                            }
+                        } else {
+                            f4 bv;
+                            for (int j = 0; j < 4; ++j) {
+                                const int v1 = 4 * g + j;
+                                bv[j] = v1 < D ? T2f[v1 * T2F_V1 + u2 * T2F_U2 + r] : 0.f;
+                            }
+                            acc = mfma_bf16x<PREC == PREC_BF16C>(S1b(gi)[(q1 * 16 + perm_row(r)) * 4 + g], split4(bv), acc);
+                        }
+                        const d4 add = (d4){(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+                        if (!tp.dpart) {
+                            Y[t] += add;
+                            continue;
+                        }
+                        for (int i = 0; i < 4; ++i) {
+                            const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
+                            if ((cmb >> child) & 1) Y[t][i] += add[i];
+                        }
+                    }
+                    for (int t = 0; t < TPW; ++t) T2[gi][t] = (f4){0.f, 0.f, 0.f, 0.f};
+                    lds_barrier();
+                }
+            }
+        }
+    }
+}
+
 // One block per output brick, over all levels at once (order[] lists (level, brick)).  CW waves
 // per block, each owning TPW input slices; PF steps of input slices are prefetched into registers.
 // For every job the in-cube cells of its box are first compacted into an LDS list (ascending L1,
@@ -411,7 +595,8 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
         lds_barrier();
         const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
         if (ns == 0) continue;
-        run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
+        if constexpr (PREC == PREC_F64) run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
+        else run_job_lp<K, CW, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
     }
     for (int t = 0; t < TPW; ++t) {
         const int u2 = wave * TPW + t;
@@ -432,7 +617,7 @@ template <int K, int CW, int PF, int WPE, int PREC>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues,
                 int accumulate) {
-    __shared__ double smem[SMEM_DOUBLES];
+    __shared__ double smem[smem_doubles<PREC, K>()];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
