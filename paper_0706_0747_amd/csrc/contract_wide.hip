@@ -2,15 +2,19 @@
 //
 // Same method as contract.hip (sibling-group bricks, 2k x 2k super-blocks S^{j;m,L} per
 // dimension, the nested-loop factorisation of Sec. 5 over boxes of coarse displacements, the
-// coefficient rule c_m = [m in R_j(L)] - [b internal][m in R_{j+1}(l)]), with every dimension of
-// the brick covered by two 16-wide MFMA tiles: v_mfma_f64_16x16x4 (A[m][k] in lane m+16k, B[k][n]
-// in lane n+16k, D[4i+g][n] in lane 16g+n, register i).  A workgroup computes one half of the
-// output columns u3 (16c .. 16c+15) of one output brick; 10 waves own two input slices v1 each.
-//   mode 3, per slice and row tile a (v2 = 16a + r): contraction over v3 in five K-steps
-//     (v3 = 4g + s for s < 4 from four consecutive doubles, then v3 = 16 + g);
-//   mode 2, per row tile b of u2, straight from the mode-3 accumulators: tile a = 0 register i
-//     holds v2 = 4i + g, tile a = 1 register 0 holds v2 = 16 + g -- again five K-steps;
-//   mode 1 through an LDS transpose of the mode-2 result, five K-steps over v1.
+// coefficient rule c_m = [m in R_j(L)] - [b internal][m in R_{j+1}(l)]).  Every dimension of the
+// brick is split 16 + 4: the first 16 indices go through v_mfma_f64_16x16x4 (A[m][k] in lane
+// m+16k, B[k][n] in lane n+16k, D[4i+g][n] in lane 16g+n, register i), the last (up to) 4 through
+// v_mfma_f64_4x4x4 with four blocks (A[i][k] of block b in lane i+4b+16k, B[k][j] in lane
+// j+4b+16k, D[i][j] in lane j+4b+16i), its four blocks spanning the 16 columns of the other tile,
+// so that a 4-row tail costs a quarter of a 16-row tile and lands in the lane layout of a
+// 16x16x4 result row 16+g.  A workgroup computes one half of the output columns u3 (16c ..
+// 16c+15) of one output brick; 10 waves own two input slices v1 each.
+//   mode 3, per slice: rows v2 < 16 by 16x16x4, rows 16..19 by 4x4x4, contraction over v3 in
+//     five K-steps (v3 = 4g + s for s < 4 from four consecutive doubles, then v3 = 16 + g);
+//   mode 2, straight from the mode-3 accumulators (register i holds v2 = 4i + g, the tail holds
+//     v2 = 16 + g): rows u2 < 16 by 16x16x4, rows 16..19 by 4x4x4, again five K-steps;
+//   mode 1 through an LDS transpose of the mode-2 result, rows u1 split the same way.
 #include <algorithm>
 
 #include "contract.h"
@@ -71,18 +75,25 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
     double* S3s = smem + W::SM_T2;
     double* S2s = S3s + W::SM_S3;
     double* S1s = S2s + W::SM_SA;
-    // byte offsets of lane (g, r)'s loads in a brick: four doubles X[v1][16a + r][4g..4g+3] and
-    // one double X[v1][16a + r][16 + g]; invalid ones point past the buffer (the load returns 0)
+    // byte offsets of lane (g, r)'s loads in a brick: four doubles X[v1][v2][4g..4g+3] and one
+    // double X[v1][v2][16 + g], v2 = r for the 16-row tile and 16 + (r & 3) for the tail (the
+    // tail's A operand repeats over the four blocks); invalid ones point past the buffer (the
+    // load returns 0)
     uint32_t off4[TPW][2], off1[TPW][2];
     for (int t = 0; t < TPW; ++t)
         for (int a = 0; a < 2; ++a) {
-            const int v1 = wave * TPW + t, v2 = 16 * a + r;
+            const int v1 = wave * TPW + t, v2 = a == 0 ? r : 16 + (r & 3);
             const bool ok = v1 < D && v2 < D;
             off4[t][a] = ok ? (uint32_t)(((v1 * D + v2) * D + 4 * g) * 8) : 0x40000000u;
             off1[t][a] = ok && 16 + g < D ? (uint32_t)(((v1 * D + v2) * D + 16 + g) * 8) : 0x40000000u;
         }
-    d4 Y[TPW][2];
-    for (int t = 0; t < TPW; ++t) Y[t][0] = Y[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+    // Y[t]: rows u1 = 4i + g; Yt[t]: row u1 = 16 + g (columns u3 = 16c + r, u2 = wave * TPW + t)
+    d4 Y[TPW];
+    double Yt[TPW];
+    for (int t = 0; t < TPW; ++t) {
+        Y[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        Yt[t] = 0.0;
+    }
     for (int ti = 0; ti < lv.ntpl; ++ti) {
         const Tpl tp = lv.tpl[ti];
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
@@ -106,8 +117,14 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
         if (ns == 0) continue;
         const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
         int m = tp.m1, si = 0;
-        d4 T1[TPW][2], T2[TPW][2];
-        for (int t = 0; t < TPW; ++t) T1[t][0] = T1[t][1] = T2[t][0] = T2[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+        // T1[t] / T1t[t]: mode-3 result rows v2 = 4i + g / 16 + g; T2[t] / T2t[t]: mode-2 result
+        // rows u2 = 4i + g / 16 + g; columns u3 = 16c + r throughout
+        d4 T1[TPW], T2[TPW];
+        double T1t[TPW], T2t[TPW];
+        for (int t = 0; t < TPW; ++t) {
+            T1[t] = T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
+            T1t[t] = T2t[t] = 0.0;
+        }
         for (int s = 0; s < total; ++s) {
             if (si == 0) {
                 // stage this term's masked super-blocks (cw folded into S1): S1, S2 as [L][v][u < 32],
@@ -146,44 +163,62 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                 typedef double dv2 __attribute__((ext_vector_type(2)));
                 for (int t = 0; t < TPW; ++t) {
                     if (!FULL && wave * TPW + t >= D) break;
-                    for (int a = 0; a < 2; ++a) {
-                        const dv2 x01 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a], 0, 0));
-                        const dv2 x23 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a] + 16, 0, 0));
-                        const double x4 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off1[t][a], 0, 0));
-                        d4 acc = T1[t][a];
+                    {
+                        const dv2 x01 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][0], 0, 0));
+                        const dv2 x23 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][0] + 16, 0, 0));
+                        const double x4 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off1[t][0], 0, 0));
+                        d4 acc = T1[t];
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x01.x, s3[0], acc, 0, 0, 0);
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x01.y, s3[1], acc, 0, 0, 0);
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x23.x, s3[2], acc, 0, 0, 0);
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x23.y, s3[3], acc, 0, 0, 0);
-                        T1[t][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(x4, s3[4], acc, 0, 0, 0);
+                        T1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x4, s3[4], acc, 0, 0, 0);
+                    }
+                    {
+                        const dv2 x01 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][1], 0, 0));
+                        const dv2 x23 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][1] + 16, 0, 0));
+                        const double x4 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off1[t][1], 0, 0));
+                        double acc = T1t[t];
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x01.x, s3[0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x01.y, s3[1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x23.x, s3[2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x23.y, s3[3], acc, 0, 0, 0);
+                        T1t[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(x4, s3[4], acc, 0, 0, 0);
                     }
                 }
             }
             if (next < 0 || (next >> 2) != (cell >> 2)) {
                 // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
-                for (int bt = 0; bt < 2; ++bt) {
-                    double s2[5];
-                    for (int i = 0; i < 4; ++i) s2[i] = S2s[(q2 * D + 4 * i + g) * WSA_V + 16 * bt + r];
-                    s2[4] = 16 + g < D ? S2s[(q2 * D + 16 + g) * WSA_V + 16 * bt + r] : 0.0;
-                    for (int t = 0; t < TPW; ++t) {
-                        if (!FULL && wave * TPW + t >= D) break;
-                        d4 acc = T2[t][bt];
-                        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][0][i], acc, 0, 0, 0);
-                        T2[t][bt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[4], T1[t][1][0], acc, 0, 0, 0);
-                    }
+                double s2[5], s2t[5];
+                for (int i = 0; i < 4; ++i) {
+                    s2[i] = S2s[(q2 * D + 4 * i + g) * WSA_V + r];
+                    s2t[i] = S2s[(q2 * D + 4 * i + g) * WSA_V + 16 + (r & 3)];
                 }
-                for (int t = 0; t < TPW; ++t) T1[t][0] = T1[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+                s2[4] = 16 + g < D ? S2s[(q2 * D + 16 + g) * WSA_V + r] : 0.0;
+                s2t[4] = 16 + g < D ? S2s[(q2 * D + 16 + g) * WSA_V + 16 + (r & 3)] : 0.0;
+                for (int t = 0; t < TPW; ++t) {
+                    if (!FULL && wave * TPW + t >= D) break;
+                    d4 acc = T2[t];
+                    double acct = T2t[t];
+                    for (int i = 0; i < 4; ++i) {
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[t][i], acc, 0, 0, 0);
+                        acct = __builtin_amdgcn_mfma_f64_4x4x4f64(s2t[i], T1[t][i], acct, 0, 0, 0);
+                    }
+                    T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[4], T1t[t], acc, 0, 0, 0);
+                    T2t[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(s2t[4], T1t[t], acct, 0, 0, 0);
+                }
+                for (int t = 0; t < TPW; ++t) {
+                    T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
+                    T1t[t] = 0.0;
+                }
             }
             if (next < 0 || (next >> 4) != (cell >> 4)) {
                 // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
                 for (int t = 0; t < TPW; ++t) {
                     const int v1 = wave * TPW + t;
                     if (!FULL && v1 >= D) break;
-                    for (int bt = 0; bt < 2; ++bt)
-                        for (int i = 0; i < 4; ++i) {
-                            const int u2 = 16 * bt + 4 * i + g;
-                            if (u2 < D) T2s[v1 * W::T2_V1 + u2 * 16 + r] = T2[t][bt][i];
-                        }
+                    for (int i = 0; i < 4; ++i) T2s[v1 * W::T2_V1 + (4 * i + g) * 16 + r] = T2[t][i];
+                    if (16 + g < D) T2s[v1 * W::T2_V1 + (16 + g) * 16 + r] = T2t[t];
                 }
                 wlds_barrier();
                 for (int t = 0; t < TPW; ++t) {
@@ -192,25 +227,33 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                     double bv[5];
                     for (int kk = 0; kk < 4; ++kk) bv[kk] = T2s[(4 * kk + g) * W::T2_V1 + u2 * 16 + r];
                     bv[4] = 16 + g < D ? T2s[(16 + g) * W::T2_V1 + u2 * 16 + r] : 0.0;
-                    for (int bt = 0; bt < 2; ++bt) {
-                        // the down band reaches only internal children: accumulate it apart, add it masked
-                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t][bt];
-                        for (int kk = 0; kk < 4; ++kk)
-                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + 16 * bt + r], bv[kk], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + 16 * bt + r] : 0.0,
-                                                                   bv[4], acc, 0, 0, 0);
-                        if (tp.dpart) {
-                            for (int i = 0; i < 4; ++i) {
-                                const int u1 = 16 * bt + 4 * i + g, u3 = 16 * c + r;
-                                const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
-                                if ((cmb >> child) & 1) Y[t][bt][i] += acc[i];
-                            }
-                        } else {
-                            Y[t][bt] = acc;
+                    // the down band reaches only internal children: accumulate it apart, add it masked
+                    d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
+                    double acct = tp.dpart ? 0.0 : Yt[t];
+                    for (int kk = 0; kk < 4; ++kk) {
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + r], bv[kk], acc, 0, 0, 0);
+                        acct = __builtin_amdgcn_mfma_f64_4x4x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + 16 + (r & 3)], bv[kk], acct, 0, 0, 0);
+                    }
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + r] : 0.0, bv[4], acc, 0, 0, 0);
+                    acct = __builtin_amdgcn_mfma_f64_4x4x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + 16 + (r & 3)] : 0.0,
+                                                              bv[4], acct, 0, 0, 0);
+                    if (tp.dpart) {
+                        const int u3 = 16 * c + r;
+                        for (int i = 0; i < 4; ++i) {
+                            const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+                            if ((cmb >> child) & 1) Y[t][i] += acc[i];
                         }
+                        const int child = 1 + 2 * (u2 >= K) + 4 * (u3 >= K);   // u1 = 16 + g >= K
+                        if ((cmb >> child) & 1) Yt[t] += acct;
+                    } else {
+                        Y[t] = acc;
+                        Yt[t] = acct;
                     }
                 }
-                for (int t = 0; t < TPW; ++t) T2[t][0] = T2[t][1] = (d4){0.0, 0.0, 0.0, 0.0};
+                for (int t = 0; t < TPW; ++t) {
+                    T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
+                    T2t[t] = 0.0;
+                }
                 wlds_barrier();
             }
             if (++si == ns) {
@@ -224,13 +267,16 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
     for (int t = 0; t < TPW; ++t) {
         const int u2 = wave * TPW + t;
         if (u2 >= D || u3 >= D) break;
-        for (int bt = 0; bt < 2; ++bt)
-            for (int i = 0; i < 4; ++i) {
-                const int u1 = 16 * bt + 4 * i + g;
-                if (u1 >= D) continue;
-                const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
-                ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][bt][i] : 0.0;
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int u1 = 4 * i + g;
+            const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+            ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Y[t][i] : 0.0;
+        }
+        const int u1 = 16 + g;
+        if (u1 < D) {
+            const int child = 1 + 2 * (u2 >= K) + 4 * (u3 >= K);
+            ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? Yt[t] : 0.0;
+        }
     }
 }
 
