@@ -8,13 +8,17 @@
 // v_mfma_f64_4x4x4 with four blocks (A[i][k] of block b in lane i+4b+16k, B[k][j] in lane
 // j+4b+16k, D[i][j] in lane j+4b+16i), its four blocks spanning the 16 columns of the other tile,
 // so that a 4-row tail costs a quarter of a 16-row tile and lands in the lane layout of a
-// 16x16x4 result row 16+g.  A workgroup computes one half of the output columns u3 (16c ..
-// 16c+15) of one output brick; 10 waves own two input slices v1 each.
+// 16x16x4 result row 16+g.  A workgroup computes the output columns u3 < 16 of one output brick,
+// or its last (up to) four columns u3 = 16 + j; 10 waves own two input slices v1 each.
 //   mode 3, per slice: rows v2 < 16 by 16x16x4, rows 16..19 by 4x4x4, contraction over v3 in
 //     five K-steps (v3 = 4g + s for s < 4 from four consecutive doubles, then v3 = 16 + g);
 //   mode 2, straight from the mode-3 accumulators (register i holds v2 = 4i + g, the tail holds
 //     v2 = 16 + g): rows u2 < 16 by 16x16x4, rows 16..19 by 4x4x4, again five K-steps;
 //   mode 1 through an LDS transpose of the mode-2 result, rows u1 split the same way.
+// The last-columns workgroup uses the 4x4x4 form only: in modes 3 and 2 its four blocks take
+// the four groups v2 = 4b + i of rows 0..15 (block b's result in mode 2 is a partial sum over its
+// group, the blocks summed across lanes at the end of a plane), rows 16..19 once more with one
+// block live; in mode 1 the blocks take the output rows u1 = 4b + i.
 #include <algorithm>
 
 #include "contract.h"
@@ -54,7 +58,7 @@ __device__ inline double wsop(const double* __restrict__ Fm, int L, int mlo, int
 
 __device__ inline void wlds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <int K>
+template <int K, bool TAIL>
 __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict__ levels, int2 job, double* smem,
                                                     int2* steps, int* nsteps) {
     using W = Wide<K>;
@@ -65,7 +69,8 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const LevelDesc lv = levels[job.x];
     const int64_t b = job.y >> 1;
-    const int c = job.y & 1;                        // output columns u3 = 16c + r
+    const int c = TAIL ? 1 : 0;                     // output columns u3 = 16c + r (16 + (r & 3) for the tail)
+    constexpr int UW = TAIL ? 4 : 16;               // staged columns of S3
     const double* __restrict__ w = lv.w;
     const int Lr = lv.Lr;
     const int NL = 2 * Lr + 1;
@@ -87,7 +92,8 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
             off4[t][a] = ok ? (uint32_t)(((v1 * D + v2) * D + 4 * g) * 8) : 0x40000000u;
             off1[t][a] = ok && 16 + g < D ? (uint32_t)(((v1 * D + v2) * D + 16 + g) * 8) : 0x40000000u;
         }
-    // Y[t]: rows u1 = 4i + g; Yt[t]: row u1 = 16 + g (columns u3 = 16c + r, u2 = wave * TPW + t)
+    // Y[t]: rows u1 = 4i + g; Yt[t]: row u1 = 16 + g (columns u3 = 16c + r, u2 = wave * TPW + t).
+    // Tail: Y[t][0]: row u1 = 4(r >> 2) + g, Yt[t]: row u1 = 16 + g, columns u3 = 16 + (r & 3).
     d4 Y[TPW];
     double Yt[TPW];
     for (int t = 0; t < TPW; ++t) {
@@ -118,12 +124,15 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
         const int total = __builtin_amdgcn_readfirstlane((tp.m2 - tp.m1 + 1) * ns);
         int m = tp.m1, si = 0;
         // T1[t] / T1t[t]: mode-3 result rows v2 = 4i + g / 16 + g; T2[t] / T2t[t]: mode-2 result
-        // rows u2 = 4i + g / 16 + g; columns u3 = 16c + r throughout
+        // rows u2 = 4i + g / 16 + g; columns u3 = 16c + r throughout.
+        // Tail: T1[t][0]: rows v2 = 4(r >> 2) + g, T1t[t]: rows v2 = 16 + g; T2u[t][q]: block
+        // (r >> 2)'s partial sum of rows u2 = 4q + g; columns u3 = 16 + (r & 3).
         d4 T1[TPW], T2[TPW];
-        double T1t[TPW], T2t[TPW];
+        double T1t[TPW], T2t[TPW], T2u[TPW][5];
         for (int t = 0; t < TPW; ++t) {
             T1[t] = T2[t] = (d4){0.0, 0.0, 0.0, 0.0};
             T1t[t] = T2t[t] = 0.0;
+            for (int q = 0; q < 5; ++q) T2u[t][q] = 0.0;
         }
         for (int s = 0; s < total; ++s) {
             if (si == 0) {
@@ -131,7 +140,7 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                 // S3 as [L][v3][u3 of this half]
                 const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
                 const double cw = tp.dpart ? -w[m] : w[m];
-                const int nA = (n1 + n2) * D * 32, nS3 = n3 * D * 16;
+                const int nA = (n1 + n2) * D * 32, nS3 = n3 * D * UW;
                 for (int e = threadIdx.x; e < nA + nS3; e += WCT) {
                     if (e < nA) {
                         const int u = e & 31, v = (e >> 5) % D, sb = (e >> 5) / D;
@@ -142,7 +151,7 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                         }
                     } else {
                         const int e3 = e - nA;
-                        const int ul = e3 & 15, v = (e3 >> 4) % D, q = (e3 >> 4) / D;
+                        const int ul = e3 % UW, v = (e3 / UW) % D, q = (e3 / UW) / D;
                         S3s[(q * D + v) * WS3_V + ul] = wsop<K>(Fm, tp.lo[2] + q, tp.mlo[2], tp.mhi[2], 16 * c + ul, v);
                     }
                 }
@@ -156,11 +165,31 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
             const double* X = idx < lv.nreal ? lv.Xr + idx * E : lv.Xg + (idx - lv.nreal) * E;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)(E * 8), 0x00020000);
             // mode 3: T1 += X x_3 S3^{L3}
-            {
+            typedef double dv2 __attribute__((ext_vector_type(2)));
+            if constexpr (TAIL) {
+                double s3[5];
+                for (int kk = 0; kk < 4; ++kk) s3[kk] = S3s[(q3 * D + 4 * g + kk) * WS3_V + (r & 3)];
+                s3[4] = 16 + g < D ? S3s[(q3 * D + 16 + g) * WS3_V + (r & 3)] : 0.0;
+                for (int t = 0; t < TPW; ++t) {
+                    if (!FULL && wave * TPW + t >= D) break;
+                    for (int a = 0; a < 2; ++a) {
+                        const dv2 x01 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a], 0, 0));
+                        const dv2 x23 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, off4[t][a] + 16, 0, 0));
+                        const double x4 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off1[t][a], 0, 0));
+                        double acc = a == 0 ? T1[t][0] : T1t[t];
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x01.x, s3[0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x01.y, s3[1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x23.x, s3[2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x23.y, s3[3], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(x4, s3[4], acc, 0, 0, 0);
+                        if (a == 0) T1[t][0] = acc;
+                        else T1t[t] = acc;
+                    }
+                }
+            } else {
                 double s3[5];
                 for (int kk = 0; kk < 4; ++kk) s3[kk] = S3s[(q3 * D + 4 * g + kk) * WS3_V + r];
                 s3[4] = 16 + g < D ? S3s[(q3 * D + 16 + g) * WS3_V + r] : 0.0;
-                typedef double dv2 __attribute__((ext_vector_type(2)));
                 for (int t = 0; t < TPW; ++t) {
                     if (!FULL && wave * TPW + t >= D) break;
                     {
@@ -189,6 +218,22 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
             }
             if (next < 0 || (next >> 2) != (cell >> 2)) {
                 // end of an (L1, L2) row -- mode 2: T2 += S2^{L2} x_2 T1
+                if constexpr (TAIL) {
+                    // block b = r >> 2 contracts its own rows v2 = 4b + k of T1[t][0]; rows 16..19
+                    // (T1t, the same in every block) go through block 0 only
+                    double sa[5], sb[5];
+                    for (int q = 0; q < 5; ++q) {
+                        sa[q] = S2s[(q2 * D + 4 * (r >> 2) + g) * WSA_V + 4 * q + (r & 3)];
+                        sb[q] = r < 4 && 16 + g < D ? S2s[(q2 * D + 16 + g) * WSA_V + 4 * q + (r & 3)] : 0.0;
+                    }
+                    for (int t = 0; t < TPW; ++t) {
+                        if (!FULL && wave * TPW + t >= D) break;
+                        for (int q = 0; q < 5; ++q) {
+                            const double acc = __builtin_amdgcn_mfma_f64_4x4x4f64(sa[q], T1[t][0], T2u[t][q], 0, 0, 0);
+                            T2u[t][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(sb[q], T1t[t], acc, 0, 0, 0);
+                        }
+                    }
+                } else {
                 double s2[5], s2t[5];
                 for (int i = 0; i < 4; ++i) {
                     s2[i] = S2s[(q2 * D + 4 * i + g) * WSA_V + r];
@@ -207,6 +252,7 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                     T2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[4], T1t[t], acc, 0, 0, 0);
                     T2t[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(s2t[4], T1t[t], acct, 0, 0, 0);
                 }
+                }
                 for (int t = 0; t < TPW; ++t) {
                     T1[t] = (d4){0.0, 0.0, 0.0, 0.0};
                     T1t[t] = 0.0;
@@ -214,6 +260,49 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
             }
             if (next < 0 || (next >> 4) != (cell >> 4)) {
                 // end of an L1 plane -- mode 1 through an LDS transpose: Y += S1^{L1} x_1 T2
+                if constexpr (TAIL) {
+                    // sum the four blocks' partial results (lanes r, r ^ 4, r ^ 8, r ^ 12), store
+                    // T2[v1][u2 = 4q + g][16 + r] from lanes r < 4
+                    for (int t = 0; t < TPW; ++t) {
+                        const int v1 = wave * TPW + t;
+                        if (!FULL && v1 >= D) break;
+                        for (int q = 0; q < 5; ++q) {
+                            double v = T2u[t][q];
+                            v += __shfl_xor(v, 4);
+                            v += __shfl_xor(v, 8);
+                            if (r < 4 && 4 * q + g < D) T2s[v1 * W::T2_V1 + (4 * q + g) * 16 + r] = v;
+                            T2u[t][q] = 0.0;
+                        }
+                    }
+                    wlds_barrier();
+                    for (int t = 0; t < TPW; ++t) {
+                        const int u2 = wave * TPW + t;
+                        if (!FULL && u2 >= D) break;
+                        // B[k][j] = T2[v1][u2][16 + j], the same in every block; block b = r >> 2
+                        // yields rows u1 = 4b + g, the second chain rows u1 = 16 + g
+                        double bv[5];
+                        for (int kk = 0; kk < 4; ++kk) bv[kk] = T2s[(4 * kk + g) * W::T2_V1 + u2 * 16 + (r & 3)];
+                        bv[4] = 16 + g < D ? T2s[(16 + g) * W::T2_V1 + u2 * 16 + (r & 3)] : 0.0;
+                        double acc = 0.0, acct = 0.0;
+                        for (int kk = 0; kk < 4; ++kk) {
+                            acc = __builtin_amdgcn_mfma_f64_4x4x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + r], bv[kk], acc, 0, 0, 0);
+                            acct = __builtin_amdgcn_mfma_f64_4x4x4f64(S1s[(q1 * D + 4 * kk + g) * WSA_V + 16 + (r & 3)], bv[kk], acct, 0, 0, 0);
+                        }
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + r] : 0.0, bv[4], acc, 0, 0, 0);
+                        acct = __builtin_amdgcn_mfma_f64_4x4x4f64(16 + g < D ? S1s[(q1 * D + 16 + g) * WSA_V + 16 + (r & 3)] : 0.0,
+                                                                  bv[4], acct, 0, 0, 0);
+                        if (tp.dpart) {
+                            // u3 = 16 + (r & 3) >= K: the z parity bit is set
+                            const int u1 = 4 * (r >> 2) + g;
+                            if ((cmb >> ((u1 >= K) + 2 * (u2 >= K) + 4)) & 1) Y[t][0] += acc;
+                            if ((cmb >> (1 + 2 * (u2 >= K) + 4)) & 1) Yt[t] += acct;
+                        } else {
+                            Y[t][0] += acc;
+                            Yt[t] += acct;
+                        }
+                    }
+                    wlds_barrier();
+                } else {
                 for (int t = 0; t < TPW; ++t) {
                     const int v1 = wave * TPW + t;
                     if (!FULL && v1 >= D) break;
@@ -255,6 +344,7 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
                     T2t[t] = 0.0;
                 }
                 wlds_barrier();
+                }
             }
             if (++si == ns) {
                 si = 0;
@@ -263,6 +353,20 @@ __device__ __forceinline__ void contract_brick_wide(const LevelDesc* __restrict_
         }
     }
     double* ob = lv.out + b * E;
+    if constexpr (TAIL) {
+        for (int t = 0; t < TPW; ++t) {
+            const int u2 = wave * TPW + t;
+            if (u2 >= D) break;
+            const int u3 = 16 + (r & 3);
+            if (u3 < D) {
+                const int u1 = 4 * (r >> 2) + g;
+                ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> ((u1 >= K) + 2 * (u2 >= K) + 4)) & 1) ? Y[t][0] : 0.0;
+                if (r < 4 && 16 + g < D)
+                    ob[((int64_t)(16 + g) * D + u2) * D + u3] = ((lv.valid >> (1 + 2 * (u2 >= K) + 4)) & 1) ? Yt[t] : 0.0;
+            }
+        }
+        return;
+    }
     const int u3 = 16 * c + r;
     for (int t = 0; t < TPW; ++t) {
         const int u2 = wave * TPW + t;
@@ -288,7 +392,9 @@ ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restric
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
-        contract_brick_wide<K>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        const int2 job = order[blockIdx.x];
+        if (job.y & 1) contract_brick_wide<K, true>(levels, job, smem, steps, &nsteps_s);
+        else contract_brick_wide<K, false>(levels, job, smem, steps, &nsteps_s);
         return;
     }
     const int x0 = blockIdx.x % NXCD;
@@ -311,7 +417,9 @@ ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restric
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0) break;
-        contract_brick_wide<K>(levels, order[pos], smem, steps, &nsteps_s);
+        const int2 job = order[pos];
+        if (job.y & 1) contract_brick_wide<K, true>(levels, job, smem, steps, &nsteps_s);
+        else contract_brick_wide<K, false>(levels, job, smem, steps, &nsteps_s);
     }
 }
 
