@@ -130,7 +130,7 @@ def mixed_measurement(M, ctx, w, f, op, g64, st64, reps):
 def batch_measurement(M, ctx, reps, nmembers=64):
     """The batch of uneven solves (seeded members of mixed kernels, k and eps): total contractions
     per second for sequential single applies, one batched persistent apply, and replays of the
-    captured apply plan."""
+    captured apply plan, in FP64 and precision-routed at tol = eps ||g|| per member."""
     import torch
     members = [workloads_member(i) for i in range(nmembers)]
     kept = members
@@ -143,6 +143,9 @@ def batch_measurement(M, ctx, reps, nmembers=64):
         fs.append(f)
     _, st = M.mwns_apply_batch(ctx, ops, fs)
     plan = M.mwns_plan_create(ctx, ops, fs)
+    tols = [w.eps * M.mwns_apply(ctx, op, f)[1]["g_norm"] for w, op, f in zip(kept, ops, fs)]
+    _, stm = M.mwns_apply_batch(ctx, ops, fs, mixed=tols)
+    planm = M.mwns_plan_create(ctx, ops, fs, mixed=tols)
 
     def timed(fn):
         fn()
@@ -156,13 +159,20 @@ def batch_measurement(M, ctx, reps, nmembers=64):
     ms_seq = timed(lambda: [M.mwns_apply(ctx, op, f, stats=False) for op, f in zip(ops, fs)])
     ms_batch = timed(lambda: M.mwns_apply_batch(ctx, ops, fs, stats=False))
     ms_plan = timed(plan.execute)
+    ms_batch_mixed = timed(lambda: M.mwns_apply_batch(ctx, ops, fs, mixed=tols, stats=False))
+    ms_plan_mixed = timed(planm.execute)
     plan.close()
+    planm.close()
     nodes = sum(M.mwns_tree_get_info(f)["nnodes"] for f in fs)
     c = st["contractions"]
     return {"members": len(kept), "orders": sorted({int(w.k) for w in kept}), "nodes": int(nodes),
             "contractions": int(c), "ms_sequential": ms_seq, "ms_batch": ms_batch, "ms_plan_replay": ms_plan,
             "contractions_per_s_sequential": c / (ms_seq * 1e-3), "contractions_per_s_batch": c / (ms_batch * 1e-3),
-            "contractions_per_s_plan": c / (ms_plan * 1e-3)}
+            "contractions_per_s_plan": c / (ms_plan * 1e-3),
+            "mixed": {"tol": "eps ||g|| per member", "ms_batch": ms_batch_mixed, "ms_plan_replay": ms_plan_mixed,
+                      "speedup_batch": ms_batch / ms_batch_mixed, "speedup_plan": ms_plan / ms_plan_mixed,
+                      "class_flop_share": {cl: stm["class_flops"][i] / stm["useful_flops"]
+                                           for i, cl in enumerate(("f64", "f32", "bf16c", "bf16"))}}}
 
 
 def workloads_member(i):
@@ -290,7 +300,7 @@ def main():
                      "variant": M.mwns_ctx_get_variant(ctx, w.k),
                      "flops_per_apply": st["useful_flops"]},
     }
-    if not args.no_mixed and w.k <= 8:
+    if not args.no_mixed:
         line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(M, ctx, w, f, op, g, st, args.steps)
     if not args.no_batch:
         line["batch"] = batch_measurement(M, ctx, args.steps)

@@ -25,7 +25,8 @@
  *    context per host thread.
  *  - Orders and sizes: 1 <= k <= 10 (basis order = number of Legendre polynomials per dimension;
  *    k <= 8 runs on the one-tile contraction kernel with every precision class and tile variant,
- *    9 <= k <= 10 on the two-tile kernel in FP64 only, whose routed applies keep every job FP64);
+ *    9 <= k <= 10 on the two-tile kernel with the FP64 and FP32 classes: there a routed apply
+ *    uses MWNS_CLASS_F32 if allowed and ignores the BF16 bits);
  *    tree levels 0..19.  Coefficient blocks are [a][b][c] with a the x degree, b the y degree and
  *    c the z degree (c fastest).  Keys are level << 57 | morton(lx, ly, lz) with the x bit lowest
  *    in each bit triple; a tree's canonical node order is ascending key.
@@ -215,7 +216,8 @@ mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int
 
 /* Precision classes of the mixed apply (bit mask of the reduced ones a call may use). */
 enum {
-    MWNS_CLASS_F32 = 1,       /* FP32 MFMA, FP32 inputs and accumulation */
+    MWNS_CLASS_F32 = 1,       /* FP32 MFMA, FP32 inputs and accumulation (for k > 8 the 4-row tails of
+                                 each mode product run in FP64) */
     MWNS_CLASS_BF16C = 2,     /* BF16 MFMA on hi/lo-split operands, all four partial products (compensated) */
     MWNS_CLASS_BF16 = 4       /* BF16 MFMA, one operand of every mode product rounded to BF16 */
 };

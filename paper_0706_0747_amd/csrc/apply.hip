@@ -347,13 +347,19 @@ __global__ void fill_kernel(double* p, int64_t n, double v) {
 
 // ---------------------------------------------------------------- precision routing
 // Rounding-error factors of the classes: a three-mode chain whose every mode has relative
-// operand errors a (matrix) and b (input) and an FP32 accumulation over at most 16 * NMAX products
-// computes (|S1| (x) |S2| (x) |S3|) |X| up to the factor ((1 + a + b + n u32)^3 - 1).
+// operand errors a (matrix) and b (input) and an FP32 accumulation over at most n = max(16, 2k)
+// * NMAX products computes (|S1| (x) |S2| (x) |S3|) |X| up to the factor ((1 + a + b + n u32)^3 - 1).
+// (The FP32 class of the two-tile kernel runs its 4-row tails in FP64, which the factor covers.)
 constexpr double U32 = 0x1p-24, UBF = 0x1p-8, USPLIT = 0x1p-16;
 constexpr double cube_minus_one(double d) { return (1.0 + d) * (1.0 + d) * (1.0 + d) - 1.0; }
-constexpr double NACC = 16.0 * NMAX * U32;
-constexpr double GAMMA[NPREC] = {0.0, cube_minus_one(2.0 * U32 + NACC), cube_minus_one(2.0 * (USPLIT + U32) + NACC),
-                                 cube_minus_one(UBF + USPLIT + 2.0 * U32 + NACC)};
+struct Gammas {
+    double g[NPREC];
+};
+Gammas class_gammas(int k) {
+    const double nacc = std::max(16.0, 2.0 * k) * NMAX * U32;
+    return Gammas{{0.0, cube_minus_one(2.0 * U32 + nacc), cube_minus_one(2.0 * (USPLIT + U32) + nacc),
+                   cube_minus_one(UBF + USPLIT + 2.0 * U32 + nacc)}};
+}
 // Relative time per unit of work, for the routing objective only.
 constexpr double COST[NPREC] = {1.0, 0.6, 0.3, 0.2};
 
@@ -367,7 +373,9 @@ struct RouteItem {
 // the FP64 contribution of the item over its whole level:
 //   || sum_b sum_{L in box} (S1 (x) S2 (x) S3) X_{b-L} || <= |w_m| prod_d sum_{L_d} ||S_d^{m,L_d}||_F ||X_level||,
 // each input brick feeding one output brick per displacement.  Returns the bound reached.
-double route(std::vector<RouteItem>& items, double tol, int allowed) {
+double route(std::vector<RouteItem>& items, double tol, int allowed, int k) {
+    const Gammas gm = class_gammas(k);
+    const double* GAMMA = gm.g;
     auto eval = [&](double lam, bool commit) {
         double err = 0.0;
         for (RouteItem& it : items) {
@@ -778,8 +786,8 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             }
         }
     }
-    // orders above 8 have no reduced-precision kernels: every job stays FP64
-    a.err_bound = route(items, opts.tol, a.k > KNARROW ? 0 : opts.classes);
+    // the two-tile kernel (orders above KNARROW) has the FP32 class only
+    a.err_bound = route(items, opts.tol, a.k > KNARROW ? (opts.classes & MWNS_CLASS_F32) : opts.classes, a.k);
     size_t pos = 0;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
@@ -805,7 +813,9 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             need32 = need32 || t.prec == PREC_F32;
             needbf = needbf || t.prec == PREC_BF16C || t.prec == PREC_BF16;
         }
-        const int64_t units = (int64_t)4 * 2 * a.k * 2 * a.k;     // 16-byte units per brick
+        // 16-byte units per brick: padded rows for the one-tile kernel, D^3 floats for the two-tile one
+        const int64_t D = 2 * a.k;
+        const int64_t units = a.k > KNARROW ? D * D * D / 4 : 4 * D * D;
         if (need32) {
             lw.xr32.reset(ctx, (size_t)lw.nout * units);
             if (lw.nghost) lw.xg32.reset(ctx, (size_t)lw.nghost * units);
@@ -823,6 +833,11 @@ void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         const double* xr = a.f->coef.p + a.f->lev[j].brick_off * E;
+        if (a.k > KNARROW) {
+            if (lw.xr32.p) launch_convert_wide(a.k, ctx->stream, lw.nout, xr, reinterpret_cast<float*>(lw.xr32.p));
+            if (lw.xg32.p) launch_convert_wide(a.k, ctx->stream, lw.nghost, lw.ghosts.p, reinterpret_cast<float*>(lw.xg32.p));
+            continue;
+        }
         if (lw.xr32.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xr32.p, false);
         if (lw.xg32.p) launch_convert(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lw.xg32.p, false);
         if (lw.xrb.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xrb.p, true);
@@ -893,8 +908,10 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
             }
-            if (k > KNARROW) {    // two-tile kernel: one job per column half of the brick
-                for (int half = 0; half < 2; ++half) cost[PREC_F64].push_back({c[PREC_F64], make_int2(di, (int)(2 * b + half))});
+            if (k > KNARROW) {    // two-tile kernel: one job per column part of the brick
+                for (int p = 0; p < NPREC; ++p)
+                    if (p == PREC_F64 || c[p] > 0.0)
+                        for (int half = 0; half < 2; ++half) cost[p].push_back({c[p], make_int2(di, (int)(2 * b + half))});
                 continue;
             }
             for (int p = 0; p < NPREC; ++p)
@@ -1128,7 +1145,7 @@ void build_launches(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& tree
             if (persistent) {
                 g.dqueue.reset(ctx, QUEUE_INTS);
                 g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
-                const int64_t res = g.k > KNARROW ? resident_blocks_wide(g.k, ctx->device)
+                const int64_t res = g.k > KNARROW ? resident_blocks_wide(g.k, g.prec, ctx->device)
                                                   : resident_blocks(g.k, g.variant, g.prec, ctx->device);
                 g.nblocks = std::min<int64_t>((int64_t)g.order.size(), res);
             } else {
@@ -1141,7 +1158,7 @@ void launch_contractions(mwns_ctx* ctx, Launches& Lz) {
     for (auto& g : Lz.groups) {
         if (g.order.empty()) continue;
         if (g.dqueue.p) zero_ints_kernel<<<1, 64, 0, ctx->stream>>>(g.dqueue.p, NXCD);
-        if (g.k > KNARROW) launch_contract_wide(g.k, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
+        if (g.k > KNARROW) launch_contract_wide(g.k, g.prec, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
         else
             launch_contract(g.k, g.variant, g.prec, g.prec != PREC_F64, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p,
                             g.dqueue.p);

@@ -28,7 +28,8 @@ constexpr int NMAX = 4;            // largest box extent per dimension of one jo
 struct LevelDesc {
     const double* Xr;        // real input bricks of the level (the level's own bricks)
     const double* Xg;        // ghost input bricks
-    const float* Xr32;       // FP32 copies, rows padded to 16: [brick][v1][v2][16]  (or null)
+    const float* Xr32;       // FP32 copies (or null): rows padded to 16, [brick][v1][v2][16], for
+                             // k <= KNARROW; [brick][v1][v2][v3] for the two-tile kernel
     const float* Xg32;
     const u4* Xrb;           // split-BF16 copies: [brick][v1][v2][4 groups] of (4 hi, 4 lo)  (or null)
     const u4* Xgb;
@@ -77,10 +78,14 @@ void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t 
                      const LevelDesc* levels, const int2* order, int* queues);
 // Workgroups of that kernel that fit on the device at once (for the persistent launch).
 int64_t resident_blocks(int k, int variant, int prec, int device);
-// The two-tile kernel for KNARROW < k <= KMAX (FP64 only): order[] entries are (level
-// descriptor, 2 * brick + column half), each half a separate workgroup job.
-void launch_contract_wide(int k, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues);
-int64_t resident_blocks_wide(int k, int device);
+// The two-tile kernel for KNARROW < k <= KMAX, classes PREC_F64 and PREC_F32 (the latter adds
+// to the output): order[] entries are (level descriptor, 2 * brick + column part), the columns
+// u3 < 16 and the last ones each a separate workgroup job.  queues as in launch_contract.
+void launch_contract_wide(int k, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
+                          int* queues);
+int64_t resident_blocks_wide(int k, int prec, int device);
+// FP32 copies of nb input bricks for the two-tile kernel: [brick][v1][v2][v3], as the FP64 bricks.
+void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out);
 // FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
 // *acc += sum of squares of nb bricks.

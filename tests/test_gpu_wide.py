@@ -88,8 +88,9 @@ def test_wide_full_plan_random_coefficients(M, ctx):
 
 
 def test_wide_in_batch_plan_and_routing(M, ctx):
-    """k = 10 and k = 8 trees in one batch equal their single applies; the plan replays them; the
-    routed apply keeps every k = 10 job in FP64 (bound 0, result identical)."""
+    """k = 10 and k = 8 trees in one batch equal their single applies; the plan replays them; asked
+    for the BF16 classes only, the routed apply keeps every k = 10 job in FP64 (bound 0, result
+    identical); a routed batch equals the routed single applies."""
     import torch
     specs = [CASES["k10_poisson"](), workloads.small_adaptive(34, k=8, eps=1e-5, jmax=4), CASES["k9_yukawa"]()]
     ops, fs = [], []
@@ -110,9 +111,81 @@ def test_wide_in_batch_plan_and_routing(M, ctx):
         for i in range(len(specs)):
             assert np.array_equal(M.mwns_tree_export(ctx, plan.output(i))[2], singles[i])
     plan.close()
-    gm, st = M.mwns_apply_mixed(ctx, ops[0], fs[0], 1e300)
+    gm, st = M.mwns_apply_mixed(ctx, ops[0], fs[0], 1e300, classes=M.MWNS_CLASS_BF16C | M.MWNS_CLASS_BF16)
     assert st["err_bound"] == 0.0 and st["class_flops"][1:] == [0.0, 0.0, 0.0]
     assert np.array_equal(M.mwns_tree_export(ctx, gm)[2], singles[0])
+    tols = [w.eps * M.mwns_apply(ctx, op, f)[1]["g_norm"] for w, op, f in zip(specs, ops, fs)]
+    routed = [M.mwns_tree_export(ctx, M.mwns_apply_mixed(ctx, op, f, tol)[0])[2] for op, f, tol in zip(ops, fs, tols)]
+    gs, st = M.mwns_apply_batch(ctx, ops, fs, mixed=tols)
+    assert 0.0 < st["err_bound"] <= max(tols)
+    for i, g in enumerate(gs):
+        assert np.array_equal(M.mwns_tree_export(ctx, g)[2], routed[i]), "routed member %d" % i
+
+
+def _lib_setup(M, ctx, w):
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    return f, M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth), tau, wt
+
+
+def _leaf_norm(leaf, coef):
+    return math.sqrt(float(np.sum(coef[leaf == 1] ** 2)))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_wide_fp32_class_alone_within_bound(M, ctx, case):
+    """Every job of the two-tile kernel forced into the FP32 class (unbounded tol): the error
+    against the FP64 apply is within the a-priori bound and at FP32 precision (a wrong operand
+    layout or K-slot permutation would give O(1) errors)."""
+    f, op, *_ = _lib_setup(M, ctx, CASES[case]())
+    g64, st64 = M.mwns_apply(ctx, op, f)
+    _, leaf, a = M.mwns_tree_export(ctx, g64)
+    gm, st = M.mwns_apply_mixed(ctx, op, f, 1e300, classes=M.MWNS_CLASS_F32)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    assert st["class_flops"][0] == 0.0 and st["class_flops"][1] == pytest.approx(st64["useful_flops"])
+    err = _leaf_norm(leaf, b - a)
+    assert 0.0 < err <= st["err_bound"]
+    assert err <= 1e-5 * st64["g_norm"], err / st64["g_norm"]
+
+
+def test_wide_mixed_at_eps_against_oracle(M, ctx):
+    """tol = eps ||g|| at k = 10: the routed result is within err_bound <= tol of the oracle's FP64
+    apply (up to FP64 round-off), with part of the work in the FP32 class."""
+    from oracle import apply as A
+    from oracle import tree as T
+    w = CASES["k10_poisson"]()
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    ot = T.redundant_tree(w.k, keys, coef)
+    f, op, tau, wt = _lib_setup(M, ctx, w)
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, oo.R)
+    g = A.assemble(ot, A.apply_modified(oo, ot))
+    gnorm = _leaf_norm(ot.leaf, g)
+    tol = w.eps * gnorm
+    gm, st = M.mwns_apply_mixed(ctx, op, f, tol)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    assert st["class_flops"][1] > 0.0 and st["class_flops"][2:] == [0.0, 0.0]
+    assert st["err_bound"] <= tol
+    assert _leaf_norm(ot.leaf, b - g) <= st["err_bound"] + 1e-12 * gnorm
+
+
+def test_c3_mixed_at_eps(M, ctx):
+    """The bound-state Helmholtz workload (k = 10, eps = 1e-8) routed at tol = eps ||g||: relative
+    L2 error against the FP64 apply <= eps, with a share of the work in the FP32 class."""
+    w = workloads.c3()
+    f, op, *_ = _lib_setup(M, ctx, w)
+    g64, st64 = M.mwns_apply(ctx, op, f)
+    _, leaf, a = M.mwns_tree_export(ctx, g64)
+    tol = w.eps * st64["g_norm"]
+    gm, st = M.mwns_apply_mixed(ctx, op, f, tol)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    err = _leaf_norm(leaf, b - a)
+    print("C3 mixed: rel err %.3e, bound %.3e, class flop shares %s, contract %.3f ms vs %.3f ms FP64"
+          % (err / st64["g_norm"], st["err_bound"] / st64["g_norm"],
+             [round(x / st["useful_flops"], 3) for x in st["class_flops"]], st["ms_contract"], st64["ms_contract"]))
+    assert err <= st["err_bound"] <= tol
+    assert st["class_flops"][1] > 0.0
 
 
 def test_c3_yukawa_full_size_sampled(M, ctx):
