@@ -71,3 +71,28 @@ def fitted_truncated(tau, w, xyz, a, c, pts):
         for tm, wm in zip(tau, w):
             out += cn * wm * _G(tm, ai, xi[0], pts[:, 0]) * _G(tm, ai, xi[1], pts[:, 1]) * _G(tm, ai, xi[2], pts[:, 2])
     return out
+
+
+def fitted_truncated_grid(tau, w, xyz, a, c, gx, gy, gz, chunk=8192):
+    """fitted_truncated on the tensor grid gx x gy x gz, [len(gx), len(gy), len(gz)]: the factors
+    G of every (source, term) pair are separable, so the sum over the pairs is one contraction of
+    three per-dimension tables (rows: pairs; columns: grid coordinates)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    gx, gy, gz = (np.asarray(v, dtype=np.float64) for v in (gx, gy, gz))
+    tau = np.asarray(tau, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    rows = [(i, m) for i in range(xyz.shape[0]) for m in range(tau.size)]
+    out = np.zeros((gx.size, gy.size, gz.size))
+    for r0 in range(0, len(rows), chunk):
+        part = rows[r0:r0 + chunk]
+        ii = np.array([i for i, _ in part])
+        mm = np.array([m for _, m in part])
+        ai = np.asarray(a, dtype=np.float64)[ii][:, None]
+        cn = (np.asarray(c, dtype=np.float64)[ii] * (np.asarray(a, dtype=np.float64)[ii] / np.pi) ** 1.5 * w[mm])[:, None]
+        tm = tau[mm][:, None]
+        G1 = cn * _G(tm, ai, xyz[ii, 0][:, None], gx[None, :])
+        G2 = _G(tm, ai, xyz[ii, 1][:, None], gy[None, :])
+        G3 = _G(tm, ai, xyz[ii, 2][:, None], gz[None, :])
+        A = (G1[:, :, None] * G2[:, None, :]).reshape(len(part), -1)
+        out += (A.T @ G3).reshape(gx.size, gy.size, gz.size)
+    return out

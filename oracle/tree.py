@@ -140,6 +140,37 @@ def project_gaussians(k, eps, j0, jmax, xyz, a, c, with_margins=False):
     return out
 
 
+def project_boxes(k, eps, jmax, xyz, a, c, keys):
+    """Alg. 1's step for arbitrary boxes: the projected coefficients, the refinement decision and
+    the l-infinity test error of every box in keys (any levels, any order), made exactly as
+    project_gaussians makes them; for checking sampled boxes of a tree too large to build here.
+    Returns (coef [n, k, k, k], refine [n], err [n]) in the order of keys."""
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    cf = np.ascontiguousarray(np.asarray(c, dtype=np.float64) * (a / np.pi) ** 1.5)
+    thr = eps * source_norm(xyz, a, c)
+    gx, gw = mra.gauss_legendre01(k)
+    keys = np.asarray(keys, dtype=np.uint64)
+    lev, _ = decode_keys(keys)
+    coef = np.zeros((keys.size, k, k, k))
+    refine = np.zeros(keys.size, dtype=np.uint8)
+    err = np.zeros(keys.size)
+    L = lib()
+    for j in np.unique(lev):
+        sel = np.nonzero(lev == j)[0]
+        cand = np.ascontiguousarray(keys[sel])
+        n = cand.size
+        s = np.zeros((n, k, k, k))
+        ref = np.zeros(n, dtype=np.uint8)
+        e = np.zeros(n)
+        st = L.orc_project_level(k, int(j), jmax, n, cand.ctypes.data, a.size, xyz.ctypes.data, a.ctypes.data,
+                                 cf.ctypes.data, thr, gx.ctypes.data, gw.ctypes.data, s.ctypes.data,
+                                 ref.ctypes.data, e.ctypes.data)
+        assert st == 0
+        coef[sel], refine[sel], err[sel] = s, ref, e
+    return coef, refine, err
+
+
 def uniform_leaves(k, n, func_coef=None):
     """Keys of the uniform tree at level n (all 8^n boxes, sorted)."""
     m = 1 << n

@@ -1,0 +1,106 @@
+"""The large single apply (Poisson, k = 10, eps = 1e-10, about 1e6 leaves from 500 Gaussians) at
+full size.  The oracle cannot build a tree that large, so the checks are the ones that hold at any
+size: the tree box by box at sampled leaves against the oracle's Alg. 1 step, and as a whole for
+structure; the FP64 potential against the fitted kernel applied in closed form to the
+cube-truncated source (seeded grid of 22^3 points); the routed apply against the FP64 one within
+its bound <= eps ||g||."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    import paper_0706_0747_amd as M
+    return M
+
+
+def _diff_norm(a, b, mask, chunk=1 << 16):
+    """||a - b|| over the masked blocks, in chunks (the arrays are several GB)."""
+    tot = 0.0
+    idx = np.nonzero(mask)[0]
+    for i in range(0, idx.size, chunk):
+        sel = idx[i:i + chunk]
+        tot += float(np.sum((a[sel] - b[sel]) ** 2))
+    return math.sqrt(tot)
+
+
+def test_c5_full_size(M):
+    from oracle import closed_forms as CF
+    from oracle import fit as OF
+    from oracle import tree as T
+    w = workloads.c5()
+    ctx = M.Context(0)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    info = M.mwns_tree_get_info(f)
+    print("C5 tree: %d leaves, %d nodes, depth %d" % (info["nleaves"], info["nnodes"], info["depth"]), flush=True)
+    assert info["nleaves"] > 500000
+    keys, leaf, coef = M.mwns_tree_export(ctx, f)
+    # structure of the whole tree: sorted distinct keys, all 8 children of every internal node,
+    # leaves tiling the cube (volumes 8^-j are exact in FP64)
+    n = keys.size
+    assert np.all(keys[1:] > keys[:-1])
+    lev, _ = T.decode_keys(keys)
+    ch = T.children_keys(keys[leaf == 0])
+    pos = np.minimum(np.searchsorted(keys, ch), n - 1)
+    assert np.array_equal(keys[pos], ch)
+    assert float(np.sum(8.0 ** -lev[leaf == 1].astype(np.float64))) == 1.0
+    # sampled leaves (and the deepest ones), box by box: the oracle keeps each leaf and projects it
+    # to the same coefficients, and refines each leaf's parent
+    rng = np.random.Generator(np.random.PCG64(55))
+    li = np.nonzero(leaf)[0]
+    pick = np.concatenate([rng.choice(li, 24, replace=False), li[lev[li] == lev.max()][:4]])
+    s, ref, _ = T.project_boxes(w.k, w.eps, w.jmax, w.xyz, w.a, w.c, keys[pick])
+    assert np.all(ref[lev[pick] < w.jmax] == 0)
+    assert np.abs(s - coef[pick]).max() <= 1e-13 * np.abs(coef[pick]).max()
+    plev, pl = T.decode_keys(keys[pick])
+    up = plev > w.j0
+    _, pref, _ = T.project_boxes(w.k, w.eps, w.jmax, w.xyz, w.a, w.c, T.make_keys(plev[up] - 1, *(pl[up] >> 1).T))
+    assert np.all(pref == 1)
+    del coef, ch, pos
+    print("C5 tree checks done", flush=True)
+    # FP64 apply against the closed form on a seeded grid
+    depth = info["depth"]
+    delta = math.sqrt(w.eps) * 2.0 ** -depth
+    tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, delta, math.sqrt(3))
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth)
+    g64, st64 = M.mwns_apply(ctx, op, f)
+    print("C5 FP64 apply: %.3e contractions, contraction kernel %.1f ms" % (st64["contractions"], st64["ms_contract"]),
+          flush=True)
+    otau, ow = OF.fit_kernel(w.mu, w.alpha, w.eps, delta, math.sqrt(3))
+    grng = np.random.Generator(np.random.PCG64(56))
+    grid = [np.sort(grng.uniform(0.0, 1.0, 22)) for _ in range(3)]
+    refv = CF.fitted_truncated_grid(otau, ow, w.xyz, w.a, w.c, *grid)
+    X, Y, Z = np.meshgrid(*grid, indexing="ij")
+    v = M.mwns_tree_eval(ctx, g64, np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)).reshape(refv.shape)
+    # Alg. 1 refines f to the absolute threshold eps ||f||_2 (tested pointwise), so the projected
+    # source is within eps ||f||_2 in L2 over the cube, and the operator's L2 norm on the unit cube
+    # is well below 1: the potential's L2 error (root mean square over the seeded points) stays
+    # below eps ||f||_2; screening adds a few eps relative to g.  Here ||f||_2 ~ 1e4 (exponents up
+    # to 1e5) against ||g||_2 ~ 3, so eps ||f||_2 is ~ 3e3 eps ||g||.  Pointwise errors are larger
+    # on the coarse leaves, where the potential is held on the input tree's boxes.
+    fnorm = T.source_norm(w.xyz, w.a, w.c)
+    e = np.abs(v - refv)
+    rms = float(np.sqrt(np.mean(e ** 2)))
+    print("C5 |g - closed form| at %d points: rms %.3e = %.3f eps ||f||, max %.3e = %.3f eps ||f|| (max |ref| %.3e)"
+          % (refv.size, rms, rms / (w.eps * fnorm), e.max(), e.max() / (w.eps * fnorm), np.abs(refv).max()), flush=True)
+    assert rms <= w.eps * fnorm
+    assert e.max() <= 50 * w.eps * fnorm
+    # routed apply against the FP64 one
+    tol = w.eps * st64["g_norm"]
+    gm, stm = M.mwns_apply_mixed(ctx, op, f, tol)
+    _, gleaf, a = M.mwns_tree_export(ctx, g64)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    e = _diff_norm(a, b, gleaf == 1)
+    print("C5 mixed: rel err %.3e, bound %.3e, class flop shares %s, contract %.1f ms vs %.1f ms FP64"
+          % (e / st64["g_norm"], stm["err_bound"] / st64["g_norm"],
+             [round(x / stm["useful_flops"], 3) for x in stm["class_flops"]], stm["ms_contract"], st64["ms_contract"]),
+          flush=True)
+    assert e <= stm["err_bound"] <= tol

@@ -42,3 +42,19 @@ def test_fitted_truncated_1d_factor():
         ref = integrate.quad(lambda y: math.exp(-tau * (x - y) ** 2 - a * (y - c) ** 2), 0, 1,
                              points=[min(max(x, 0), 1)], epsabs=0, epsrel=1e-13, limit=200)[0]
         assert abs(cf._G(tau, a, c, np.array([x]))[0] - ref) <= 1e-11 * ref + 1e-300
+
+
+def test_fitted_truncated_grid_matches_points():
+    """The tensor-grid evaluation (one contraction over (source, term) pairs) equals the pointwise
+    sum at every grid point, chunks smaller than the pair count included."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    xyz = rng.uniform(0.2, 0.8, (4, 3))
+    a = 10.0 ** rng.uniform(1.0, 3.0, 4)
+    c = rng.normal(0.0, 1.0, 4)
+    tau = 10.0 ** rng.uniform(-1.0, 3.0, 5)
+    w = rng.uniform(0.1, 1.0, 5)
+    gx, gy, gz = rng.uniform(0.0, 1.0, 3), rng.uniform(0.0, 1.0, 4), rng.uniform(0.0, 1.0, 5)
+    G = cf.fitted_truncated_grid(tau, w, xyz, a, c, gx, gy, gz, chunk=7)
+    X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
+    ref = cf.fitted_truncated(tau, w, xyz, a, c, np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)).reshape(G.shape)
+    assert np.abs(G - ref).max() <= 1e-14 * np.abs(ref).max()

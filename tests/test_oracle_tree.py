@@ -107,3 +107,20 @@ def test_projection_accuracy_against_source():
     P = workloads.points(3000, seed=9)
     thr = w.eps * T.source_norm(w.xyz, w.a, w.c)
     assert np.abs(T.evaluate(tr, P) - closed_forms.gauss_sum(w.xyz, w.a, w.c, P)).max() < 10 * thr
+
+
+def test_project_boxes_reproduces_the_tree():
+    """The per-box step on the leaves of a built tree says 'keep' (below jmax) and returns the
+    same coefficients; on their parents it says 'refine'."""
+    w = workloads.small_adaptive(8, k=6, eps=1e-4, jmax=5)
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    rng = np.random.Generator(np.random.PCG64(3))
+    pick = rng.choice(keys.size, 20, replace=False)
+    s, ref, _ = T.project_boxes(w.k, w.eps, w.jmax, w.xyz, w.a, w.c, keys[pick])
+    lev, l = T.decode_keys(keys[pick])
+    assert np.array_equal(s, coef[pick])
+    assert np.all(ref[lev < w.jmax] == 0)
+    deeper = lev > w.j0
+    parents = T.make_keys(lev[deeper] - 1, *(l[deeper] >> 1).T)
+    _, pref, _ = T.project_boxes(w.k, w.eps, w.jmax, w.xyz, w.a, w.c, parents)
+    assert np.all(pref == 1)
