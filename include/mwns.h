@@ -230,9 +230,11 @@ typedef struct {
 /* g = T f as mwns_apply, with every (level, displacement box, term) contraction job routed to FP64
  * or to one of the allowed reduced classes.  Not part of the paper's method: a system layer that
  * keeps the result within opts->tol of the all-FP64 apply.  A job's contribution to g over its
- * whole level is bounded by beta = |w_m| prod_d sum_{L_d in box} ||S_d^{m,L_d}||_F ||X_level||_2
- * (S_d the masked 2k x 2k super-blocks, X_level every input sibling group of the level), and a
- * class with unit rounding factor gamma computes it within gamma * beta; classes are chosen so
+ * whole level, with every block taken entrywise in absolute value, is bounded by
+ * beta = |w_m| ||X_level||_2 min(prod_d sum_{L_d in box} ||S_d^{m,L_d}||_F,
+ * prod_d || sum_{L_d in box} |S_d^{m,L_d}| ||_2) (S_d the masked 2k x 2k super-blocks, X_level
+ * every input sibling group of the level), and a class with unit rounding factor gamma computes
+ * it within gamma * beta; classes are chosen so
  * that the sum of gamma * beta is at most tol (stats->err_bound), minimising modelled time.  The
  * transforms, the interpolation, the assembly and the output accumulation stay FP64.  flags: 0 or
  * MWNS_NO_ASSEMBLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM, EDEVICE. */

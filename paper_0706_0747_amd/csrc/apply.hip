@@ -370,9 +370,13 @@ struct RouteItem {
 
 // Chooses a class for every (level, job, term) minimising the modelled time subject to
 // sum gamma_class * beta <= tol (Lagrangian relaxation, bisection on the multiplier); beta bounds
-// the FP64 contribution of the item over its whole level:
-//   || sum_b sum_{L in box} (S1 (x) S2 (x) S3) X_{b-L} || <= |w_m| prod_d sum_{L_d} ||S_d^{m,L_d}||_F ||X_level||,
-// each input brick feeding one output brick per displacement.  Returns the bound reached.
+// the item's contribution over its whole level, and the rounding error of a class is at most gamma
+// times the same sum with every block replaced by its entrywise absolute value.  Two bounds of it:
+//   |w_m| prod_d sum_{L_d} ||S_d^{m,L_d}||_F ||X_level||  (each input brick feeds one output brick
+//   per displacement), and
+//   |w_m| prod_d || sum_{L_d} |S_d^{m,L_d}| ||_2 ||X_level||  (the box is a product set, and a block
+//   convolution with nonnegative blocks B_L has norm at most || sum_L B_L ||_2).
+// beta is the smaller.  Returns the bound reached.
 double route(std::vector<RouteItem>& items, double tol, int allowed, int k) {
     const Gammas gm = class_gammas(k);
     const double* GAMMA = gm.g;
@@ -751,12 +755,62 @@ void launch_level_norms(mwns_ctx* ctx, TreeApply& a, double* lsq) {
     MWNS_HIP(hipGetLastError());
 }
 
+// Upper bound of || B ||_2 for B = sum_{L=lo..hi} |S^{j;m,L}|, the entrywise absolute values of the
+// super-blocks masked to fine displacements [mlo, mhi] (2k x 2k).  For the nonnegative C = B^T B,
+// rho(C) <= max_i (C v)_i / v_i for every positive v (Collatz-Wielandt); v after a few power steps
+// from the ones vector makes the bound tight.  Cached in the operator.
+double abs_box_norm(const mwns_op* op, int j, int m, int lo, int hi, int mlo, int mhi) {
+    const std::array<int, 6> key{j, m, lo, hi, mlo, mhi};
+    const auto it = op->absnorm.find(key);
+    if (it != op->absnorm.end()) return it->second;
+    const int k = op->k, D = 2 * k;
+    const double* Fm = op->Fh.data() + ((size_t)j * op->M + m) * NLF * k * k;
+    std::vector<double> B((size_t)D * D, 0.0), C((size_t)D * D, 0.0), v(D, 1.0), cv(D);
+    for (int L = lo; L <= hi; ++L)
+        for (int su = 0; su < 2; ++su)
+            for (int sv = 0; sv < 2; ++sv) {
+                const int l = 2 * L + su - sv;
+                if (l < mlo || l > mhi || l < -LF || l > LF) continue;
+                for (int a = 0; a < k; ++a)
+                    for (int b = 0; b < k; ++b) B[(su * k + a) * D + sv * k + b] += std::fabs(Fm[((l + LF) * k + a) * k + b]);
+            }
+    for (int p = 0; p < D; ++p)
+        for (int q = 0; q < D; ++q) {
+            double c = 0.0;
+            for (int r = 0; r < D; ++r) c += B[r * D + p] * B[r * D + q];
+            C[p * D + q] = c;
+        }
+    auto apply_c = [&]() {
+        for (int p = 0; p < D; ++p) {
+            double c = 0.0;
+            for (int q = 0; q < D; ++q) c += C[p * D + q] * v[q];
+            cv[p] = c;
+        }
+    };
+    for (int iter = 0; iter < 30; ++iter) {
+        apply_c();
+        const double mx = *std::max_element(cv.begin(), cv.end());
+        if (!(mx > 0.0)) break;
+        for (int p = 0; p < D; ++p) v[p] = std::max(cv[p] / mx, 1e-30);     // stays positive
+    }
+    apply_c();
+    double rho = 0.0;
+    for (int p = 0; p < D; ++p) rho = std::max(rho, cv[p] / v[p]);
+    const double bound = std::sqrt(rho) * (1.0 + 1e-12);     // margin for the rounding of this estimate
+    op->absnorm.emplace(key, bound);
+    return bound;
+}
+
 // Routed apply: classes of every (level, job, term) from the level norms, jobs split into runs of
 // one class, reduced-precision input copies allocated.
 void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed_opts& opts) {
     const mwns_op* op = a.op;
     std::vector<RouteItem> items;
     const int M = op->M;
+    if (op->Fh.empty()) {
+        op->Fh.resize(op->F.n);
+        MWNS_HIP(hipMemcpy(op->Fh.data(), op->F.p, op->F.n * sizeof(double), hipMemcpyDeviceToHost));
+    }
     for (int j = 0; j <= a.depth; ++j) {
         const LevelWork& lw = a.W[j];
         const double xn = std::sqrt(lsq[j]);
@@ -768,7 +822,8 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             const double n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
             for (int m = tp.m1; m <= tp.m2; ++m) {
                 const double* fr = op->fro.data() + ((int64_t)j * M + m) * NLF;
-                double beta = std::fabs(op->w[m]) * xn;
+                // two bounds of the job's contribution; the smaller one is used
+                double bfro = 1.0, babs = 1.0;
                 for (int d = 0; d < 3; ++d) {
                     double s = 0.0;
                     for (int L = tp.lo[d]; L <= tp.hi[d]; ++L) {
@@ -780,8 +835,10 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
                             }
                         s += std::sqrt(s2);
                     }
-                    beta *= s;
+                    bfro *= s;
+                    babs *= abs_box_norm(op, j, m, tp.lo[d], tp.hi[d], tp.mlo[d], tp.mhi[d]);
                 }
+                const double beta = std::fabs(op->w[m]) * xn * std::min(bfro, babs);
                 items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1)});
             }
         }

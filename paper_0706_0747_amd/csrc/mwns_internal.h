@@ -2,8 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -159,6 +161,10 @@ struct mwns_op {
     mwns::DevArray<double> dw;       // [M]
     std::vector<int32_t> plan;       // [max_level+1][NLP^3][2]
     std::vector<double> fro;         // [max_level+1][M][NLF] Frobenius norms of the blocks F^{j;m,l}
+    // for the precision routing: a host copy of F (made by the first routed apply) and upper
+    // bounds of || sum_{L=lo..hi} |S^{j;m,L}| ||_2 keyed by (j, m, lo, hi, mlo, mhi)
+    mutable std::vector<double> Fh;
+    mutable std::map<std::array<int, 6>, double> absnorm;
 };
 
 struct mwns_level {
