@@ -71,6 +71,8 @@ typedef void (*mwns_free_fn)(void* ptr, void* user);
  * Errors: EINVAL (bad device, one of alloc/free missing), EDEVICE (HIP runtime failure). */
 mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_free_fn free_fn, void* user,
                             size_t byte_budget, mwns_ctx** out);
+/* Releases the context handle.  Trees, operators and plans made with it may outlive the call: the
+ * context's memory and cached device blocks are released when the last of them is destroyed. */
 void mwns_ctx_destroy(mwns_ctx* ctx);
 /* Block until all work on the context's stream has completed.  Errors: EDEVICE. */
 mwns_status mwns_ctx_synchronize(mwns_ctx* ctx);
@@ -85,11 +87,16 @@ mwns_status mwns_ctx_release_cache(mwns_ctx* ctx);
 /* Thread-local text for the last non-OK status returned on this thread ("" if none). */
 const char* mwns_last_error(void);
 
-/* Tile variant of the contraction kernel used by this context for basis order k: an index in
- * [0, mwns_num_variants()) (waves per workgroup, prefetch depth, waves per SIMD), or -1 for the
- * library's default.  Variants differ in speed only; every variant computes the same result
- * bit for bit.  mwns_tune_apply picks one by timing.  Errors: EINVAL (k or variant out of range). */
+/* Tile variant of the FP64 one-tile contraction kernel (k <= 8) used by this context for basis
+ * order k: an index in [0, mwns_num_variants()), or -1 for the library's default.  Variants differ
+ * in speed only: those with one term per pass compute the same result bit for bit; those with
+ * several terms per pass add the plane results of consecutive terms in another order, so they
+ * agree with the others up to rounding.  mwns_tune_apply picks one by timing.
+ * Errors: EINVAL (k or variant out of range). */
 int mwns_num_variants(void);
+/* Shape of variant v: waves per workgroup, register prefetch depth of the input slices, waves
+ * per SIMD, and FP64 terms per pass over a job's cells.  Errors: EINVAL (v out of range, NULL). */
+mwns_status mwns_variant_shape(int v, int* waves, int* prefetch, int* waves_per_simd, int* terms_per_pass);
 mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant);
 /* The variant in use for order k (the library's default when none was set). */
 mwns_status mwns_ctx_get_variant(const mwns_ctx* ctx, int k, int* variant);

@@ -23,7 +23,7 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
-           "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_ctx_set_variant",
+           "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
@@ -255,6 +255,13 @@ def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):
 
 def mwns_num_variants():
     return lib.mwns_num_variants()
+
+
+def mwns_variant_shape(v):
+    """(waves per workgroup, prefetch depth, waves per SIMD, FP64 terms per pass) of variant v."""
+    out = [ctypes.c_int() for _ in range(4)]
+    check(lib.mwns_variant_shape(v, *[ctypes.byref(o) for o in out]), "mwns_variant_shape")
+    return tuple(o.value for o in out)
 
 
 def mwns_ctx_set_variant(ctx, k, variant):

@@ -62,6 +62,7 @@ SIGNATURES = {
     "mwns_ctx_release_cache": (c_int, [c_vp]),
     "mwns_last_error": (ctypes.c_char_p, []),
     "mwns_num_variants": (c_int, []),
+    "mwns_variant_shape": (c_int, [c_int, P(c_int), P(c_int), P(c_int), P(c_int)]),
     "mwns_ctx_set_variant": (c_int, [c_vp, c_int, c_int]),
     "mwns_ctx_get_variant": (c_int, [c_vp, c_int, P(c_int)]),
     "mwns_fit_kernel": (c_int, [c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_int, P(c_int), c_vp, c_vp]),

@@ -588,6 +588,7 @@ void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
     a.out.reset(new mwns_tree);
     mwns_tree* out = a.out.get();
     out->ctx = ctx;
+    out->hold.set(ctx);
     out->k = k;
     out->depth = f->depth;
     out->nnodes = f->nnodes;
@@ -1263,6 +1264,7 @@ void apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tre
 // A reusable apply: structure, closure, ghost keys, routing and buffers fixed at creation; the
 // value phase (ghost values, input copies, contractions, assembly) captured once as a hipGraph.
 struct mwns_plan {
+    mwns::CtxHold hold;
     mwns_ctx* ctx = nullptr;
     int mode = 0;
     std::vector<std::unique_ptr<TreeApply>> trees;
@@ -1343,6 +1345,7 @@ extern "C" mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* con
         for (int i = 0; i < n; ++i) check_mixed(mixed + i);
     std::unique_ptr<mwns_plan> pl(new mwns_plan);
     pl->ctx = ctx;
+    pl->hold.set(ctx);
     pl->mode = flags;
     for (int i = 0; i < n; ++i) pl->trees.emplace_back(new TreeApply);
     {

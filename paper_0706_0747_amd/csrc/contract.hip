@@ -40,9 +40,11 @@ struct LpShape {
     static constexpr int T2_BYTES = 16 * T2F_V1 * 4;
     static constexpr int SMEM = (T2_BYTES + GT * TERM_BYTES + 7) / 8;                  // doubles
 };
-template <int PREC, int K>
+// The FP64 class with G terms per pass keeps the staged super-blocks of every term of the group.
+constexpr int SM_TERM = SM_S3 + SM_S2 + SM_S1;
+template <int PREC, int K, int G = 1>
 constexpr int smem_doubles() {
-    if constexpr (PREC == PREC_F64) return SMEM_DOUBLES;
+    if constexpr (PREC == PREC_F64) return SM_T2 + G * SM_TERM;
     else return LpShape<PREC, K>::SMEM;
 }
 static_assert(smem_doubles<PREC_F32, 8>() * 8 <= 80 * 1024 && smem_doubles<PREC_BF16C, 8>() * 8 <= 80 * 1024,
@@ -361,6 +363,118 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
     }
 }
 
+// The terms of one job for one output brick in the FP64 class, G terms per pass (see run_job for
+// the operand layouts): every step loads the input slices once and feeds them to the G terms'
+// chains; the super-blocks of the G terms are staged side by side; mode 1 goes through the LDS
+// transpose term by term.  The terms keep their order within each plane, but the plane results of
+// consecutive terms interleave in Y, so the sums agree with run_job up to rounding.
+template <int K, int CW, int G>
+__device__ __forceinline__ void run_job_g(const LevelDesc& lv, const Tpl& tp, const double* __restrict__ w, int ns,
+                                          const int2* steps, double* smem, int wave, int g, int r, int cmb,
+                                          d4 (&Y)[(2 * K + CW - 1) / CW]) {
+    constexpr int CT = 64 * CW;
+    constexpr int D = 2 * K;
+    constexpr int TPW = (D + CW - 1) / CW;
+    constexpr bool FULL = (CW * TPW == D);
+    constexpr int64_t E = (int64_t)D * D * D;
+    const int n1 = tp.hi[0] - tp.lo[0] + 1, n2 = tp.hi[1] - tp.lo[1] + 1, n3 = tp.hi[2] - tp.lo[2] + 1;
+    double* T2s = smem;
+    auto S3s = [&](int gi) { return smem + SM_T2 + gi * SM_TERM; };
+    auto S2s = [&](int gi) { return S3s(gi) + SM_S3; };
+    auto S1s = [&](int gi) { return S2s(gi) + SM_S2; };
+    uint32_t xoff[TPW];
+    for (int t = 0; t < TPW; ++t) xoff[t] = slice_offset<K>(wave * TPW + t, g, r);
+    for (int m0 = tp.m1; m0 <= tp.m2; m0 += G) {
+        const int gn = __builtin_amdgcn_readfirstlane(min(G, tp.m2 - m0 + 1));
+        // stage the super-blocks of the pass's terms (the previous pass ended with a barrier)
+        const int per = (n1 + n2 + n3) * 256;
+        for (int e = threadIdx.x; e < gn * per; e += CT) {
+            const int gi = e / per, ee = e % per;
+            const int sb = ee >> 8, v = (ee >> 4) & 15, uu = ee & 15;
+            const int m = m0 + gi;
+            const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+            int q, d;
+            if (sb < n1) { q = sb; d = 0; }
+            else if (sb < n1 + n2) { q = sb - n1; d = 1; }
+            else { q = sb - n1 - n2; d = 2; }
+            const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
+            double* dst = d == 0 ? S1s(gi) + q * 256 + v * 16 : d == 1 ? S2s(gi) + q * 256 + v * 16 : S3s(gi) + q * 16 * S3_V + v * S3_V;
+            dst[uu] = sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v);
+        }
+        lds_barrier();
+        d4 T1[G][TPW], T2[G][TPW];
+        for (int gi = 0; gi < G; ++gi)
+            for (int t = 0; t < TPW; ++t) T1[gi][t] = T2[gi][t] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int si = 0; si < ns; ++si) {
+            const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
+            const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
+            const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
+            const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
+            const bool real = idx < lv.nreal;
+            const int64_t qi = real ? idx : idx - lv.nreal;
+            d4 x[TPW];
+            load_slices<K, TPW>((real ? lv.Xr : lv.Xg) + qi * E, (int)(E * 8), xoff, x);
+            // mode 3 for every term of the pass
+            for (int gi = 0; gi < G; ++gi) {
+                if (gi >= gn) break;
+                const double* s3p = S3s(gi) + q3 * 16 * S3_V + r;
+                double s3[4];
+                for (int kk = 0; kk < 4; ++kk) s3[kk] = s3p[(4 * g + kk) * S3_V];
+                for (int kk = 0; kk < 4; ++kk)
+                    for (int t = 0; t < TPW; ++t)
+                        if (FULL || wave * TPW + t < D) T1[gi][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t][kk], s3[kk], T1[gi][t], 0, 0, 0);
+            }
+            if (next < 0 || (next >> 2) != (cell >> 2)) {
+                // end of an (L1, L2) row -- mode 2 for every term
+                for (int gi = 0; gi < G; ++gi) {
+                    if (gi >= gn) break;
+                    const double* s2p = S2s(gi) + q2 * 256 + r;
+                    double s2[4];
+                    for (int i = 0; i < 4; ++i) s2[i] = s2p[(4 * i + g) * 16];
+                    for (int i = 0; i < 4; ++i)
+                        for (int t = 0; t < TPW; ++t)
+                            if (FULL || wave * TPW + t < D)
+                                T2[gi][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2[i], T1[gi][t][i], T2[gi][t], 0, 0, 0);
+                    for (int t = 0; t < TPW; ++t) T1[gi][t] = (d4){0.0, 0.0, 0.0, 0.0};
+                }
+            }
+            if (next < 0 || (next >> 4) != (cell >> 4)) {
+                // end of an L1 plane -- mode 1, term by term through the one LDS transpose buffer
+                for (int gi = 0; gi < G; ++gi) {
+                    if (gi >= gn) break;
+                    for (int t = 0; t < TPW; ++t) {
+                        const int v1 = wave * TPW + t;
+                        if (!FULL && v1 >= D) break;
+                        for (int i = 0; i < 4; ++i) T2s[v1 * T2S_V1 + (4 * i + g) * T2S_U2 + r] = T2[gi][t][i];
+                    }
+                    lds_barrier();
+                    for (int t = 0; t < TPW; ++t) {
+                        const int u2 = wave * TPW + t;
+                        if (!FULL && u2 >= D) break;
+                        const double* s1p = S1s(gi) + q1 * 256 + r;
+                        d4 acc = tp.dpart ? (d4){0.0, 0.0, 0.0, 0.0} : Y[t];
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const int v1 = 4 * kk + g;
+                            const double bv = v1 < D ? T2s[v1 * T2S_V1 + u2 * T2S_U2 + r] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s1p[(4 * kk + g) * 16], bv, acc, 0, 0, 0);
+                        }
+                        if (!tp.dpart) {
+                            Y[t] = acc;
+                            continue;
+                        }
+                        for (int i = 0; i < 4; ++i) {
+                            const int child = (4 * i + g >= K) + 2 * (u2 >= K) + 4 * (r >= K);
+                            if ((cmb >> child) & 1) Y[t][i] += acc[i];
+                        }
+                    }
+                    for (int t = 0; t < TPW; ++t) T2[gi][t] = (d4){0.0, 0.0, 0.0, 0.0};
+                    lds_barrier();
+                }
+            }
+        }
+    }
+}
+
 // The terms of one job for one output brick in a reduced class, GT terms per pass: every step
 // loads the input slices once and feeds them to the GT terms' chains (FP32 or split-BF16; see
 // run_job for the operand layouts); mode 1 goes through the LDS transpose term by term.
@@ -543,7 +657,7 @@ __device__ __forceinline__ void run_job_lp(const LevelDesc& lv, const Tpl& tp, c
 // classes (v_mfma_f32_16x16x32_bf16, lane 16g+n holding K slots 8g..8g+7) give every lane the 4
 // contraction indices 4g..4g+3 as (4 hi | 4 lo) halves, which is exactly what the FP32 mode-3
 // accumulators of the lane hold, so mode 2 again needs no data movement.
-template <int K, int CW, int PF, int PREC>
+template <int K, int CW, int PF, int G, int PREC>
 __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ levels, int2 job, int accumulate, double* smem,
                                                int2* steps, int* nsteps) {
     constexpr int D = 2 * K;
@@ -595,7 +709,8 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
         lds_barrier();
         const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
         if (ns == 0) continue;
-        if constexpr (PREC == PREC_F64) run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
+        if constexpr (PREC == PREC_F64 && G > 1) run_job_g<K, CW, G>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
+        else if constexpr (PREC == PREC_F64) run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
         else run_job_lp<K, CW, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
     }
     for (int t = 0; t < TPW; ++t) {
@@ -613,15 +728,15 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
 // One launch per precision class PREC: it runs the jobs of that class only (each class's chain
 // alone keeps the register count low) and, with accumulate set, adds to the output the launches
 // of the other classes wrote.
-template <int K, int CW, int PF, int WPE, int PREC>
+template <int K, int CW, int PF, int WPE, int G, int PREC>
 __global__ void __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues,
                 int accumulate) {
-    __shared__ double smem[smem_doubles<PREC, K>()];
+    __shared__ double smem[smem_doubles<PREC, K, G>()];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
-        contract_brick<K, CW, PF, PREC>(levels, order[blockIdx.x], accumulate, smem, steps, &nsteps_s);
+        contract_brick<K, CW, PF, G, PREC>(levels, order[blockIdx.x], accumulate, smem, steps, &nsteps_s);
         return;
     }
     // persistent: pull positions from this XCD's queue, then from the others; every workgroup
@@ -646,7 +761,7 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0) break;
-        contract_brick<K, CW, PF, PREC>(levels, order[pos], accumulate, smem, steps, &nsteps_s);
+        contract_brick<K, CW, PF, G, PREC>(levels, order[pos], accumulate, smem, steps, &nsteps_s);
     }
 }
 
@@ -684,25 +799,29 @@ __global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ X
     if (threadIdx.x == 0) atomicAdd(acc, red[0]);
 }
 
-// Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD).
+// Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD, FP64
+// terms per pass over the cells).
 struct Variant {
-    int cw, pf, wpe;
+    int cw, pf, wpe, g;
 };
-constexpr Variant VARIANTS[] = {{8, 0, 4}, {8, 1, 2}, {8, 2, 2}, {16, 1, 4}, {16, 2, 4}, {16, 3, 4}};
+constexpr Variant VARIANTS[] = {{8, 0, 4, 1},  {8, 1, 2, 1},  {8, 2, 2, 1},
+                                {16, 1, 4, 1}, {16, 2, 4, 1}, {16, 3, 4, 1}, {16, 0, 4, 2}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
-constexpr int DEFAULT_VARIANT = 0;   // (8 waves, no prefetch, 4 waves per SIMD): fastest on the k = 8 Poisson workload
+// Default shape: (8 waves, no prefetch, 4 waves per SIMD, one term per pass), except at k = 8, where
+// (16 waves, one workgroup per CU, two FP64 terms per pass) is faster on the Poisson workload.
+constexpr int default_variant(int k) { return k == 8 ? 6 : 0; }
 
 template <int K, int V, int PREC>
 void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues, int acc) {
     constexpr Variant v = VARIANTS[V];
-    ns_apply_kernel<K, v.cw, v.pf, v.wpe, PREC><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, queues, acc);
+    ns_apply_kernel<K, v.cw, v.pf, v.wpe, v.g, PREC><<<(unsigned)nblocks, 64 * v.cw, 0, st>>>(levels, order, queues, acc);
 }
 
 template <int K, int V, int PREC>
 int64_t resident_variant(int device) {
     constexpr Variant v = VARIANTS[V];
     int per_cu = 0, ncu = 0;
-    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_kernel<K, v.cw, v.pf, v.wpe, PREC>, 64 * v.cw, 0));
+    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_kernel<K, v.cw, v.pf, v.wpe, v.g, PREC>, 64 * v.cw, 0));
     MWNS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     return (int64_t)std::max(1, per_cu) * ncu;
 }
@@ -732,6 +851,7 @@ struct ApplyLaunch {
             case 3: go(std::integral_constant<int, 3>{}, F{}); break;
             case 4: go(std::integral_constant<int, 4>{}, F{}); break;
             case 5: go(std::integral_constant<int, 5>{}, F{}); break;
+            case 6: go(std::integral_constant<int, 6>{}, F{}); break;
             default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
         }
     }
@@ -759,7 +879,7 @@ int num_variants() { return NVARIANTS; }
 
 int variant_for(const mwns_ctx* ctx, int k) {
     const int v = ctx->variant[k];
-    return k > KNARROW ? 0 : (v >= 0 ? v : DEFAULT_VARIANT);
+    return k > KNARROW ? 0 : (v >= 0 ? v : default_variant(k));
 }
 
 template <template <int> class Fn, class... Args>
@@ -803,6 +923,18 @@ void launch_sumsq(int k, hipStream_t st, int64_t nb, const double* X, double* ac
 using namespace mwns;
 
 extern "C" int mwns_num_variants(void) { return NVARIANTS; }
+
+extern "C" mwns_status mwns_variant_shape(int v, int* waves, int* prefetch, int* waves_per_simd, int* terms_per_pass) {
+    MWNS_GUARD_BEGIN
+    if (v < 0 || v >= NVARIANTS || !waves || !prefetch || !waves_per_simd || !terms_per_pass)
+        fail(MWNS_EINVAL, "variant out of range or NULL output");
+    *waves = VARIANTS[v].cw;
+    *prefetch = VARIANTS[v].pf;
+    *waves_per_simd = VARIANTS[v].wpe;
+    *terms_per_pass = VARIANTS[v].g;
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
 
 extern "C" mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant) {
     MWNS_GUARD_BEGIN

@@ -40,6 +40,13 @@ void release_cache(mwns_ctx* ctx) {
     ctx->cached = 0;
 }
 
+void ctx_release(mwns_ctx* ctx) {
+    if (--ctx->refs > 0) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    release_cache(ctx);
+    delete ctx;
+}
+
 void* dalloc(mwns_ctx* ctx, size_t bytes) {
     if (bytes == 0) return nullptr;
     const size_t cls = size_class(bytes);
@@ -230,7 +237,7 @@ void mwns_ctx_destroy(mwns_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     release_cache(ctx);
-    delete ctx;
+    mwns::ctx_release(ctx);     // trees, operators and plans of the context may still hold it
 }
 
 mwns_status mwns_ctx_release_cache(mwns_ctx* ctx) {

@@ -112,12 +112,31 @@ struct mwns_ctx {
     size_t cached = 0;                                  // bytes of freed blocks kept for reuse
     std::vector<std::pair<size_t, void*>> cache;        // (size class, block), most recent last
     int variant[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};   // per basis order k
+    int refs = 1;            // the handle itself plus every live tree, operator and plan of the context
 };
 
 namespace mwns {
 void* dalloc(mwns_ctx* ctx, size_t bytes);
 void dfree(mwns_ctx* ctx, void* p, size_t bytes);
 void release_cache(mwns_ctx* ctx);
+// Drops one reference to ctx; the last one returns the cached blocks and frees the context.
+void ctx_release(mwns_ctx* ctx);
+// A tree, operator or plan keeps its context alive: declared as the object's first member, it is
+// destroyed after every device array of the object has gone back to the context.
+struct CtxHold {
+    mwns_ctx* ctx = nullptr;
+    CtxHold() = default;
+    CtxHold(const CtxHold&) = delete;
+    CtxHold& operator=(const CtxHold&) = delete;
+    void set(mwns_ctx* c) {
+        if (c) ++c->refs;
+        if (ctx) ctx_release(ctx);
+        ctx = c;
+    }
+    ~CtxHold() {
+        if (ctx) ctx_release(ctx);
+    }
+};
 template <class T>
 struct DevArray {
     mwns_ctx* ctx = nullptr;
@@ -153,6 +172,7 @@ struct DevArray {
 
 // Handles --------------------------------------------------------------------------------------
 struct mwns_op {
+    mwns::CtxHold hold;
     mwns_ctx* ctx = nullptr;
     int k = 0, M = 0, max_level = 0, group = 1;
     double eps = 0.0, theta = 0.0;
@@ -173,6 +193,7 @@ struct mwns_level {
 };
 
 struct mwns_tree {
+    mwns::CtxHold hold;
     mwns_ctx* ctx = nullptr;
     int k = 0, depth = 0;
     int64_t nnodes = 0, nleaves = 0, nbricks = 0;

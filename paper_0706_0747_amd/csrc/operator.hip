@@ -268,6 +268,7 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
             fail(MWNS_EINVAL, "tau must be > 0 and w >= 0, finite");
     std::unique_ptr<mwns_op> op(new mwns_op);
     op->ctx = ctx;
+    op->hold.set(ctx);
     op->k = k;
     op->M = M;
     op->max_level = max_level;

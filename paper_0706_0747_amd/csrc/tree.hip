@@ -495,6 +495,7 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     hipStream_t st = ctx->stream;
     std::unique_ptr<mwns_tree> t(new mwns_tree);
     t->ctx = ctx;
+    t->hold.set(ctx);
     t->k = k;
     const int k3 = k * k * k;
     // source terms: x, y, z, a, c (a/pi)^{3/2}
@@ -620,6 +621,7 @@ mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const u
     all.erase(std::unique(all.begin(), all.end()), all.end());
     std::unique_ptr<mwns_tree> t(new mwns_tree);
     t->ctx = ctx;
+    t->hold.set(ctx);
     t->k = k;
     t->keys = all;
     t->leaf.assign(all.size(), 0);

@@ -63,3 +63,16 @@ def test_fit_error_paths():
     Mv = ctypes.c_int(0)
     st = M.lib.mwns_fit_kernel(0.0, 1.0, 1.0, 1e-6, 1e-3, 1.0, 3, ctypes.byref(Mv), None, None)
     assert st == _lib.MWNS_ERANGE and Mv.value > 3
+
+
+def test_variant_shapes():
+    """Variant 0 is the default shape (8 waves, no prefetch, 4 waves per SIMD, one term per pass);
+    some variants run several FP64 terms per pass; out-of-range indices are rejected."""
+    import paper_0706_0747_amd as M
+    n = M.mwns_num_variants()
+    shapes = [M.mwns_variant_shape(v) for v in range(n)]
+    assert shapes[0] == (8, 0, 4, 1)
+    assert any(s[3] > 1 for s in shapes)
+    assert all(s[0] in (8, 16) and s[3] >= 1 for s in shapes)
+    with pytest.raises(M.MwnsError):
+        M.mwns_variant_shape(n)

@@ -108,8 +108,10 @@ def test_apply_is_deterministic(M, ctx):
 
 @pytest.mark.parametrize("case", ["adaptive_k6", "adaptive_k8"])
 def test_tile_variants_bit_identical(M, case):
-    """Every contraction-kernel tile variant computes the same g bit for bit (variants change only
-    the wave count, prefetch depth and occupancy, not the order of the arithmetic)."""
+    """Every contraction-kernel tile variant with one term per pass computes the same g bit for bit
+    (they change only the wave count, prefetch depth and occupancy, not the order of the
+    arithmetic); variants with several terms per pass add the plane results of consecutive terms
+    in another order and agree to rounding."""
     w = CASES[case]()
     c = M.Context(0)
     f = M.mwns_project_gaussians(c, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
@@ -122,7 +124,10 @@ def test_tile_variants_bit_identical(M, case):
         assert M.mwns_ctx_get_variant(c, w.k) == v
         outs.append(M.mwns_tree_export(c, M.mwns_apply(c, op, f)[0])[2])
     for v, o in enumerate(outs[1:], 1):
-        assert np.array_equal(o, outs[0]), "variant %d differs from variant 0" % v
+        if M.mwns_variant_shape(v)[3] == 1:
+            assert np.array_equal(o, outs[0]), "variant %d differs from variant 0" % v
+        else:
+            assert np.linalg.norm(o - outs[0]) <= 1e-14 * np.linalg.norm(outs[0]), "variant %d" % v
     with pytest.raises(M.MwnsError):
         M.mwns_ctx_set_variant(c, w.k, M.mwns_num_variants())
 
