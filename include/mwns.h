@@ -194,7 +194,10 @@ mwns_status mwns_tree_set_leaves(mwns_ctx* ctx, mwns_tree* t, const double* coef
 
 enum {
     MWNS_F64 = 0,             /* every contraction in FP64 (FP64 MFMA) */
-    MWNS_NO_ASSEMBLY = 1 << 8 /* flag: g holds the per-scale blocks ghat before eq. g_assemble */
+    MWNS_NO_ASSEMBLY = 1 << 8, /* flag: g holds the per-scale blocks ghat before eq. g_assemble */
+    MWNS_TIMES_ONLY = 1 << 9   /* flag: stats without the device passes that count contractions and
+                                  sum ||g||^2 (contractions = -1, g_norm = 0); the times, flops and
+                                  bounds are filled as usual */
 };
 
 typedef struct {
@@ -216,7 +219,8 @@ typedef struct {
  * (x) F^{j;m,l3}) f_{b-l} with c_m = [m in R_j(L)] - [b internal][m in R_{j+1}(l)]
  * (L = coarse displacement of the parents), missing inputs being interpolated from the deepest
  * existing ancestor (Alg. 3 Step 2), and g = ghat + up(g_parent) top-down (eq. g_assemble).
- * op->max_level must be >= depth of f.  `mode` is MWNS_F64, optionally | MWNS_NO_ASSEMBLY.
+ * op->max_level must be >= depth of f.  `mode` is MWNS_F64, optionally | MWNS_NO_ASSEMBLY and
+ * | MWNS_TIMES_ONLY.
  * stats may be NULL; filling it synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
 mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
                        mwns_apply_stats* stats);
@@ -243,8 +247,9 @@ typedef struct {
  * every input sibling group of the level), and a class with unit rounding factor gamma computes
  * it within gamma * beta; classes are chosen so
  * that the sum of gamma * beta is at most tol (stats->err_bound), minimising modelled time.  The
- * transforms, the interpolation, the assembly and the output accumulation stay FP64.  flags: 0 or
- * MWNS_NO_ASSEMBLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM, EDEVICE. */
+ * transforms, the interpolation, the assembly and the output accumulation stay FP64.  flags: 0,
+ * MWNS_NO_ASSEMBLY, MWNS_TIMES_ONLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM,
+ * EDEVICE. */
 mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts, int flags,
                              mwns_tree** g, mwns_apply_stats* stats);
 

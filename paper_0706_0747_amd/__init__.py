@@ -17,10 +17,10 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, MWNS_NO_ASSEMBLY, MwnsError, check,
+from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, MWNS_NO_ASSEMBLY, MWNS_TIMES_ONLY, MwnsError, check,
                    lib)
 
-__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_CLASS_F32",
+__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_variant_shape", "mwns_ctx_set_variant",

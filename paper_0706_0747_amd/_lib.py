@@ -27,6 +27,7 @@ P = ctypes.POINTER
 MWNS_OK, MWNS_EINVAL, MWNS_ENOMEM, MWNS_EDEVICE, MWNS_ERANGE, MWNS_ESTATE = range(6)
 MWNS_F64 = 0
 MWNS_NO_ASSEMBLY = 1 << 8
+MWNS_TIMES_ONLY = 1 << 9
 MWNS_CLASS_F32, MWNS_CLASS_BF16C, MWNS_CLASS_BF16 = 1, 2, 4
 STATUS_NAMES = {0: "MWNS_OK", 1: "MWNS_EINVAL", 2: "MWNS_ENOMEM", 3: "MWNS_EDEVICE", 4: "MWNS_ERANGE", 5: "MWNS_ESTATE"}
 

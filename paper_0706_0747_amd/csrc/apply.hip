@@ -1047,6 +1047,15 @@ void make_order(const std::vector<std::pair<double, int2>>& cost, bool persisten
 
 // Device contraction count and ||g|| of one apply into s (synchronises).
 void collect_stats(mwns_ctx* ctx, TreeApply& a, int mode, mwns_apply_stats& s) {
+    s.brick_jobs += a.jobs;
+    s.ghost_bricks += a.total_ghosts;
+    s.useful_flops += a.flops;
+    s.err_bound = std::max(s.err_bound, a.err_bound);
+    for (int p = 0; p < NPREC; ++p) s.class_flops[p] += a.class_flops[p];
+    if (mode & MWNS_TIMES_ONLY) {
+        s.contractions = -1;
+        return;
+    }
     hipStream_t st = ctx->stream;
     const int64_t planrow = (int64_t)NLP3 * 2;
     const int64_t E = brick_elems(a.k);
@@ -1087,12 +1096,7 @@ void collect_stats(mwns_ctx* ctx, TreeApply& a, int mode, mwns_apply_stats& s) {
     gsq.download(&g2, 1, st);
     MWNS_HIP(hipStreamSynchronize(st));
     s.contractions += (int64_t)c;
-    s.brick_jobs += a.jobs;
-    s.ghost_bricks += a.total_ghosts;
-    s.useful_flops += a.flops;
-    s.err_bound = std::max(s.err_bound, a.err_bound);
     s.g_norm = std::sqrt(s.g_norm * s.g_norm + g2);
-    for (int p = 0; p < NPREC; ++p) s.class_flops[p] += a.class_flops[p];
 }
 
 // Everything before the value phase: structure, closure (one host round trip for the whole
@@ -1297,7 +1301,7 @@ void record_values(mwns_plan* pl, hipStream_t st) {
 extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int mode, mwns_tree** g,
                                   mwns_apply_stats* stats) {
     MWNS_GUARD_BEGIN
-    if ((mode & 0xff) != MWNS_F64 || (mode & ~(0xff | MWNS_NO_ASSEMBLY))) fail(MWNS_EINVAL, "unsupported mode");
+    if ((mode & 0xff) != MWNS_F64 || (mode & ~(0xff | MWNS_NO_ASSEMBLY | MWNS_TIMES_ONLY))) fail(MWNS_EINVAL, "unsupported mode");
     if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
     apply_batch(ctx, 1, &op, &f, nullptr, mode, false, g, stats);
     return MWNS_OK;
@@ -1316,7 +1320,7 @@ extern "C" mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const 
     MWNS_GUARD_BEGIN
     if (!opts) fail(MWNS_EINVAL, "opts is NULL");
     check_mixed(opts);
-    if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
+    if (flags & ~(MWNS_NO_ASSEMBLY | MWNS_TIMES_ONLY)) fail(MWNS_EINVAL, "unsupported flags");
     if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
     apply_batch(ctx, 1, &op, &f, opts, flags, false, g, stats);
     return MWNS_OK;
@@ -1326,7 +1330,7 @@ extern "C" mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const 
 extern "C" mwns_status mwns_apply_batch(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,
                                         const mwns_mixed_opts* mixed, int flags, mwns_tree** gs, mwns_apply_stats* stats) {
     MWNS_GUARD_BEGIN
-    if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
+    if (flags & ~(MWNS_NO_ASSEMBLY | MWNS_TIMES_ONLY)) fail(MWNS_EINVAL, "unsupported flags");
     if (mixed)
         for (int i = 0; i < n; ++i) check_mixed(mixed + i);
     if (gs)

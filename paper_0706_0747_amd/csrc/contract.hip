@@ -368,7 +368,7 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
 // chains; the super-blocks of the G terms are staged side by side; mode 1 goes through the LDS
 // transpose term by term.  The terms keep their order within each plane, but the plane results of
 // consecutive terms interleave in Y, so the sums agree with run_job up to rounding.
-template <int K, int CW, int G>
+template <int K, int CW, int G, int PF>
 __device__ __forceinline__ void run_job_g(const LevelDesc& lv, const Tpl& tp, const double* __restrict__ w, int ns,
                                           const int2* steps, double* smem, int wave, int g, int r, int cmb,
                                           d4 (&Y)[(2 * K + CW - 1) / CW]) {
@@ -384,6 +384,16 @@ __device__ __forceinline__ void run_job_g(const LevelDesc& lv, const Tpl& tp, co
     auto S1s = [&](int gi) { return S2s(gi) + SM_S2; };
     uint32_t xoff[TPW];
     for (int t = 0; t < TPW; ++t) xoff[t] = slice_offset<K>(wave * TPW + t, g, r);
+    auto load = [&](int si, d4 (&x)[TPW]) {
+        const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
+        const bool real = idx < lv.nreal;
+        const int64_t qi = real ? idx : idx - lv.nreal;
+        load_slices<K, TPW>((real ? lv.Xr : lv.Xg) + qi * E, (int)(E * 8), xoff, x);
+    };
+    // PF = 1: the slices of the next step are loaded while the current one is computed (the step
+    // list is the same for every pass of the job)
+    d4 xn[TPW];
+    if constexpr (PF > 0) load(0, xn);
     for (int m0 = tp.m1; m0 <= tp.m2; m0 += G) {
         const int gn = __builtin_amdgcn_readfirstlane(min(G, tp.m2 - m0 + 1));
         // stage the super-blocks of the pass's terms (the previous pass ended with a barrier)
@@ -406,14 +416,17 @@ __device__ __forceinline__ void run_job_g(const LevelDesc& lv, const Tpl& tp, co
         for (int gi = 0; gi < G; ++gi)
             for (int t = 0; t < TPW; ++t) T1[gi][t] = T2[gi][t] = (d4){0.0, 0.0, 0.0, 0.0};
         for (int si = 0; si < ns; ++si) {
-            const int idx = __builtin_amdgcn_readfirstlane(steps[si].x);
             const int cell = __builtin_amdgcn_readfirstlane(steps[si].y);
             const int next = si + 1 < ns ? __builtin_amdgcn_readfirstlane(steps[si + 1].y) : -1;
             const int q1 = cell >> 4, q2 = (cell >> 2) & 3, q3 = cell & 3;
-            const bool real = idx < lv.nreal;
-            const int64_t qi = real ? idx : idx - lv.nreal;
             d4 x[TPW];
-            load_slices<K, TPW>((real ? lv.Xr : lv.Xg) + qi * E, (int)(E * 8), xoff, x);
+            if constexpr (PF > 0) {
+                for (int t = 0; t < TPW; ++t) x[t] = xn[t];
+                if (si + 1 < ns) load(si + 1, xn);
+                else if (m0 + G <= tp.m2) load(0, xn);
+            } else {
+                load(si, x);
+            }
             // mode 3 for every term of the pass
             for (int gi = 0; gi < G; ++gi) {
                 if (gi >= gn) break;
@@ -709,7 +722,7 @@ __device__ __forceinline__ void contract_brick(const LevelDesc* __restrict__ lev
         lds_barrier();
         const int ns = __builtin_amdgcn_readfirstlane(nsteps_s);
         if (ns == 0) continue;
-        if constexpr (PREC == PREC_F64 && G > 1) run_job_g<K, CW, G>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
+        if constexpr (PREC == PREC_F64 && G > 1) run_job_g<K, CW, G, PF>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
         else if constexpr (PREC == PREC_F64) run_job<K, CW, PF, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
         else run_job_lp<K, CW, PREC>(lv, tp, w, ns, steps, smem, wave, g, r, cmb, Y);
     }
@@ -804,8 +817,8 @@ __global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ X
 struct Variant {
     int cw, pf, wpe, g;
 };
-constexpr Variant VARIANTS[] = {{8, 0, 4, 1},  {8, 1, 2, 1},  {8, 2, 2, 1},
-                                {16, 1, 4, 1}, {16, 2, 4, 1}, {16, 3, 4, 1}, {16, 0, 4, 2}};
+constexpr Variant VARIANTS[] = {{8, 0, 4, 1},  {8, 1, 2, 1},  {8, 2, 2, 1},  {16, 1, 4, 1},
+                                {16, 2, 4, 1}, {16, 3, 4, 1}, {16, 0, 4, 2}, {16, 1, 4, 2}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 // Default shape: (8 waves, no prefetch, 4 waves per SIMD, one term per pass), except at k = 8, where
 // (16 waves, one workgroup per CU, two FP64 terms per pass) is faster on the Poisson workload.
@@ -852,6 +865,7 @@ struct ApplyLaunch {
             case 4: go(std::integral_constant<int, 4>{}, F{}); break;
             case 5: go(std::integral_constant<int, 5>{}, F{}); break;
             case 6: go(std::integral_constant<int, 6>{}, F{}); break;
+            case 7: go(std::integral_constant<int, 7>{}, F{}); break;
             default: fail(MWNS_EINVAL, "unknown contraction kernel variant");
         }
     }

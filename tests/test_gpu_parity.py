@@ -267,3 +267,18 @@ def test_error_paths(M, ctx):
     bad[1, 3, 3, 3] = (0, tau.size + 5)
     with pytest.raises(M.MwnsError):
         M.mwns_op_plan_import(op, bad)
+
+
+def test_times_only_statistics(M, ctx):
+    """MWNS_TIMES_ONLY fills the device times and the host-known figures, skips the contraction
+    count and ||g|| (-1 and 0), and leaves g unchanged."""
+    w = CASES["adaptive_k6"]()
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth)
+    g1, s1 = M.mwns_apply(ctx, op, f)
+    g2, s2 = M.mwns_apply(ctx, op, f, M.MWNS_TIMES_ONLY)
+    assert s2["contractions"] == -1 and s2["g_norm"] == 0.0 and s1["contractions"] > 0
+    assert s2["ms_contract"] > 0.0 and s2["useful_flops"] == s1["useful_flops"]
+    assert np.array_equal(M.mwns_tree_export(ctx, g1)[2], M.mwns_tree_export(ctx, g2)[2])
