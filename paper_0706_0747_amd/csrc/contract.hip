@@ -821,8 +821,9 @@ constexpr Variant VARIANTS[] = {{8, 0, 4, 1},  {8, 1, 2, 1},  {8, 2, 2, 1},  {16
                                 {16, 2, 4, 1}, {16, 3, 4, 1}, {16, 0, 4, 2}, {16, 1, 4, 2}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 // Default shape: (8 waves, no prefetch, 4 waves per SIMD, one term per pass), except at k = 8, where
-// (16 waves, one workgroup per CU, two FP64 terms per pass) is faster on the Poisson workload.
-constexpr int default_variant(int k) { return k == 8 ? 6 : 0; }
+// (16 waves, one workgroup per CU, two FP64 terms per pass, the next step's slice prefetched) is
+// faster on the Poisson workload.
+constexpr int default_variant(int k) { return k == 8 ? 7 : 0; }
 
 template <int K, int V, int PREC>
 void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues, int acc) {
