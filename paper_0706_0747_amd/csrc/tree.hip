@@ -71,8 +71,8 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     key_coords(keys[box], l);
     const double h = ldexp(1.0, -j);
     // The source is separable per term, f = sum_i w_i e_i(x) e_i(y) e_i(z): a thread owns (y, z)
-    // pairs and sweeps x, reading e_i(y), e_i(z) once per term and e_i(x) as LDS broadcasts.
-    // Every value is still accumulated as sum_i (e_i(x) e_i(y)) e_i(z) in term order.
+    // pairs and sweeps x, forming e_i(y) e_i(z) once per term and adding w_i e_i(x) times it with
+    // one fused multiply-add per grid value, in term order.
     double accc[PPT][P2];                    // children grid: [pair][x]
     double acco[K];                          // own grid, pair threadIdx.x < K*K: [x]
     for (int p = 0; p < PPT; ++p)
@@ -99,15 +99,15 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
             if (pr >= NPAIR) break;
             const int qy = K + pr / P2, qz = K + pr % P2;
             for (int i = 0; i < nc; ++i) {
-                const double ey = E[i][1][qy], ez = E[i][2][qz];
-                for (int q = 0; q < P2; ++q) accc[p][q] += E[i][0][K + q] * ey * ez;
+                const double eyz = E[i][1][qy] * E[i][2][qz];
+                for (int q = 0; q < P2; ++q) accc[p][q] = fma(E[i][0][K + q], eyz, accc[p][q]);
             }
         }
         if (threadIdx.x < K * K) {
             const int oy = threadIdx.x / K, oz = threadIdx.x % K;
             for (int i = 0; i < nc; ++i) {
-                const double ey = E[i][1][oy], ez = E[i][2][oz];
-                for (int q = 0; q < K; ++q) acco[q] += E[i][0][q] * ey * ez;
+                const double eyz = E[i][1][oy] * E[i][2][oz];
+                for (int q = 0; q < K; ++q) acco[q] = fma(E[i][0][q], eyz, acco[q]);
             }
         }
         __syncthreads();
