@@ -73,7 +73,8 @@ int variant_for(const mwns_ctx* ctx, int k);
 // b takes order[b] (nblocks = number of listed bricks); otherwise nblocks resident workgroups pull
 // positions from the 8 per-XCD queues (their own XCD's first, then the others') until all are
 // drained.  accumulate: add to the output brick instead of overwriting it.  The tile variant
-// applies to the FP64 class; the reduced classes run in the default shape.
+// applies to the FP64 class; the reduced classes run in the shape of variant 0 (8 waves, two
+// workgroups per CU).
 void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t st, int64_t nblocks,
                      const LevelDesc* levels, const int2* order, int* queues);
 // Workgroups of that kernel that fit on the device at once (for the persistent launch).

@@ -840,7 +840,7 @@ int64_t resident_variant(int device) {
     return (int64_t)std::max(1, per_cu) * ncu;
 }
 
-// The FP64 class exists in every tile variant; the reduced classes in the default shape only.
+// The FP64 class exists in every tile variant; the reduced classes in the shape of variant 0 only.
 template <int K>
 struct ApplyLaunch {
     static void run(hipStream_t st, int variant, int prec, int acc, int64_t nblocks, const LevelDesc* levels,

@@ -66,7 +66,7 @@ def test_fit_error_paths():
 
 
 def test_variant_shapes():
-    """Variant 0 is the default shape (8 waves, no prefetch, 4 waves per SIMD, one term per pass);
+    """Variant 0 is the basic shape (8 waves, no prefetch, 4 waves per SIMD, one term per pass);
     some variants run several FP64 terms per pass; out-of-range indices are rejected."""
     import paper_0706_0747_amd as M
     n = M.mwns_num_variants()
