@@ -88,8 +88,8 @@ mwns_status mwns_ctx_release_cache(mwns_ctx* ctx);
 const char* mwns_last_error(void);
 
 /* Tile variant of the FP64 one-tile contraction kernel (k <= 8) used by this context for basis
- * order k: an index in [0, mwns_num_variants()), or -1 for the library's default (at k = 8 the
- * shape with two terms per pass and a prefetched input slice, elsewhere variant 0).  Variants differ
+ * order k: an index in [0, mwns_num_variants()), or -1 for the library's default (for 6 <= k <= 8
+ * the shape with two terms per pass and a prefetched input slice, below variant 0).  Variants differ
  * in speed only: those with one term per pass compute the same result bit for bit; those with
  * several terms per pass add the plane results of consecutive terms in another order, so they
  * agree with the others up to rounding.  mwns_tune_apply picks one by timing.

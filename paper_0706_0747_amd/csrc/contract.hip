@@ -820,10 +820,10 @@ struct Variant {
 constexpr Variant VARIANTS[] = {{8, 0, 4, 1},  {8, 1, 2, 1},  {8, 2, 2, 1},  {16, 1, 4, 1},
                                 {16, 2, 4, 1}, {16, 3, 4, 1}, {16, 0, 4, 2}, {16, 1, 4, 2}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
-// Default shape: (8 waves, no prefetch, 4 waves per SIMD, one term per pass), except at k = 8, where
-// (16 waves, one workgroup per CU, two FP64 terms per pass, the next step's slice prefetched) is
-// faster on the Poisson workload.
-constexpr int default_variant(int k) { return k == 8 ? 7 : 0; }
+// Default shape: (16 waves, one workgroup per CU, two FP64 terms per pass, the next step's slice
+// prefetched) for 6 <= k <= 8, where it was fastest (k = 8 Poisson workload; k = 6, 7 adaptive
+// trees); (8 waves, no prefetch, 4 waves per SIMD, one term per pass) below.
+constexpr int default_variant(int k) { return k >= 6 && k <= 8 ? 7 : 0; }
 
 template <int K, int V, int PREC>
 void launch_variant(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues, int acc) {
