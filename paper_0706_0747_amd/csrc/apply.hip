@@ -703,13 +703,40 @@ void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
     }
 }
 
+// Sorts the keys and drops repeats (a missing parent is reported once per neighbouring output
+// box).  An LSD radix sort over only the bytes in which the keys differ: level bits and the
+// Morton bits of the deepest level, a few passes over data that stays in cache.
+void sort_unique_keys(std::vector<uint64_t>& keys) {
+    const size_t n = keys.size();
+    if (n < 2) return;
+    uint64_t diff = 0;
+    for (const uint64_t key : keys) diff |= key ^ keys[0];
+    std::vector<uint64_t> tmp(n);
+    uint64_t* src = keys.data();
+    uint64_t* dst = tmp.data();
+    for (int sh = 0; sh < 64; sh += 8) {
+        if (((diff >> sh) & 0xff) == 0) continue;
+        size_t pos[256] = {};
+        for (size_t i = 0; i < n; ++i) ++pos[(src[i] >> sh) & 0xff];
+        size_t s = 0;
+        for (size_t& p : pos) {
+            const size_t c = p;
+            p = s;
+            s += c;
+        }
+        for (size_t i = 0; i < n; ++i) dst[pos[(src[i] >> sh) & 0xff]++] = src[i];
+        std::swap(src, dst);
+    }
+    if (src != keys.data()) keys.swap(tmp);
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+}
+
 // The distinct missing keys of every level become its ghost bricks (Alg. 3 Step 2): their
 // indices complete the neighbour tables and their storage is allocated.
 void discover_ghosts(mwns_ctx* ctx, TreeApply& a, std::vector<uint64_t>& keys, uint64_t* dmiss) {
     a.total_ghosts = 0;
     // a missing parent key of level j-1 belongs to the closure of output level j
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    sort_unique_keys(keys);
     size_t pos = 0;
     for (int j = 1; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
