@@ -38,150 +38,191 @@ namespace {
 
 constexpr int PT = 256;   // threads of the projection / transform blocks
 constexpr int CH = 32;    // source terms per chunk
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// One line of a separable transform: out[o * so] = scale * sum_i M[o][i] in[i * si] for o < NO,
+// the sum in ascending i.  The thread reads its NI inputs once; M's addresses are the same in
+// every lane, so its entries come through the scalar cache.
+template <int NO, int NI>
+__device__ inline void line_apply(const double* __restrict__ M, const double* in, int si, double* out, int so,
+                                  double scale) {
+    double v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) v[i] = in[i * si];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        double sm = 0.0;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) sm += M[o * NI + i] * v[i];
+        out[o * so] = sm * scale;
+    }
+}
 
 // One block per candidate box of level j (Alg. 1): source values at the box's k^3 Gauss-Legendre
 // nodes and at the 8 children's nodes, coefficients s (eq. fvals2coefs in 3-D), values
 // interpolated from s at the children's nodes, max |f - f~| and the refinement decision.
+//
+// The source is separable per term, f = sum_i w_i e_i(x) e_i(y) e_i(z), so the values on a grid
+// are a product over the terms: F[x][(y, z)] = sum_i (w_i e_i(x)) (e_i(y) e_i(z)).  It runs on
+// v_mfma_f64_16x16x4 (A[m][k] in lane m+16k, B[k][n] in lane n+16k, D[4i+g][n] in register i of
+// lane n+16g): rows are x points, columns (y, z) pairs, the inner index four terms per step.  The
+// children grid takes MT x NTC tiles, the own grid NTO tiles; wave w owns tiles w, w+NW, ...
+// The interpolant on the children grid is one more product in the same layout, so |f - f~| is
+// formed in registers.
 template <int K>
 __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
                                                      const double* __restrict__ src /* x,y,z,a,cf per term */,
-                                                     double thr, const double* __restrict__ tab, double* __restrict__ s_out,
-                                                     uint8_t* __restrict__ refine, double* __restrict__ err_out) {
+                                                     double thr, double nc3, double ni, const double* __restrict__ tab,
+                                                     double* __restrict__ s_out, uint8_t* __restrict__ refine,
+                                                     double* __restrict__ err_out) {
+    // nc3 = 2^{-3j/2} and ni = 2^{3j/2}, the level's normalisation of the scaling functions
     constexpr int K3 = K * K * K;
     constexpr int P2 = 2 * K;
     constexpr int NQ = 3 * K;                // 1-D points: K own nodes, then 2K children nodes
-    constexpr int NC = 8 * K3;               // children grid (2K)^3, points 0..NC-1
-    constexpr int NP = 9 * K3;               // then the box's own K^3 nodes
-    constexpr int NPAIR = P2 * P2;           // (y, z) pairs of the children grid
-    constexpr int PPT = (NPAIR + PT - 1) / PT;
-    static_assert(K * K <= PT, "one thread per (y, z) pair of the own grid");
-    (void)NC;
-    (void)NP;
-    __shared__ double E[CH][3][NQ];          // E[i][0][q] already carries the source weight
-    __shared__ double fown[K3];
-    __shared__ double t1[2 * K3];
-    __shared__ double t2[6 * K3];
-    __shared__ double red[PT];
+    constexpr int MT = (P2 + 15) / 16, NTC = (P2 * P2 + 15) / 16, NTO = (K * K + 15) / 16;
+    constexpr int NTCH = MT * NTC;           // children tiles come first
+    constexpr int NT = NTCH + NTO;
+    constexpr int NW = PT / 64;
+    constexpr int TPW = (NT + NW - 1) / NW;
+    constexpr int KS = (K + 3) / 4;          // inner steps of the interpolation product
+    constexpr int NE = CH * 3 * NQ;          // term table E[i][d][q]; E[i][0][q] carries the weight
+    constexpr int NTR = 8 * K3;              // transform buffers t1 (2 K^3) and t2 (6 K^3)
+    static_assert(K <= 16, "the own grid's x points fit one tile");
+    // the term table is dead once the grids are summed: the transforms reuse its storage
+    __shared__ double smem[(NE > NTR ? NE : NTR) + K3];
+    __shared__ double red[NW];
+    __shared__ double xq[3 * NQ];            // 1-D points [d][q]
+    __shared__ double st[CH * 5];            // the current chunk of terms
+    double* E = smem;
+    double* t1 = smem;
+    double* t2 = smem + 2 * K3;
+    double* fown = smem + (NE > NTR ? NE : NTR);
     // tab: P[a][i] = phi_a(x_i) w_i (K*K), Q[q][a] = phi_a((s + x_i)/2), q = s*K + i (2K*K), gx[K]
     const double* P = tab;
     const double* Q = tab + K * K;
     const double* gx = tab + 3 * K * K;
     const int box = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
     int64_t l[3];
     key_coords(keys[box], l);
     const double h = ldexp(1.0, -j);
-    // The source is separable per term, f = sum_i w_i e_i(x) e_i(y) e_i(z): a thread owns (y, z)
-    // pairs and sweeps x, forming e_i(y) e_i(z) once per term and adding w_i e_i(x) times it with
-    // one fused multiply-add per grid value, in term order.
-    double accc[PPT][P2];                    // children grid: [pair][x]
-    double acco[K];                          // own grid, pair threadIdx.x < K*K: [x]
-    for (int p = 0; p < PPT; ++p)
-        for (int q = 0; q < P2; ++q) accc[p][q] = 0.0;
-    for (int q = 0; q < K; ++q) acco[q] = 0.0;
+    const bool fine = j < jmax;              // children values enter only the refinement test
+    d4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    // the box's 1-D points per dimension: its own nodes, then the children's nodes
+    for (int e = threadIdx.x; e < 3 * NQ; e += PT) {
+        const int d = e / NQ, q = e % NQ;
+        double x;
+        if (q < K) x = h * (l[d] + gx[q]);
+        else {
+            const int sg = (q - K) / K, pp = (q - K) % K;
+            x = 0.5 * h * (2 * l[d] + sg + gx[pp]);
+        }
+        xq[e] = x;
+    }
     for (int c0 = 0; c0 < nsrc; c0 += CH) {
         const int nc = min(CH, nsrc - c0);
-        for (int e = threadIdx.x; e < nc * 3 * NQ; e += PT) {
+        const int nc4 = (nc + 3) & ~3;       // whole steps of four terms; the padding terms are zero
+        for (int e = threadIdx.x; e < nc * 5; e += PT) st[e] = src[(int64_t)c0 * 5 + e];
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc4 * 3 * NQ; e += PT) {
             const int q = e % NQ, d = (e / NQ) % 3, i = e / (3 * NQ);
-            const double* sp = src + (int64_t)(c0 + i) * 5;
-            double x;
-            if (q < K) x = h * (l[d] + gx[q]);
-            else {
-                const int sg = (q - K) / K, pp = (q - K) % K;
-                x = 0.5 * h * (2 * l[d] + sg + gx[pp]);
+            double v = 0.0;
+            if (i < nc) {
+                const double* sp = st + i * 5;
+                const double dx = xq[d * NQ + q] - sp[d];
+                const double ev = exp(-sp[3] * dx * dx);
+                v = d == 0 ? sp[4] * ev : ev;
             }
-            const double dx = x - sp[d];
-            const double ev = exp(-sp[3] * dx * dx);
-            E[i][d][q] = d == 0 ? sp[4] * ev : ev;
+            E[e] = v;
         }
         __syncthreads();
-        for (int p = 0; p < PPT; ++p) {
-            const int pr = threadIdx.x + p * PT;
-            if (pr >= NPAIR) break;
-            const int qy = K + pr / P2, qz = K + pr % P2;
-            for (int i = 0; i < nc; ++i) {
-                const double eyz = E[i][1][qy] * E[i][2][qz];
-                for (int q = 0; q < P2; ++q) accc[p][q] = fma(E[i][0][K + q], eyz, accc[p][q]);
-            }
-        }
-        if (threadIdx.x < K * K) {
-            const int oy = threadIdx.x / K, oz = threadIdx.x % K;
-            for (int i = 0; i < nc; ++i) {
-                const double eyz = E[i][1][oy] * E[i][2][oz];
-                for (int q = 0; q < K; ++q) acco[q] = fma(E[i][0][q], eyz, acco[q]);
+        for (int i0 = 0; i0 < nc4; i0 += 4) {
+            const double* Ei = E + (i0 + g) * 3 * NQ;
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                const int t = wave + NW * u;
+                if (t >= NT || (t < NTCH && !fine)) continue;
+                double a, b;
+                if (t < NTCH) {
+                    const int x = (t / NTC) * 16 + r, pr = (t % NTC) * 16 + r;
+                    a = x < P2 ? Ei[K + x] : 0.0;
+                    b = pr < P2 * P2 ? Ei[NQ + K + pr / P2] * Ei[2 * NQ + K + pr % P2] : 0.0;
+                } else {
+                    const int pr = (t - NTCH) * 16 + r;
+                    a = r < K ? Ei[r] : 0.0;
+                    b = pr < K * K ? Ei[NQ + pr / K] * Ei[2 * NQ + pr % K] : 0.0;
+                }
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x < K * K)
-        for (int q = 0; q < K; ++q) fown[q * K * K + threadIdx.x] = acco[q];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wave + NW * u;
+        if (t < NTCH || t >= NT) continue;
+        const int pr = (t - NTCH) * 16 + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = 4 * i + g;
+            if (x < K && pr < K * K) fown[x * K * K + pr] = acc[u][i];
+        }
+    }
     __syncthreads();
-    // s = 2^{-3j/2} (P (x) P (x) P) f_own, contracting the last index first
-    const double nc3 = pow(2.0, -1.5 * j);
+    // s = 2^{-3j/2} (P (x) P (x) P) f_own, contracting the last index first; one thread per line
     double* ta = t1;
     double* s_l = t1 + K3;
-    for (int e = threadIdx.x; e < K3; e += PT) {
-        const int i1 = e / (K * K), i2 = (e / K) % K, a3 = e % K;
-        double sm = 0.0;
-        for (int i3 = 0; i3 < K; ++i3) sm += P[a3 * K + i3] * fown[(i1 * K + i2) * K + i3];
-        ta[e] = sm;
-    }
+    const int ln = threadIdx.x;    // line of the current stage
+    if (ln < K * K) line_apply<K, K>(P, fown + ln * K, 1, ta + ln * K, 1, 1.0);
     __syncthreads();
-    for (int e = threadIdx.x; e < K3; e += PT) {
-        const int i1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
-        double sm = 0.0;
-        for (int i2 = 0; i2 < K; ++i2) sm += P[a2 * K + i2] * ta[(i1 * K + i2) * K + a3];
-        t2[e] = sm;
-    }
+    if (ln < K * K) line_apply<K, K>(P, ta + (ln / K) * K * K + ln % K, K, t2 + (ln / K) * K * K + ln % K, K, 1.0);
     __syncthreads();
-    double* sb = s_out + (int64_t)box * K3;
-    for (int e = threadIdx.x; e < K3; e += PT) {
-        const int a1 = e / (K * K), a2 = (e / K) % K, a3 = e % K;
-        double sm = 0.0;
-        for (int i1 = 0; i1 < K; ++i1) sm += P[a1 * K + i1] * t2[(i1 * K + a2) * K + a3];
-        sm *= nc3;
-        sb[e] = sm;
-        s_l[e] = sm;   // keep s for the interpolation
+    if (ln < K * K) {
+        line_apply<K, K>(P, t2 + ln, K * K, s_l + ln, K * K, nc3);
+        double* sb = s_out + (int64_t)box * K3;
+        for (int a1 = 0; a1 < K; ++a1) sb[a1 * K * K + ln] = s_l[a1 * K * K + ln];
     }
     __syncthreads();
     double emax = 0.0;
-    if (j < jmax) {
-        // f~ on the (2K)^3 children grid = 2^{3j/2} (Q (x) Q (x) Q) s; compared with the values each
-        // thread holds for the same grid points
-        const double ni = pow(2.0, 1.5 * j);
+    if (fine) {
+        // f~ on the (2K)^3 children grid = 2^{3j/2} (Q (x) Q (x) Q) s, compared with the values the
+        // children tiles hold for the same grid points
         double* u1 = t2;                     // [a1][a2][q3]   K*K*2K
-        for (int e = threadIdx.x; e < K * K * P2; e += PT) {
-            const int a1 = e / (K * P2), a2 = (e / P2) % K, q3 = e % P2;
-            double sm = 0.0;
-            for (int a3 = 0; a3 < K; ++a3) sm += Q[q3 * K + a3] * s_l[(a1 * K + a2) * K + a3];
-            u1[e] = sm;
-        }
-        __syncthreads();
         double* u2 = t2 + 2 * K3;            // [a1][q2][q3] K*2K*2K
-        for (int e = threadIdx.x; e < K * P2 * P2; e += PT) {
-            const int a1 = e / (P2 * P2), q2 = (e / P2) % P2, q3 = e % P2;
-            double sm = 0.0;
-            for (int a2 = 0; a2 < K; ++a2) sm += Q[q2 * K + a2] * u1[(a1 * K + a2) * P2 + q3];
-            u2[e] = sm;
-        }
+        if (ln < K * K) line_apply<P2, K>(Q, s_l + ln * K, 1, u1 + ln * P2, 1, 1.0);
         __syncthreads();
-        for (int p = 0; p < PPT; ++p) {
-            const int pr = threadIdx.x + p * PT;
-            if (pr >= NPAIR) break;
-            const int q2 = pr / P2, q3 = pr % P2;
-            for (int q1 = 0; q1 < P2; ++q1) {
-                double sm = 0.0;
-                for (int a1 = 0; a1 < K; ++a1) sm += Q[q1 * K + a1] * u2[(a1 * P2 + q2) * P2 + q3];
-                emax = fmax(emax, fabs(accc[p][q1] - ni * sm));
+        if (ln < K * P2)
+            line_apply<P2, K>(Q, u1 + (ln / P2) * K * P2 + ln % P2, P2, u2 + (ln / P2) * P2 * P2 + ln % P2, P2, 1.0);
+        __syncthreads();
+        // last factor as a product: rows q1, columns (q2, q3), inner index a1
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int t = wave + NW * u;
+            if (t >= NTCH) continue;
+            const int mt = t / NTC, x = mt * 16 + r, pr = (t % NTC) * 16 + r;
+            d4 fi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) {
+                const int a1 = 4 * kk + g;
+                const double a = x < P2 && a1 < K ? Q[x * K + a1] : 0.0;
+                const double b = pr < P2 * P2 && a1 < K ? u2[a1 * P2 * P2 + pr] : 0.0;
+                fi = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, fi, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q1 = mt * 16 + 4 * i + g;
+                if (q1 < P2 && pr < P2 * P2) emax = fmax(emax, fabs(acc[u][i] - ni * fi[i]));
             }
         }
     }
-    red[threadIdx.x] = emax;
+    for (int off = 32; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off));
+    if (lane == 0) red[wave] = emax;
     __syncthreads();
-    for (int sh = PT / 2; sh > 0; sh >>= 1) {
-        if (threadIdx.x < sh) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + sh]);
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        for (int w = 1; w < NW; ++w) red[0] = fmax(red[0], red[w]);
         err_out[box] = red[0];
         refine[box] = (uint8_t)((j < jmax) && (red[0] > thr));
     }
@@ -332,7 +373,8 @@ template <int K>
 struct ProjectLaunch {
     static void run(hipStream_t st, int64_t n, int j, int jmax, const uint64_t* keys, int nsrc, const double* src,
                     double thr, const double* tab, double* s, uint8_t* ref, double* err) {
-        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, thr, tab, s, ref, err);
+        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, thr, std::pow(2.0, -1.5 * j),
+                                                      std::pow(2.0, 1.5 * j), tab, s, ref, err);
     }
 };
 template <int K>
