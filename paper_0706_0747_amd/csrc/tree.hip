@@ -60,7 +60,8 @@ __device__ inline void line_apply(const double* __restrict__ M, const double* in
 
 // One block per candidate box of level j (Alg. 1): source values at the box's k^3 Gauss-Legendre
 // nodes and at the 8 children's nodes, coefficients s (eq. fvals2coefs in 3-D), values
-// interpolated from s at the children's nodes, max |f - f~| and the refinement decision.
+// interpolated from s at the children's nodes and max |f - f~|, which the host compares with the
+// threshold.
 //
 // The source is separable per term, f = sum_i w_i e_i(x) e_i(y) e_i(z), so the values on a grid
 // are a product over the terms: F[x][(y, z)] = sum_i (w_i e_i(x)) (e_i(y) e_i(z)).  It runs on
@@ -72,9 +73,8 @@ __device__ inline void line_apply(const double* __restrict__ M, const double* in
 template <int K>
 __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
                                                      const double* __restrict__ src /* x,y,z,a,cf per term */,
-                                                     double thr, double nc3, double ni, const double* __restrict__ tab,
-                                                     double* __restrict__ s_out, uint8_t* __restrict__ refine,
-                                                     double* __restrict__ err_out) {
+                                                     double nc3, double ni, const double* __restrict__ tab,
+                                                     double* __restrict__ s_out, double* __restrict__ err_out) {
     // nc3 = 2^{-3j/2} and ni = 2^{3j/2}, the level's normalisation of the scaling functions
     constexpr int K3 = K * K * K;
     constexpr int P2 = 2 * K;
@@ -224,7 +224,6 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     if (threadIdx.x == 0) {
         for (int w = 1; w < NW; ++w) red[0] = fmax(red[0], red[w]);
         err_out[box] = red[0];
-        refine[box] = (uint8_t)((j < jmax) && (red[0] > thr));
     }
 }
 
@@ -372,9 +371,9 @@ void dispatch_k(int k, Args&&... args) {
 template <int K>
 struct ProjectLaunch {
     static void run(hipStream_t st, int64_t n, int j, int jmax, const uint64_t* keys, int nsrc, const double* src,
-                    double thr, const double* tab, double* s, uint8_t* ref, double* err) {
-        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, thr, std::pow(2.0, -1.5 * j),
-                                                      std::pow(2.0, 1.5 * j), tab, s, ref, err);
+                    const double* tab, double* s, double* err) {
+        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, std::pow(2.0, -1.5 * j),
+                                                      std::pow(2.0, 1.5 * j), tab, s, err);
     }
 };
 template <int K>
@@ -456,21 +455,26 @@ void finalize_structure(mwns_tree* t) {
 void compress_tree(mwns_tree* t, const double* dH) {
     mwns_ctx* ctx = t->ctx;
     LevelTab lt = level_tab(t);
+    // parent node and child brick of every brick of levels 1..depth, one upload; the levels run
+    // in stream order from the deepest up, each reading what the one below wrote
+    const int64_t nb = t->nbricks - 1;
+    if (nb <= 0) return;
+    std::vector<int64_t> pc(2 * nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        pc[b] = t->brick_parent[1 + b];
+        pc[nb + b] = 1 + b;
+    }
+    DevArray<int64_t> dpc(ctx, pc.size());
+    dpc.upload(pc.data(), pc.size(), ctx->stream);
     for (int j = t->depth - 1; j >= 0; --j) {
         const mwns_level& L = t->lev[j + 1];
         if (L.nbricks == 0) continue;
-        std::vector<int64_t> pn(L.nbricks), cb(L.nbricks);
-        for (int64_t b = 0; b < L.nbricks; ++b) {
-            pn[b] = t->brick_parent[L.brick_off + b];
-            cb[b] = L.brick_off + b;
-        }
-        DevArray<int64_t> dpn(ctx, pn.size()), dcb(ctx, cb.size());
-        dpn.upload(pn.data(), pn.size(), ctx->stream);
-        dcb.upload(cb.data(), cb.size(), ctx->stream);
-        dispatch_k<CompressLaunch>(t->k, ctx->stream, L.nbricks, j, dpn.p, dcb.p, lt, dH, t->coef.p);
+        dispatch_k<CompressLaunch>(t->k, ctx->stream, L.nbricks, j, dpc.p + (L.brick_off - 1),
+                                   dpc.p + nb + (L.brick_off - 1), lt, dH, t->coef.p);
         MWNS_HIP(hipGetLastError());
-        MWNS_HIP(hipStreamSynchronize(ctx->stream));
     }
+    // the host index array is the source of an asynchronous copy
+    MWNS_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 }  // namespace mwns
@@ -582,19 +586,20 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
         const int64_t nc = (int64_t)cand.size();
         DevArray<uint64_t> dk(ctx, nc);
         DevArray<double> ds(ctx, (size_t)nc * k3), derr(ctx, nc);
-        DevArray<uint8_t> dref(ctx, nc);
         dk.upload(cand.data(), nc, st);
-        dispatch_k<ProjectLaunch>(k, st, nc, j, jmax, dk.p, n, dsrc.p, thr, dtab.p, ds.p, dref.p, derr.p);
+        dispatch_k<ProjectLaunch>(k, st, nc, j, jmax, dk.p, n, dsrc.p, dtab.p, ds.p, derr.p);
         MWNS_HIP(hipGetLastError());
-        std::vector<uint8_t> ref(nc);
         std::vector<double> err(nc);
-        dref.download(ref.data(), nc, st);
         derr.download(err.data(), nc, st);
         MWNS_HIP(hipStreamSynchronize(st));
+        // refine where the interpolation error exceeds the threshold, below the finest level (Alg. 1)
+        std::vector<uint8_t> ref(nc), lf(nc);
+        for (int64_t i = 0; i < nc; ++i) {
+            ref[i] = (uint8_t)(j < jmax && err[i] > thr);
+            lf[i] = ref[i] ? 0 : 1;
+        }
         if (j < jmax)
             for (int64_t i = 0; i < nc; ++i) min_margin = std::min(min_margin, std::fabs(err[i] - thr) / thr);
-        std::vector<uint8_t> lf(nc);
-        for (int64_t i = 0; i < nc; ++i) lf[i] = ref[i] ? 0 : 1;
         lkeys.push_back(cand);
         lleaf.push_back(lf);
         lcoef.push_back(std::move(ds));
@@ -613,13 +618,10 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
     MWNS_HIP(hipMemsetAsync(t->coef.p, 0, t->coef.n * sizeof(double), st));
     LevelTab lt = level_tab(t.get());
-    std::vector<DevArray<uint8_t>> dls(t->depth + 1);
     for (int j = j0; j <= t->depth; ++j) {
         const int64_t nn = t->lev[j].nnodes;
-        dls[j].reset(ctx, nn);
-        dls[j].upload(t->leaf.data() + t->lev[j].node_off, nn, st);
-        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(k, j, nn, lcoef[j].p, dls[j].p, lt,
-                                                                                  t->coef.p);
+        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(
+            k, j, nn, lcoef[j].p, t->dleaf.p + t->lev[j].node_off, lt, t->coef.p);
         MWNS_HIP(hipGetLastError());
     }
     DevArray<double> dH = upload_filters(ctx, k);
