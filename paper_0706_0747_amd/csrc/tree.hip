@@ -303,7 +303,9 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const double x[3] = {xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]};
-    for (int j = 0; j <= lt.depth; ++j) {
+    // The deepest node that contains the point is its leaf (the children of a node partition it),
+    // so the levels are searched from the finest up, each within its own slice of the keys.
+    for (int j = lt.depth; j >= 0; --j) {
         const int64_t side = (int64_t)1 << j;
         int64_t l[3];
         double u[3];
@@ -313,9 +315,11 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
             l[d] = v;
             u[d] = x[d] * side - v;
         }
-        const int64_t node = find_sorted(keys, nnodes, make_key(j, l[0], l[1], l[2]));
-        if (node < 0) break;
-        if (!leaf[node]) continue;
+        const int64_t off = lt.node_off[j], end = j < lt.depth ? lt.node_off[j + 1] : nnodes;
+        const int64_t f = find_sorted(keys + off, end - off, make_key(j, l[0], l[1], l[2]));
+        if (f < 0) continue;
+        const int64_t node = off + f;
+        if (!leaf[node]) break;   // an internal node none of whose children holds the point
         double ph[3][K];
         for (int d = 0; d < 3; ++d) {
             const double t = 2.0 * u[d] - 1.0;
@@ -387,7 +391,8 @@ template <int K>
 struct EvalLaunch {
     static void run(hipStream_t st, int64_t n, const double* xyz, const uint64_t* keys, int64_t nn, const uint8_t* leaf,
                     const LevelTab& lt, const double* coef, double* out, int* bad) {
-        eval_kernel<K><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, xyz, keys, nn, leaf, lt, coef, out, bad);
+        // one point per thread; small blocks spread the points over the compute units
+        eval_kernel<K><<<(unsigned)((n + 63) / 64), 64, 0, st>>>(n, xyz, keys, nn, leaf, lt, coef, out, bad);
     }
 };
 
