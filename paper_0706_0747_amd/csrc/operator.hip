@@ -29,50 +29,67 @@ constexpr int NGL = 24;          // points per panel
 constexpr int MAXBRK = 40;       // panel end points per integral
 constexpr int MOMW = 64;         // threads per moment block
 
-__global__ void __launch_bounds__(MOMW) moments_kernel(int k, int M, int nlev, const double* __restrict__ tau,
+// One block per (j, m, l).  The panel end points are the distinct values among 0, 1, the eighths
+// and p -+ s 2^q inside (0, 1); every candidate is placed by its rank, then repeats are dropped.
+template <int K>
+__global__ void __launch_bounds__(MOMW) moments_kernel(int M, const double* __restrict__ tau,
                                                        const double* __restrict__ glx, const double* __restrict__ glw,
                                                        double* __restrict__ mom /* [nlev][M][NLF][2k] */) {
+    constexpr int K2 = 2 * K;
+    constexpr int NCAND = 9 + 20;     // 0, 1, i/8 (i = 1..7), p - s 2^q and p + s 2^q (q = -3..6)
+    static_assert(NCAND <= MOMW && NCAND <= MAXBRK, "one candidate per thread");
     const int blk = blockIdx.x;
     const int li = blk % NLF;
     const int m = (blk / NLF) % M;
     const int j = blk / (NLF * M);
-    const int K2 = 2 * k;
+    const int tid = threadIdx.x;
     const double l = (double)(li - LF);
     const double beta = tau[m] * ldexp(1.0, -2 * j);
+    __shared__ double cand[NCAND];    // -1 marks a candidate outside (0, 1)
+    __shared__ double srt[NCAND];
     __shared__ double brk[MAXBRK];
     __shared__ int nbrk;
-    __shared__ double part[MOMW][2 * KMAX];
-    if (threadIdx.x == 0) {
-        const double c = -l;
-        const double p = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
-        const double s = 1.0 / sqrt(beta);
-        double v[MAXBRK];
-        int n = 0;
-        v[n++] = 0.0;
-        v[n++] = 1.0;
-        for (int i = 1; i < 8; ++i) v[n++] = i / 8.0;
-        for (int q = -3; q <= 6; ++q) {
-            double d = s * ldexp(1.0, q);
-            if (p - d > 0.0 && p - d < 1.0) v[n++] = p - d;
-            if (p + d > 0.0 && p + d < 1.0) v[n++] = p + d;
+    __shared__ double part[MOMW][K2];
+    if (tid < NCAND) {
+        double v;
+        if (tid == 0) v = 0.0;
+        else if (tid == 1) v = 1.0;
+        else if (tid < 9) v = (tid - 1) / 8.0;
+        else {
+            const double c = -l;
+            const double p = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
+            const double sc = 1.0 / sqrt(beta);
+            const double d = sc * ldexp(1.0, (tid - 9) / 2 - 3);
+            v = (tid - 9) % 2 == 0 ? p - d : p + d;
+            if (!(v > 0.0 && v < 1.0)) v = -1.0;
         }
-        // insertion sort, then drop duplicates
-        for (int a = 1; a < n; ++a) {
-            double x = v[a];
-            int b = a - 1;
-            while (b >= 0 && v[b] > x) { v[b + 1] = v[b]; --b; }
-            v[b + 1] = x;
-        }
-        int u = 0;
-        for (int a = 0; a < n; ++a)
-            if (u == 0 || v[a] > brk[u - 1]) brk[u++] = v[a];
-        nbrk = u;
+        cand[tid] = v;
     }
     __syncthreads();
-    double acc[2 * KMAX];
+    if (tid < NCAND && cand[tid] >= 0.0) {
+        const double v = cand[tid];
+        int rank = 0;
+        for (int u = 0; u < NCAND; ++u) {
+            const double w = cand[u];
+            rank += (w >= 0.0) && (w < v || (w == v && u < tid));
+        }
+        srt[rank] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int nv = 0;
+        for (int u = 0; u < NCAND; ++u) nv += cand[u] >= 0.0;
+        int n = 0;
+        for (int a = 0; a < nv; ++a)
+            if (n == 0 || srt[a] > brk[n - 1]) brk[n++] = srt[a];
+        nbrk = n;
+    }
+    __syncthreads();
+    double acc[K2];
+#pragma unroll
     for (int n = 0; n < K2; ++n) acc[n] = 0.0;
     const int npts = (nbrk - 1) * NGL;
-    for (int pt = threadIdx.x; pt < npts; pt += MOMW) {
+    for (int pt = tid; pt < npts; pt += MOMW) {
         const int pan = pt / NGL, g = pt % NGL;
         const double a = brk[pan], b = brk[pan + 1];
         const double x = a + (b - a) * glx[g];
@@ -82,6 +99,7 @@ __global__ void __launch_bounds__(MOMW) moments_kernel(int k, int M, int nlev, c
         double p0 = 1.0, p1 = t;
         acc[0] += wt;
         if (K2 > 1) acc[1] += wt * t * 1.7320508075688772;
+#pragma unroll
         for (int n = 2; n < K2; ++n) {
             double p2 = ((2 * n - 1) * t * p1 - (n - 1) * p0) / n;
             acc[n] += wt * p2 * sqrt(2.0 * n + 1.0);
@@ -89,13 +107,19 @@ __global__ void __launch_bounds__(MOMW) moments_kernel(int k, int M, int nlev, c
             p1 = p2;
         }
     }
-    for (int n = 0; n < K2; ++n) part[threadIdx.x][n] = acc[n];
+#pragma unroll
+    for (int n = 0; n < K2; ++n) part[tid][n] = acc[n];
     __syncthreads();
-    if (threadIdx.x < K2) {
+    if (tid < K2) {
         double s = 0.0;
-        for (int r = 0; r < MOMW; ++r) s += part[r][threadIdx.x];
-        mom[(int64_t)blk * K2 + threadIdx.x] = s;
+        for (int r = 0; r < MOMW; ++r) s += part[r][tid];
+        mom[(int64_t)blk * K2 + tid] = s;
     }
+}
+
+template <int K>
+void launch_moments(int nlev, int M, const double* tau, const double* gx, const double* gw, double* mom, hipStream_t st) {
+    moments_kernel<K><<<nlev * M * NLF, MOMW, 0, st>>>(M, tau, gx, gw, mom);
 }
 
 __global__ void combine_kernel(int k, int M, int nlev, const double* __restrict__ C, const double* __restrict__ mom,
@@ -191,10 +215,13 @@ __global__ void fro_kernel(int k, int64_t n, const double* __restrict__ F, doubl
 }
 
 // One thread per (scale j >= 1, canonical class (c0 <= c1 <= c2)): term range.
-__global__ void plan_kernel(int M, int nlev, double eps, const double* __restrict__ w, const double* __restrict__ norms,
-                            const double* __restrict__ nf0, int32_t* __restrict__ ranges /* [nlev][20][2] */) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (nlev - 1) * 20) return;
+// One wave per (level j >= 1, class of sorted |L|): the lanes evaluate the weighted estimates of 64
+// terms at a time into LDS and lane 0 forms the prefix and suffix sums in term order.
+__global__ void __launch_bounds__(64) plan_kernel(int M, double eps, const double* __restrict__ w,
+                                                  const double* __restrict__ norms, const double* __restrict__ nf0,
+                                                  int32_t* __restrict__ ranges /* [nlev][20][2] */) {
+    const int idx = blockIdx.x;
+    const int lane = threadIdx.x;
     const int cls = idx % 20;
     const int j = 1 + idx / 20;
     int c[3] = {0, 0, 0}, cnt = 0;
@@ -221,22 +248,46 @@ __global__ void plan_kernel(int M, int nlev, double eps, const double* __restric
         }
         return w[m] * (tot / 6.0);
     };
+    __shared__ double est[64];
+    __shared__ int flag;
     double total = 0.0;
     int m1 = -1;
-    for (int m = 0; m < M; ++m) {
-        total += e_of(m);
-        if (m1 < 0 && total > 0.5 * theta) m1 = m;
+    for (int m0 = 0; m0 < M; m0 += 64) {
+        if (m0 + lane < M) est[lane] = e_of(m0 + lane);
+        __syncthreads();
+        if (lane == 0)
+            for (int u = 0; u < min(64, M - m0); ++u) {
+                total += est[u];
+                if (m1 < 0 && total > 0.5 * theta) m1 = m0 + u;
+            }
+        __syncthreads();
     }
     int32_t* out = ranges + (int64_t)idx * 2;
-    if (total <= theta) { out[0] = 0; out[1] = -1; return; }
+    if (lane == 0) flag = total <= theta;
+    __syncthreads();
+    if (flag) {
+        if (lane == 0) { out[0] = 0; out[1] = -1; }
+        return;
+    }
     double suf = 0.0;
     int m2 = M - 1;
-    for (int m = M - 1; m >= 0; --m) {
-        suf += e_of(m);
-        if (suf > 0.5 * theta) { m2 = m; break; }
+    for (int m0 = ((M - 1) / 64) * 64; m0 >= 0; m0 -= 64) {
+        if (m0 + lane < M) est[lane] = e_of(m0 + lane);
+        __syncthreads();
+        if (lane == 0) {
+            flag = 0;
+            for (int u = min(64, M - m0) - 1; u >= 0; --u) {
+                suf += est[u];
+                if (suf > 0.5 * theta) { m2 = m0 + u; flag = 1; break; }
+            }
+        }
+        __syncthreads();
+        if (flag) break;
     }
-    out[0] = m1;
-    out[1] = m2;
+    if (lane == 0) {
+        out[0] = m1;
+        out[1] = m2;
+    }
 }
 
 int class_index(int a, int b, int c) {   // a <= b <= c
@@ -292,7 +343,19 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     op->dw.upload(w, M, st);
     DevArray<double> mom(ctx, (size_t)nlev * M * NLF * K2);
     op->F.reset(ctx, (size_t)nlev * M * NLF * k * k);
-    moments_kernel<<<nlev * M * NLF, MOMW, 0, st>>>(k, M, nlev, dtau.p, dgx.p, dgw.p, mom.p);
+    switch (k) {
+        case 1: launch_moments<1>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 2: launch_moments<2>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 3: launch_moments<3>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 4: launch_moments<4>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 5: launch_moments<5>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 6: launch_moments<6>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 7: launch_moments<7>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 8: launch_moments<8>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 9: launch_moments<9>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        case 10: launch_moments<10>(nlev, M, dtau.p, dgx.p, dgw.p, mom.p, st); break;
+        default: fail(MWNS_EINVAL, "unsupported k");
+    }
     MWNS_HIP(hipGetLastError());
     const int64_t nF = (int64_t)nlev * M * NLF * k * k;
     combine_kernel<<<(unsigned)((nF + 255) / 256), 256, 0, st>>>(k, M, nlev, dC.p, mom.p, op->F.p);
@@ -306,7 +369,7 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     std::vector<int32_t> ranges(std::max(1, (nlev - 1) * 20) * 2);
     if (nlev > 1) {
         DevArray<int32_t> dr(ctx, ranges.size());
-        plan_kernel<<<((nlev - 1) * 20 + 63) / 64, 64, 0, st>>>(M, nlev, eps, op->dw.p, norms.p, nf0.p, dr.p);
+        plan_kernel<<<(nlev - 1) * 20, 64, 0, st>>>(M, eps, op->dw.p, norms.p, nf0.p, dr.p);
         MWNS_HIP(hipGetLastError());
         dr.download(ranges.data(), ranges.size(), st);
     }
