@@ -145,6 +145,32 @@ def test_eval_matches_oracle(M, ctx):
     assert np.abs(v - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("k", list(range(1, 11)))
+def test_every_order_tables_plan_tree_eval(M, ctx, k):
+    """Every order has its own instantiation of the projection, moment and evaluation kernels: the
+    projected tree (keys and leaves exact), the operator's 1-D blocks, plan and threshold, and
+    point values against the oracle."""
+    from oracle import apply as A, tree as T
+    w = workloads.small_adaptive(5, k=k, eps=1e-3 if k > 2 else 1e-2, jmax=3)
+    ot = _oracle_tree(w)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    keys, leaf, coef = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(keys, ot.keys) and np.array_equal(leaf, ot.leaf)
+    assert np.abs(coef - ot.coef).max() <= 1e-13 * np.abs(ot.coef).max()
+    tau, wt = _fit(w, ot.depth)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    F = M.mwns_op_tables_export(ctx, op)
+    scale = np.abs(oo.F[:, :, 7]).max(axis=(2, 3))
+    assert (np.abs(F - oo.F).max(axis=(2, 3, 4)) / scale).max() < 1e-13
+    assert np.array_equal(M.mwns_op_plan_export(op), oo.R)
+    assert abs(op.threshold - oo.theta) <= 1e-14 * oo.theta
+    P = workloads.points(500, seed=30 + k)
+    v = M.mwns_tree_eval(ctx, f, P)
+    ref = T.evaluate(ot, P)
+    assert np.abs(v - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_c2_full_size_sampled(M, ctx):
     """The benchmark workload (Poisson, k=8, eps=1e-6, 50 Gaussians) at full size: tree bit-exact,
     and g at sampled leaves (and their ancestor chains) within 1e-12 of the oracle."""
