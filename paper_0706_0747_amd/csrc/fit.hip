@@ -10,6 +10,7 @@
 //   B  = ln(t_B / delta^2) / 2                    Gamma(nu, t_B)/Gamma(nu) <= eps/4 (upper tail)
 // and h = h0 * 0.9^i, i = 0, 1, ..., until the relative error on 64 points per decade over
 // [delta, R] is at most eps/2.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -18,16 +19,6 @@
 namespace {
 
 double c_alpha(double alpha) { return 2.0 * std::pow(2.0, -2.0 * alpha) * std::pow(M_PI, -1.5) / std::tgamma(alpha); }
-
-double kernel0(double alpha, double r) {
-    return std::tgamma(1.5 - alpha) * c_alpha(alpha) / (2.0 * std::pow(r, 3.0 - 2.0 * alpha));
-}
-
-double kernel(double mu, double alpha, double r) {
-    if (mu == 0.0) return kernel0(alpha, r);
-    double nu = 1.5 - alpha;
-    return std::pow(2.0, alpha - 1.5) * c_alpha(alpha) * std::pow(mu / r, nu) * std::cyl_bessel_k(nu, mu * r);
-}
 
 double upper_t(double nu, double eps) {
     if (nu <= 1.0) return std::max(1.0, std::log(4.0 / (eps * std::tgamma(nu))));
@@ -56,10 +47,14 @@ extern "C" mwns_status mwns_fit_kernel(double mu, double alpha, double scale, do
     // check grid: 64 points per decade on [delta, R]
     const int ngrid = (int)std::ceil(64.0 * std::log10(R / delta));
     std::vector<double> r(ngrid + 1), ref(ngrid + 1), ref0(ngrid + 1);
+    // the kernel at the check points, K(r) = c1 (mu/r)^nu K_nu(mu r), and its mu = 0 form
+    // K0(r) = c0 / (2 r^{3-2 alpha}), with the constant factors formed once
+    const double c0 = std::tgamma(1.5 - alpha) * c_alpha(alpha);
+    const double c1 = std::pow(2.0, alpha - 1.5) * c_alpha(alpha);
     for (int i = 0; i <= ngrid; ++i) {
         r[i] = (i == ngrid) ? R : delta * std::pow(10.0, i / 64.0);
-        ref[i] = scale * kernel(mu, alpha, r[i]);
-        ref0[i] = scale * kernel0(alpha, r[i]);
+        ref0[i] = scale * (c0 / (2.0 * std::pow(r[i], 3.0 - 2.0 * alpha)));
+        ref[i] = mu == 0.0 ? ref0[i] : scale * (c1 * std::pow(mu / r[i], nu) * std::cyl_bessel_k(nu, mu * r[i]));
     }
     std::vector<double> t, ww;
     for (int it = 0; it < 40; ++it) {
