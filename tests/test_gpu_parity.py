@@ -69,6 +69,22 @@ def test_operator_tables_and_plan(M, ctx, case):
     assert abs(op.threshold - oo.theta) <= 1e-14 * oo.theta
 
 
+def test_operator_plan_many_terms(M, ctx):
+    """157 Gaussian terms (Poisson, eps = 1e-8): the plan kernel sums the terms' estimates in
+    chunks of 64, so the prefix and suffix scans cross chunk boundaries."""
+    from oracle import apply as A, fit
+    eps, depth = 1e-8, 4
+    tau, wt = fit.fit_kernel(0.0, 1.0, eps, math.sqrt(eps) * 2.0 ** -depth, math.sqrt(3))
+    assert len(tau) > 128
+    op = M.mwns_op_create(ctx, 6, tau, wt, eps, depth)
+    oo = A.Operator(6, tau, wt, eps, depth)
+    F = M.mwns_op_tables_export(ctx, op)
+    scale = np.abs(oo.F[:, :, 7]).max(axis=(2, 3))
+    assert (np.abs(F - oo.F).max(axis=(2, 3, 4)) / scale).max() < 1e-13
+    assert np.array_equal(M.mwns_op_plan_export(op), oo.R)
+    assert abs(op.threshold - oo.theta) <= 1e-14 * oo.theta
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_apply_matches_oracle(M, ctx, case):
     """FP64 apply with the oracle's plan imported: relative L2 <= 1e-12 on every node, both before
