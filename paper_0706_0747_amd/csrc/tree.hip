@@ -36,7 +36,9 @@ __device__ inline int64_t brick_index(int k, int child, int a, int b, int c) {
 
 namespace {
 
-constexpr int PT = 256;   // threads of the projection / transform blocks
+constexpr int PT = 256;   // threads of the transform blocks
+// threads of a projection block: eight waves above k = 8, where a box has 48-57 MFMA tiles
+constexpr int proj_threads(int k) { return k >= 9 ? 512 : 256; }
 constexpr int CH = 32;    // source terms per chunk
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -71,7 +73,7 @@ __device__ inline void line_apply(const double* __restrict__ M, const double* in
 // The interpolant on the children grid is one more product in the same layout, so |f - f~| is
 // formed in registers.
 template <int K>
-__global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
+__global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
                                                      const double* __restrict__ src /* x,y,z,a,cf per term */,
                                                      double nc3, double ni, const double* __restrict__ tab,
                                                      double* __restrict__ s_out, double* __restrict__ err_out) {
@@ -82,7 +84,8 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     constexpr int MT = (P2 + 15) / 16, NTC = (P2 * P2 + 15) / 16, NTO = (K * K + 15) / 16;
     constexpr int NTCH = MT * NTC;           // children tiles come first
     constexpr int NT = NTCH + NTO;
-    constexpr int NW = PT / 64;
+    constexpr int BT = proj_threads(K);
+    constexpr int NW = BT / 64;
     constexpr int TPW = (NT + NW - 1) / NW;
     constexpr int KS = (K + 3) / 4;          // inner steps of the interpolation product
     constexpr int NE = CH * 3 * NQ;          // term table E[i][d][q]; E[i][0][q] carries the weight
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
     // the box's 1-D points per dimension: its own nodes, then the children's nodes
-    for (int e = threadIdx.x; e < 3 * NQ; e += PT) {
+    for (int e = threadIdx.x; e < 3 * NQ; e += BT) {
         const int d = e / NQ, q = e % NQ;
         double x;
         if (q < K) x = h * (l[d] + gx[q]);
@@ -125,9 +128,9 @@ __global__ void __launch_bounds__(PT) project_kernel(int j, int jmax, const uint
     for (int c0 = 0; c0 < nsrc; c0 += CH) {
         const int nc = min(CH, nsrc - c0);
         const int nc4 = (nc + 3) & ~3;       // whole steps of four terms; the padding terms are zero
-        for (int e = threadIdx.x; e < nc * 5; e += PT) st[e] = src[(int64_t)c0 * 5 + e];
+        for (int e = threadIdx.x; e < nc * 5; e += BT) st[e] = src[(int64_t)c0 * 5 + e];
         __syncthreads();
-        for (int e = threadIdx.x; e < nc4 * 3 * NQ; e += PT) {
+        for (int e = threadIdx.x; e < nc4 * 3 * NQ; e += BT) {
             const int q = e % NQ, d = (e / NQ) % 3, i = e / (3 * NQ);
             double v = 0.0;
             if (i < nc) {
@@ -376,7 +379,7 @@ template <int K>
 struct ProjectLaunch {
     static void run(hipStream_t st, int64_t n, int j, int jmax, const uint64_t* keys, int nsrc, const double* src,
                     const double* tab, double* s, double* err) {
-        project_kernel<K><<<(unsigned)n, PT, 0, st>>>(j, jmax, keys, nsrc, src, std::pow(2.0, -1.5 * j),
+        project_kernel<K><<<(unsigned)n, proj_threads(K), 0, st>>>(j, jmax, keys, nsrc, src, std::pow(2.0, -1.5 * j),
                                                       std::pow(2.0, 1.5 * j), tab, s, err);
     }
 };
