@@ -159,16 +159,31 @@ __device__ void load_block(const double* __restrict__ brick, int child, double* 
 
 // Ghost bricks: the children of a node Q of level j-1 that is not internal, interpolated from the
 // deepest existing ancestor (a leaf) by repeated zero-detail reconstruction (Alg. 3 Step 2).
+// The ghost bricks of every level of one apply, one block each: block b belongs to entry li with
+// start[li] <= b < start[li + 1], parent level jm1[li], key keys[li][b - start[li]] and brick
+// out[li] + (b - start[li]) (2k)^3.
+struct GhostTab {
+    int n = 0;
+    int jm1[MAXLEV + 1];
+    int64_t start[MAXLEV + 2];
+    const uint64_t* keys[MAXLEV + 1];
+    double* out[MAXLEV + 1];
+};
+
 template <int K>
-__global__ void __launch_bounds__(AT) ghost_kernel(int jm1, const uint64_t* __restrict__ gkeys, const uint64_t* __restrict__ keys,
-                                                   int64_t nnodes, LevelTab2 lt, const double* __restrict__ coef,
-                                                   const double* __restrict__ Htg, double* __restrict__ gout) {
+__global__ void __launch_bounds__(AT) ghost_kernel(GhostTab gt, const uint64_t* __restrict__ keys, int64_t nnodes,
+                                                   LevelTab2 lt, const double* __restrict__ coef,
+                                                   const double* __restrict__ Htg) {
     constexpr int P = 2 * K, K3 = K * K * K;
     __shared__ double Ht[2 * K * K];
     __shared__ double blk[K3], tmp1[K * P * P], tmp2[K * P * P];
     for (int e = threadIdx.x; e < 2 * K * K; e += AT) Ht[e] = Htg[e];
     __syncthreads();
-    const uint64_t q = gkeys[blockIdx.x];
+    int li = 0;
+    while (li + 1 < gt.n && (int64_t)blockIdx.x >= gt.start[li + 1]) ++li;
+    const int64_t gi = (int64_t)blockIdx.x - gt.start[li];
+    const int jm1 = gt.jm1[li];
+    const uint64_t q = gt.keys[li][gi];
     int64_t l[3];
     key_coords(q, l);
     int i = jm1;
@@ -177,7 +192,7 @@ __global__ void __launch_bounds__(AT) ghost_kernel(int jm1, const uint64_t* __re
         node = find_sorted(keys, nnodes, make_key(i, l[0] >> (jm1 - i), l[1] >> (jm1 - i), l[2] >> (jm1 - i)));
         if (node >= 0) break;
     }
-    double* go = gout + (int64_t)blockIdx.x * P * P * P;
+    double* go = gt.out[li] + gi * P * P * P;
     if (node < 0) {   // cannot happen for a tree with a root; keep the brick defined
         for (int e = threadIdx.x; e < P * P * P; e += AT) go[e] = 0.0;
         return;
@@ -295,9 +310,9 @@ __global__ void count_kernel(const CountLevel* __restrict__ lv, int nlev, int64_
 
 template <int K>
 struct GhostLaunch {
-    static void run(hipStream_t st, int64_t ng, int jm1, const uint64_t* gk, const uint64_t* keys, int64_t nn,
-                    const LevelTab2& lt, const double* coef, const double* Ht, double* gout) {
-        ghost_kernel<K><<<(unsigned)ng, AT, 0, st>>>(jm1, gk, keys, nn, lt, coef, Ht, gout);
+    static void run(hipStream_t st, int64_t ng, const GhostTab& gt, const uint64_t* keys, int64_t nn,
+                    const LevelTab2& lt, const double* coef, const double* Ht) {
+        ghost_kernel<K><<<(unsigned)ng, AT, 0, st>>>(gt, keys, nn, lt, coef, Ht);
     }
 };
 template <int K>
@@ -551,7 +566,7 @@ struct LevelWork {
     DevArray<int32_t> nbr;
     DevView<uint8_t> cmask;
     DevView<Tpl> dtpl;
-    DevArray<double> ghosts;
+    DevView<double> ghosts;         // this level's part of TreeApply::ghost_store
     DevView<uint64_t> pkeys, gkeys;
     DevArray<u4> xr32, xg32, xrb, xgb;     // reduced-precision copies of the inputs (routed applies)
     DevView<int64_t> apb;                  // assembly: parent's brick of every brick of the level
@@ -567,6 +582,7 @@ struct TreeApply {
     std::vector<LevelWork> W;
     DevView<double> dHt;
     UploadArena setup_arena, ghost_arena, desc_arena;
+    DevArray<double> ghost_store;    // the ghost bricks of all levels, level by level
     LevelTab2 lt{};
     int64_t miss_base = 0, miss_total = 0, total_ghosts = 0, jobs = 0;
     double err_bound = 0.0, flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
@@ -748,27 +764,41 @@ void discover_ghosts(mwns_ctx* ctx, TreeApply& a, std::vector<uint64_t>& keys, u
         if (lw.nghost) a.ghost_arena.add(keys.data() + b0, lw.nghost, lw.gkeys);
     }
     a.ghost_arena.commit(ctx);
+    a.ghost_store.reset(ctx, (size_t)a.total_ghosts * brick_elems(a.k));
+    size_t goff = 0;
     for (int j = 1; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
+        lw.ghosts.p = nullptr;
         if (lw.tpl.empty() || !lw.nghost) continue;
         const int NL = 2 * lw.Lr + 1;
         const int64_t n = lw.nout * NL * NL * NL;
         closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(
             n, dmiss + a.miss_base + lw.miss_off, lw.gkeys.p, lw.nghost, lw.nout, lw.nbr.p);
         MWNS_HIP(hipGetLastError());
-        lw.ghosts.reset(ctx, (size_t)lw.nghost * brick_elems(a.k));
+        lw.ghosts.p = a.ghost_store.p + goff;
+        goff += (size_t)lw.nghost * brick_elems(a.k);
     }
 }
 
 // Ghost values: interpolation from the deepest existing ancestor (depends on f's coefficients).
+// All levels in one launch: the ghosts of different levels are independent.
 void launch_ghosts(mwns_ctx* ctx, TreeApply& a) {
+    GhostTab gt;
+    int64_t total = 0;
     for (int j = 1; j <= a.depth; ++j) {
-        LevelWork& lw = a.W[j];
+        const LevelWork& lw = a.W[j];
         if (lw.tpl.empty() || !lw.nghost) continue;
-        dispatch_k<GhostLaunch>(a.k, ctx->stream, lw.nghost, j - 1, lw.gkeys.p, a.f->dkeys.p, a.f->nnodes, a.lt,
-                                a.f->coef.p, a.dHt.p, lw.ghosts.p);
-        MWNS_HIP(hipGetLastError());
+        gt.jm1[gt.n] = j - 1;
+        gt.start[gt.n] = total;
+        gt.keys[gt.n] = lw.gkeys.p;
+        gt.out[gt.n] = lw.ghosts.p;
+        ++gt.n;
+        total += lw.nghost;
     }
+    if (!total) return;
+    gt.start[gt.n] = total;
+    dispatch_k<GhostLaunch>(a.k, ctx->stream, total, gt, a.f->dkeys.p, a.f->nnodes, a.lt, a.f->coef.p, a.dHt.p);
+    MWNS_HIP(hipGetLastError());
 }
 
 // Routed apply: the sum of squares of every level's inputs (real and ghost) into lsq[0..depth].
