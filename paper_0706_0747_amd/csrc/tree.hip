@@ -236,20 +236,33 @@ __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jma
 namespace mwns {
 namespace {
 
-// Copy leaf coefficients (node-major [n][k^3], candidates of one level) into their bricks.
-__global__ void scatter_leaves_kernel(int k, int j, int64_t n, const double* __restrict__ s, const uint8_t* __restrict__ is_leaf,
-                                      LevelTab lt, double* __restrict__ coef) {
+// The projected candidates of the levels j0..depth, one entry per level: coefficients s[li]
+// node-major [n][k^3]; entry li covers the elements [start[li], start[li + 1]) of one launch.
+struct LeafTab {
+    int n = 0;
+    int j[MAXLEV + 1];
+    int64_t start[MAXLEV + 2];
+    const double* s[MAXLEV + 1];
+};
+
+// Copy the leaves' coefficients into their bricks, all levels in one launch.
+__global__ void scatter_leaves_kernel(int k, LeafTab lf, const uint8_t* __restrict__ is_leaf, LevelTab lt,
+                                      double* __restrict__ coef) {
     const int k3 = k * k * k;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * k3) return;
-    const int64_t c = idx / k3;
-    if (is_leaf && !is_leaf[c]) return;
-    const int e = (int)(idx % k3);
+    if (idx >= lf.start[lf.n]) return;
+    int li = 0;
+    while (li + 1 < lf.n && idx >= lf.start[li + 1]) ++li;
+    const int64_t loc = idx - lf.start[li];
+    const int j = lf.j[li];
+    const int64_t c = loc / k3;
+    if (!is_leaf[lt.node_off[j] + c]) return;
+    const int e = (int)(loc % k3);
     int64_t brick;
     int child;
     node_to_brick(lt, j, lt.node_off[j] + c, &brick, &child);
     const int a = e / (k * k), b = (e / k) % k, cc = e % k;
-    coef[brick * (int64_t)(8 * k3) + brick_index(k, child, a, b, cc)] = s[idx];
+    coef[brick * (int64_t)(8 * k3) + brick_index(k, child, a, b, cc)] = lf.s[li][loc];
 }
 
 // Parent block of every internal node of level j from its brick of level j+1:
@@ -520,14 +533,16 @@ double source_norm(int n, const double* xyz, const double* a, const double* c) {
     return std::sqrt(tot);
 }
 
+// The 8 children of every selected key, in ascending order: child s of (j, l) is
+// (j + 1, 2 l + (s & 1, (s >> 1) & 1, s >> 2)), whose interleaved bits are the parent's shifted by
+// three with s below them.
 std::vector<uint64_t> children_of(const std::vector<uint64_t>& keys, const std::vector<uint8_t>& sel) {
     std::vector<uint64_t> out;
+    constexpr uint64_t MORTON = (1ull << 57) - 1;
     for (size_t i = 0; i < keys.size(); ++i) {
         if (!sel[i]) continue;
-        int64_t l[3];
-        key_coords(keys[i], l);
-        const int j = key_level(keys[i]) + 1;
-        for (int s = 0; s < 8; ++s) out.push_back(make_key(j, 2 * l[0] + (s & 1), 2 * l[1] + ((s >> 1) & 1), 2 * l[2] + (s >> 2)));
+        const uint64_t base = ((uint64_t)(key_level(keys[i]) + 1) << 57) | ((keys[i] & MORTON) << 3);
+        for (uint64_t s = 0; s < 8; ++s) out.push_back(base | s);
     }
     return out;
 }
@@ -608,8 +623,8 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
         }
         if (j < jmax)
             for (int64_t i = 0; i < nc; ++i) min_margin = std::min(min_margin, std::fabs(err[i] - thr) / thr);
-        lkeys.push_back(cand);
-        lleaf.push_back(lf);
+        lkeys.push_back(std::move(cand));
+        lleaf.push_back(std::move(lf));
         lcoef.push_back(std::move(ds));
         cand = children_of(lkeys.back(), ref);
     }
@@ -626,10 +641,18 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
     MWNS_HIP(hipMemsetAsync(t->coef.p, 0, t->coef.n * sizeof(double), st));
     LevelTab lt = level_tab(t.get());
-    for (int j = j0; j <= t->depth; ++j) {
-        const int64_t nn = t->lev[j].nnodes;
-        scatter_leaves_kernel<<<(unsigned)((nn * k3 + 255) / 256), 256, 0, st>>>(
-            k, j, nn, lcoef[j].p, t->dleaf.p + t->lev[j].node_off, lt, t->coef.p);
+    {
+        LeafTab lf;
+        int64_t total = 0;
+        for (int j = j0; j <= t->depth; ++j) {
+            lf.j[lf.n] = j;
+            lf.start[lf.n] = total;
+            lf.s[lf.n] = lcoef[j].p;
+            ++lf.n;
+            total += t->lev[j].nnodes * k3;
+        }
+        lf.start[lf.n] = total;
+        scatter_leaves_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(k, lf, t->dleaf.p, lt, t->coef.p);
         MWNS_HIP(hipGetLastError());
     }
     DevArray<double> dH = upload_filters(ctx, k);
