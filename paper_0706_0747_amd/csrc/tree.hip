@@ -454,12 +454,12 @@ void finalize_structure(mwns_tree* t) {
         int64_t b = 0;
         for (int64_t i = Lp.node_off; i < Lp.node_off + Lp.nnodes; ++i) {
             if (t->leaf[i]) continue;
-            int64_t pl[3];
-            key_coords(t->keys[i], pl);
+            // child s of (j - 1, l) is (j, 2 l + (s & 1, (s >> 1) & 1, s >> 2)): the parent's
+            // interleaved bits shifted by three with s below them
+            const uint64_t base = ((uint64_t)j << 57) | ((t->keys[i] & ((1ull << 57) - 1)) << 3);
             for (int s = 0; s < 8; ++s) {
                 const int64_t ci = L.node_off + 8 * b + s;
-                if (b >= L.nbricks ||
-                    t->keys[ci] != make_key(j, 2 * pl[0] + (s & 1), 2 * pl[1] + ((s >> 1) & 1), 2 * pl[2] + (s >> 2)))
+                if (b >= L.nbricks || t->keys[ci] != (base | (uint64_t)s))
                     fail(MWNS_EINVAL, "children of an internal node are missing at level " + std::to_string(j));
             }
             t->brick_parent.push_back(i);
@@ -527,8 +527,9 @@ double source_norm(int n, const double* xyz, const double* a, const double* c) {
             const double s = a[i] + a[q];
             double d2 = 0.0;
             for (int d = 0; d < 3; ++d) d2 += (xyz[3 * i + d] - xyz[3 * q + d]) * (xyz[3 * i + d] - xyz[3 * q + d]);
-            tot += c[i] * c[q] * std::pow(a[i] * a[q] / (M_PI * M_PI), 1.5) * std::pow(M_PI / s, 1.5) *
-                   std::exp(-a[i] * a[q] * d2 / s);
+            // (a_i a_q / pi^2)^{3/2} (pi / s)^{3/2} = u^{3/2}, u = a_i a_q / (pi s)
+            const double u = a[i] * a[q] / (M_PI * s);
+            tot += c[i] * c[q] * (u * std::sqrt(u)) * std::exp(-a[i] * a[q] * d2 / s);
         }
     return std::sqrt(tot);
 }
