@@ -308,6 +308,42 @@ __global__ void count_kernel(const CountLevel* __restrict__ lv, int nlev, int64_
     if (cnt) atomicAdd(total, (unsigned long long)cnt);
 }
 
+// Bricks of several levels for one launch of level_sumsq_kernel: entry i covers the blocks
+// [start[i], start[i + 1]), bricks X[i] + (b - start[i]) 8k^3, and adds to *acc[i].
+struct SumsqTab {
+    int n = 0;
+    int64_t start[2 * (MAXLEV + 1) + 1];
+    const double* X[2 * (MAXLEV + 1)];
+    double* acc[2 * (MAXLEV + 1)];
+};
+
+// Sum of squares of every brick element, one 256-thread block per brick, reduced in LDS and
+// added to its entry's accumulator.
+template <int K>
+__global__ void __launch_bounds__(256) level_sumsq_kernel(SumsqTab tb) {
+    constexpr int E = 8 * K * K * K;
+    __shared__ double red[256];
+    int i = 0;
+    while (i + 1 < tb.n && (int64_t)blockIdx.x >= tb.start[i + 1]) ++i;
+    const double* x = tb.X[i] + ((int64_t)blockIdx.x - tb.start[i]) * E;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < E; e += 256) s += x[e] * x[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(tb.acc[i], red[0]);
+}
+
+template <int K>
+struct LevelSumsqLaunch {
+    static void run(hipStream_t st, int64_t nb, const SumsqTab& tb) {
+        level_sumsq_kernel<K><<<(unsigned)nb, 256, 0, st>>>(tb);
+    }
+};
+
 template <int K>
 struct GhostLaunch {
     static void run(hipStream_t st, int64_t ng, const GhostTab& gt, const uint64_t* keys, int64_t nn,
@@ -804,12 +840,25 @@ void launch_ghosts(mwns_ctx* ctx, TreeApply& a) {
 // Routed apply: the sum of squares of every level's inputs (real and ghost) into lsq[0..depth].
 void launch_level_norms(mwns_ctx* ctx, TreeApply& a, double* lsq) {
     const int64_t E = brick_elems(a.k);
+    SumsqTab tb;
+    int64_t total = 0;
+    auto add = [&](int64_t nb, const double* X, double* acc) {
+        if (nb <= 0) return;
+        tb.start[tb.n] = total;
+        tb.X[tb.n] = X;
+        tb.acc[tb.n] = acc;
+        ++tb.n;
+        total += nb;
+    };
     for (int j = 0; j <= a.depth; ++j) {
         const LevelWork& lw = a.W[j];
         if (lw.tpl.empty()) continue;
-        launch_sumsq(a.k, ctx->stream, lw.nout, a.f->coef.p + a.f->lev[j].brick_off * E, lsq + j);
-        launch_sumsq(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lsq + j);
+        add(lw.nout, a.f->coef.p + a.f->lev[j].brick_off * E, lsq + j);
+        add(lw.nghost, lw.ghosts.p, lsq + j);
     }
+    if (!total) return;
+    tb.start[tb.n] = total;
+    dispatch_k<LevelSumsqLaunch>(a.k, ctx->stream, total, tb);
     MWNS_HIP(hipGetLastError());
 }
 
