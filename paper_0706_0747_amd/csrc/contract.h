@@ -89,7 +89,5 @@ int64_t resident_blocks_wide(int k, int prec, int device);
 void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out);
 // FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
-// *acc += sum of squares of nb bricks.
-void launch_sumsq(int k, hipStream_t st, int64_t nb, const double* X, double* acc);
 
 }  // namespace mwns

@@ -794,24 +794,6 @@ __global__ void convert_kernel(int64_t nbricks, const double* __restrict__ X, u4
     out[i] = BF ? split4(v) : __builtin_bit_cast(u4, v);
 }
 
-// Sum of squares of every brick element of one level (real and ghost inputs): one 256-thread
-// block per brick, reduced in LDS and added to *acc.
-template <int K>
-__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ X, double* __restrict__ acc) {
-    constexpr int E = 8 * K * K * K;
-    __shared__ double red[256];
-    const double* x = X + (int64_t)blockIdx.x * E;
-    double s = 0.0;
-    for (int e = threadIdx.x; e < E; e += 256) s += x[e] * x[e];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(acc, red[0]);
-}
-
 // Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD, FP64
 // terms per pass over the cells).
 struct Variant {
@@ -873,12 +855,6 @@ struct ApplyLaunch {
 };
 
 template <int K>
-struct SumsqLaunch {
-    static void run(hipStream_t st, int64_t nb, const double* X, double* acc) {
-        if (nb > 0) sumsq_kernel<K><<<(unsigned)nb, 256, 0, st>>>(X, acc);
-    }
-};
-template <int K>
 struct ConvertLaunch {
     static void run(hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
         const int64_t n = nb * 2 * K * 2 * K * 4;
@@ -927,10 +903,6 @@ int64_t resident_blocks(int k, int variant, int prec, int device) {
 
 void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
     dispatch_narrow<ConvertLaunch>(k, st, nb, X, out, bf);
-}
-
-void launch_sumsq(int k, hipStream_t st, int64_t nb, const double* X, double* acc) {
-    dispatch_k<SumsqLaunch>(k, st, nb, X, acc);
 }
 
 }  // namespace mwns
