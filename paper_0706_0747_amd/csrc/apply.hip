@@ -70,12 +70,32 @@ __global__ void closure_kernel(int64_t nout, int jm1, const uint64_t* __restrict
     miss[idx] = key;
 }
 
-// The missing keys (entries != ~0) of one apply's closure, appended to out (order immaterial).
-__global__ void compact_miss_kernel(int64_t n, const uint64_t* __restrict__ miss, uint64_t* __restrict__ out,
-                                    unsigned int* __restrict__ count) {
+__global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || miss[i] == ~0ull) return;
-    out[atomicAdd(count, 1u)] = miss[i];
+    if (i < n) p[i] = v;
+}
+
+// The distinct missing keys (entries != ~0) of one apply's closure, appended to out in no
+// particular order (a missing parent is reported once per neighbouring output box).  tab is an
+// open-addressing set of cap entries (a power of two, at least twice n, all ~0 on entry); the
+// first insertion of a key appends it.  No key equals ~0, and the set never fills, so every
+// probe sequence ends at the key or at an empty slot.
+__global__ void compact_distinct_kernel(int64_t n, const uint64_t* __restrict__ miss, uint64_t* __restrict__ tab,
+                                        int64_t cap, uint64_t* __restrict__ out, unsigned int* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = miss[i];
+    if (key == ~0ull) return;
+    int64_t slot = (int64_t)((key * 0x9E3779B97F4A7C15ull) >> 20) & (cap - 1);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+        const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(tab + slot), ~0ull, key);
+        if (prev == ~0ull) {
+            out[atomicAdd(count, 1u)] = key;
+            return;
+        }
+        if (prev == key) return;
+        slot = (slot + 1) & (cap - 1);
+    }
 }
 
 __global__ void closure_fill_kernel(int64_t n, const uint64_t* __restrict__ miss, const uint64_t* __restrict__ gkeys,
@@ -1220,16 +1240,28 @@ void prepare(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& trees, cons
     }
     miss.reset(ctx, std::max<int64_t>(1, miss_total));
     for (auto& a : trees) launch_closure(ctx, *a, miss.p);
-    // only the missing keys travel to the host: compact them per tree on the device
+    // only the distinct missing keys travel to the host: compact them per tree on the device
     const int nt = (int)trees.size();
     DevArray<uint64_t> comp(ctx, std::max<int64_t>(1, miss_total));
     DevArray<unsigned int> cnt(ctx, nt);
     zero_ints_kernel<<<(nt + 63) / 64, 64, 0, st>>>(reinterpret_cast<int*>(cnt.p), nt);
+    std::vector<int64_t> cap(nt, 0), tab_off(nt + 1, 0);
+    for (int i = 0; i < nt; ++i) {
+        if (trees[i]->miss_total) {
+            int64_t c = 1;
+            while (c < 2 * trees[i]->miss_total) c <<= 1;
+            cap[i] = c;
+        }
+        tab_off[i + 1] = tab_off[i] + cap[i];
+    }
+    DevArray<uint64_t> tab(ctx, std::max<int64_t>(1, tab_off[nt]));
+    if (tab_off[nt])
+        fill_u64_kernel<<<(unsigned)((tab_off[nt] + 255) / 256), 256, 0, st>>>(tab.p, tab_off[nt], ~0ull);
     for (int i = 0; i < nt; ++i) {
         const TreeApply& a = *trees[i];
         if (a.miss_total)
-            compact_miss_kernel<<<(unsigned)((a.miss_total + 255) / 256), 256, 0, st>>>(
-                a.miss_total, miss.p + a.miss_base, comp.p + a.miss_base, cnt.p + i);
+            compact_distinct_kernel<<<(unsigned)((a.miss_total + 255) / 256), 256, 0, st>>>(
+                a.miss_total, miss.p + a.miss_base, tab.p + tab_off[i], cap[i], comp.p + a.miss_base, cnt.p + i);
     }
     MWNS_HIP(hipGetLastError());
     std::vector<unsigned int> hc(nt);
