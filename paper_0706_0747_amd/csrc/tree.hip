@@ -313,29 +313,37 @@ __global__ void __launch_bounds__(PT) compress_kernel(int j, const int64_t* __re
 
 // f at points from the leaf holding each point (App. A.1).
 template <int K>
-__global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const uint64_t* __restrict__ keys, int64_t nnodes,
+__global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const int32_t* __restrict__ child,
                             const uint8_t* __restrict__ leaf, LevelTab lt, const double* __restrict__ coef,
                             double* __restrict__ out, int* __restrict__ bad) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const double x[3] = {xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]};
-    // The deepest node that contains the point is its leaf (the children of a node partition it),
-    // so the levels are searched from the finest up, each within its own slice of the keys.
-    for (int j = lt.depth; j >= 0; --j) {
+    // Walk down from the root: the child of a node that holds the point is the one whose parity
+    // bits at the next level are those of floor(2^{j+1} x) (clamped to the cube).
+    int64_t node = 0;
+    for (int j = 0; j <= lt.depth; ++j) {
+        if (!leaf[node]) {
+            const int32_t cb = j < lt.depth ? child[node] : -1;
+            if (cb < 0) break;   // an internal node without children: not a valid tree
+            const int64_t side1 = (int64_t)1 << (j + 1);
+            int oct = 0;
+            for (int d = 0; d < 3; ++d) {
+                int64_t v = (int64_t)floor(x[d] * side1);
+                v = v < 0 ? 0 : (v > side1 - 1 ? side1 - 1 : v);
+                oct |= (int)(v & 1) << d;
+            }
+            node = lt.node_off[j + 1] + 8 * ((int64_t)cb - lt.brick_off[j + 1]) + oct;
+            continue;
+        }
+        // the leaf: local coordinates u in [0, 1] of the point in the box
         const int64_t side = (int64_t)1 << j;
-        int64_t l[3];
         double u[3];
         for (int d = 0; d < 3; ++d) {
             int64_t v = (int64_t)floor(x[d] * side);
             v = v < 0 ? 0 : (v > side - 1 ? side - 1 : v);
-            l[d] = v;
             u[d] = x[d] * side - v;
         }
-        const int64_t off = lt.node_off[j], end = j < lt.depth ? lt.node_off[j + 1] : nnodes;
-        const int64_t f = find_sorted(keys + off, end - off, make_key(j, l[0], l[1], l[2]));
-        if (f < 0) continue;
-        const int64_t node = off + f;
-        if (!leaf[node]) break;   // an internal node none of whose children holds the point
         double ph[3][K];
         for (int d = 0; d < 3; ++d) {
             const double t = 2.0 * u[d] - 1.0;
@@ -351,15 +359,15 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
             for (int a = 0; a < K; ++a) ph[d][a] *= sqrt(2.0 * a + 1.0);
         }
         int64_t brick;
-        int child;
-        node_to_brick(lt, j, node, &brick, &child);
+        int sib;
+        node_to_brick(lt, j, node, &brick, &sib);
         const double* cb = coef + brick * (int64_t)(8 * K * K * K);
         double s = 0.0;
         for (int a = 0; a < K; ++a) {
             double sa = 0.0;
             for (int b = 0; b < K; ++b) {
                 double sb = 0.0;
-                for (int c = 0; c < K; ++c) sb += cb[brick_index(K, child, a, b, c)] * ph[2][c];
+                for (int c = 0; c < K; ++c) sb += cb[brick_index(K, sib, a, b, c)] * ph[2][c];
                 sa += sb * ph[1][b];
             }
             s += sa * ph[0][a];
@@ -405,10 +413,10 @@ struct CompressLaunch {
 };
 template <int K>
 struct EvalLaunch {
-    static void run(hipStream_t st, int64_t n, const double* xyz, const uint64_t* keys, int64_t nn, const uint8_t* leaf,
+    static void run(hipStream_t st, int64_t n, const double* xyz, const int32_t* child, const uint8_t* leaf,
                     const LevelTab& lt, const double* coef, double* out, int* bad) {
         // one point per thread; small blocks spread the points over the compute units
-        eval_kernel<K><<<(unsigned)((n + 63) / 64), 64, 0, st>>>(n, xyz, keys, nn, leaf, lt, coef, out, bad);
+        eval_kernel<K><<<(unsigned)((n + 63) / 64), 64, 0, st>>>(n, xyz, child, leaf, lt, coef, out, bad);
     }
 };
 
@@ -836,7 +844,12 @@ mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, cons
     dx.upload(xyz, 3 * npts, st);
     MWNS_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), st));
     LevelTab lt = level_tab(t);
-    dispatch_k<EvalLaunch>(t->k, st, npts, dx.p, t->dkeys.p, t->nnodes, t->dleaf.p, lt, t->coef.p, dout.p, dbad.p);
+    // child brick of every internal node (-1 for leaves), from the parent of every brick
+    std::vector<int32_t> child(t->nnodes, -1);
+    for (int64_t b = 1; b < t->nbricks; ++b) child[t->brick_parent[b]] = (int32_t)b;
+    DevArray<int32_t> dchild(ctx, t->nnodes);
+    dchild.upload(child.data(), t->nnodes, st);
+    dispatch_k<EvalLaunch>(t->k, st, npts, dx.p, dchild.p, t->dleaf.p, lt, t->coef.p, dout.p, dbad.p);
     MWNS_HIP(hipGetLastError());
     int bad = 0;
     dout.download(out, npts, st);
