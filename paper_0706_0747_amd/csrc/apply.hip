@@ -70,6 +70,7 @@ __global__ void closure_kernel(int64_t nout, int jm1, const uint64_t* __restrict
     miss[idx] = key;
 }
 
+// p[0..n) = v.
 __global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -177,8 +178,6 @@ __device__ void load_block(const double* __restrict__ brick, int child, double* 
     __syncthreads();
 }
 
-// Ghost bricks: the children of a node Q of level j-1 that is not internal, interpolated from the
-// deepest existing ancestor (a leaf) by repeated zero-detail reconstruction (Alg. 3 Step 2).
 // The ghost bricks of every level of one apply, one block each: block b belongs to entry li with
 // start[li] <= b < start[li + 1], parent level jm1[li], key keys[li][b - start[li]] and brick
 // out[li] + (b - start[li]) (2k)^3.
@@ -190,6 +189,8 @@ struct GhostTab {
     double* out[MAXLEV + 1];
 };
 
+// Ghost bricks: the children of a node Q of level j-1 that is not internal, interpolated from the
+// deepest existing ancestor (a leaf) by repeated zero-detail reconstruction (Alg. 3 Step 2).
 template <int K>
 __global__ void __launch_bounds__(AT) ghost_kernel(GhostTab gt, const uint64_t* __restrict__ keys, int64_t nnodes,
                                                    LevelTab2 lt, const double* __restrict__ coef,
@@ -775,9 +776,9 @@ void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
     }
 }
 
-// Sorts the keys and drops repeats (a missing parent is reported once per neighbouring output
-// box).  An LSD radix sort over only the bytes in which the keys differ: level bits and the
-// Morton bits of the deepest level, a few passes over data that stays in cache.
+// Sorts the keys and drops any repeats.  An LSD radix sort over only the bytes in which the keys
+// differ (level bits and the Morton bits of the deepest level): a few passes over data that stays
+// in cache.
 void sort_unique_keys(std::vector<uint64_t>& keys) {
     const size_t n = keys.size();
     if (n < 2) return;
