@@ -69,8 +69,10 @@ extern "C" mwns_status mwns_fit_kernel(double mu, double alpha, double scale, do
         }
         double emax = 0.0;
         for (int g = 0; g <= ngrid; ++g) {
+            // t grows with i; once t_i r^2 > 746, exp(-t_i r^2) is below half the smallest
+            // subnormal and rounds to +0, so the remaining terms add nothing to the sum
             double acc = 0.0;
-            for (int i = 0; i < m; ++i) acc += ww[i] * std::exp(-t[i] * r[g] * r[g]);
+            for (int i = 0; i < m && t[i] * r[g] * r[g] <= 746.0; ++i) acc += ww[i] * std::exp(-t[i] * r[g] * r[g]);
             emax = std::max(emax, std::fabs(ref[g] - acc) / ref0[g]);
         }
         if (emax <= 0.5 * eps) {
