@@ -41,13 +41,40 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int AT = 256;            // threads per block of the transform kernels
 
 // ---------------------------------------------------------------- closure
+// The output levels of one apply's closure for one launch: level entry li takes the 256-thread
+// blocks [bstart[li], bstart[li + 1]) (a block never spans two levels); its output bricks are
+// the nout[li] parents pkeys[li] of level jm1[li] with band radius Lr[li], and it writes
+// nbr[li] and miss[li] ([nout][NL^3] each); the fill maps the missing entries to the ng[li]
+// sorted ghost keys gkeys[li].
+struct ClosTab {
+    int n = 0;
+    int jm1[MAXLEV + 1], Lr[MAXLEV + 1];
+    int64_t nout[MAXLEV + 1], ng[MAXLEV + 1];
+    int64_t bstart[MAXLEV + 2];
+    const uint64_t* pkeys[MAXLEV + 1];
+    const uint64_t* gkeys[MAXLEV + 1];
+    int32_t* nbr[MAXLEV + 1];
+    uint64_t* miss[MAXLEV + 1];
+};
+
+__device__ inline int clos_entry(const ClosTab& ct) {
+    int li = 0;
+    while (li + 1 < ct.n && (int64_t)blockIdx.x >= ct.bstart[li + 1]) ++li;
+    return li;
+}
+
 // For every output brick of level j (parent P at level j-1) and L in [-Lr,Lr]^3: index of the
 // brick whose parent is P - L among the level's real bricks, -1 outside the cube, -2 when P - L is
 // not an internal node (the key is written to miss[] for interpolation).
-__global__ void closure_kernel(int64_t nout, int jm1, const uint64_t* __restrict__ pkeys, int Lr,
-                               int32_t* __restrict__ nbr, uint64_t* __restrict__ miss) {
+__global__ void closure_kernel(ClosTab ct) {
+    const int li = clos_entry(ct);
+    const int64_t nout = ct.nout[li];
+    const int jm1 = ct.jm1[li], Lr = ct.Lr[li];
+    const uint64_t* __restrict__ pkeys = ct.pkeys[li];
+    int32_t* __restrict__ nbr = ct.nbr[li];
+    uint64_t* __restrict__ miss = ct.miss[li];
     const int NL = 2 * Lr + 1, NL3 = NL * NL * NL;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = ((int64_t)blockIdx.x - ct.bstart[li]) * 256 + threadIdx.x;
     if (idx >= nout * NL3) return;
     const int64_t b = idx / NL3;
     const int e = (int)(idx % NL3);
@@ -99,11 +126,17 @@ __global__ void compact_distinct_kernel(int64_t n, const uint64_t* __restrict__ 
     }
 }
 
-__global__ void closure_fill_kernel(int64_t n, const uint64_t* __restrict__ miss, const uint64_t* __restrict__ gkeys,
-                                    int64_t ng, int64_t nreal, int32_t* __restrict__ nbr) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n || nbr[idx] != -2) return;
-    nbr[idx] = (int32_t)(nreal + find_sorted(gkeys, ng, miss[idx]));
+// The missing neighbours (nbr = -2) of every level point past the level's real bricks to its
+// ghost bricks, in the order of the level's sorted ghost keys.
+__global__ void closure_fill_kernel(ClosTab ct) {
+    const int li = clos_entry(ct);
+    const int NL = 2 * ct.Lr[li] + 1;
+    const int64_t nreal = ct.nout[li];
+    const int64_t idx = ((int64_t)blockIdx.x - ct.bstart[li]) * 256 + threadIdx.x;
+    if (idx >= nreal * NL * NL * NL) return;
+    int32_t* __restrict__ nbr = ct.nbr[li];
+    if (nbr[idx] != -2) return;
+    nbr[idx] = (int32_t)(nreal + find_sorted(ct.gkeys[li], ct.ng[li], ct.miss[li][idx]));
 }
 
 // LDS helpers for the two-scale transforms with zero details (App. A.3, eqs. recon_even/odd).
@@ -764,16 +797,36 @@ void setup(mwns_ctx* ctx, TreeApply& a, const mwns_op* op, const mwns_tree* f) {
 }
 
 // Neighbour closure kernels of every level; missing parents' keys go to miss[miss_base + ...].
-void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
+// The table of the closure launches of one apply: the output levels j >= 1 with work (with_ghosts:
+// only those that have ghosts).
+ClosTab closure_table(const TreeApply& a, uint64_t* miss, bool with_ghosts) {
+    ClosTab ct;
+    int64_t blocks = 0;
     for (int j = 1; j <= a.depth; ++j) {
-        LevelWork& lw = a.W[j];
-        if (lw.tpl.empty()) continue;
+        const LevelWork& lw = a.W[j];
+        if (lw.tpl.empty() || (with_ghosts && !lw.nghost)) continue;
         const int NL = 2 * lw.Lr + 1;
-        const int64_t n = lw.nout * NL * NL * NL;
-        closure_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(lw.nout, j - 1, lw.pkeys.p, lw.Lr, lw.nbr.p,
-                                                                             miss + a.miss_base + lw.miss_off);
-        MWNS_HIP(hipGetLastError());
+        ct.jm1[ct.n] = j - 1;
+        ct.Lr[ct.n] = lw.Lr;
+        ct.nout[ct.n] = lw.nout;
+        ct.ng[ct.n] = lw.nghost;
+        ct.bstart[ct.n] = blocks;
+        ct.pkeys[ct.n] = lw.pkeys.p;
+        ct.gkeys[ct.n] = lw.gkeys.p;
+        ct.nbr[ct.n] = lw.nbr.p;
+        ct.miss[ct.n] = miss + a.miss_base + lw.miss_off;
+        ++ct.n;
+        blocks += (lw.nout * NL * NL * NL + 255) / 256;
     }
+    ct.bstart[ct.n] = blocks;
+    return ct;
+}
+
+void launch_closure(mwns_ctx* ctx, TreeApply& a, uint64_t* miss) {
+    const ClosTab ct = closure_table(a, miss, false);
+    if (ct.bstart[ct.n] == 0) return;
+    closure_kernel<<<(unsigned)ct.bstart[ct.n], 256, 0, ctx->stream>>>(ct);
+    MWNS_HIP(hipGetLastError());
 }
 
 // Sorts the keys and drops any repeats.  An LSD radix sort over only the bytes in which the keys
@@ -827,13 +880,13 @@ void discover_ghosts(mwns_ctx* ctx, TreeApply& a, std::vector<uint64_t>& keys, u
         LevelWork& lw = a.W[j];
         lw.ghosts.p = nullptr;
         if (lw.tpl.empty() || !lw.nghost) continue;
-        const int NL = 2 * lw.Lr + 1;
-        const int64_t n = lw.nout * NL * NL * NL;
-        closure_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(
-            n, dmiss + a.miss_base + lw.miss_off, lw.gkeys.p, lw.nghost, lw.nout, lw.nbr.p);
-        MWNS_HIP(hipGetLastError());
         lw.ghosts.p = a.ghost_store.p + goff;
         goff += (size_t)lw.nghost * brick_elems(a.k);
+    }
+    const ClosTab ct = closure_table(a, dmiss, true);
+    if (ct.bstart[ct.n]) {
+        closure_fill_kernel<<<(unsigned)ct.bstart[ct.n], 256, 0, ctx->stream>>>(ct);
+        MWNS_HIP(hipGetLastError());
     }
 }
 

@@ -237,32 +237,34 @@ namespace mwns {
 namespace {
 
 // The projected candidates of the levels j0..depth, one entry per level: coefficients s[li]
-// node-major [n][k^3]; entry li covers the elements [start[li], start[li + 1]) of one launch.
+// node-major [n[li]][k^3], taken by the 256-thread blocks [bstart[li], bstart[li + 1]) of one
+// launch (a block never spans two levels, so its level is found once per block).
 struct LeafTab {
     int n = 0;
     int j[MAXLEV + 1];
-    int64_t start[MAXLEV + 2];
+    int64_t nn[MAXLEV + 1];
+    int64_t bstart[MAXLEV + 2];
     const double* s[MAXLEV + 1];
 };
 
 // Copy the leaves' coefficients into their bricks, all levels in one launch.
-__global__ void scatter_leaves_kernel(int k, LeafTab lf, const uint8_t* __restrict__ is_leaf, LevelTab lt,
-                                      double* __restrict__ coef) {
-    const int k3 = k * k * k;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= lf.start[lf.n]) return;
+template <int K>
+__global__ void __launch_bounds__(256) scatter_leaves_kernel(LeafTab lf, const uint8_t* __restrict__ is_leaf,
+                                                            LevelTab lt, double* __restrict__ coef) {
+    constexpr int K3 = K * K * K;
     int li = 0;
-    while (li + 1 < lf.n && idx >= lf.start[li + 1]) ++li;
-    const int64_t loc = idx - lf.start[li];
+    while (li + 1 < lf.n && (int64_t)blockIdx.x >= lf.bstart[li + 1]) ++li;
+    const int64_t loc = ((int64_t)blockIdx.x - lf.bstart[li]) * 256 + threadIdx.x;
+    if (loc >= lf.nn[li] * K3) return;
     const int j = lf.j[li];
-    const int64_t c = loc / k3;
+    const int64_t c = loc / K3;
     if (!is_leaf[lt.node_off[j] + c]) return;
-    const int e = (int)(loc % k3);
+    const int e = (int)(loc % K3);
     int64_t brick;
     int child;
     node_to_brick(lt, j, lt.node_off[j] + c, &brick, &child);
-    const int a = e / (k * k), b = (e / k) % k, cc = e % k;
-    coef[brick * (int64_t)(8 * k3) + brick_index(k, child, a, b, cc)] = lf.s[li][loc];
+    const int a = e / (K * K), bb = (e / K) % K, cc = e % K;
+    coef[brick * (int64_t)(8 * K3) + brick_index(K, child, a, bb, cc)] = lf.s[li][loc];
 }
 
 // Parent block of every internal node of level j from its brick of level j+1:
@@ -402,6 +404,13 @@ struct ProjectLaunch {
                     const double* tab, double* s, double* err) {
         project_kernel<K><<<(unsigned)n, proj_threads(K), 0, st>>>(j, jmax, keys, nsrc, src, std::pow(2.0, -1.5 * j),
                                                       std::pow(2.0, 1.5 * j), tab, s, err);
+    }
+};
+template <int K>
+struct ScatterLaunch {
+    static void run(hipStream_t st, int64_t blocks, const LeafTab& lf, const uint8_t* leaf, const LevelTab& lt,
+                    double* coef) {
+        scatter_leaves_kernel<K><<<(unsigned)blocks, 256, 0, st>>>(lf, leaf, lt, coef);
     }
 };
 template <int K>
@@ -652,16 +661,17 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     LevelTab lt = level_tab(t.get());
     {
         LeafTab lf;
-        int64_t total = 0;
+        int64_t blocks = 0;
         for (int j = j0; j <= t->depth; ++j) {
             lf.j[lf.n] = j;
-            lf.start[lf.n] = total;
+            lf.nn[lf.n] = t->lev[j].nnodes;
+            lf.bstart[lf.n] = blocks;
             lf.s[lf.n] = lcoef[j].p;
             ++lf.n;
-            total += t->lev[j].nnodes * k3;
+            blocks += (t->lev[j].nnodes * k3 + 255) / 256;
         }
-        lf.start[lf.n] = total;
-        scatter_leaves_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(k, lf, t->dleaf.p, lt, t->coef.p);
+        lf.bstart[lf.n] = blocks;
+        dispatch_k<ScatterLaunch>(k, st, blocks, lf, t->dleaf.p, lt, t->coef.p);
         MWNS_HIP(hipGetLastError());
     }
     DevArray<double> dH = upload_filters(ctx, k);
