@@ -1068,6 +1068,7 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
 // Routed apply: fill the reduced-precision input copies.
 void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
     const int64_t E = brick_elems(a.k);
+    ConvTab tb;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         const double* xr = a.f->coef.p + a.f->lev[j].brick_off * E;
@@ -1076,11 +1077,12 @@ void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
             if (lw.xg32.p) launch_convert_wide(a.k, ctx->stream, lw.nghost, lw.ghosts.p, reinterpret_cast<float*>(lw.xg32.p));
             continue;
         }
-        if (lw.xr32.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xr32.p, false);
-        if (lw.xg32.p) launch_convert(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lw.xg32.p, false);
-        if (lw.xrb.p) launch_convert(a.k, ctx->stream, lw.nout, xr, lw.xrb.p, true);
-        if (lw.xgb.p) launch_convert(a.k, ctx->stream, lw.nghost, lw.ghosts.p, lw.xgb.p, true);
+        if (lw.xr32.p) tb.add(a.k, lw.nout, xr, lw.xr32.p, false);
+        if (lw.xg32.p) tb.add(a.k, lw.nghost, lw.ghosts.p, lw.xg32.p, false);
+        if (lw.xrb.p) tb.add(a.k, lw.nout, xr, lw.xrb.p, true);
+        if (lw.xgb.p) tb.add(a.k, lw.nghost, lw.ghosts.p, lw.xgb.p, true);
     }
+    if (tb.n) launch_convert(a.k, ctx->stream, tb);   // the one-tile kernel's copies, one launch
     MWNS_HIP(hipGetLastError());
 }
 

@@ -87,7 +87,30 @@ void launch_contract_wide(int k, int prec, hipStream_t st, int64_t nblocks, cons
 int64_t resident_blocks_wide(int k, int prec, int device);
 // FP32 copies of nb input bricks for the two-tile kernel: [brick][v1][v2][v3], as the FP64 bricks.
 void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out);
-// FP32 (bf = false) or split-BF16 copies of nb input bricks, 16-byte groups as the kernel reads them.
-void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf);
+// FP32 or split-BF16 copies of input bricks, 16-byte groups as the one-tile kernel reads them, for
+// several arrays in one launch: entry i converts nb[i] bricks X[i] into out[i] (split BF16 when
+// bf[i]); the launch gives entry i the 256-thread blocks [bstart[i], bstart[i + 1]).
+constexpr int MAXCONV = 4 * (MAXLEV + 1);
+struct ConvTab {
+    int n = 0;
+    int bf[MAXCONV];
+    int64_t nb[MAXCONV];
+    int64_t bstart[MAXCONV + 1];
+    const double* X[MAXCONV];
+    u4* out[MAXCONV];
+    // appends nb bricks X -> out (nothing for nb = 0)
+    void add(int k, int64_t nbricks, const double* x, u4* o, bool split) {
+        if (nbricks <= 0) return;
+        const int64_t blocks = (nbricks * 2 * k * 2 * k * 4 + 255) / 256;
+        if (n == 0) bstart[0] = 0;
+        bf[n] = split;
+        nb[n] = nbricks;
+        X[n] = x;
+        out[n] = o;
+        bstart[n + 1] = bstart[n] + blocks;
+        ++n;
+    }
+};
+void launch_convert(int k, hipStream_t st, const ConvTab& tb);
 
 }  // namespace mwns

@@ -779,19 +779,21 @@ ns_apply_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ o
 }
 
 // Reduced-precision copies of input bricks: one thread per (brick, v1, v2, group of 4 columns)
-// writes 16 bytes -- four FP32 values (F32) or their split BF16 (hi | lo) (BF16); columns at or
-// beyond 2K are zero.
-template <int K, bool BF>
-__global__ void convert_kernel(int64_t nbricks, const double* __restrict__ X, u4* __restrict__ out) {
+// writes 16 bytes -- four FP32 values or their split BF16 (hi | lo); columns at or beyond 2K are
+// zero.  Every entry of the table has whole blocks, so a block's entry is uniform.
+template <int K>
+__global__ void __launch_bounds__(256) convert_kernel(ConvTab tb) {
     constexpr int D = 2 * K;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nbricks * D * D * 4) return;
+    int e = 0;
+    while (e + 1 < tb.n && (int64_t)blockIdx.x >= tb.bstart[e + 1]) ++e;
+    const int64_t i = ((int64_t)blockIdx.x - tb.bstart[e]) * 256 + threadIdx.x;
+    if (i >= tb.nb[e] * D * D * 4) return;
     const int gg = (int)(i & 3);
     const int64_t row = i >> 2;     // (brick, v1, v2)
-    const double* x = X + row * D;
+    const double* x = tb.X[e] + row * D;
     f4 v;
     for (int c = 0; c < 4; ++c) v[c] = 4 * gg + c < D ? (float)x[4 * gg + c] : 0.f;
-    out[i] = BF ? split4(v) : __builtin_bit_cast(u4, v);
+    tb.out[e][i] = tb.bf[e] ? split4(v) : __builtin_bit_cast(u4, v);
 }
 
 // Tile variants of the contraction kernel: (waves per block, prefetch depth, waves per SIMD, FP64
@@ -856,11 +858,9 @@ struct ApplyLaunch {
 
 template <int K>
 struct ConvertLaunch {
-    static void run(hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
-        const int64_t n = nb * 2 * K * 2 * K * 4;
-        if (n == 0) return;
-        if (bf) convert_kernel<K, true><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
-        else convert_kernel<K, false><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nb, X, out);
+    static void run(hipStream_t st, const ConvTab& tb) {
+        if (tb.n == 0) return;
+        convert_kernel<K><<<(unsigned)tb.bstart[tb.n], 256, 0, st>>>(tb);
     }
 };
 
@@ -901,8 +901,9 @@ int64_t resident_blocks(int k, int variant, int prec, int device) {
     return n;
 }
 
-void launch_convert(int k, hipStream_t st, int64_t nb, const double* X, u4* out, bool bf) {
-    dispatch_narrow<ConvertLaunch>(k, st, nb, X, out, bf);
+void launch_convert(int k, hipStream_t st, const ConvTab& tb) {
+    if (tb.n == 0) return;
+    dispatch_narrow<ConvertLaunch>(k, st, tb);
 }
 
 }  // namespace mwns
