@@ -61,9 +61,18 @@ def test_term_count_grows_like_log_inverse_delta():
 
 
 def test_figure4_ballpark():
-    """Fig. 4: about 300 terms cover 15 decades at eps = 1e-10 (the paper reports 299)."""
-    tau, w = fit.fit_kernel(0.0, 1.0, 1e-10, 1e-15, 1.0)
-    assert 250 <= len(tau) <= 400
+    """Fig. 4: about 300 terms cover 15 decades at eps = 1e-10 (tests/golden/fit_figure4.txt); the
+    quadrature range differs from the paper's (taken from a reference it does not reproduce), so
+    the count is held to within a factor of about 4/3 of the printed one."""
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fit_figure4.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    tau, w = fit.fit_kernel(0.0, 1.0, vals["eps"], 10.0 ** -vals["decades"], 1.0)
+    assert 0.8 * vals["terms"] <= len(tau) <= 1.34 * vals["terms"]
 
 
 def test_invalid_parameters():
