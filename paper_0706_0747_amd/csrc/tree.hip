@@ -91,6 +91,7 @@ __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jma
     constexpr int NE = CH * 3 * NQ;          // term table E[i][d][q]; E[i][0][q] carries the weight
     constexpr int NTR = 8 * K3;              // transform buffers t1 (2 K^3) and t2 (6 K^3)
     static_assert(K <= 16, "the own grid's x points fit one tile");
+    static_assert(K * P2 <= BT, "one thread per line of every transform stage");
     // the term table is dead once the grids are summed: the transforms reuse its storage
     __shared__ double smem[(NE > NTR ? NE : NTR) + K3];
     __shared__ double red[NW];
