@@ -39,7 +39,8 @@ namespace {
 constexpr int PT = 256;   // threads of the transform blocks
 // threads of a projection block: eight waves above k = 8, where a box has 48-57 MFMA tiles
 constexpr int proj_threads(int k) { return k >= 9 ? 512 : 256; }
-constexpr int CH = 32;    // source terms per chunk
+// source terms per chunk: 64 above k = 8, where the term table still fits in the transform buffers
+constexpr int proj_chunk(int k) { return k >= 9 ? 64 : 32; }
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // One line of a separable transform: out[o * so] = scale * sum_i M[o][i] in[i * si] for o < NO,
@@ -85,6 +86,7 @@ __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jma
     constexpr int NTCH = MT * NTC;           // children tiles come first
     constexpr int NT = NTCH + NTO;
     constexpr int BT = proj_threads(K);
+    constexpr int CH = proj_chunk(K);
     constexpr int NW = BT / 64;
     constexpr int TPW = (NT + NW - 1) / NW;
     constexpr int KS = (K + 3) / 4;          // inner steps of the interpolation product
