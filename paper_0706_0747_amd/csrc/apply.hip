@@ -1324,12 +1324,16 @@ void prepare(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& trees, cons
     cnt.download(hc.data(), nt, st);
     MWNS_HIP(hipStreamSynchronize(st));
     std::vector<std::vector<uint64_t>> keys(nt);
-    for (int i = 0; i < nt; ++i) {
-        keys[i].resize(hc[i]);
-        if (hc[i]) MWNS_HIP(hipMemcpyAsync(keys[i].data(), comp.p + trees[i]->miss_base, hc[i] * sizeof(uint64_t),
+    size_t nkeys = 0;
+    for (int i = 0; i < nt; ++i) nkeys += hc[i];
+    uint64_t* pin = static_cast<uint64_t*>(pinned_staging(ctx, std::max<size_t>(1, nkeys) * sizeof(uint64_t)));
+    size_t off = 0;
+    for (int i = 0; i < nt; off += hc[i], ++i)
+        if (hc[i]) MWNS_HIP(hipMemcpyAsync(pin + off, comp.p + trees[i]->miss_base, hc[i] * sizeof(uint64_t),
                                           hipMemcpyDeviceToHost, st));
-    }
     MWNS_HIP(hipStreamSynchronize(st));
+    off = 0;
+    for (int i = 0; i < nt; off += hc[i], ++i) keys[i].assign(pin + off, pin + off + hc[i]);
     for (int i = 0; i < nt; ++i) discover_ghosts(ctx, *trees[i], keys[i], miss.p);
     if (mixed) {
         // routing needs the ghosts' values for the level norms

@@ -44,7 +44,25 @@ void ctx_release(mwns_ctx* ctx) {
     if (--ctx->refs > 0) return;
     (void)hipStreamSynchronize(ctx->stream);
     release_cache(ctx);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
+}
+
+void* pinned_staging(mwns_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->pinned_bytes) return ctx->pinned;
+    MWNS_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->pinned) {
+        MWNS_HIP(hipHostFree(ctx->pinned));
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+    }
+    size_t cap = (size_t)1 << 20;
+    while (cap < bytes) cap <<= 1;
+    void* p = nullptr;
+    MWNS_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+    ctx->pinned = p;
+    ctx->pinned_bytes = cap;
+    return p;
 }
 
 void* dalloc(mwns_ctx* ctx, size_t bytes) {

@@ -113,12 +113,17 @@ struct mwns_ctx {
     std::vector<std::pair<size_t, void*>> cache;        // (size class, block), most recent last
     int variant[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};   // per basis order k
     int refs = 1;            // the handle itself plus every live tree, operator and plan of the context
+    void* pinned = nullptr;  // pinned host staging of the host round trips (hipHostMalloc)
+    size_t pinned_bytes = 0;
 };
 
 namespace mwns {
 void* dalloc(mwns_ctx* ctx, size_t bytes);
 void dfree(mwns_ctx* ctx, void* p, size_t bytes);
 void release_cache(mwns_ctx* ctx);
+// A pinned host block of at least `bytes` for the copies of one host round trip; the caller
+// synchronises the stream before the next call (growing the block waits for the stream).
+void* pinned_staging(mwns_ctx* ctx, size_t bytes);
 // Drops one reference to ctx; the last one returns the cached blocks and frees the context.
 void ctx_release(mwns_ctx* ctx);
 // A tree, operator or plan keeps its context alive: declared as the object's first member, it is

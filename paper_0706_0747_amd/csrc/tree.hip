@@ -8,6 +8,7 @@
 // dimension (s = child parity, a = degree), so the 8 siblings of a level form one dense block; the
 // root occupies child 0 of a level-0 brick whose other 7 children are zero.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <memory>
 #include <numeric>
@@ -630,11 +631,15 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
         const int64_t nc = (int64_t)cand.size();
         DevArray<uint64_t> dk(ctx, nc);
         DevArray<double> ds(ctx, (size_t)nc * k3), derr(ctx, nc);
-        dk.upload(cand.data(), nc, st);
+        // candidates up and errors down through the context's pinned staging block
+        char* pin = static_cast<char*>(pinned_staging(ctx, (size_t)nc * 16));
+        uint64_t* pkeys = reinterpret_cast<uint64_t*>(pin);
+        const double* err = reinterpret_cast<const double*>(pin + (size_t)nc * 8);
+        std::memcpy(pkeys, cand.data(), (size_t)nc * 8);
+        MWNS_HIP(hipMemcpyAsync(dk.p, pkeys, (size_t)nc * 8, hipMemcpyHostToDevice, st));
         dispatch_k<ProjectLaunch>(k, st, nc, j, jmax, dk.p, n, dsrc.p, dtab.p, ds.p, derr.p);
         MWNS_HIP(hipGetLastError());
-        std::vector<double> err(nc);
-        derr.download(err.data(), nc, st);
+        MWNS_HIP(hipMemcpyAsync(pin + (size_t)nc * 8, derr.p, (size_t)nc * 8, hipMemcpyDeviceToHost, st));
         MWNS_HIP(hipStreamSynchronize(st));
         // refine where the interpolation error exceeds the threshold, below the finest level (Alg. 1)
         std::vector<uint8_t> ref(nc), lf(nc);
