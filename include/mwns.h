@@ -68,6 +68,9 @@ typedef void (*mwns_free_fn)(void* ptr, void* user);
  *   alloc/free   device allocator; both NULL means hipMalloc/hipFree.  Both or neither.
  *   user         passed back to alloc/free unchanged.
  *   byte_budget  upper bound on device bytes the context may hold at once; 0 = unlimited.
+ * The context also keeps one pinned host block (hipHostMalloc, at least 1 MiB, grown to the
+ * largest host round trip of a projection or apply) for its host<->device copies; it is not part
+ * of byte_budget and is freed with the context.
  * Errors: EINVAL (bad device, one of alloc/free missing), EDEVICE (HIP runtime failure). */
 mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_free_fn free_fn, void* user,
                             size_t byte_budget, mwns_ctx** out);
