@@ -18,6 +18,7 @@
 // estimate stays <= theta/2 (empty if the total is <= theta), theta = eps sum_m w_m ||F^{0;m,0}||_F^3.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <memory>
 
 #include "mwns_internal.h"
@@ -366,25 +367,29 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     DevArray<double> norms(ctx, (size_t)nlev * M * nL * 3), nf0(ctx, M);
     norms_kernel<<<(nlev - 1) * M * nL + 1, 64, 0, st>>>(k, M, nlev, op->F.p, dH.p, norms.p, nf0.p);
     MWNS_HIP(hipGetLastError());
+    // the plan's ranges, the terms' norms and the blocks' Frobenius norms come down together
+    // through the context's pinned staging block, behind one synchronisation
     std::vector<int32_t> ranges(std::max(1, (nlev - 1) * 20) * 2);
+    const int64_t nb = (int64_t)nlev * M * NLF;
+    const size_t b_rng = (ranges.size() * sizeof(int32_t) + 7) & ~(size_t)7;
+    char* pin = static_cast<char*>(pinned_staging(ctx, b_rng + (size_t)(M + nb) * sizeof(double)));
+    double* pin_nf0 = reinterpret_cast<double*>(pin + b_rng);
+    double* pin_fro = pin_nf0 + M;
+    DevArray<int32_t> dr(ctx, ranges.size());
     if (nlev > 1) {
-        DevArray<int32_t> dr(ctx, ranges.size());
         plan_kernel<<<(nlev - 1) * 20, 64, 0, st>>>(M, eps, op->dw.p, norms.p, nf0.p, dr.p);
         MWNS_HIP(hipGetLastError());
-        dr.download(ranges.data(), ranges.size(), st);
+        MWNS_HIP(hipMemcpyAsync(pin, dr.p, ranges.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
-    std::vector<double> hnf0(M);
-    nf0.download(hnf0.data(), M, st);
-    {
-        const int64_t nb = (int64_t)nlev * M * NLF;
-        DevArray<double> dfro(ctx, nb);
-        fro_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(k, nb, op->F.p, dfro.p);
-        MWNS_HIP(hipGetLastError());
-        op->fro.resize(nb);
-        dfro.download(op->fro.data(), nb, st);
-        MWNS_HIP(hipStreamSynchronize(st));
-    }
+    MWNS_HIP(hipMemcpyAsync(pin_nf0, nf0.p, M * sizeof(double), hipMemcpyDeviceToHost, st));
+    DevArray<double> dfro(ctx, nb);
+    fro_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(k, nb, op->F.p, dfro.p);
+    MWNS_HIP(hipGetLastError());
+    MWNS_HIP(hipMemcpyAsync(pin_fro, dfro.p, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     MWNS_HIP(hipStreamSynchronize(st));
+    if (nlev > 1) std::memcpy(ranges.data(), pin, ranges.size() * sizeof(int32_t));
+    std::vector<double> hnf0(pin_nf0, pin_nf0 + M);
+    op->fro.assign(pin_fro, pin_fro + nb);
     double theta = 0.0;
     for (int m = 0; m < M; ++m) theta += w[m] * hnf0[m] * hnf0[m] * hnf0[m];
     op->theta = theta * eps;

@@ -859,20 +859,31 @@ mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, cons
     hipStream_t st = ctx->stream;
     DevArray<double> dx(ctx, 3 * npts), dout(ctx, npts);
     DevArray<int> dbad(ctx, 1);
-    dx.upload(xyz, 3 * npts, st);
+    DevArray<int32_t> dchild(ctx, t->nnodes);
+    // points and the child table go up, values come down through the context's pinned block:
+    // [points][child table][values][bad count]
+    const size_t b_x = (size_t)npts * 3 * sizeof(double);
+    const size_t b_c = ((size_t)t->nnodes * sizeof(int32_t) + 7) & ~(size_t)7;
+    const size_t b_o = (size_t)npts * sizeof(double);
+    char* pin = static_cast<char*>(pinned_staging(ctx, b_x + b_c + b_o + sizeof(double)));
+    std::memcpy(pin, xyz, b_x);
+    // child brick of every internal node (-1 for leaves), from the parent of every brick
+    int32_t* child = reinterpret_cast<int32_t*>(pin + b_x);
+    std::fill(child, child + t->nnodes, -1);
+    for (int64_t b = 1; b < t->nbricks; ++b) child[t->brick_parent[b]] = (int32_t)b;
+    MWNS_HIP(hipMemcpyAsync(dx.p, pin, b_x, hipMemcpyHostToDevice, st));
+    MWNS_HIP(hipMemcpyAsync(dchild.p, child, (size_t)t->nnodes * sizeof(int32_t), hipMemcpyHostToDevice, st));
     MWNS_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), st));
     LevelTab lt = level_tab(t);
-    // child brick of every internal node (-1 for leaves), from the parent of every brick
-    std::vector<int32_t> child(t->nnodes, -1);
-    for (int64_t b = 1; b < t->nbricks; ++b) child[t->brick_parent[b]] = (int32_t)b;
-    DevArray<int32_t> dchild(ctx, t->nnodes);
-    dchild.upload(child.data(), t->nnodes, st);
     dispatch_k<EvalLaunch>(t->k, st, npts, dx.p, dchild.p, t->dleaf.p, lt, t->coef.p, dout.p, dbad.p);
     MWNS_HIP(hipGetLastError());
-    int bad = 0;
-    dout.download(out, npts, st);
-    dbad.download(&bad, 1, st);
+    double* pout = reinterpret_cast<double*>(pin + b_x + b_c);
+    int* pbad = reinterpret_cast<int*>(pin + b_x + b_c + b_o);
+    MWNS_HIP(hipMemcpyAsync(pout, dout.p, b_o, hipMemcpyDeviceToHost, st));
+    MWNS_HIP(hipMemcpyAsync(pbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, st));
     MWNS_HIP(hipStreamSynchronize(st));
+    std::memcpy(out, pout, b_o);
+    const int bad = *pbad;
     if (bad) fail(MWNS_ESTATE, "points without a leaf: the tree does not cover the cube");
     return MWNS_OK;
     MWNS_GUARD_END
