@@ -11,12 +11,67 @@
       G(tau, a, c, x) = int_0^1 e^{-tau (x-y)^2} e^{-a (y-c)^2} dy
                       = e^{-tau a (x-c)^2/(tau+a)} sqrt(pi)/(2 sqrt(tau+a)) [erf(s (1-q)) + erf(s q)],
       s = sqrt(tau+a), q = (tau x + a c)/(tau+a).
+  * three_gaussians / three_gaussians_laplacian / ..._l2norm: the Poisson test of Sec. 6.1:
+    phi = sum_{i=1..3} e^{-alpha |r - r_i|^2} with alpha = 300 and the three printed centres, the
+    source rho = -Laplacian(phi), so that phi is the exact potential of rho under 1/(4 pi r).
 These are references for the exact operator; the method approximates them to about eps.
 """
 import numpy as np
 from scipy import special
 
-__all__ = ["poisson_gaussian", "yukawa_gaussian", "fitted_truncated", "gauss_sum"]
+__all__ = ["poisson_gaussian", "yukawa_gaussian", "fitted_truncated", "gauss_sum", "SEC61_ALPHA", "SEC61_CENTRES",
+           "three_gaussians", "three_gaussians_laplacian", "three_gaussians_laplacian_l2norm"]
+
+# Sec. 6.1: exponent and centres of the three Gaussians of the Poisson test
+SEC61_ALPHA = 300.0
+SEC61_CENTRES = np.array([[0.5, 0.5, 0.5], [0.6, 0.6, 0.5], [0.35, 0.6, 0.5]])
+
+
+def three_gaussians(x, y, z, alpha=SEC61_ALPHA, centres=SEC61_CENTRES):
+    """phi(r) = sum_i exp(-alpha |r - r_i|^2) (Sec. 6.1), at broadcastable coordinate arrays."""
+    out = 0.0
+    for cx, cy, cz in centres:
+        out = out + np.exp(-alpha * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2))
+    return out
+
+
+def three_gaussians_laplacian(x, y, z, alpha=SEC61_ALPHA, centres=SEC61_CENTRES):
+    """rho = -Laplacian(phi) = sum_i (6 alpha - 4 alpha^2 |r - r_i|^2) exp(-alpha |r - r_i|^2):
+    each term of phi is a product of three 1-D Gaussians g(t) = exp(-alpha t^2) with
+    g'' = (4 alpha^2 t^2 - 2 alpha) g."""
+    out = 0.0
+    for cx, cy, cz in centres:
+        r2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
+        out = out + (6.0 * alpha - 4.0 * alpha * alpha * r2) * np.exp(-alpha * r2)
+    return out
+
+
+def three_gaussians_laplacian_l2norm(alpha=SEC61_ALPHA, centres=SEC61_CENTRES):
+    """||rho||_2 over R^3, exact: rho_i = sum_t c_t prod_d p_td(x_d - r_id) e^{-alpha (x_d - r_id)^2}
+    with the separable terms (t = 0: 6 alpha; t = d: -4 alpha^2 (x_d - r_id)^2), so <rho_i, rho_q>
+    is a sum of products of 1-D integrals of polynomials (degree <= 4) times
+    e^{-alpha (x-a)^2 - alpha (x-b)^2} = e^{-alpha (a-b)^2 / 2} e^{-2 alpha (x - (a+b)/2)^2},
+    which 8-point Gauss-Hermite quadrature integrates exactly."""
+    t, wh = np.polynomial.hermite.hermgauss(8)
+
+    def one_d(pa, pb, a, b):
+        # int (x-a)^pa (x-b)^pb e^{-alpha (x-a)^2 - alpha (x-b)^2} dx, substituting x = m + t / sqrt(2 alpha)
+        m = 0.5 * (a + b)
+        x = m + t / np.sqrt(2.0 * alpha)
+        return np.exp(-0.5 * alpha * (a - b) ** 2) * np.sum(wh * (x - a) ** pa * (x - b) ** pb) / np.sqrt(2.0 * alpha)
+
+    terms = [(6.0 * alpha, (0, 0, 0))] + [(-4.0 * alpha * alpha, tuple(2 if e == d else 0 for e in range(3)))
+                                          for d in range(3)]
+    tot = 0.0
+    for ri in centres:
+        for rq in centres:
+            for ct, pt in terms:
+                for cu, pu in terms:
+                    v = ct * cu
+                    for d in range(3):
+                        v *= one_d(pt[d], pu[d], ri[d], rq[d])
+                    tot += v
+    return float(np.sqrt(tot))
 
 
 def gauss_sum(xyz, a, c, pts):

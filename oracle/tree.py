@@ -24,7 +24,7 @@ from . import mra
 from ._native import lib
 
 __all__ = ["make_keys", "decode_keys", "children_keys", "source_norm", "project_gaussians",
-           "redundant_tree", "compress", "upsample", "evaluate", "uniform_leaves", "Tree"]
+           "project_function", "redundant_tree", "compress", "upsample", "evaluate", "uniform_leaves", "Tree"]
 
 
 def _spread3(v):
@@ -138,6 +138,66 @@ def project_gaussians(k, eps, j0, jmax, xyz, a, c, with_margins=False):
     if with_margins:
         return out + ((np.concatenate(margins) if margins else np.zeros(0), thr),)
     return out
+
+
+def _modes(x, A1, A2, A3):
+    """out[n, a, b, c] = sum_{ijk} x[n, i, j, k] A1[i, a] A2[j, b] A3[k, c], one mode at a time."""
+    x = np.einsum("nijk,kc->nijc", x, A3)
+    x = np.einsum("nijc,jb->nibc", x, A2)
+    return np.einsum("nibc,ia->nabc", x, A1)
+
+
+def project_function(k, eps, j0, jmax, f, fnorm, chunk=4096):
+    """Alg. 1 for any source given as a vectorised callable f(x, y, z) -> values (numpy arrays of
+    equal shape), with the refinement threshold eps * fnorm (fnorm: the caller's ||f||_2, the same
+    reading as project_gaussians).  Level by level from j0: every candidate box gets its
+    coefficients from the values at its own k^3 Gauss-Legendre nodes (eq. fvals2coefs in 3-D);
+    the polynomial they define is evaluated at the k^3 nodes of each of the 8 children and
+    compared with f there; the box is refined (all 8 children become candidates) when the
+    largest difference exceeds the threshold, and boxes at jmax are leaves.
+    Returns (leaf_keys, leaf_coef) sorted by key."""
+    thr = eps * fnorm
+    gx, gw = mra.gauss_legendre01(k)
+    P = mra.phi(k, gx) * gw[:, None]                               # [node i, degree a]: phi_a(x_i) w_i
+    Q = [mra.phi(k, 0.5 * (s + gx)) for s in (0, 1)]                # [node i, degree a]: phi_a((s + x_i)/2)
+    n0 = 1 << j0
+    lz, ly, lx = np.meshgrid(np.arange(n0), np.arange(n0), np.arange(n0), indexing="ij")
+    cand = np.sort(make_keys(np.full(lx.size, j0), lx.ravel(), ly.ravel(), lz.ravel()))
+    leaf_keys, leaf_coef = [], []
+    j = j0
+    while cand.size:
+        h = 2.0 ** -j
+        refine = np.zeros(cand.size, dtype=bool)
+        coef = np.zeros((cand.size, k, k, k))
+        for b0 in range(0, cand.size, chunk):
+            _, l = decode_keys(cand[b0:b0 + chunk])
+            X = h * (l[:, 0, None] + gx[None, :])                    # [box, node] per dimension
+            Y = h * (l[:, 1, None] + gx[None, :])
+            Z = h * (l[:, 2, None] + gx[None, :])
+            fv = f(X[:, :, None, None], Y[:, None, :, None], Z[:, None, None, :])
+            s = 2.0 ** (-1.5 * j) * _modes(fv, P, P, P)
+            coef[b0:b0 + chunk] = s
+            if j >= jmax:
+                continue
+            err = np.zeros(s.shape[0])
+            for sg in range(8):
+                sx, sy, sz = sg & 1, (sg >> 1) & 1, (sg >> 2) & 1
+                ft = 2.0 ** (1.5 * j) * _modes(s, Q[sx].T, Q[sy].T, Q[sz].T)
+                hc = 0.5 * h
+                Xc = hc * (2 * l[:, 0, None] + sx + gx[None, :])
+                Yc = hc * (2 * l[:, 1, None] + sy + gx[None, :])
+                Zc = hc * (2 * l[:, 2, None] + sz + gx[None, :])
+                fc = f(Xc[:, :, None, None], Yc[:, None, :, None], Zc[:, None, None, :])
+                err = np.maximum(err, np.abs(fc - ft).reshape(s.shape[0], -1).max(axis=1))
+            refine[b0:b0 + chunk] = err > thr
+        leaf_keys.append(cand[~refine])
+        leaf_coef.append(coef[~refine])
+        cand = children_keys(cand[refine])
+        j += 1
+    keys = np.concatenate(leaf_keys)
+    coef = np.concatenate(leaf_coef)
+    order = np.argsort(keys, kind="stable")
+    return keys[order], coef[order]
 
 
 def project_boxes(k, eps, jmax, xyz, a, c, keys):

@@ -157,8 +157,11 @@ def test_wide_mixed_at_eps_against_oracle(M, ctx):
     w = CASES["k10_poisson"]()
     keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
     ot = T.redundant_tree(w.k, keys, coef)
-    f, op, tau, wt = _lib_setup(M, ctx, w)
-    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth)
+    f, op, tau, _ = _lib_setup(M, ctx, w)
+    # the oracle's operator comes from the oracle's own fit; the library applies the oracle's plan
+    to, wo = _fit(w, ot.depth)
+    assert to.size == tau.size
+    oo = A.Operator(w.k, to, wo, w.eps, ot.depth)
     M.mwns_op_plan_import(op, oo.R)
     g = A.assemble(ot, A.apply_modified(oo, ot))
     gnorm = _leaf_norm(ot.leaf, g)

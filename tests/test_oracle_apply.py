@@ -154,3 +154,21 @@ def test_adaptive_against_semi_closed_form():
     v = T.evaluate(T.Tree(w.k, tr.keys, tr.leaf, g), P)
     ref = closed_forms.fitted_truncated(op.tau, op.w, w.xyz, w.a, w.c, P)
     assert np.abs(v - ref).max() <= 50 * w.eps * np.abs(ref).max()
+
+
+def test_assemble_chain_equals_whole_tree_assembly():
+    """assemble_chain (g at one node from the ghat of its ancestor chain, used by the full-size
+    parity tests) equals the whole-tree assembly of eq. g_assemble at sampled nodes of adaptive
+    trees, with an arbitrary ghat so that a dropped transpose, parity bit or ancestor shows."""
+    for seed, k in ((11, 6), (8, 5)):
+        w = workloads.small_adaptive(seed, k=k, eps=1e-3, jmax=5)
+        tr = _tree_of(w)
+        ghat = np.random.default_rng(seed).normal(size=tr.coef.shape)
+        g = A.assemble(tr, ghat)
+        deep = np.nonzero(tr.level == tr.depth)[0]
+        pick = np.concatenate([deep[:3], np.random.default_rng(seed + 1).choice(tr.keys.size, 12, replace=False)])
+        for i in pick:
+            gc = A.assemble_chain(tr, int(i), lambda n: ghat[n])
+            assert np.abs(gc - g[i]).max() <= 1e-13 * np.abs(g[i]).max(), (seed, i)
+        # the root has no ancestors: its g is its own ghat
+        assert np.array_equal(A.assemble_chain(tr, 0, lambda n: ghat[n]), ghat[0])

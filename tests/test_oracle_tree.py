@@ -124,3 +124,33 @@ def test_project_boxes_reproduces_the_tree():
     parents = T.make_keys(lev[deeper] - 1, *(l[deeper] >> 1).T)
     _, pref, _ = T.project_boxes(w.k, w.eps, w.jmax, w.xyz, w.a, w.c, parents)
     assert np.all(pref == 1)
+
+
+def test_project_function_matches_gaussian_projection():
+    """Alg. 1 for a source given as a callable (numpy) makes the same decisions and coefficients
+    as the plain-C projection of the same Gaussian sum."""
+    from oracle import closed_forms
+    for seed, k in ((11, 6), (3, 8)):
+        w = workloads.small_adaptive(seed, k=k, eps=1e-4, jmax=5)
+        kg, cg = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+
+        def f(x, y, z):
+            out = 0.0
+            for (cx, cy, cz), a, c in zip(w.xyz, w.a, w.c):
+                out = out + c * (a / np.pi) ** 1.5 * np.exp(-a * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2))
+            return out
+        kf, cf = T.project_function(w.k, w.eps, w.j0, w.jmax, f, T.source_norm(w.xyz, w.a, w.c))
+        assert np.array_equal(kg, kf)
+        assert np.abs(cg - cf).max() <= 1e-12 * np.abs(cg).max()
+        pts = workloads.points(500, seed=seed)
+        v = T.evaluate(T.redundant_tree(w.k, kf, cf), pts)
+        ref = closed_forms.gauss_sum(w.xyz, w.a, w.c, pts)
+        assert np.abs(v - ref).max() <= 50 * w.eps * T.source_norm(w.xyz, w.a, w.c)
+
+
+def test_project_function_low_degree_polynomial_is_one_level():
+    """A polynomial of degree < k is reproduced exactly by every box: no box is refined."""
+    k = 5
+    keys, coef = T.project_function(k, 1e-12, 1, 6, lambda x, y, z: 1.0 + x * y - 2 * z ** 3 + x ** 4, 1.0)
+    lev, _ = T.decode_keys(keys)
+    assert keys.size == 8 and np.all(lev == 1)
