@@ -127,6 +127,11 @@ typedef struct {
     /* 1 (default): every coarse displacement L gets the union of the term ranges of its set
      * Core / Boundary-1 / Boundary-2 / Boundary-3 (Sec. 4); 0: per-L ranges. */
     int group_regions;
+    /* 0 (default): mwns_op_create fails with MWNS_ERANGE when the screening keeps a term at the
+     * edge of the band (a coarse displacement with max |L_d| = 3, the widest the plan covers),
+     * since displacements beyond the band would then still matter (the paper's remark that a
+     * narrow band suffices in practice, Sec. 4); 1: build the operator anyway. */
+    int allow_band_overflow;
 } mwns_op_opts;
 
 /* Build the operator for basis order k on levels 0..max_level from M Gaussian terms (host arrays
@@ -137,7 +142,8 @@ typedef struct {
  *   - the screening plan: for every scale j >= 1 and coarse displacement L in [-3,3]^3, the
  *     inclusive term range R_j(L) kept after discarding terms whose cumulative estimated
  *     contribution is below eps (Sec. 4, eqs. BlockNorms and NormEstimateUsing1DBlocks).
- * opts may be NULL (defaults).  Errors: EINVAL, ENOMEM, EDEVICE. */
+ * opts may be NULL (defaults).  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE (band overflow, see
+ * mwns_op_opts; the message names the level and displacement). */
 mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const double* w, double eps,
                            int max_level, const mwns_op_opts* opts, mwns_op** out);
 /* Plan as int32 [max_level+1][7][7][7][2] (j, L1+3, L2+3, L3+3, {m1, m2}); an empty range has
@@ -215,6 +221,14 @@ typedef struct {
     double err_bound;         /* a-priori bound on ||g - g_F64||_2 of the precision routing (0: all FP64) */
     double g_norm;            /* ||g||_2 over [0,1]^3 (0 with MWNS_NO_ASSEMBLY) */
     double class_flops[4];    /* useful_flops by precision class: FP64, FP32, BF16 compensated, BF16 */
+    double own_flops;         /* the method's own share of useful_flops: without the down-band jobs whose
+                                 terms all lie in the whole band's range at every coarse displacement of
+                                 their box (at internal children such a job only cancels whole-band terms
+                                 whose net coefficient c_m is 0; the brick-wide whole-band job computes
+                                 them because the leaf children of the same sibling group need them) */
+    double f64_mfma_flops;    /* FP64 matrix-core flops issued by the FP64 class's contraction launches,
+                                 padding of the 16 x 16 and 4 x 4 tiles included (what the hardware's
+                                 FP64 MFMA operation counter reports, times 512 per operation) */
 } mwns_apply_stats;
 
 /* g = T f with T given by `op` (its F tables and plan), in the modified ns-form (eq. apply_algo;

@@ -24,7 +24,7 @@ __all__ = ["Operator", "apply_modified", "apply_difference", "assemble", "dense_
 class Operator:
     """F tables for scales 0..nlev and the plan R[j, L] (j = 0..nlev)."""
 
-    def __init__(self, k, tau, w, eps, nlev, group=True, R=None):
+    def __init__(self, k, tau, w, eps, nlev, group=True, R=None, allow_overflow=False):
         self.k, self.eps, self.nlev = k, eps, nlev
         self.tau = np.ascontiguousarray(tau, dtype=np.float64)
         self.w = np.ascontiguousarray(w, dtype=np.float64)
@@ -32,7 +32,8 @@ class Operator:
         self.F = np.ascontiguousarray(mra.F_table(k, self.tau, nlev))
         self.H0, self.H1 = (np.ascontiguousarray(h) for h in mra.two_scale_filters(k))
         if R is None:
-            R, self.theta = _plan.make_plan(self.F, self.H0, self.H1, self.w, eps, nlev, group=group)
+            R, self.theta = _plan.make_plan(self.F, self.H0, self.H1, self.w, eps, nlev, group=group,
+                                            allow_overflow=allow_overflow)
         self.R = np.ascontiguousarray(R, dtype=np.int32)
 
 

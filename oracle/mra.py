@@ -189,7 +189,10 @@ def _panel_breaks(u0, u1, c, s):
 
 def _moments(nbasis, beta, l, shift, breaks, ngl):
     """For every block i: mu[i, n] = int exp(-beta_i (x+l_i)^2) phi_n(x+shift) dx over
-    [breaks_i[0], breaks_i[-1]] by composite Gauss-Legendre with ngl points per panel."""
+    [breaks_i[0], breaks_i[-1]] by composite Gauss-Legendre with ngl points per panel.  The
+    breaks are given in the offset u = x + l_i from the Gaussian's centre, so that the exponent
+    beta u^2 keeps its relative accuracy for narrow Gaussians centred at an end of the interval
+    (x near 1 would lose the low digits of x + l_i = x - 1)."""
     t, w = gauss_legendre01(ngl)
     xs, ws, starts, pos = [], [], [], 0
     for br in breaks:
@@ -204,14 +207,14 @@ def _moments(nbasis, beta, l, shift, breaks, ngl):
     sizes = np.diff(np.append(starts, pos))
     bb = np.repeat(beta, sizes)
     ll = np.repeat(l, sizes)
-    g = wx * np.exp(-bb * (x + ll) ** 2)
-    return np.add.reduceat(g[:, None] * phi(nbasis, x + shift), np.array(starts), axis=0)
+    g = wx * np.exp(-bb * x ** 2)
+    return np.add.reduceat(g[:, None] * phi(nbasis, x - ll + shift), np.array(starts), axis=0)
 
 
 def _half_moments(nbasis, beta, l, u0, u1, shift, ngl, rtol):
     """Gaussian moments on one half [u0,u1] for a batch of (beta, l); panels graded around
     x = -l are halved until every block's moments change by less than rtol * max|mu|."""
-    breaks = [_panel_breaks(u0, u1, -float(li), 1.0 / np.sqrt(bi)) for bi, li in zip(beta, l)]
+    breaks = [_panel_breaks(u0 + float(li), u1 + float(li), 0.0, 1.0 / np.sqrt(bi)) for bi, li in zip(beta, l)]
     mu = _moments(nbasis, beta, l, shift, breaks, ngl)
     # exp(-A) with A = beta (x+l)^2 is only good to about A*1e-16 relative: the attainable
     # tolerance grows with the smallest exponent on the interval

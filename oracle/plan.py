@@ -23,7 +23,7 @@ The plan is returned as an int32 array R[j, L1+Lmax, L2+Lmax, L3+Lmax, 2] of inc
 import itertools
 import numpy as np
 
-__all__ = ["block_norms", "estimate", "term_range", "make_plan", "LMAX", "EMPTY"]
+__all__ = ["block_norms", "estimate", "term_range", "make_plan", "BandOverflow", "LMAX", "EMPTY"]
 
 LMAX = 3
 EMPTY = (0, -1)
@@ -77,8 +77,15 @@ def _region(Lc):
     return sum(1 for x in Lc if x > 1)
 
 
-def make_plan(Ftab, H0, H1, w, eps, nlev, group=True):
-    """Plan R[j, L, 2] for j = 0..nlev (Ftab must hold scales 0..nlev).  Also returns theta."""
+class BandOverflow(RuntimeError):
+    """The screening keeps a term at a displacement on the edge of the band (max |L_d| = LMAX):
+    displacements beyond it, which the plan does not cover, would still matter (the remark of
+    Sec. 4 that a narrow band suffices in practice does not hold for this operator and eps)."""
+
+
+def make_plan(Ftab, H0, H1, w, eps, nlev, group=True, allow_overflow=False):
+    """Plan R[j, L, 2] for j = 0..nlev (Ftab must hold scales 0..nlev).  Also returns theta.
+    Raises BandOverflow when a per-L range on the band's edge is not empty (unless allowed)."""
     M = Ftab.shape[1]
     w = np.asarray(w, dtype=np.float64)
     theta = 0.0
@@ -93,6 +100,9 @@ def make_plan(Ftab, H0, H1, w, eps, nlev, group=True):
     for j in range(1, nlev + 1):
         NF, NU, ND = block_norms(Ftab, H0, H1, j)
         rng = {Lc: term_range(w * estimate(NF, NU, ND, Lc), theta) for Lc in canon}
+        for Lc, (a, b) in rng.items():
+            if max(Lc) == LMAX and b >= a and not allow_overflow:
+                raise BandOverflow("scale %d keeps terms %d..%d at |L| = %s, the edge of the band" % (j, a, b, Lc))
         if group:
             hull = {}
             for Lc, (a, b) in rng.items():

@@ -284,9 +284,9 @@ def mwns_fit_kernel(mu, alpha, eps, delta, R, scale=1.0, cap=4096):
     return tau[:M.value].copy(), w[:M.value].copy()
 
 
-def mwns_op_create(ctx, k, tau, w, eps, max_level, group_regions=1):
+def mwns_op_create(ctx, k, tau, w, eps, max_level, group_regions=1, allow_band_overflow=0):
     tau, w = _f64(tau), _f64(w)
-    opts = _lib.OpOpts(int(group_regions))
+    opts = _lib.OpOpts(int(group_regions), int(allow_band_overflow))
     h = ctypes.c_void_p()
     check(lib.mwns_op_create(ctx.h, k, tau.size, tau.ctypes.data, w.ctypes.data, eps, max_level, ctypes.byref(opts),
                              ctypes.byref(h)), "mwns_op_create")

@@ -36,7 +36,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp)
 
 
 class OpOpts(ctypes.Structure):
-    _fields_ = [("group_regions", c_int)]
+    _fields_ = [("group_regions", c_int), ("allow_band_overflow", c_int)]
 
 
 class TreeInfo(ctypes.Structure):
@@ -47,7 +47,7 @@ class TreeInfo(ctypes.Structure):
 class ApplyStats(ctypes.Structure):
     _fields_ = [("contractions", c_i64), ("brick_jobs", c_i64), ("ghost_bricks", c_i64), ("useful_flops", c_dbl),
                 ("ms_closure", c_dbl), ("ms_contract", c_dbl), ("ms_assemble", c_dbl), ("err_bound", c_dbl),
-                ("g_norm", c_dbl), ("class_flops", c_dbl * 4)]
+                ("g_norm", c_dbl), ("class_flops", c_dbl * 4), ("own_flops", c_dbl), ("f64_mfma_flops", c_dbl)]
 
 
 class MixedOpts(ctypes.Structure):

@@ -676,6 +676,7 @@ struct TreeApply {
     LevelTab2 lt{};
     int64_t miss_base = 0, miss_total = 0, total_ghosts = 0, jobs = 0;
     double err_bound = 0.0, flops = 0.0, class_flops[NPREC] = {0.0, 0.0, 0.0, 0.0};
+    double own_flops = 0.0, mfma_flops = 0.0;
     size_t desc_base = 0;
 };
 
@@ -1101,6 +1102,14 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
     a.jobs = 0;
     a.flops = 0.0;
     for (int p = 0; p < NPREC; ++p) a.class_flops[p] = 0.0;
+    a.own_flops = 0.0;
+    a.mfma_flops = 0.0;
+    // FP64 matrix-core flops issued per (brick, term) and unit of `steps`: the one-tile kernel runs
+    // four 16x16x4 products (2048 flops each) per slice and step on its 2k real slices; the two-tile
+    // kernel per slice five 16x16x4 and five 4x4x4 (512 flops) products in the first-columns job
+    // and ten 4x4x4 products in the last-columns job
+    const double D2 = 2.0 * k;
+    const double mfma_per_step = k > KNARROW ? (5.0 * 2048.0 + 15.0 * 512.0) * D2 : 4.0 * 2048.0 * D2;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         LevelDesc d{};
@@ -1127,12 +1136,30 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
         d.valid = lw.valid;
         d.ntpl = (int)lw.tpl.size();
         descs.push_back(d);
+        // down-band jobs whose terms all lie in the whole band's range R_j(L) at every coarse L of
+        // their box: at internal children they cancel whole-band terms (net coefficient 0)
+        std::vector<char> nested(lw.tpl.size(), 0);
+        const int32_t* row = a.op->plan.data() + (int64_t)j * NLP3 * 2;
+        for (size_t ti = 0; ti < lw.tpl.size(); ++ti) {
+            const Tpl& t = lw.tpl[ti];
+            if (!t.dpart) continue;
+            bool in = true;
+            for (int x = t.lo[0]; x <= t.hi[0] && in; ++x)
+                for (int y = t.lo[1]; y <= t.hi[1] && in; ++y)
+                    for (int z = t.lo[2]; z <= t.hi[2] && in; ++z) {
+                        if (std::abs(x) > LP || std::abs(y) > LP || std::abs(z) > LP) { in = false; break; }
+                        const int32_t* r = row + (((x + LP) * NLP + (y + LP)) * NLP + (z + LP)) * 2;
+                        in = r[0] <= t.m1 && t.m2 <= r[1];
+                    }
+            nested[ti] = in;
+        }
         const int64_t pside = j > 0 ? ((int64_t)1 << (j - 1)) : 1;
         for (int64_t b = 0; b < lw.nout; ++b) {
             int64_t pp[3] = {0, 0, 0};
             if (j > 0) key_coords(lw.pk[b], pp);
             double c[NPREC] = {0.0, 0.0, 0.0, 0.0};
-            for (const Tpl& t : lw.tpl) {
+            for (size_t ti = 0; ti < lw.tpl.size(); ++ti) {
+                const Tpl& t = lw.tpl[ti];
                 if (t.dpart && lw.cm[b] == 0) continue;
                 double nin[3];     // displacements L of the box with P - L inside the cube
                 for (int dd = 0; dd < 3; ++dd)
@@ -1142,11 +1169,12 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 const double nt = t.m2 - t.m1 + 1;
                 const double steps = nin[0] * nin[1] * nin[2] + nin[0] * nin[1] + nin[0];
                 c[t.prec] += nt * steps;
-                const double D2 = 2.0 * k;
                 a.jobs += (int64_t)nt;
                 const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
+                if (!nested[ti]) a.own_flops += fl;
+                if (t.prec == PREC_F64) a.mfma_flops += nt * mfma_per_step * steps;
             }
             if (k > KNARROW) {    // two-tile kernel: one job per column part of the brick
                 for (int p = 0; p < NPREC; ++p)
@@ -1232,6 +1260,8 @@ void collect_stats(mwns_ctx* ctx, TreeApply& a, int mode, mwns_apply_stats& s) {
     s.brick_jobs += a.jobs;
     s.ghost_bricks += a.total_ghosts;
     s.useful_flops += a.flops;
+    s.own_flops += a.own_flops;
+    s.f64_mfma_flops += a.mfma_flops;
     s.err_bound = std::max(s.err_bound, a.err_bound);
     for (int p = 0; p < NPREC; ++p) s.class_flops[p] += a.class_flops[p];
     if (mode & MWNS_TIMES_ONLY) {

@@ -388,6 +388,21 @@ mwns_status mwns_op_create(mwns_ctx* ctx, int k, int M, const double* tau, const
     MWNS_HIP(hipMemcpyAsync(pin_fro, dfro.p, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     MWNS_HIP(hipStreamSynchronize(st));
     if (nlev > 1) std::memcpy(ranges.data(), pin, ranges.size() * sizeof(int32_t));
+    // band overflow: a term kept at the edge of the band (max |L_d| = LP) means that the
+    // displacements beyond it, which the plan cannot hold, would still contribute
+    if (!(opts && opts->allow_band_overflow))
+        for (int j = 1; j < nlev; ++j)
+            for (int a = 0; a <= LP; ++a)
+                for (int b = a; b <= LP; ++b)
+                    for (int c = b; c <= LP; ++c) {
+                        if (c < LP) continue;
+                        const int32_t* r = ranges.data() + (size_t)(j - 1) * 40 + class_index(a, b, c) * 2;
+                        if (r[1] >= r[0])
+                            fail(MWNS_ERANGE, "band overflow: level " + std::to_string(j) + " keeps terms " +
+                                                  std::to_string(r[0]) + ".." + std::to_string(r[1]) + " at |L| = (" +
+                                                  std::to_string(a) + "," + std::to_string(b) + "," + std::to_string(c) +
+                                                  "), the edge of the band |L_d| <= 3");
+                    }
     std::vector<double> hnf0(pin_nf0, pin_nf0 + M);
     op->fro.assign(pin_fro, pin_fro + nb);
     double theta = 0.0;

@@ -167,7 +167,7 @@ def test_every_order_tables_plan_tree_eval(M, ctx, k):
     projected tree (keys and leaves exact), the operator's 1-D blocks, plan and threshold, and
     point values against the oracle."""
     from oracle import apply as A, tree as T
-    w = workloads.small_adaptive(5, k=k, eps=1e-3 if k > 2 else 1e-2, jmax=3)
+    w = workloads.small_adaptive(5, k=k, eps=1e-3 if k > 2 else (1e-2 if k == 2 else 5e-2), jmax=3)
     ot = _oracle_tree(w)
     f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
     keys, leaf, coef = M.mwns_tree_export(ctx, f)
@@ -225,7 +225,7 @@ def test_c2_full_size_sampled(M, ctx):
 def test_odd_and_small_orders(M, ctx, k):
     """Orders whose 2k is not a multiple of 4 take the element-wise load path of the kernel."""
     from oracle import apply as A
-    w = workloads.small_adaptive(4, k=k, eps=1e-3 if k > 2 else 1e-2, jmax=4)
+    w = workloads.small_adaptive(4, k=k, eps=1e-3 if k > 2 else (1e-2 if k == 2 else 5e-2), jmax=4)
     ot = _oracle_tree(w)
     f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
     keys, leaf, _ = M.mwns_tree_export(ctx, f)
@@ -324,3 +324,62 @@ def test_times_only_statistics(M, ctx):
     assert s2["contractions"] == -1 and s2["g_norm"] == 0.0 and s1["contractions"] > 0
     assert s2["ms_contract"] > 0.0 and s2["useful_flops"] == s1["useful_flops"]
     assert np.array_equal(M.mwns_tree_export(ctx, g1)[2], M.mwns_tree_export(ctx, g2)[2])
+
+
+def test_band_overflow_is_erange(M, ctx):
+    """An operator whose screening keeps terms at the edge of the band fails with ERANGE (the oracle
+    raises BandOverflow on the same inputs); allowed explicitly, it carries the oracle's plan."""
+    from oracle import apply as A
+    from oracle import plan as Pl
+    from paper_0706_0747_amd import _lib
+    from oracle import fit
+    tau, wt = fit.fit_kernel(0.0, 1.0, 1e-4, 1e-2 * 2.0 ** -4, math.sqrt(3))
+    with pytest.raises(Pl.BandOverflow):
+        A.Operator(2, tau, wt, 1e-4, 4)
+    with pytest.raises(M.MwnsError) as e:
+        M.mwns_op_create(ctx, 2, tau, wt, 1e-4, 4)
+    assert e.value.status == _lib.MWNS_ERANGE and "band" in str(e.value)
+    op = M.mwns_op_create(ctx, 2, tau, wt, 1e-4, 4, allow_band_overflow=1)
+    assert np.array_equal(M.mwns_op_plan_export(op), A.Operator(2, tau, wt, 1e-4, 4, allow_overflow=True).R)
+
+
+def test_byte_budget_enomem_without_leaks(M):
+    """A context whose byte budget is too small for a call fails with ENOMEM, creates no handle and
+    holds no more device memory afterwards than before the call: for the projection, and for an
+    apply whose tree and operator fit but whose working set does not."""
+    from paper_0706_0747_amd import _lib
+    w = CASES["adaptive_k6"]()
+    small = M.Context(0, byte_budget=1 << 16)
+    with pytest.raises(M.MwnsError) as e:
+        M.mwns_project_gaussians(small, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    assert e.value.status == _lib.MWNS_ENOMEM
+    small.release_cache()
+    assert small.bytes_in_use() == 0
+    probe = M.Context(0)
+    f = M.mwns_project_gaussians(probe, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    tau, wt = _fit(w, depth)
+    op = M.mwns_op_create(probe, w.k, tau, wt, w.eps, depth)
+    probe.release_cache()
+    held = probe.bytes_in_use()
+    # budgets between what the tree and operator hold and what the apply needs on top (the
+    # projection's own transient arrays may need more than the first ones)
+    failed_apply = 0
+    for factor in (1.15, 1.3, 1.5, 1.75, 2.0):
+        tight = M.Context(0, byte_budget=int(held * factor))
+        try:
+            f2 = M.mwns_project_gaussians(tight, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+            op2 = M.mwns_op_create(tight, w.k, tau, wt, w.eps, depth)
+        except M.MwnsError as e:
+            assert e.status == _lib.MWNS_ENOMEM
+            continue
+        tight.release_cache()
+        held2 = tight.bytes_in_use()
+        try:
+            M.mwns_apply(tight, op2, f2)
+        except M.MwnsError as e:
+            assert e.status == _lib.MWNS_ENOMEM
+            tight.release_cache()
+            assert tight.bytes_in_use() == held2
+            failed_apply += 1
+    assert failed_apply >= 1

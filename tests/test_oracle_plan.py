@@ -76,3 +76,17 @@ def test_plan_symmetry_monotonicity_and_grouping(op_tables):
     # root row: every term at L = 0 only
     assert tuple(R[0][3, 3, 3]) == (0, len(w) - 1)
     assert (R[0][..., 1] < R[0][..., 0]).sum() == 7 ** 3 - 1
+
+
+def test_band_overflow_is_reported():
+    """A term kept at the edge of the band (max |L_d| = 3) means displacements beyond the band
+    would still matter: few vanishing moments (k = 2) at a small eps do that, the configurations
+    of the workloads do not."""
+    from oracle import apply as A
+    tau, wt = fit.fit_kernel(0.0, 1.0, 1e-4, 1e-2 * 2.0 ** -4, math.sqrt(3))
+    with pytest.raises(P.BandOverflow):
+        A.Operator(2, tau, wt, 1e-4, 4)
+    op = A.Operator(2, tau, wt, 1e-4, 4, allow_overflow=True)
+    edge = op.R[1:, [0, 6]]     # L_1 = -3 or 3
+    assert np.any(edge[..., 1] >= edge[..., 0])
+    A.Operator(6, tau, wt, 1e-4, 4)     # within the band: no error
