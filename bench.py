@@ -1,21 +1,25 @@
 """Benchmark of the modified ns-form operator apply on one MI355X.
 
-A step is one pass of the whole path on the Poisson workload with k = 8, eps = 1e-6 and a
-50-Gaussian seeded source: Gaussian-sum fit (host FP64), operator build (1-D blocks and screening
-plan, device), adaptive projection to a redundant tree (device), the apply (neighbour closure,
-FP64-MFMA contractions, assembly; device) and evaluation at 1e4 points.  The printed JSON line
-reports NS-apply block-contractions per second of step time, the roofline of the contraction
-kernel (FP64 MFMA) and the CPU oracle timed on a bounded sample of the same apply.  Beside it:
-the precision-routed apply against the FP64 one on the same tree at tol = eps ||g|| ("mixed"),
-and the batch of uneven seeded solves applied one by one, as one persistent batched launch and
-as replays of a captured plan ("batch").
+A step is one pass of the whole path on the large single apply (Poisson, k = 10, eps = 1e-10,
+500 seeded Gaussians, about 9e5 leaves): Gaussian-sum fit (host FP64), operator build (1-D
+blocks and screening plan, device), adaptive projection to a redundant tree (device), the FP64
+apply (neighbour closure, FP64-MFMA contractions, assembly; device) and evaluation at 1e4
+points.  The printed JSON line reports NS-apply block-contractions per second of step time, the
+roofline of the contraction kernel (FP64 MFMA; the method's own flops over the kernel's HIP-event
+time), the precision-routed apply against the FP64 one on the same tree at tol = eps ||g||
+("mixed"), the potential against the closed form of the fitted kernel on a 22^3 grid, and the CPU
+oracle timed on a bounded sample with the same operator.  Beside it ("extra"): the Poisson k = 8
+and bound-state Helmholtz k = 10 workloads, and the batch of 64 uneven solves applied one by one,
+as one persistent batched launch and as replays of a captured plan.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-mixed] [--no-batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c2|c3]
+                    [--no-cpu-baseline] [--no-mixed] [--no-extra] [--no-batch]
 """
 import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -23,6 +27,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+METRIC = "NS apply block-contractions/s + FP64-MFMA util; mixed-vs-FP64 speedup at eps"
+
+# Sec. 6.1, Table 2 of the paper: the 3-D Poisson test (rho = -Laplacian of three Gaussians,
+# alpha = 300) on one Pentium-4 at 2.8 GHz with 2 GB of RAM; the rate counts nodes x p^3 per second
+PAPER_TABLE2 = {
+    "hardware": "one Pentium-4 at 2.8 GHz, 2 GB RAM (precision and compiler not stated)",
+    "workload": "3-D Poisson, rho = -Laplacian(sum of 3 Gaussians, alpha = 300), exact answer known",
+    "rows": [{"eps": 1e-3, "p": 6, "E2": 5.0e-3, "Einf": 7.9e-1, "time_s": 1.2, "rate_pts_per_s": 7.2e4},
+             {"eps": 1e-3, "p": 8, "E2": 1.7e-3, "Einf": 1.2e-1, "time_s": 0.51, "rate_pts_per_s": 7.3e4},
+             {"eps": 1e-3, "p": 10, "E2": 4.4e-4, "Einf": 3.7e-2, "time_s": 0.68, "rate_pts_per_s": 1.1e5},
+             {"eps": 1e-6, "p": 10, "E2": 4.7e-6, "Einf": 3.6e-4, "time_s": 10.3, "rate_pts_per_s": 5.7e4},
+             {"eps": 1e-6, "p": 12, "E2": 8.5e-6, "Einf": 4.3e-5, "time_s": 13.5, "rate_pts_per_s": 7.5e4},
+             {"eps": 1e-6, "p": 14, "E2": 6.9e-8, "Einf": 5.2e-6, "time_s": 20.0, "rate_pts_per_s": 8.0e4},
+             {"eps": 1e-9, "p": 16, "E2": 2.5e-10, "Einf": 2.2e-8, "time_s": 68.1, "rate_pts_per_s": 3.5e4},
+             {"eps": 1e-9, "p": 18, "E2": 7.7e-11, "Einf": 3.5e-9, "time_s": 100.3, "rate_pts_per_s": 3.4e4},
+             {"eps": 1e-9, "p": 20, "E2": 1.2e-10, "Einf": 1.8e-8, "time_s": 133.4, "rate_pts_per_s": 3.5e4}],
+    "note": "context only: other hardware and era; the paper prints no apply-only time, flop rate or GPU figure",
+}
+
+
+def progress(msg):
+    """A line on stderr as each part of the run ends (the JSON line alone goes to stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -30,15 +57,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["c5", "c2", "c3"], default="c5",
+                    help="c5: Poisson k=10 eps=1e-10, 500 Gaussians (the reported configuration); "
+                         "c2: Poisson k=8 eps=1e-6; c3: Yukawa k=10 eps=1e-8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-vs-FP64 measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the c2/c3 extra workloads")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-apply measurement")
-    ap.add_argument("--cpu-sample-nodes", type=int, default=15000)
+    ap.add_argument("--cpu-sample-nodes", type=int, default=1200)
     ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: Poisson k=8 eps=1e-6 (the reported configuration); c3: Yukawa k=10 eps=1e-8")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -55,7 +85,8 @@ def calibrate_copy():
     print(json.dumps({"calibration": "elementwise copy", "bytes_read": n * 8, "bytes_written": n * 8}))
 
 
-PROFILES = {"c2": ("ns_apply_kernel_poisson_k8_eps1e-6.md", "contract.hip"),
+PROFILES = {"c5": ("ns_apply_wide_kernel_poisson_k10_eps1e-10.md", "contract_wide.hip"),
+            "c2": ("ns_apply_kernel_poisson_k8_eps1e-6.md", "contract.hip"),
             "c3": ("ns_apply_wide_kernel_yukawa_k10_eps1e-8.md", "contract_wide.hip")}
 
 
@@ -96,15 +127,69 @@ def step(M, ctx, w, pts, mode=0):
     return g, stats, depth, vals, f, op
 
 
-def leaf_norm(leaf, coef):
+def leaf_norm(leaf, coef, chunk=1 << 16):
     import numpy as np
-    return math.sqrt(float(np.sum(coef[leaf == 1] ** 2)))
+    idx = np.nonzero(leaf == 1)[0]
+    tot = 0.0
+    for i in range(0, idx.size, chunk):
+        tot += float(np.sum(coef[idx[i:i + chunk]] ** 2))
+    return math.sqrt(tot)
+
+
+def measure(M, ctx, w, steps, warmup, pts):
+    """Timed steps of the whole path on workload w; the figures of one FP64 apply."""
+    import torch
+    for _ in range(warmup):
+        step(M, ctx, w, pts)
+    torch.cuda.synchronize()
+    progress("%s: %d warm-up steps done" % (w.name, warmup))
+    t0 = time.perf_counter()
+    stats_all = []
+    for _ in range(steps):
+        g, stats, depth, _, f, op = step(M, ctx, w, pts, M.MWNS_TIMES_ONLY)
+        stats_all.append(stats)
+        del g
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / steps
+    progress("%s: %d timed steps, %.1f ms per step" % (w.name, steps, 1e3 * dt / steps))
+    # the plan's contraction count and ||g|| (the same for every step) from one untimed apply
+    g, st = M.mwns_apply(ctx, op, f)
+    info = M.mwns_tree_get_info(g)
+    avg = lambda key: sum(s[key] for s in stats_all) / len(stats_all)
+    ms_con, ms_clo, ms_asm = avg("ms_contract"), avg("ms_closure"), avg("ms_assemble")
+    own = st["own_flops"] / (ms_con * 1e-3) / 1e12
+    executed = st["useful_flops"] / (ms_con * 1e-3) / 1e12
+    kernel = ("ns_apply_kernel<%d> (all levels of one apply)" % w.k if w.k <= 8 else
+              "ns_apply_wide_kernel<%d> (all levels of one apply)" % w.k)
+    out = {
+        "ms_per_step": ms_step, "contractions_per_step": int(st["contractions"]),
+        "value": st["contractions"] / (ms_step * 1e-3),
+        "config": {"workload": w.name,
+                   "kernel": "poisson 1/(4 pi r)" if w.mu == 0.0 else "yukawa exp(-mu r)/(4 pi r), mu=%.4f" % w.mu,
+                   "k": w.k, "eps": w.eps, "sources": int(w.a.size), "seed": w.seed,
+                   "leaves": int(info["nleaves"]), "nodes": int(info["nnodes"]), "depth": int(info["depth"]),
+                   "terms": int(op.M), "eval_points": int(pts.shape[0])},
+        "apply_contractions_per_s": st["contractions"] / ((ms_clo + ms_con + ms_asm) * 1e-3),
+        "apply_ms": {"closure": ms_clo, "contract": ms_con, "assemble": ms_asm},
+        "roofline": {"bound": "mfma", "achieved": own, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": own / PEAK_FP64_TFLOPS, "traffic": None, "traffic_unit": "bytes per launch",
+                     "kernel": kernel, "variant": M.mwns_ctx_get_variant(ctx, w.k),
+                     "own_flops_per_apply": st["own_flops"],
+                     "executed_flops_per_apply": st["useful_flops"],
+                     "executed_tflops": executed,
+                     "f64_mfma_flops_per_apply": st["f64_mfma_flops"],
+                     "flops": "own: the factorised contraction flops 2 (2k)^4 (n1 n2 n3 + n1 n2 + n1) of every "
+                              "(sibling group, term, box of displacements) job, padding excluded, without the "
+                              "down-band jobs whose terms the whole band holds at every displacement of their box; "
+                              "executed: with them; f64_mfma: what the matrix cores issue, tile padding included"},
+    }
+    return out, (g, st, f, op)
 
 
 def mixed_measurement(M, ctx, w, f, op, g64, st64, reps, ms_con64):
     """Apply-only wall time of the FP64 and the precision-routed apply on the same tree and
-    operator, the latter at tol = eps ||g_F64||; the measured relative L2 error against FP64.
-    ms_con64 is the FP64 contraction time of the timed steps (their average)."""
+    operator, the latter at tol = eps ||g_F64||; the measured relative L2 error against FP64."""
     import torch
     tol = w.eps * st64["g_norm"]
     times = {}
@@ -120,14 +205,36 @@ def mixed_measurement(M, ctx, w, f, op, g64, st64, reps, ms_con64):
     gm, stm = M.mwns_apply_mixed(ctx, op, f, tol)
     _, leaf, a = M.mwns_tree_export(ctx, g64)
     _, _, b = M.mwns_tree_export(ctx, gm)
-    err = leaf_norm(leaf, b - a)
+    b -= a
+    err = leaf_norm(leaf, b)
+    del a, b
     return times["fp64"] / times["mixed"], {
         "tol_rel": w.eps, "err_rel_measured": err / st64["g_norm"], "err_rel_bound": stm["err_bound"] / st64["g_norm"],
-        "apply_ms_fp64": times["fp64"], "apply_ms_mixed": times["mixed"],
+        "apply_ms_fp64": times["fp64"], "apply_ms_mixed": times["mixed"], "reps": reps,
         "contract_ms_fp64": ms_con64, "contract_ms_mixed": stm["ms_contract"],
         "class_flop_share": {c: stm["class_flops"][i] / stm["useful_flops"]
                              for i, c in enumerate(("f64", "f32", "bf16c", "bf16"))},
         "classes": "FP64 MFMA; FP32 MFMA; BF16 MFMA on hi/lo splits (4 partial products); BF16 MFMA"}
+
+
+def closed_form_check(M, ctx, w, g, depth):
+    """The FP64 potential against the fitted kernel applied in closed form to the cube-truncated
+    source on a seeded 22^3 grid (about 1e4 points); errors relative to max |ref| and to eps ||f||."""
+    import numpy as np
+    from oracle import closed_forms as CF
+    from oracle import fit as OF
+    from oracle import tree as T
+    otau, ow = OF.fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    grng = np.random.Generator(np.random.PCG64(56))
+    grid = [np.sort(grng.uniform(0.0, 1.0, 22)) for _ in range(3)]
+    ref = CF.fitted_truncated_grid(otau, ow, w.xyz, w.a, w.c, *grid)
+    X, Y, Z = np.meshgrid(*grid, indexing="ij")
+    v = M.mwns_tree_eval(ctx, g, np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)).reshape(ref.shape)
+    e = np.abs(v - ref)
+    fnorm = T.source_norm(w.xyz, w.a, w.c)
+    return {"points": int(ref.size), "max_abs_err": float(e.max()), "rms_err": float(np.sqrt(np.mean(e ** 2))),
+            "max_abs_ref": float(np.abs(ref).max()), "rel_max": float(e.max() / np.abs(ref).max()),
+            "rms_over_eps_fnorm": float(np.sqrt(np.mean(e ** 2)) / (w.eps * fnorm))}
 
 
 def batch_measurement(M, ctx, reps, nmembers=64):
@@ -135,18 +242,22 @@ def batch_measurement(M, ctx, reps, nmembers=64):
     per second for sequential single applies, one batched persistent apply, and replays of the
     captured apply plan, in FP64 and precision-routed at tol = eps ||g|| per member."""
     import torch
-    members = [workloads_member(i) for i in range(nmembers)]
-    kept = members
+    import workloads
+    members = [workloads.c4_member(i) for i in range(nmembers)]
     ops, fs = [], []
-    for w in kept:
+    for w in members:
         f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
         depth = M.mwns_tree_get_info(f)["depth"]
         tau, wt = M.mwns_fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
         ops.append(M.mwns_op_create(ctx, w.k, tau, wt, w.eps, depth))
         fs.append(f)
+    tuned = {}
+    for k in sorted({int(w.k) for w in members}):   # the autotuner's pick per basis order
+        i = next(i for i, w in enumerate(members) if w.k == k)
+        tuned[k] = M.autotune(ctx, ops[i], fs[i])
     _, st = M.mwns_apply_batch(ctx, ops, fs)
     plan = M.mwns_plan_create(ctx, ops, fs)
-    tols = [w.eps * M.mwns_apply(ctx, op, f)[1]["g_norm"] for w, op, f in zip(kept, ops, fs)]
+    tols = [w.eps * M.mwns_apply(ctx, op, f)[1]["g_norm"] for w, op, f in zip(members, ops, fs)]
     _, stm = M.mwns_apply_batch(ctx, ops, fs, mixed=tols)
     planm = M.mwns_plan_create(ctx, ops, fs, mixed=tols)
 
@@ -166,43 +277,81 @@ def batch_measurement(M, ctx, reps, nmembers=64):
     ms_plan_mixed = timed(planm.execute)
     plan.close()
     planm.close()
+    leaves = [int(M.mwns_tree_get_info(f)["nleaves"]) for f in fs]
     nodes = sum(M.mwns_tree_get_info(f)["nnodes"] for f in fs)
     c = st["contractions"]
-    return {"members": len(kept), "orders": sorted({int(w.k) for w in kept}), "nodes": int(nodes),
+    return {"members": len(members), "orders": sorted({int(w.k) for w in members}), "nodes": int(nodes),
+            "leaves_per_member": leaves, "leaves_min": min(leaves), "leaves_max": max(leaves),
+            "tuned_variant_per_k": {str(k): v for k, v in tuned.items()},
             "contractions": int(c), "ms_sequential": ms_seq, "ms_batch": ms_batch, "ms_plan_replay": ms_plan,
             "contractions_per_s_sequential": c / (ms_seq * 1e-3), "contractions_per_s_batch": c / (ms_batch * 1e-3),
             "contractions_per_s_plan": c / (ms_plan * 1e-3),
+            "own_tflops_batch": st["own_flops"] / (ms_batch * 1e-3) / 1e12,
             "mixed": {"tol": "eps ||g|| per member", "ms_batch": ms_batch_mixed, "ms_plan_replay": ms_plan_mixed,
                       "speedup_batch": ms_batch / ms_batch_mixed, "speedup_plan": ms_plan / ms_plan_mixed,
                       "class_flop_share": {cl: stm["class_flops"][i] / stm["useful_flops"]
                                            for i, cl in enumerate(("f64", "f32", "bf16c", "bf16"))}}}
 
 
-def workloads_member(i):
-    import workloads
-    return workloads.c4_member(i)
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(w, depth, nsample):
-    """The oracle's modified-form apply on a seeded sample of output nodes of the same tree."""
-    import numpy as np
+def _oracle_sample_setup(w, depth, nsub):
+    """The oracle's operator for workload w (its own fit at the workload's depth) and its tree of the
+    first nsub source Gaussians (a tree the oracle builds in seconds; the per-node work of the apply
+    depends on the order, the operator and the plan, which are the workload's)."""
     from oracle import apply as A
     from oracle import fit
     from oracle import tree as T
-    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz[:nsub], w.a[:nsub], w.c[:nsub])
     tr = T.redundant_tree(w.k, keys, coef)
     tau, wt = fit.fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
-    op = A.Operator(w.k, tau, wt, w.eps, tr.depth)
-    rng = np.random.Generator(np.random.PCG64(77))
+    op = A.Operator(w.k, tau, wt, w.eps, max(depth, tr.depth))
+    return tr, op
+
+
+def _oracle_rate(tr, op, nsample, seed):
+    import numpy as np
+    from oracle import apply as A
+    rng = np.random.Generator(np.random.PCG64(seed))
     idx = np.sort(rng.choice(tr.keys.size, size=min(nsample, tr.keys.size), replace=False))
     cnt = _count_contractions(op.R, tr, idx)
     t0 = time.perf_counter()
     A.apply_modified(op, tr, idx)
     dt = time.perf_counter() - t0
+    return cnt, dt, idx.size
+
+
+def cpu_baseline(w, depth, nsample, nsub=6):
+    """The oracle's modified-form apply (plain C, OpenMP over output nodes) with workload w's operator
+    on a seeded sample of output nodes, on all host threads and, in a child process, on one."""
+    tr, op = _oracle_sample_setup(w, depth, nsub)
+    progress("oracle tree and operator for the CPU baseline built")
+    cnt, dt, n = _oracle_rate(tr, op, nsample, 77)
+    progress("CPU baseline on all threads done (%.1f s)" % dt)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = None
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--workload",
+                              w.get("key", "c5")], env=env, capture_output=True, text=True, timeout=300)
+        one = json.loads(res.stdout.strip().splitlines()[-1])
+    except Exception as e:     # the one-thread figure is context; report why it is missing
+        one = {"error": repr(e)[:200]}
     return {"value": cnt / dt, "unit": "block-contractions/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d output nodes (seed 77), %d contractions in %.1f s; plain C, OpenMP over nodes"
-                      % (idx.size, tr.keys.size, cnt, dt)}
+            "cpu_model": _cpu_model(), "one_thread": one,
+            "sample": "%d of %d output nodes (seed 77) of the oracle's tree of the first %d of the %d source Gaussians "
+                      "(%d leaves), with the workload's operator (k=%d, eps=%g, %d terms, its own plan); %d "
+                      "contractions in %.1f s; plain C, OpenMP over nodes"
+                      % (n, tr.keys.size, nsub, w.a.size, int(tr.leaf.sum()), w.k, w.eps, op.M, cnt, dt)}
 
 
 def _count_contractions(R, tr, idx):
@@ -241,77 +390,93 @@ def _count_contractions(R, tr, idx):
     return total
 
 
+def _workload(name):
+    import workloads
+    w = getattr(workloads, name)()
+    w["key"] = name
+    return w
+
+
+def cpu_baseline_only(args):
+    """Child process of cpu_baseline: the one-thread rate (OMP_NUM_THREADS=1 set by the parent) on a
+    smaller sample of the same nodes."""
+    w = _workload(args.workload)
+    depth = {"c5": 11, "c2": 8, "c3": 8}[args.workload]
+    tr, op = _oracle_sample_setup(w, depth, 6)
+    cnt, dt, n = _oracle_rate(tr, op, max(20, args.cpu_sample_nodes // 16), 77)
+    print(json.dumps({"value": cnt / dt, "unit": "block-contractions/s", "cores": 1,
+                      "sample": "%d output nodes, %d contractions in %.1f s" % (n, cnt, dt)}))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.cpu_baseline_only:
+        cpu_baseline_only(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    import torch
     import paper_0706_0747_amd as M
     import workloads
-    w = workloads.c2() if args.workload == "c2" else workloads.c3()
+    w = _workload(args.workload)
     pts = workloads.points(10000)
     ctx = M.Context(0)
     M.mwns_ctx_set_variant(ctx, w.k, args.variant)
-    for _ in range(args.warmup):
-        step(M, ctx, w, pts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats_all = []
-    for _ in range(args.steps):
-        g, stats, depth, _, f, op = step(M, ctx, w, pts, M.MWNS_TIMES_ONLY)
-        stats_all.append(stats)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
-    # the plan's contraction count and ||g|| (the same for every step) from one untimed apply
-    g, st = M.mwns_apply(ctx, op, f)
-    info = M.mwns_tree_get_info(g)
-    contr = st["contractions"]
-    ms_con = sum(s["ms_contract"] for s in stats_all) / len(stats_all)
-    ms_clo = sum(s["ms_closure"] for s in stats_all) / len(stats_all)
-    ms_asm = sum(s["ms_assemble"] for s in stats_all) / len(stats_all)
-    achieved = st["useful_flops"] / (ms_con * 1e-3) / 1e12
+    head, (g, st, f, op) = measure(M, ctx, w, args.steps, args.warmup, pts)
+    head["roofline"]["traffic"] = traffic_from_profile(args.workload)
     line = {
-        "metric": "NS apply block-contractions/s + FP64-MFMA util; mixed-vs-FP64 speedup at eps",
-        "value": contr / (ms_step * 1e-3),
+        "metric": METRIC,
+        "value": head.pop("value"),
         "unit": "block-contractions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name,
-                   "kernel": "poisson 1/(4 pi r)" if w.mu == 0.0 else "yukawa exp(-mu r)/(4 pi r), mu=%.4f" % w.mu,
-                   "k": w.k, "eps": w.eps,
-                   "sources": int(w.a.size), "seed": w.seed, "leaves": int(info["nleaves"]),
-                   "nodes": int(info["nnodes"]), "depth": int(info["depth"]), "eval_points": int(pts.shape[0])},
-        "contractions_per_step": int(contr),
-        "apply_contractions_per_s": contr / ((ms_clo + ms_con + ms_asm) * 1e-3),
-        "apply_ms": {"closure": ms_clo, "contract": ms_con, "assemble": ms_asm},
-        "mixed_vs_fp64_speedup": None,
-        "mixed": None,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic_from_profile(args.workload),
-                     "traffic_unit": "bytes per launch",
-                     "kernel": ("ns_apply_kernel<8> (all levels of one apply)" if w.k <= 8 else
-                                "ns_apply_wide_kernel<%d> (all levels of one apply)" % w.k),
-                     "variant": M.mwns_ctx_get_variant(ctx, w.k),
-                     "flops_per_apply": st["useful_flops"]},
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
     }
+    line.update(head)
+    line["mixed_vs_fp64_speedup"], line["mixed"] = None, None
     if not args.no_mixed:
-        line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(M, ctx, w, f, op, g, st, args.steps, ms_con)
+        reps = min(args.steps, 3) if w.k > 8 else args.steps
+        line["mixed_vs_fp64_speedup"], line["mixed"] = mixed_measurement(
+            M, ctx, w, f, op, g, st, reps, line["apply_ms"]["contract"])
+        progress("mixed-vs-FP64 measurement done")
+    if args.workload == "c5":
+        line["closed_form"] = closed_form_check(M, ctx, w, g, line["config"]["depth"])
+        progress("closed-form check done")
+    del g
+    ctx.release_cache()
+    line["paper_table2"] = PAPER_TABLE2
+    if not args.no_extra:
+        line["extra"] = {}
+        for name in ("c2", "c3"):
+            if name == args.workload:
+                continue
+            wx = _workload(name)
+            M.mwns_ctx_set_variant(ctx, wx.k, -1)
+            ex, (gx, stx, fx, opx) = measure(M, ctx, wx, max(args.steps, 5), 2, pts)
+            ex["roofline"]["traffic"] = traffic_from_profile(name)
+            if not args.no_mixed:
+                ex["mixed_vs_fp64_speedup"], ex["mixed"] = mixed_measurement(
+                    M, ctx, wx, fx, opx, gx, stx, max(args.steps, 5), ex["apply_ms"]["contract"])
+            line["extra"][name] = ex
+            progress("extra workload %s done" % name)
+            del gx
+        ctx.release_cache()
     if not args.no_batch:
-        line["batch"] = batch_measurement(M, ctx, args.steps)
+        line["batch"] = batch_measurement(M, ctx, min(args.steps, 5))
+        progress("batch done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, info["depth"], args.cpu_sample_nodes)
+        line["cpu_baseline"] = cpu_baseline(w, line["config"]["depth"], args.cpu_sample_nodes)
     print(json.dumps(line))
 
 

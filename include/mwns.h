@@ -90,14 +90,18 @@ mwns_status mwns_ctx_release_cache(mwns_ctx* ctx);
 /* Thread-local text for the last non-OK status returned on this thread ("" if none). */
 const char* mwns_last_error(void);
 
-/* Tile variant of the FP64 one-tile contraction kernel (k <= 8) used by this context for basis
- * order k: an index in [0, mwns_num_variants()), or -1 for the library's default (for 6 <= k <= 8
- * the shape with two terms per pass and a prefetched input slice, below variant 0).  Variants differ
- * in speed only: those with one term per pass compute the same result bit for bit; those with
- * several terms per pass add the plane results of consecutive terms in another order, so they
+/* Tile variant of the FP64 contraction kernel used by this context for basis order k: an index in
+ * [0, mwns_num_variants_for(k)), or -1 for the library's default.  For k <= 8 (the one-tile kernel,
+ * mwns_num_variants() shapes, mwns_variant_shape) the default is the shape with two terms per pass
+ * and a prefetched input slice for 6 <= k <= 8, variant 0 below; for k = 9, 10 (one workgroup of four
+ * waves per sibling group) variant 0, the default, loads the next input slice while computing the
+ * current one and variant 1 loads each when it is needed (the two agree bit for bit).  Variants
+ * differ in speed only: those with one term per pass compute the same result bit for bit; those
+ * with several terms per pass add the plane results of consecutive terms in another order, so they
  * agree with the others up to rounding.  mwns_tune_apply picks one by timing.
  * Errors: EINVAL (k or variant out of range). */
 int mwns_num_variants(void);
+int mwns_num_variants_for(int k);
 /* Shape of variant v: waves per workgroup, register prefetch depth of the input slices, waves
  * per SIMD, and FP64 terms per pass over a job's cells.  Errors: EINVAL (v out of range, NULL). */
 mwns_status mwns_variant_shape(int v, int* waves, int* prefetch, int* waves_per_simd, int* terms_per_pass);
@@ -297,7 +301,7 @@ typedef struct mwns_plan mwns_plan;
 /* Autotuner: times the FP64 contraction launch of the apply of f by op in every tile variant
  * (one warm-up and `reps` timed launches each, HIP events on the context's stream), stores the
  * fastest as the context's variant for f's k and returns it in *best; times_ms (NULL or
- * mwns_num_variants() doubles) receives the average launch time of each variant.  Synchronises.
+ * mwns_num_variants_for(k) doubles) receives the average launch time of each variant.  Synchronises.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 mwns_status mwns_tune_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, int reps, int* best, double* times_ms);
 mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* const* ops, const mwns_tree* const* fs,

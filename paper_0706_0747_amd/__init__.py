@@ -23,7 +23,7 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
-           "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_variant_shape", "mwns_ctx_set_variant",
+           "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
            "mwns_fit_kernel", "mwns_op_create", "mwns_op_plan_export", "mwns_op_plan_import",
            "mwns_op_tables_export", "mwns_project_gaussians", "mwns_tree_from_leaves", "mwns_tree_export",
@@ -215,7 +215,7 @@ def mwns_tree_set_leaves(ctx, tree, coeffs):
 def mwns_tune_apply(ctx, op, f, reps=3):
     """Times every tile variant on this apply, selects the fastest for f's k; returns (best, ms[])."""
     best = ctypes.c_int(0)
-    t = np.zeros(mwns_num_variants())
+    t = np.zeros(mwns_num_variants_for(mwns_tree_get_info(f)["k"]))
     check(lib.mwns_tune_apply(ctx.h, op.h, f.h, reps, ctypes.byref(best), t.ctypes.data), "mwns_tune_apply")
     return best.value, t
 
@@ -232,7 +232,7 @@ def autotune(ctx, op, f, cache_path=None, reps=3):
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
-    if key in cache and 0 <= int(cache[key]) < mwns_num_variants():
+    if key in cache and 0 <= int(cache[key]) < mwns_num_variants_for(k):
         mwns_ctx_set_variant(ctx, k, int(cache[key]))
         return int(cache[key])
     best, _ = mwns_tune_apply(ctx, op, f, reps)
@@ -255,6 +255,10 @@ def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):
 
 def mwns_num_variants():
     return lib.mwns_num_variants()
+
+
+def mwns_num_variants_for(k):
+    return lib.mwns_num_variants_for(k)
 
 
 def mwns_variant_shape(v):
@@ -383,3 +387,4 @@ def mwns_tree_eval(ctx, tree, pts):
     out = np.zeros(pts.shape[0])
     check(lib.mwns_tree_eval(ctx.h, tree.h, pts.shape[0], pts.ctypes.data, out.ctypes.data), "mwns_tree_eval")
     return out
+

@@ -63,6 +63,7 @@ SIGNATURES = {
     "mwns_ctx_release_cache": (c_int, [c_vp]),
     "mwns_last_error": (ctypes.c_char_p, []),
     "mwns_num_variants": (c_int, []),
+    "mwns_num_variants_for": (c_int, [c_int]),
     "mwns_variant_shape": (c_int, [c_int, P(c_int), P(c_int), P(c_int), P(c_int)]),
     "mwns_ctx_set_variant": (c_int, [c_vp, c_int, c_int]),
     "mwns_ctx_get_variant": (c_int, [c_vp, c_int, P(c_int)]),

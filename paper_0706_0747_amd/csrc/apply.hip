@@ -1105,11 +1105,14 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
     a.own_flops = 0.0;
     a.mfma_flops = 0.0;
     // FP64 matrix-core flops issued per (brick, term) and unit of `steps`: the one-tile kernel runs
-    // four 16x16x4 products (2048 flops each) per slice and step on its 2k real slices; the two-tile
-    // kernel per slice five 16x16x4 and five 4x4x4 (512 flops) products in the first-columns job
-    // and ten 4x4x4 products in the last-columns job
+    // four 16x16x4 products (2048 flops each) per slice and step on its 2k real slices; the brick
+    // kernel (orders above KNARROW) per slice five 16x16x4 and fifteen 4x4x4 (512 flops) products
+    // in modes 3 and 2, and the same per output row u2 in mode 1, except that mode 1 of a down-band
+    // job at a brick with leaf children runs two passes: per row and K step two 16x16x4 and four
+    // 4x4x4 products instead of one and three
     const double D2 = 2.0 * k;
     const double mfma_per_step = k > KNARROW ? (5.0 * 2048.0 + 15.0 * 512.0) * D2 : 4.0 * 2048.0 * D2;
+    const double mfma_mode1_split = 5.0 * (2.0 * 2048.0 + 4.0 * 512.0) * D2;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         LevelDesc d{};
@@ -1174,12 +1177,17 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
                 if (!nested[ti]) a.own_flops += fl;
-                if (t.prec == PREC_F64) a.mfma_flops += nt * mfma_per_step * steps;
+                if (t.prec == PREC_F64) {
+                    if (k > KNARROW && t.dpart && lw.cm[b] != 0xff)
+                        a.mfma_flops += nt * (mfma_per_step * (steps - nin[0]) + mfma_mode1_split * nin[0]);
+                    else
+                        a.mfma_flops += nt * mfma_per_step * steps;
+                }
             }
-            if (k > KNARROW) {    // two-tile kernel: one job per column part of the brick
-                for (int p = 0; p < NPREC; ++p)
-                    if (p == PREC_F64 || c[p] > 0.0)
-                        for (int half = 0; half < 2; ++half) cost[p].push_back({c[p], make_int2(di, (int)(2 * b + half))});
+            if (k > KNARROW) {    // FP64: one workgroup per brick; FP32: one per column part of the brick
+                cost[PREC_F64].push_back({c[PREC_F64], make_int2(di, (int)b)});
+                if (c[PREC_F32] > 0.0)
+                    for (int half = 0; half < 2; ++half) cost[PREC_F32].push_back({c[PREC_F32], make_int2(di, (int)(2 * b + half))});
                 continue;
             }
             for (int p = 0; p < NPREC; ++p)
@@ -1435,7 +1443,7 @@ void build_launches(mwns_ctx* ctx, std::vector<std::unique_ptr<TreeApply>>& tree
             if (persistent) {
                 g.dqueue.reset(ctx, QUEUE_INTS);
                 g.dqueue.upload(g.queue_init.data(), QUEUE_INTS, ctx->stream);
-                const int64_t res = g.k > KNARROW ? resident_blocks_wide(g.k, g.prec, ctx->device)
+                const int64_t res = g.k > KNARROW ? resident_blocks_wide(g.k, g.variant, g.prec, ctx->device)
                                                   : resident_blocks(g.k, g.variant, g.prec, ctx->device);
                 g.nblocks = std::min<int64_t>((int64_t)g.order.size(), res);
             } else {
@@ -1448,7 +1456,8 @@ void launch_contractions(mwns_ctx* ctx, Launches& Lz) {
     for (auto& g : Lz.groups) {
         if (g.order.empty()) continue;
         if (g.dqueue.p) zero_ints_kernel<<<1, 64, 0, ctx->stream>>>(g.dqueue.p, NXCD);
-        if (g.k > KNARROW) launch_contract_wide(g.k, g.prec, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
+        if (g.k > KNARROW)
+            launch_contract_wide(g.k, g.variant, g.prec, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p, g.dqueue.p);
         else
             launch_contract(g.k, g.variant, g.prec, g.prec != PREC_F64, ctx->stream, g.nblocks, Lz.ddesc.p, g.dorder.p,
                             g.dqueue.p);
@@ -1651,7 +1660,7 @@ extern "C" mwns_status mwns_tune_apply(mwns_ctx* ctx, const mwns_op* op, const m
     Launches Lz;
     build_launches(ctx, trees, false, Lz);
     launch_zero_outputs(ctx, *trees[0]);
-    const int nv = num_variants();
+    const int nv = f->k > KNARROW ? num_wide_variants() : num_variants();
     std::vector<double> t(nv, 0.0);
     Timer tm(ctx->stream);
     for (int v = 0; v < nv; ++v) {

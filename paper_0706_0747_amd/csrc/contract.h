@@ -17,6 +17,10 @@ struct Tpl {
     int prec;              // precision class of the job's terms (PREC_*)
 };
 
+// Entry d of a per-dimension triple, without indexing the array at run time (a private array
+// indexed with a run-time value is placed in scratch memory).
+__host__ __device__ inline int pick3(const int (&a)[3], int d) { return d == 0 ? a[0] : (d == 1 ? a[1] : a[2]); }
+
 // Precision classes of a job.  Every class accumulates into the FP64 output; the reduced ones
 // take their inputs from FP32 or split-BF16 copies of the input bricks and accumulate each
 // mode product in FP32.
@@ -79,12 +83,15 @@ void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t 
                      const LevelDesc* levels, const int2* order, int* queues);
 // Workgroups of that kernel that fit on the device at once (for the persistent launch).
 int64_t resident_blocks(int k, int variant, int prec, int device);
-// The two-tile kernel for KNARROW < k <= KMAX, classes PREC_F64 and PREC_F32 (the latter adds
-// to the output): order[] entries are (level descriptor, 2 * brick + column part), the columns
-// u3 < 16 and the last ones each a separate workgroup job.  queues as in launch_contract.
-void launch_contract_wide(int k, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
-                          int* queues);
-int64_t resident_blocks_wide(int k, int prec, int device);
+// The contraction kernels for KNARROW < k <= KMAX (2k = 18, 20: 16-wide tiles plus 4-row tails).
+// PREC_F64: one workgroup of four waves per output brick, order[] entries (level descriptor,
+// brick); variant 0 loads the next input slice ahead, variant 1 when it is needed.  PREC_F32 (adds to the output):
+// order[] entries (level descriptor, 2 * brick + column part), the columns u3 < 16 and the last
+// ones each a separate workgroup job.  queues as in launch_contract.
+int num_wide_variants();
+void launch_contract_wide(int k, int variant, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels,
+                          const int2* order, int* queues);
+int64_t resident_blocks_wide(int k, int variant, int prec, int device);
 // FP32 copies of nb input bricks for the two-tile kernel: [brick][v1][v2][v3], as the FP64 bricks.
 void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out);
 // FP32 or split-BF16 copies of input bricks, 16-byte groups as the one-tile kernel reads them, for

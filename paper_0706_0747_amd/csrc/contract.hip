@@ -219,7 +219,7 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
                         if (sb < n1) { q = sb; d = 0; }
                         else if (sb < n1 + n2) { q = sb - n1; d = 1; }
                         else { q = sb - n1 - n2; d = 2; }
-                        const double val = (d == 0 ? cw : 1.0) * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v);
+                        const double val = (d == 0 ? cw : 1.0) * sop<K>(Fm, pick3(tp.lo, d) + q, pick3(tp.mlo, d), pick3(tp.mhi, d), uu, v);
                         if constexpr (PREC == PREC_F64) {
                             double* dst = d == 0 ? S1s + q * 256 + v * 16 : d == 1 ? S2s + q * 256 + v * 16 : S3s + q * 16 * S3_V + v * S3_V;
                             dst[uu] = val;
@@ -238,7 +238,7 @@ __device__ __forceinline__ void run_job(const LevelDesc& lv, const Tpl& tp, cons
                         else { q = sb - n1 - n2; d = 2; }
                         const double sc = d == 0 ? cw : 1.0;
                         f4 v4;
-                        for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, 4 * gg + c));
+                        for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, pick3(tp.lo, d) + q, pick3(tp.mlo, d), pick3(tp.mhi, d), uu, 4 * gg + c));
                         (d == 0 ? S1b : d == 1 ? S2b : S3b)[(q * 16 + uu) * 4 + gg] = split4(v4);
                     }
                 }
@@ -409,7 +409,7 @@ __device__ __forceinline__ void run_job_g(const LevelDesc& lv, const Tpl& tp, co
             else { q = sb - n1 - n2; d = 2; }
             const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
             double* dst = d == 0 ? S1s(gi) + q * 256 + v * 16 : d == 1 ? S2s(gi) + q * 256 + v * 16 : S3s(gi) + q * 16 * S3_V + v * S3_V;
-            dst[uu] = sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v);
+            dst[uu] = sc * sop<K>(Fm, pick3(tp.lo, d) + q, pick3(tp.mlo, d), pick3(tp.mhi, d), uu, v);
         }
         lds_barrier();
         d4 T1[G][TPW], T2[G][TPW];
@@ -531,7 +531,7 @@ __device__ __forceinline__ void run_job_lp(const LevelDesc& lv, const Tpl& tp, c
                 else { q = sb - n1 - n2; d = 2; }
                 const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
                 float* dst = (d == 0 ? S1f(gi) : d == 1 ? S2f(gi) : S3f(gi)) + (q * 16 + v) * SF_V;
-                dst[uu] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, v));
+                dst[uu] = (float)(sc * sop<K>(Fm, pick3(tp.lo, d) + q, pick3(tp.mlo, d), pick3(tp.mhi, d), uu, v));
             }
         } else {
             const int per = (n1 + n2 + n3) * 64;
@@ -546,7 +546,7 @@ __device__ __forceinline__ void run_job_lp(const LevelDesc& lv, const Tpl& tp, c
                 else { q = sb - n1 - n2; d = 2; }
                 const double sc = d == 0 ? (tp.dpart ? -w[m] : w[m]) : 1.0;
                 f4 v4;
-                for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, tp.lo[d] + q, tp.mlo[d], tp.mhi[d], uu, 4 * gg + c));
+                for (int c = 0; c < 4; ++c) v4[c] = (float)(sc * sop<K>(Fm, pick3(tp.lo, d) + q, pick3(tp.mlo, d), pick3(tp.mhi, d), uu, 4 * gg + c));
                 (d == 0 ? S1b(gi) : d == 1 ? S2b(gi) : S3b(gi))[(q * 16 + uu) * 4 + gg] = split4(v4);
             }
         }
@@ -870,7 +870,7 @@ int num_variants() { return NVARIANTS; }
 
 int variant_for(const mwns_ctx* ctx, int k) {
     const int v = ctx->variant[k];
-    return k > KNARROW ? 0 : (v >= 0 ? v : default_variant(k));
+    return v >= 0 ? v : (k > KNARROW ? 0 : default_variant(k));
 }
 
 template <template <int> class Fn, class... Args>
@@ -912,6 +912,8 @@ using namespace mwns;
 
 extern "C" int mwns_num_variants(void) { return NVARIANTS; }
 
+extern "C" int mwns_num_variants_for(int k) { return k > KNARROW ? num_wide_variants() : (k >= 1 ? NVARIANTS : 0); }
+
 extern "C" mwns_status mwns_variant_shape(int v, int* waves, int* prefetch, int* waves_per_simd, int* terms_per_pass) {
     MWNS_GUARD_BEGIN
     if (v < 0 || v >= NVARIANTS || !waves || !prefetch || !waves_per_simd || !terms_per_pass)
@@ -928,8 +930,7 @@ extern "C" mwns_status mwns_ctx_set_variant(mwns_ctx* ctx, int k, int variant) {
     MWNS_GUARD_BEGIN
     if (!ctx) fail(MWNS_EINVAL, "ctx is NULL");
     if (k < 1 || k > KMAX) fail(MWNS_EINVAL, "k out of range");
-    if (variant < -1 || variant >= NVARIANTS) fail(MWNS_EINVAL, "variant out of range");
-    if (k > KNARROW && variant > 0) fail(MWNS_EINVAL, "orders above 8 have a single tile shape (variant 0)");
+    if (variant < -1 || variant >= (k > KNARROW ? num_wide_variants() : NVARIANTS)) fail(MWNS_EINVAL, "variant out of range");
     ctx->variant[k] = variant;
     return MWNS_OK;
     MWNS_GUARD_END

@@ -580,22 +580,24 @@ __device__ __forceinline__ void contract_brick_wide_f32(const LevelDesc* __restr
     }
 }
 
-template <int K, int PREC>
-__device__ __forceinline__ void wide_job(const LevelDesc* __restrict__ levels, int2 job, double* smem, int2* steps, int* nsteps) {
-    if (job.y & 1) contract_brick_wide<K, true, PREC>(levels, job, smem, steps, nsteps);
-    else if constexpr (PREC == PREC_F64) contract_brick_wide<K, false, PREC_F64>(levels, job, smem, steps, nsteps);
+// The FP32 class: the first-columns job (u3 < 16) or the last-columns job of one output brick.
+template <int K>
+__device__ __forceinline__ void wide_job_f32(const LevelDesc* __restrict__ levels, int2 job, double* smem, int2* steps,
+                                             int* nsteps) {
+    if (job.y & 1) contract_brick_wide<K, true, PREC_F32>(levels, job, smem, steps, nsteps);
     else contract_brick_wide_f32<K>(levels, job, smem, steps, nsteps);
 }
 
-// order[] entries are (level descriptor, 2 * brick + column part).  queues: as the one-tile kernel.
-template <int K, int PREC>
+// FP32 class: order[] entries are (level descriptor, 2 * brick + column part).  queues: as the
+// one-tile kernel.
+template <int K>
 __global__ void __launch_bounds__(WCT) __attribute__((amdgpu_waves_per_eu(3, 3)))
-ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
+ns_apply_wide_f32_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
     __shared__ double smem[Wide<K>::SMEM];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
-        wide_job<K, PREC>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        wide_job_f32<K>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
         return;
     }
     const int x0 = blockIdx.x % NXCD;
@@ -618,7 +620,348 @@ ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restric
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0) break;
-        wide_job<K, PREC>(levels, order[pos], smem, steps, &nsteps_s);
+        wide_job_f32<K>(levels, order[pos], smem, steps, &nsteps_s);
+    }
+}
+
+// ---------------------------------------------------------------- FP64 class, whole brick
+// One workgroup of four waves per output brick, two workgroups per CU (two waves per SIMD, so that
+// one hides the other's loads and barriers).  A plane of cells (fixed L1) runs in five rounds; in
+// round i wave w takes input slice v1 = w + 4i: every row (fixed L2) of the plane runs mode 3 over
+// its cells and then mode 2, and the slice's mode-2 result goes to LDS.  After a barrier, each
+// wave adds the round's four slices to its output rows u2 = w + 4q (q < 5) by one K step of mode 1,
+// accumulating straight into the output registers.  The input slice of the next item (slice, cell)
+// is loaded while the current one is computed.
+// LDS holds the term's super-blocks S_d^{L} for the job's box, staged with the coefficient c w_m
+// folded into mode 1, the fine-displacement mask applied, and zeros up to the padded extent
+// DP = 20 (so k = 9 needs no bounds tests in the loops), plus two buffers of four exchanged slices.
+// Tiles: 16 x 16 x 4 for rows and columns < 16, and the 4 x 4 x 4 four-block form for the rest:
+//   row tail (rows 16..19, columns < 16): blocks = column groups; A replicated over the blocks;
+//   column tail (rows < 16, columns 16..19): blocks = row groups; B replicated;
+//   corner (rows and columns 16..19): both replicated (every block computes the same result).
+// Lane (g, r) = (lane >> 4, lane & 15).  The K index of step s is 4g + s (s < 4) or 16 + g
+// (s = 4) in mode 3, where the slice is loaded as four consecutive doubles per lane, and 4s + g in
+// modes 2 and 1, where it is the row index of the previous mode's result registers (mode 1: the
+// slot of the exchanged slice).
+template <int K>
+struct BrickShape {
+    static constexpr int D = 2 * K;              // 18 or 20
+    static constexpr int DP = 20;                // padded extent of staged blocks and exchanged slices
+    static constexpr int BLK = DP * DP;
+    static constexpr int SM_S = 3 * NMAX * BLK;  // staged super-blocks [d][L - lo_d][v][u]
+    static constexpr int SM_X = 2 * 4 * BLK;     // exchange buffers [2][slot][u2][u3]
+    static constexpr int SMEM = SM_S + SM_X;
+    static_assert(D > 16 && D <= DP, "rows and columns 16..D-1 are the 4-row tails");
+    static_assert(SMEM * 8 + 1024 <= 80 * 1024, "two workgroups per CU");
+};
+
+__device__ inline double mfma4(double a, double b, double c) { return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0); }
+__device__ inline d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// Stages term m of job tp: for each mode d and L in [lo_d, hi_d], S_d^{L}[v][u] (u output, v input,
+// u = su*K + a, v = sv*K + b) = F^{2L+su-sv}_{ab} when that fine displacement lies in the job's mask,
+// else 0, and 0 for u or v >= 2K; block (d, L - lo_d) of Ss.  Mode 1 carries c w_m.
+template <int K>
+__device__ inline void brick_stage_mode(const double* __restrict__ Fm, int lo, int hi, int mlo, int mhi, double scale,
+                                        double* __restrict__ Sd) {
+    using B = BrickShape<K>;
+    const int tot = (hi - lo + 1) * B::BLK;
+    for (int e = threadIdx.x; e < tot; e += 256) {
+        const int blk = e / B::BLK;
+        const int rem = e - blk * B::BLK;
+        const int v = rem / B::DP, u = rem - v * B::DP;
+        double val = 0.0;
+        if (u < 2 * K && v < 2 * K) {
+            const int su = u >= K, sv = v >= K;
+            const int l = 2 * (lo + blk) + su - sv;
+            if (l >= mlo && l <= mhi) val = scale * Fm[(l + LF) * K * K + (u - su * K) * K + (v - sv * K)];
+        }
+        Sd[blk * B::BLK + v * B::DP + u] = val;
+    }
+}
+
+template <int K>
+__device__ inline void brick_stage(const LevelDesc& lv, const Tpl& tp, int m, double* __restrict__ Ss) {
+    using B = BrickShape<K>;
+    const double* Fm = lv.Fj + (int64_t)m * NLF * K * K;
+    const double cw = tp.dpart ? -lv.w[m] : lv.w[m];
+    brick_stage_mode<K>(Fm, tp.lo[0], tp.hi[0], tp.mlo[0], tp.mhi[0], cw, Ss);
+    brick_stage_mode<K>(Fm, tp.lo[1], tp.hi[1], tp.mlo[1], tp.mhi[1], 1.0, Ss + NMAX * B::BLK);
+    brick_stage_mode<K>(Fm, tp.lo[2], tp.hi[2], tp.mlo[2], tp.mhi[2], 1.0, Ss + 2 * NMAX * B::BLK);
+}
+
+// Lane constants of the input-slice loads: byte offsets within slice 0 of X[v1][v2][v3] of lane
+// (g, r)'s four consecutive doubles of row r (of) and of tail row 16 + (r & 3) (ot), from column
+// 4g, and of its single doubles in column 16 + g (of4, ot4); entries outside the brick get an
+// offset past the buffer's record size, which reads as zero.
+struct SliceOffsets {
+    uint32_t of, ot, of4, ot4;
+};
+template <int D>
+__device__ inline SliceOffsets slice_offsets(int g, int r) {
+    const uint32_t BAD = 0x40000000u;
+    const int rt = 16 + (r & 3);
+    SliceOffsets o;
+    o.of = (uint32_t)((r * D + 4 * g) * 8);
+    o.ot = rt < D ? (uint32_t)((rt * D + 4 * g) * 8) : BAD;
+    o.of4 = 16 + g < D ? (uint32_t)((r * D + 16 + g) * 8) : BAD;
+    o.ot4 = rt < D && 16 + g < D ? (uint32_t)((rt * D + 16 + g) * 8) : BAD;
+    return o;
+}
+
+// The ten doubles of lane (g, r) of input slice v1 of brick X: xf[s] = X[v1][r][v3] (rows < 16),
+// xt[s] = X[v1][16 + (r & 3)][v3] (the tail rows, the same in every block), v3 = 4g + s or 16 + g.
+template <int D>
+__device__ inline void brick_slice_load(const double* __restrict__ X, int v1, const SliceOffsets& o, double (&xf)[5],
+                                        double (&xt)[5]) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, D * D * D * 8, 0x00020000);
+    const int so = v1 * D * D * 8;
+    const dv2 a0 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, o.of, so, 0));
+    const dv2 a1 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, o.of + 16, so, 0));
+    const dv2 b0 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, o.ot, so, 0));
+    const dv2 b1 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(rs, o.ot + 16, so, 0));
+    xf[0] = a0.x; xf[1] = a0.y; xf[2] = a1.x; xf[3] = a1.y;
+    xt[0] = b0.x; xt[1] = b0.y; xt[2] = b1.x; xt[3] = b1.y;
+    xf[4] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, o.of4, so, 0));
+    xt[4] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, o.ot4, so, 0));
+}
+
+// One job of the FP64 class for one output brick (see above); Y accumulates over the jobs.
+// PF = 1 loads the input slice of the next item while the current one is computed, PF = 0 each
+// slice when it is needed.  Down-band jobs whose brick has leaf children run mode 1 in two passes,
+// one per half u1 < K, u1 >= K, each with the output columns of leaf children masked out of the
+// exchanged slices.
+template <int K, int PF>
+__device__ __forceinline__ void brick_job(const LevelDesc& lv, const Tpl& tp, int ns, const int2* __restrict__ steps,
+                                          double* __restrict__ smem, int wave, int g, int r, int cmb,
+                                          d4 (&Yf)[5], double (&Yr)[5], double (&Yc)[5], double (&Yx)[5]) {
+    using B = BrickShape<K>;
+    constexpr int D = B::D, DP = B::DP, BLK = B::BLK;
+    constexpr int64_t E = (int64_t)D * D * D;
+    double* Ss = smem;
+    double* XB = smem + B::SM_S;
+    const int rt = 16 + (r & 3);
+    const int nsl = (D - wave + 3) / 4;      // rounds with a slice for this wave (5; 4 for waves 2, 3 at k = 9)
+    const bool split = tp.dpart && cmb != 0xff;
+    const SliceOffsets so = slice_offsets<D>(g, r);
+    // the step list in registers, lane c holding step c (read back with readlane, no LDS wait)
+    const int lane = threadIdx.x & 63;
+    const int2 stl = lane < ns ? steps[lane] : make_int2(0, 0);
+    auto sx = [&](int c) { return __builtin_amdgcn_readlane(stl.x, c); };
+    auto sy = [&](int c) { return __builtin_amdgcn_readlane(stl.y, c); };
+    auto xload = [&](int c, int i, double (&xf)[5], double (&xt)[5]) {
+        const int idx = sx(c);
+        const double* X = idx < lv.nreal ? lv.Xr + (int64_t)idx * E : lv.Xg + (int64_t)(idx - lv.nreal) * E;
+        brick_slice_load<D>(X, wave + 4 * i, so, xf, xt);
+    };
+    double nf[5], nt[5];
+    if (PF) xload(0, 0, nf, nt);      // the job's first item
+    int buf = 0;
+    for (int m = tp.m1; m <= tp.m2; ++m) {
+        if (m > tp.m1) wlds_barrier();      // the previous term's readers are done
+        brick_stage<K>(lv, tp, m, Ss);
+        wlds_barrier();
+        for (int p0 = 0; p0 < ns;) {
+            const int q1 = sy(p0) >> 4;
+            int p1 = p0 + 1;
+            while (p1 < ns && (sy(p1) >> 4) == q1) ++p1;
+            const double* S1 = Ss + q1 * BLK;
+            for (int i = 0; i < 5; ++i) {
+                double* xo = XB + (buf * 4 + wave) * BLK;
+                if (i < nsl) {
+                    d4 T2f = (d4){0.0, 0.0, 0.0, 0.0};
+                    double T2r = 0.0, T2c = 0.0, T2x = 0.0;
+                    for (int r0 = p0; r0 < p1;) {
+                        const int q12 = sy(r0) >> 2;
+                        int r1 = r0 + 1;
+                        while (r1 < p1 && (sy(r1) >> 2) == q12) ++r1;
+                        d4 T1f = (d4){0.0, 0.0, 0.0, 0.0};
+                        double T1r = 0.0, T1c = 0.0, T1x = 0.0;
+                        for (int c = r0; c < r1; ++c) {
+                            double xf[5], xt[5];
+                            if (PF) {
+#pragma unroll
+                                for (int s = 0; s < 5; ++s) {
+                                    xf[s] = nf[s];
+                                    xt[s] = nt[s];
+                                }
+                                // the next item: the next cell of the plane, else the plane's first
+                                // cell for the next round, else the next plane, else the first item
+                                // again (the next term's, or an unused load after the last)
+                                int cn = c + 1, in = i;
+                                if (cn == p1) {
+                                    if (i + 1 < nsl) {
+                                        cn = p0;
+                                        in = i + 1;
+                                    } else {
+                                        cn = p1 < ns ? p1 : 0;
+                                        in = 0;
+                                    }
+                                }
+                                xload(cn, in, nf, nt);
+                            } else {
+                                xload(c, i, xf, xt);
+                            }
+                            // mode 3: T1 += X x_3 S3 (B operands S3[u3][v3])
+                            const double* S3 = Ss + (2 * NMAX + (sy(c) & 3)) * BLK;
+#pragma unroll
+                            for (int s = 0; s < 5; ++s) {
+                                const int v3 = s < 4 ? 4 * g + s : 16 + g;
+                                const double bs = S3[v3 * DP + r];
+                                const double bt = S3[v3 * DP + rt];
+                                T1f = mfma16(xf[s], bs, T1f);
+                                T1r = mfma4(xt[s], bs, T1r);
+                                T1c = mfma4(xf[s], bt, T1c);
+                                T1x = mfma4(xt[s], bt, T1x);
+                            }
+                        }
+                        // mode 2 at the end of the row: T2 += S2 x_2 T1 (A operands S2[u2][v2])
+                        const double* S2 = Ss + (NMAX + (q12 & 3)) * BLK;
+#pragma unroll
+                        for (int s = 0; s < 5; ++s) {
+                            const int v2 = 4 * s + g;
+                            // rows 4s..4s+3 of T1, columns 16..19, sit in block s of the column tail
+                            const double b1 = s < 4 ? T1f[s] : T1r;
+                            const double bc = s < 4 ? __shfl(T1c, 16 * g + 4 * s + (r & 3)) : T1x;
+                            const double as = S2[v2 * DP + r];
+                            const double ar = S2[v2 * DP + rt];
+                            T2f = mfma16(as, b1, T2f);
+                            T2r = mfma4(ar, b1, T2r);
+                            T2c = mfma4(as, bc, T2c);
+                            T2x = mfma4(ar, bc, T2x);
+                        }
+                        r0 = r1;
+                    }
+                    // the slice's mode-2 result to its slot, [u2][u3]
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; ++c4) xo[(4 * c4 + g) * DP + r] = T2f[c4];
+                    xo[(16 + g) * DP + r] = T2r;
+                    xo[(4 * (r >> 2) + g) * DP + rt] = T2c;
+                    xo[(16 + g) * DP + rt] = T2x;      // the same value from every block
+                } else {
+                    for (int e = lane; e < BLK; e += 64) xo[e] = 0.0;
+                }
+                wlds_barrier();
+                // mode 1, K step i: Y += c w_m S1 x_1 T2 over the round's slices v1 = 4i + slot
+                const double* xs = XB + buf * 4 * BLK + g * BLK;
+                const double af = S1[(4 * i + g) * DP + r];
+                const double ar = S1[(4 * i + g) * DP + rt];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const int u2 = wave + 4 * q;
+                    if (u2 >= D) continue;
+                    const double bf = xs[u2 * DP + r];
+                    const double bt = xs[u2 * DP + rt];
+                    if (!split) {
+                        Yf[q] = mfma16(af, bf, Yf[q]);
+                        Yr[q] = mfma4(ar, bf, Yr[q]);
+                        Yc[q] = mfma4(af, bt, Yc[q]);
+                        Yx[q] = mfma4(ar, bt, Yx[q]);
+                        continue;
+                    }
+                    // child of output (u1, u2, u3) = (u1 >= K) + 2 (u2 >= K) + 4 (u3 >= K); u3 = rt >= K
+                    const int c2 = 2 * (u2 >= K);
+                    const int cf = c2 + 4 * (r >= K);
+                    const double a0 = r < K ? af : 0.0;
+                    const double a1 = r < K ? 0.0 : af;
+                    Yf[q] = mfma16(a0, (cmb >> cf) & 1 ? bf : 0.0, Yf[q]);
+                    Yc[q] = mfma4(a0, (cmb >> (c2 + 4)) & 1 ? bt : 0.0, Yc[q]);
+                    const double bf1 = (cmb >> (1 + cf)) & 1 ? bf : 0.0;
+                    const double bt1 = (cmb >> (1 + c2 + 4)) & 1 ? bt : 0.0;
+                    Yf[q] = mfma16(a1, bf1, Yf[q]);
+                    Yc[q] = mfma4(a1, bt1, Yc[q]);
+                    Yr[q] = mfma4(ar, bf1, Yr[q]);
+                    Yx[q] = mfma4(ar, bt1, Yx[q]);
+                }
+                buf ^= 1;
+            }
+            p0 = p1;
+        }
+    }
+}
+
+// Every FP64 job of one output brick, then the brick written (zero for children the level does
+// not hold, i.e. the siblings of the root).
+template <int K, int PF>
+__device__ __forceinline__ void brick_contract(const LevelDesc* __restrict__ levels, int2 job, double* smem, int2* steps,
+                                               int* nsteps) {
+    using B = BrickShape<K>;
+    constexpr int D = B::D;
+    constexpr int64_t E = (int64_t)D * D * D;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const LevelDesc lv = levels[job.x];
+    const int64_t b = job.y;
+    const int Lr = lv.Lr;
+    const int NL = 2 * Lr + 1;
+    const int32_t* nb = lv.nbr + b * NL * NL * NL;
+    const int cmb = lv.cmask[b];
+    d4 Yf[5];
+    double Yr[5], Yc[5], Yx[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        Yf[i] = (d4){0.0, 0.0, 0.0, 0.0};
+        Yr[i] = Yc[i] = Yx[i] = 0.0;
+    }
+    for (int ti = 0; ti < lv.ntpl; ++ti) {
+        const Tpl tp = lv.tpl[ti];
+        if (tp.prec != PREC_F64) continue;      // another class's launch runs this job
+        if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
+        const int ns = wide_steps(tp, nb, Lr, steps, nsteps);
+        if (ns == 0) continue;
+        brick_job<K, PF>(lv, tp, ns, steps, smem, wave, g, r, cmb, Yf, Yr, Yc, Yx);
+    }
+    double* ob = lv.out + b * E;
+    const int rt = 16 + (r & 3);
+    auto put = [&](int u1, int u2, int u3, double v) {
+        const int child = (u1 >= K) + 2 * (u2 >= K) + 4 * (u3 >= K);
+        ob[((int64_t)u1 * D + u2) * D + u3] = ((lv.valid >> child) & 1) ? v : 0.0;
+    };
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int u2 = wave + 4 * i;
+        if (u2 >= D) continue;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) put(4 * c4 + g, u2, r, Yf[i][c4]);
+        if (16 + g < D) put(16 + g, u2, r, Yr[i]);
+        if (rt < D) put(4 * (r >> 2) + g, u2, rt, Yc[i]);
+        if (16 + g < D && rt < D && (r >> 2) == 0) put(16 + g, u2, rt, Yx[i]);
+    }
+}
+
+// order[] entries are (level descriptor, brick).  queues: as the one-tile kernel.
+template <int K, int PF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
+    __shared__ double smem[BrickShape<K>::SMEM];
+    __shared__ int2 steps[NMAX * NMAX * NMAX];
+    __shared__ int nsteps_s, pos_s;
+    if (!queues) {
+        brick_contract<K, PF>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        return;
+    }
+    const int x0 = blockIdx.x % NXCD;
+    int tried = 0;   // meaningful in thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int pos = -1;
+            while (tried < NXCD) {
+                const int q = (x0 + tried) % NXCD;
+                const int i = atomicAdd(&queues[q], 1);
+                if (queues[NXCD + q] + i < queues[2 * NXCD + q]) {
+                    pos = queues[NXCD + q] + i;
+                    break;
+                }
+                ++tried;
+            }
+            pos_s = pos;
+        }
+        __syncthreads();
+        const int pos = pos_s;
+        __syncthreads();
+        if (pos < 0) break;
+        brick_contract<K, PF>(levels, order[pos], smem, steps, &nsteps_s);
     }
 }
 
@@ -628,43 +971,52 @@ __global__ void convert_wide_kernel(int64_t n, const double* __restrict__ X, flo
     if (i < n) out[i] = (float)X[i];
 }
 
-template <int K, int PREC>
-void launch_wide_k(hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
-    ns_apply_wide_kernel<K, PREC><<<(unsigned)nblocks, WCT, 0, st>>>(levels, order, queues);
+// Variants of the FP64 kernel: 0 loads the next item's input slice while computing the current one
+// (default), 1 loads each slice when it is needed.
+constexpr int WIDE_VARIANTS = 2;
+constexpr int wide_prefetch(int variant) { return variant == 1 ? 0 : 1; }
+
+template <int K>
+void launch_wide_k(int variant, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
+                   int* queues) {
+    if (prec == PREC_F32) ns_apply_wide_f32_kernel<K><<<(unsigned)nblocks, WCT, 0, st>>>(levels, order, queues);
+    else if (wide_prefetch(variant)) ns_apply_wide_kernel<K, 1><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
+    else ns_apply_wide_kernel<K, 0><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
 }
 
-template <int K, int PREC>
-int64_t resident_wide_k(int device) {
+template <int K>
+int64_t resident_wide_k(int variant, int prec, int device) {
     int per_cu = 0, ncu = 0;
-    MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_wide_kernel<K, PREC>, WCT, 0));
+    if (prec == PREC_F32)
+        MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_wide_f32_kernel<K>, WCT, 0));
+    else if (wide_prefetch(variant))
+        MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_wide_kernel<K, 1>, 256, 0));
+    else
+        MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns_apply_wide_kernel<K, 0>, 256, 0));
     MWNS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     return (int64_t)std::max(1, per_cu) * ncu;
 }
 
 void check_wide(int k, int prec) {
-    if (k != 9 && k != 10) fail(MWNS_EINVAL, "the two-tile contraction kernel takes 8 < k <= 10");
-    if (prec != PREC_F64 && prec != PREC_F32) fail(MWNS_EINVAL, "the two-tile contraction kernel has the FP64 and FP32 classes");
+    if (k != 9 && k != 10) fail(MWNS_EINVAL, "the two-tile contraction kernels take 8 < k <= 10");
+    if (prec != PREC_F64 && prec != PREC_F32) fail(MWNS_EINVAL, "the two-tile contraction kernels have the FP64 and FP32 classes");
 }
 
 }  // namespace
 
-void launch_contract_wide(int k, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order,
-                          int* queues) {
+int num_wide_variants() { return WIDE_VARIANTS; }
+
+void launch_contract_wide(int k, int variant, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels,
+                          const int2* order, int* queues) {
     check_wide(k, prec);
     if (nblocks <= 0) return;
-    if (k == 9) {
-        if (prec == PREC_F64) launch_wide_k<9, PREC_F64>(st, nblocks, levels, order, queues);
-        else launch_wide_k<9, PREC_F32>(st, nblocks, levels, order, queues);
-    } else {
-        if (prec == PREC_F64) launch_wide_k<10, PREC_F64>(st, nblocks, levels, order, queues);
-        else launch_wide_k<10, PREC_F32>(st, nblocks, levels, order, queues);
-    }
+    if (k == 9) launch_wide_k<9>(variant, prec, st, nblocks, levels, order, queues);
+    else launch_wide_k<10>(variant, prec, st, nblocks, levels, order, queues);
 }
 
-int64_t resident_blocks_wide(int k, int prec, int device) {
+int64_t resident_blocks_wide(int k, int variant, int prec, int device) {
     check_wide(k, prec);
-    if (k == 9) return prec == PREC_F64 ? resident_wide_k<9, PREC_F64>(device) : resident_wide_k<9, PREC_F32>(device);
-    return prec == PREC_F64 ? resident_wide_k<10, PREC_F64>(device) : resident_wide_k<10, PREC_F32>(device);
+    return k == 9 ? resident_wide_k<9>(variant, prec, device) : resident_wide_k<10>(variant, prec, device);
 }
 
 void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out) {

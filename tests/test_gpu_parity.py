@@ -71,13 +71,16 @@ def test_operator_tables_and_plan(M, ctx, case):
 
 def test_operator_plan_many_terms(M, ctx):
     """157 Gaussian terms (Poisson, eps = 1e-8): the plan kernel sums the terms' estimates in
-    chunks of 64, so the prefix and suffix scans cross chunk boundaries."""
+    chunks of 64, so the prefix and suffix scans cross chunk boundaries.  At k = 6 this eps keeps
+    terms at the edge of the band; built with the overflow allowed on both sides, the edge ranges
+    are compared too."""
     from oracle import apply as A, fit
     eps, depth = 1e-8, 4
     tau, wt = fit.fit_kernel(0.0, 1.0, eps, math.sqrt(eps) * 2.0 ** -depth, math.sqrt(3))
     assert len(tau) > 128
-    op = M.mwns_op_create(ctx, 6, tau, wt, eps, depth)
-    oo = A.Operator(6, tau, wt, eps, depth)
+    op = M.mwns_op_create(ctx, 6, tau, wt, eps, depth, allow_band_overflow=1)
+    oo = A.Operator(6, tau, wt, eps, depth, allow_overflow=True)
+    assert np.any(oo.R[1:, 0, :, :, 1] >= oo.R[1:, 0, :, :, 0])
     F = M.mwns_op_tables_export(ctx, op)
     scale = np.abs(oo.F[:, :, 7]).max(axis=(2, 3))
     assert (np.abs(F - oo.F).max(axis=(2, 3, 4)) / scale).max() < 1e-13
