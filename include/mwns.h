@@ -320,6 +320,23 @@ void mwns_plan_destroy(mwns_plan* plan);
  * EDEVICE. */
 mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out);
 
+/* mwns_tree_eval for callers that cannot allocate memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation: it calls no allocator (neither hipMalloc nor the
+ * context's), copies nothing between host and device and does not synchronise.  Its working memory
+ * (the tree's child-brick table and a counter) is one fixed array of 16.02 MiB in device memory that
+ * every GPU the library runs on holds until the process ends; its address is looked up when a context
+ * is created on that GPU.
+ *   xyz   DEVICE pointer, npts x 3 doubles (caller-owned, readable on the context's stream).
+ *   out   DEVICE pointer, npts doubles (caller-owned); written on the context's stream.  A point outside
+ *         [0,1]^3 (or NaN) and a point whose leaf is missing get NaN (no error is reported: the call does
+ *         not wait for the device).
+ *   The tree may have at most 4194304 nodes.
+ * Every call on one GPU uses that GPU's one array, which keeps the contents of the last call: calls
+ * that may overlap on one GPU (several streams or host threads) race and must be serialised by the
+ * caller.  Errors: EINVAL (NULL pointers, npts < 0, tree of another context), ERANGE (more nodes than
+ * the array holds), ESTATE (no array address for the device), EDEVICE (launch failure). */
+mwns_status mwns_tree_eval_noalloc(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -388,3 +388,10 @@ def mwns_tree_eval(ctx, tree, pts):
     check(lib.mwns_tree_eval(ctx.h, tree.h, pts.shape[0], pts.ctypes.data, out.ctypes.data), "mwns_tree_eval")
     return out
 
+
+def mwns_tree_eval_noalloc(ctx, tree, npts, xyz_dev, out_dev):
+    """Values of tree at npts points on the device: xyz_dev and out_dev are device addresses (ints,
+    e.g. torch tensors' data_ptr()) of npts x 3 and npts doubles; nothing is allocated, copied or
+    waited for (the values are ready when the context's stream passes the call)."""
+    check(lib.mwns_tree_eval_noalloc(ctx.h, tree.h, int(npts), ctypes.c_void_p(int(xyz_dev)), ctypes.c_void_p(int(out_dev))),
+          "mwns_tree_eval_noalloc")

@@ -90,6 +90,7 @@ SIGNATURES = {
     "mwns_tree_set_leaves": (c_int, [c_vp, c_vp, c_vp]),
     "mwns_tune_apply": (c_int, [c_vp, c_vp, c_vp, c_int, P(c_int), c_vp]),
     "mwns_tree_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "mwns_tree_eval_noalloc": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

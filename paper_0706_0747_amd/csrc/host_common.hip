@@ -239,6 +239,7 @@ mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_
     MWNS_HIP(hipGetDeviceProperties(&prop, device));
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         fail(MWNS_EDEVICE, std::string("libmwns is built for gfx950, device is ") + prop.gcnArchName);
+    noalloc_scratch_init(device);
     auto* c = new mwns_ctx;
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);

@@ -124,6 +124,9 @@ void release_cache(mwns_ctx* ctx);
 // A pinned host block of at least `bytes` for the copies of one host round trip; the caller
 // synchronises the stream before the next call (growing the block waits for the stream).
 void* pinned_staging(mwns_ctx* ctx, size_t bytes);
+// Looks up this GPU's device address of the fixed scratch array of mwns_tree_eval_noalloc (once
+// per device; called by mwns_ctx_create with the device current).
+void noalloc_scratch_init(int device);
 // Drops one reference to ctx; the last one returns the cached blocks and frees the context.
 void ctx_release(mwns_ctx* ctx);
 // A tree, operator or plan keeps its context alive: declared as the object's first member, it is

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "mwns_internal.h"
@@ -325,6 +326,11 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const double x[3] = {xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]};
+    if (!(x[0] >= 0.0 && x[0] <= 1.0 && x[1] >= 0.0 && x[1] <= 1.0 && x[2] >= 0.0 && x[2] <= 1.0)) {
+        atomicAdd(bad, 1);      // outside the cube (or NaN): no value
+        out[p] = __builtin_nan("");
+        return;
+    }
     // Walk down from the root: the child of a node that holds the point is the one whose parity
     // bits at the next level are those of floor(2^{j+1} x) (clamped to the cube).
     int64_t node = 0;
@@ -382,7 +388,7 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
         return;
     }
     atomicAdd(bad, 1);
-    out[p] = 0.0;
+    out[p] = __builtin_nan("");
 }
 
 template <template <int> class Fn, class... Args>
@@ -443,7 +449,100 @@ LevelTab level_tab(const mwns_tree* t) {
     return lt;
 }
 
+// ------------------------------------------------- evaluation without allocation
+// mwns_tree_eval_noalloc keeps its working memory -- the child-brick table of the tree, the
+// per-group offsets of the scan that builds it, and the count of points without a value -- in
+// one fixed array in device memory, which every GPU the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel: it is a host-side stand-in; the
+// device address of each GPU's copy is looked up once when a context is created on that GPU.
+constexpr int64_t NOALLOC_MAX_NODES = (int64_t)1 << 22;     // largest tree the entry point takes
+constexpr int SCAN_BLOCK = 1024;                            // nodes per scan group (one block)
+constexpr int64_t SCAN_GROUPS = NOALLOC_MAX_NODES / SCAN_BLOCK;
+// int32 layout: child table [MAX_NODES] | group offsets [SCAN_GROUPS] | counter (+ padding)
+constexpr int64_t SCRATCH_INTS = NOALLOC_MAX_NODES + SCAN_GROUPS + 64;
+static __device__ __align__(256) int32_t scratch[SCRATCH_INTS];
+
+// Internal nodes among nodes [1024 g, 1024 g + 1024) into group[g].
+__global__ void __launch_bounds__(SCAN_BLOCK) internal_count_kernel(int64_t n, const uint8_t* __restrict__ leaf,
+                                                                    int32_t* __restrict__ group) {
+    __shared__ int wsum[SCAN_BLOCK / 64];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    const unsigned long long b = __ballot(i < n && !leaf[i]);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < SCAN_BLOCK / 64; ++w) s += wsum[w];
+        group[blockIdx.x] = s;
+    }
+}
+
+// Exclusive prefix sums of group[0..ngroups) in place (one block; ngroups <= 4 * 1024), and the
+// counter of points without a value set to zero.
+__global__ void __launch_bounds__(1024) group_scan_kernel(int ngroups, int32_t* __restrict__ group,
+                                                          int32_t* __restrict__ counter) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (ngroups + 1023) / 1024;
+    int loc[SCAN_GROUPS / 1024];
+    int s = 0;
+    for (int q = 0; q < per; ++q) {
+        const int g = t * per + q;
+        loc[q] = g < ngroups ? group[g] : 0;
+        s += loc[q];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int q = 0; q < per; ++q) {
+        const int g = t * per + q;
+        if (g < ngroups) {
+            group[g] = run;
+            run += loc[q];
+        }
+    }
+    if (t == 0) *counter = 0;
+}
+
+// child[i] = brick of the children of node i (1 + the number of internal nodes before i: the
+// bricks of a tree follow its internal nodes in canonical order, brick 0 holding the root), or -1
+// for a leaf.
+__global__ void __launch_bounds__(SCAN_BLOCK) child_table_kernel(int64_t n, const uint8_t* __restrict__ leaf,
+                                                                 const int32_t* __restrict__ group,
+                                                                 int32_t* __restrict__ child) {
+    __shared__ int wsum[SCAN_BLOCK / 64];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    const bool internal = i < n && !leaf[i];
+    const unsigned long long b = __ballot(internal);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = __popcll(b);
+    __syncthreads();
+    int before = group[blockIdx.x];
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    before += __popcll(b & ((1ull << lane) - 1ull));
+    if (i < n) child[i] = internal ? 1 + before : -1;
+}
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[64] = {};
+
 }  // namespace
+
+// Device address of this GPU's copy of the evaluation scratch array; called by mwns_ctx_create
+// with the context's device current.
+void noalloc_scratch_init(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (device < 0 || device >= 64 || g_scratch_ptr[device]) return;
+    void* p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress of the evaluation scratch array");
+    g_scratch_ptr[device] = p;
+}
 
 // Levels, node offsets and bricks from sorted keys and leaf flags.  Every internal node must have
 // its 8 children and every non-root node a parent.
@@ -882,9 +981,33 @@ mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, cons
     MWNS_HIP(hipMemcpyAsync(pout, dout.p, b_o, hipMemcpyDeviceToHost, st));
     MWNS_HIP(hipMemcpyAsync(pbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, st));
     MWNS_HIP(hipStreamSynchronize(st));
+    if (*pbad) fail(MWNS_ESTATE, "points without a leaf: the tree does not cover the cube");
     std::memcpy(out, pout, b_o);
-    const int bad = *pbad;
-    if (bad) fail(MWNS_ESTATE, "points without a leaf: the tree does not cover the cube");
+    return MWNS_OK;
+    MWNS_GUARD_END
+}
+
+mwns_status mwns_tree_eval_noalloc(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !t || npts < 0 || (npts && (!xyz || !out))) fail(MWNS_EINVAL, "NULL argument or npts < 0");
+    if (t->ctx != ctx) fail(MWNS_EINVAL, "tree belongs to another context");
+    if (t->nnodes > NOALLOC_MAX_NODES)
+        fail(MWNS_ERANGE, "tree has " + std::to_string(t->nnodes) + " nodes; the allocation-free evaluation takes at most " +
+                              std::to_string(NOALLOC_MAX_NODES));
+    int32_t* base = (ctx->device >= 0 && ctx->device < 64) ? static_cast<int32_t*>(g_scratch_ptr[ctx->device]) : nullptr;
+    if (!base) fail(MWNS_ESTATE, "no evaluation scratch address for this device");
+    if (npts == 0) return MWNS_OK;
+    hipStream_t st = ctx->stream;
+    int32_t* child = base;
+    int32_t* group = base + NOALLOC_MAX_NODES;
+    int32_t* counter = group + SCAN_GROUPS;
+    const int ng = (int)((t->nnodes + SCAN_BLOCK - 1) / SCAN_BLOCK);
+    internal_count_kernel<<<ng, SCAN_BLOCK, 0, st>>>(t->nnodes, t->dleaf.p, group);
+    group_scan_kernel<<<1, 1024, 0, st>>>(ng, group, counter);
+    child_table_kernel<<<ng, SCAN_BLOCK, 0, st>>>(t->nnodes, t->dleaf.p, group, child);
+    const LevelTab lt = level_tab(t);
+    dispatch_k<EvalLaunch>(t->k, st, npts, xyz, child, t->dleaf.p, lt, t->coef.p, out, counter);
+    MWNS_HIP(hipGetLastError());
     return MWNS_OK;
     MWNS_GUARD_END
 }

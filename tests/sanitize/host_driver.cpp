@@ -8,6 +8,10 @@
 
 #include "../../paper_0706_0747_amd/csrc/mwns_internal.h"
 
+// Context creation (host_common) looks up the allocation-free evaluation's array, which lives
+// with the tree kernels; this driver creates no context, so the lookup is never reached.
+void mwns::noalloc_scratch_init(int) {}
+
 int main() {
     int bad = 0;
     std::vector<double> tau(2000), w(2000);
