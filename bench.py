@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-vs-FP64 measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the c2/c3 extra workloads")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-apply measurement")
-    ap.add_argument("--cpu-sample-nodes", type=int, default=1200)
+    ap.add_argument("--cpu-sample-nodes", type=int, default=3000)
     ap.add_argument("--variant", type=int, default=-1, help="contraction-kernel tile variant (-1: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")

@@ -25,8 +25,9 @@
  *    context per host thread.
  *  - Orders and sizes: 1 <= k <= 10 (basis order = number of Legendre polynomials per dimension;
  *    k <= 8 runs on the one-tile contraction kernel with every precision class and tile variant,
- *    9 <= k <= 10 on the two-tile kernel with the FP64 and FP32 classes: there a routed apply
- *    uses MWNS_CLASS_F32 if allowed and ignores the BF16 bits);
+ *    9 <= k <= 10 on the whole-brick kernel with the FP64 and FP32 classes, whose FP32 class runs
+ *    the 4-row tails of the 2k = 16 + 4 split in FP64: there a routed apply uses MWNS_CLASS_F32 if
+ *    allowed and ignores the BF16 bits);
  *    tree levels 0..19.  Coefficient blocks are [a][b][c] with a the x degree, b the y degree and
  *    c the z degree (c fastest).  Keys are level << 57 | morton(lx, ly, lz) with the x bit lowest
  *    in each bit triple; a tree's canonical node order is ascending key.
@@ -94,8 +95,10 @@ const char* mwns_last_error(void);
  * [0, mwns_num_variants_for(k)), or -1 for the library's default.  For k <= 8 (the one-tile kernel,
  * mwns_num_variants() shapes, mwns_variant_shape) the default is the shape with two terms per pass
  * and a prefetched input slice for 6 <= k <= 8, variant 0 below; for k = 9, 10 (one workgroup of four
- * waves per sibling group) variant 0, the default, loads the next input slice while computing the
- * current one and variant 1 loads each when it is needed (the two agree bit for bit).  Variants
+ * waves per sibling group, or two such groups on alternate terms) variant 0, the default, is one
+ * group per workgroup loading the next input slice while computing the current one, variant 1 two
+ * groups per workgroup (their sums are added at the end, so it agrees with variant 0 up to
+ * rounding), variant 2 as 0 loading each slice when it is needed (bit for bit as 0).  Variants
  * differ in speed only: those with one term per pass compute the same result bit for bit; those
  * with several terms per pass add the plane results of consecutive terms in another order, so they
  * agree with the others up to rounding.  mwns_tune_apply picks one by timing.

@@ -454,7 +454,8 @@ __global__ void fill_kernel(double* p, int64_t n, double v) {
 // Rounding-error factors of the classes: a three-mode chain whose every mode has relative
 // operand errors a (matrix) and b (input) and an FP32 accumulation over at most n = max(16, 2k)
 // * NMAX products computes (|S1| (x) |S2| (x) |S3|) |X| up to the factor ((1 + a + b + n u32)^3 - 1).
-// (The FP32 class of the two-tile kernel runs its 4-row tails in FP64, which the factor covers.)
+// (The FP32 class of the whole-brick kernel, orders above KNARROW, runs its 4-row tails in FP64 and
+// adds each K step of mode 1 in FP64, which the factor covers.)
 constexpr double U32 = 0x1p-24, UBF = 0x1p-8, USPLIT = 0x1p-16;
 constexpr double cube_minus_one(double d) { return (1.0 + d) * (1.0 + d) * (1.0 + d) - 1.0; }
 struct Gammas {
@@ -1025,7 +1026,7 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             }
         }
     }
-    // the two-tile kernel (orders above KNARROW) has the FP32 class only
+    // the whole-brick kernel (orders above KNARROW) has the FP32 class only
     a.err_bound = route(items, opts.tol, a.k > KNARROW ? (opts.classes & MWNS_CLASS_F32) : opts.classes, a.k);
     size_t pos = 0;
     for (int j = 0; j <= a.depth; ++j) {
@@ -1052,9 +1053,11 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
             need32 = need32 || t.prec == PREC_F32;
             needbf = needbf || t.prec == PREC_BF16C || t.prec == PREC_BF16;
         }
-        // 16-byte units per brick: padded rows for the one-tile kernel, D^3 floats for the two-tile one
+        // 16-byte units per brick of the one-tile kernel's copies (padded rows); the whole-brick
+        // kernel (orders above KNARROW) rounds its FP64 inputs to FP32 as they enter a product
         const int64_t D = 2 * a.k;
-        const int64_t units = a.k > KNARROW ? D * D * D / 4 : 4 * D * D;
+        const int64_t units = 4 * D * D;
+        if (a.k > KNARROW) need32 = needbf = false;
         if (need32) {
             lw.xr32.reset(ctx, (size_t)lw.nout * units);
             if (lw.nghost) lw.xg32.reset(ctx, (size_t)lw.nghost * units);
@@ -1073,11 +1076,6 @@ void launch_convert_inputs(mwns_ctx* ctx, TreeApply& a) {
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         const double* xr = a.f->coef.p + a.f->lev[j].brick_off * E;
-        if (a.k > KNARROW) {
-            if (lw.xr32.p) launch_convert_wide(a.k, ctx->stream, lw.nout, xr, reinterpret_cast<float*>(lw.xr32.p));
-            if (lw.xg32.p) launch_convert_wide(a.k, ctx->stream, lw.nghost, lw.ghosts.p, reinterpret_cast<float*>(lw.xg32.p));
-            continue;
-        }
         if (lw.xr32.p) tb.add(a.k, lw.nout, xr, lw.xr32.p, false);
         if (lw.xg32.p) tb.add(a.k, lw.nghost, lw.ghosts.p, lw.xg32.p, false);
         if (lw.xrb.p) tb.add(a.k, lw.nout, xr, lw.xrb.p, true);
@@ -1109,10 +1107,12 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
     // kernel (orders above KNARROW) per slice five 16x16x4 and fifteen 4x4x4 (512 flops) products
     // in modes 3 and 2, and the same per output row u2 in mode 1, except that mode 1 of a down-band
     // job at a brick with leaf children runs two passes: per row and K step two 16x16x4 and four
-    // 4x4x4 products instead of one and three
+    // 4x4x4 products instead of one and three.  Its FP32 class runs the 4x4x4 products (the tails)
+    // in FP64 and the 16x16x4 ones in FP32.
     const double D2 = 2.0 * k;
-    const double mfma_per_step = k > KNARROW ? (5.0 * 2048.0 + 15.0 * 512.0) * D2 : 4.0 * 2048.0 * D2;
-    const double mfma_mode1_split = 5.0 * (2.0 * 2048.0 + 4.0 * 512.0) * D2;
+    const double tile16 = k > KNARROW ? 5.0 * 2048.0 * D2 : 4.0 * 2048.0 * D2;
+    const double tails = k > KNARROW ? 15.0 * 512.0 * D2 : 0.0;
+    const double tile16_split = 5.0 * 2.0 * 2048.0 * D2, tails_split = 5.0 * 4.0 * 512.0 * D2;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
         LevelDesc d{};
@@ -1177,18 +1177,13 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
                 if (!nested[ti]) a.own_flops += fl;
-                if (t.prec == PREC_F64) {
+                if (t.prec == PREC_F64 || (k > KNARROW && t.prec == PREC_F32)) {
+                    const double f16 = t.prec == PREC_F64 ? 1.0 : 0.0;
                     if (k > KNARROW && t.dpart && lw.cm[b] != 0xff)
-                        a.mfma_flops += nt * (mfma_per_step * (steps - nin[0]) + mfma_mode1_split * nin[0]);
+                        a.mfma_flops += nt * ((f16 * tile16 + tails) * (steps - nin[0]) + (f16 * tile16_split + tails_split) * nin[0]);
                     else
-                        a.mfma_flops += nt * mfma_per_step * steps;
+                        a.mfma_flops += nt * (f16 * tile16 + tails) * steps;
                 }
-            }
-            if (k > KNARROW) {    // FP64: one workgroup per brick; FP32: one per column part of the brick
-                cost[PREC_F64].push_back({c[PREC_F64], make_int2(di, (int)b)});
-                if (c[PREC_F32] > 0.0)
-                    for (int half = 0; half < 2; ++half) cost[PREC_F32].push_back({c[PREC_F32], make_int2(di, (int)(2 * b + half))});
-                continue;
             }
             for (int p = 0; p < NPREC; ++p)
                 if (p == PREC_F64 || c[p] > 0.0) cost[p].push_back({c[p], make_int2(di, (int)b)});

@@ -17,9 +17,15 @@ struct Tpl {
     int prec;              // precision class of the job's terms (PREC_*)
 };
 
-// Entry d of a per-dimension triple, without indexing the array at run time (a private array
-// indexed with a run-time value is placed in scratch memory).
-__host__ __device__ inline int pick3(const int (&a)[3], int d) { return d == 0 ? a[0] : (d == 1 ? a[1] : a[2]); }
+// Entry d of a per-dimension triple of a job (the same in every lane), without indexing the array at
+// run time: a private array indexed with a run-time value is placed in scratch memory, and the
+// compiler turns a select between the entries back into such an index unless each entry is first
+// read into a register on its own.
+__device__ inline int pick3(const int (&a)[3], int d) {
+    const int a0 = __builtin_amdgcn_readfirstlane(a[0]), a1 = __builtin_amdgcn_readfirstlane(a[1]);
+    const int a2 = __builtin_amdgcn_readfirstlane(a[2]);
+    return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
 
 // Precision classes of a job.  Every class accumulates into the FP64 output; the reduced ones
 // take their inputs from FP32 or split-BF16 copies of the input bricks and accumulate each
@@ -32,8 +38,7 @@ constexpr int NMAX = 4;            // largest box extent per dimension of one jo
 struct LevelDesc {
     const double* Xr;        // real input bricks of the level (the level's own bricks)
     const double* Xg;        // ghost input bricks
-    const float* Xr32;       // FP32 copies (or null): rows padded to 16, [brick][v1][v2][16], for
-                             // k <= KNARROW; [brick][v1][v2][v3] for the two-tile kernel
+    const float* Xr32;       // FP32 copies (or null): rows padded to 16, [brick][v1][v2][16] (k <= KNARROW)
     const float* Xg32;
     const u4* Xrb;           // split-BF16 copies: [brick][v1][v2][4 groups] of (4 hi, 4 lo)  (or null)
     const u4* Xgb;
@@ -83,17 +88,15 @@ void launch_contract(int k, int variant, int prec, bool accumulate, hipStream_t 
                      const LevelDesc* levels, const int2* order, int* queues);
 // Workgroups of that kernel that fit on the device at once (for the persistent launch).
 int64_t resident_blocks(int k, int variant, int prec, int device);
-// The contraction kernels for KNARROW < k <= KMAX (2k = 18, 20: 16-wide tiles plus 4-row tails).
-// PREC_F64: one workgroup of four waves per output brick, order[] entries (level descriptor,
-// brick); variant 0 loads the next input slice ahead, variant 1 when it is needed.  PREC_F32 (adds to the output):
-// order[] entries (level descriptor, 2 * brick + column part), the columns u3 < 16 and the last
-// ones each a separate workgroup job.  queues as in launch_contract.
+// The whole-brick contraction kernel for KNARROW < k <= KMAX (2k = 18, 20: 16-wide tiles plus
+// 4-row tails), classes PREC_F64 and PREC_F32 (which adds to the output): one workgroup per output
+// brick, order[] entries (level descriptor, brick); variant 0 four waves loading the next input
+// slice ahead, 1 eight waves in two groups on alternate terms, 2 as 0 loading each slice when it is
+// needed.  queues as in launch_contract.
 int num_wide_variants();
 void launch_contract_wide(int k, int variant, int prec, hipStream_t st, int64_t nblocks, const LevelDesc* levels,
                           const int2* order, int* queues);
 int64_t resident_blocks_wide(int k, int variant, int prec, int device);
-// FP32 copies of nb input bricks for the two-tile kernel: [brick][v1][v2][v3], as the FP64 bricks.
-void launch_convert_wide(int k, hipStream_t st, int64_t nb, const double* X, float* out);
 // FP32 or split-BF16 copies of input bricks, 16-byte groups as the one-tile kernel reads them, for
 // several arrays in one launch: entry i converts nb[i] bricks X[i] into out[i] (split BF16 when
 // bf[i]); the launch gives entry i the 256-thread blocks [bstart[i], bstart[i + 1]).

@@ -87,6 +87,41 @@ def test_wide_full_plan_random_coefficients(M, ctx):
     assert np.linalg.norm(gg - g) <= 1e-12 * np.linalg.norm(g)
 
 
+@pytest.mark.parametrize("case", ["k10_poisson", "k9_yukawa"])
+def test_wide_variants_match_oracle(M, ctx, case):
+    """Every tile variant of the k = 9, 10 kernel (one term group with and without the slice
+    prefetch, two term groups) under the full plan on random leaf coefficients, so that every mask,
+    the down band at bricks with leaf children (two-pass mode 1) and odd term counts (the second
+    group idle for the last term) are exercised: each against the oracle within 1e-12; the
+    one-group variants bit for bit equal."""
+    from oracle import apply as A
+    from oracle import tree as T
+    w = CASES[case]()
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, 3, w.xyz, w.a, w.c)
+    rng = np.random.Generator(np.random.PCG64(52))
+    coef = rng.standard_normal(coef.shape)
+    ot = T.redundant_tree(w.k, keys, coef)
+    tau, wt = _fit(w, ot.depth)
+    tau, wt = tau[::9].copy(), wt[::9].copy()
+    R = A.full_plan(tau.size, ot.depth)
+    oo = A.Operator(w.k, tau, wt, w.eps, ot.depth, R=R)
+    gh = A.apply_modified(oo, ot)
+    f = M.mwns_tree_from_leaves(ctx, w.k, keys, coef)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
+    M.mwns_op_plan_import(op, R)
+    assert M.mwns_num_variants_for(w.k) == 3
+    out = []
+    try:
+        for v in range(3):
+            M.mwns_ctx_set_variant(ctx, w.k, v)
+            _, _, ghat = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)[0])
+            assert np.linalg.norm(ghat - gh) <= 1e-12 * np.linalg.norm(gh), "variant %d" % v
+            out.append(ghat)
+    finally:
+        M.mwns_ctx_set_variant(ctx, w.k, -1)
+    assert np.array_equal(out[0], out[2])
+
+
 def test_wide_in_batch_plan_and_routing(M, ctx):
     """k = 10 and k = 8 trees in one batch equal their single applies; the plan replays them; asked
     for the BF16 classes only, the routed apply keeps every k = 10 job in FP64 (bound 0, result
