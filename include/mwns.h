@@ -26,8 +26,8 @@
  *  - Orders and sizes: 1 <= k <= 10 (basis order = number of Legendre polynomials per dimension;
  *    k <= 8 runs on the one-tile contraction kernel with every precision class and tile variant,
  *    9 <= k <= 10 on the whole-brick kernel with the FP64 and FP32 classes, whose FP32 class runs
- *    the 4-row tails of the 2k = 16 + 4 split in FP64: there a routed apply uses MWNS_CLASS_F32 if
- *    allowed and ignores the BF16 bits);
+ *    the 4-row tails of the 2k = 16 + 4 split in FP64: there a routed apply takes MWNS_CLASS_F32
+ *    alone and rejects the BF16 bits with EINVAL);
  *    tree levels 0..19.  Coefficient blocks are [a][b][c] with a the x degree, b the y degree and
  *    c the z degree (c fastest).  Keys are level << 57 | morton(lx, ly, lz) with the x bit lowest
  *    in each bit triple; a tree's canonical node order is ascending key.
@@ -271,10 +271,14 @@ typedef struct {
  * prod_d || sum_{L_d in box} |S_d^{m,L_d}| ||_2) (S_d the masked 2k x 2k super-blocks, X_level
  * every input sibling group of the level), and a class with unit rounding factor gamma computes
  * it within gamma * beta; classes are chosen so
- * that the sum of gamma * beta is at most tol (stats->err_bound), minimising modelled time.  The
- * transforms, the interpolation, the assembly and the output accumulation stay FP64.  flags: 0,
- * MWNS_NO_ASSEMBLY, MWNS_TIMES_ONLY.  Errors: EINVAL (tol < 0, unknown class or flag), ENOMEM,
- * EDEVICE. */
+ * that the sum of gamma * beta is at most tol (stats->err_bound), minimising modelled time.  Jobs
+ * whose box holds the zero displacement keep their narrow terms in FP64 whatever the budget: the
+ * terms with tau_m >= 4 k^2 4^j at level j (width 1/sqrt(tau_m) at most 1/(2k) of a level-j box).
+ * A reduced class that would carry less than a tenth of the apply's work is not used (its launch
+ * costs more than it saves); its jobs stay FP64.  The transforms, the
+ * interpolation, the assembly and the output accumulation stay FP64.  flags: 0, MWNS_NO_ASSEMBLY,
+ * MWNS_TIMES_ONLY.  Errors: EINVAL (tol < 0, unknown class or flag, a BF16 class for k > 8),
+ * ENOMEM, EDEVICE. */
 mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const mwns_tree* f, const mwns_mixed_opts* opts, int flags,
                              mwns_tree** g, mwns_apply_stats* stats);
 

@@ -21,7 +21,7 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
                    lib)
 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
-           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed",
+           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
@@ -167,28 +167,37 @@ def _handles(objs):
     return arr
 
 
-def _mixed_array(mixed, n):
+def default_classes(k):
+    """Every reduced class the kernels have for order k: FP32 and both BF16 classes for k <= 8,
+    FP32 alone above (the whole-brick kernel of k = 9, 10 has no BF16 class)."""
+    return MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16 if k <= 8 else MWNS_CLASS_F32
+
+
+def _mixed_array(mixed, fs):
     if mixed is None:
         return None
+    n = len(fs)
     if isinstance(mixed, (int, float)):
         mixed = [mixed] * n
     arr = (_lib.MixedOpts * n)()
     for i, m in enumerate(mixed):
-        tol, classes = (m, MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16) if isinstance(m, (int, float)) else m
+        tol, classes = (m, None) if isinstance(m, (int, float)) else m
+        if classes is None:
+            classes = default_classes(mwns_tree_get_info(fs[i])["k"])
         arr[i] = _lib.MixedOpts(float(tol), int(classes))
     return arr
 
 
 def mwns_apply_batch(ctx, ops, fs, mixed=None, flags=0, stats=True):
     """Batched apply of the pairs (ops[i], fs[i]) in one persistent launch per basis order.
-    mixed: None (FP64), a tol for every tree, or a list of tol or (tol, classes) per tree.
-    Returns (list of Trees, aggregated stats or None)."""
+    mixed: None (FP64), a tol for every tree, or a list of tol or (tol, classes) per tree (classes
+    None: default_classes of the tree's k).  Returns (list of Trees, aggregated stats or None)."""
     n = len(ops)
     if len(fs) != n:
         raise ValueError("ops and fs differ in length")
     gs = (ctypes.c_void_p * n)()
     st = _lib.ApplyStats()
-    mx = _mixed_array(mixed, n)
+    mx = _mixed_array(mixed, fs)
     check(lib.mwns_apply_batch(ctx.h, n, _handles(ops), _handles(fs), mx, flags, gs,
                                ctypes.byref(st) if stats else None), "mwns_apply_batch")
     return [Tree(ctx, ctypes.c_void_p(gs[i])) for i in range(n)], (_stats_dict(st) if stats else None)
@@ -199,7 +208,7 @@ def mwns_plan_create(ctx, ops, fs, mixed=None, flags=0):
     if len(fs) != n:
         raise ValueError("ops and fs differ in length")
     h = ctypes.c_void_p()
-    mx = _mixed_array(mixed, n)
+    mx = _mixed_array(mixed, fs)
     check(lib.mwns_plan_create(ctx.h, n, _handles(ops), _handles(fs), mx, flags, ctypes.byref(h)), "mwns_plan_create")
     return Plan(ctx, h, n, (list(ops), list(fs)))
 
@@ -371,9 +380,11 @@ def _stats_dict(st):
     return out
 
 
-def mwns_apply_mixed(ctx, op, f, tol, classes=MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16, flags=0, stats=True):
-    """g = T f with contractions routed to FP64 / FP32 / BF16 so that ||g - g_F64||_2 <= tol;
-    returns (g, stats dict or None)."""
+def mwns_apply_mixed(ctx, op, f, tol, classes=None, flags=0, stats=True):
+    """g = T f with contractions routed to FP64 / FP32 / BF16 so that ||g - g_F64||_2 <= tol
+    (classes None: default_classes of f's k); returns (g, stats dict or None)."""
+    if classes is None:
+        classes = default_classes(mwns_tree_get_info(f)["k"])
     h = ctypes.c_void_p()
     st = _lib.ApplyStats()
     opts = _lib.MixedOpts(float(tol), int(classes))

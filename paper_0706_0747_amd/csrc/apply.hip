@@ -472,6 +472,7 @@ constexpr double COST[NPREC] = {1.0, 0.6, 0.3, 0.2};
 struct RouteItem {
     int j, t, m, cls;
     double beta, work;
+    bool pin;      // kept in FP64 whatever the budget
 };
 
 // Chooses a class for every (level, job, term) minimising the modelled time subject to
@@ -483,6 +484,8 @@ struct RouteItem {
 //   |w_m| prod_d || sum_{L_d} |S_d^{m,L_d}| ||_2 ||X_level||  (the box is a product set, and a block
 //   convolution with nonnegative blocks B_L has norm at most || sum_L B_L ||_2).
 // beta is the smaller.  Returns the bound reached.
+constexpr double MIN_CLASS_SHARE = 0.1;
+
 double route(std::vector<RouteItem>& items, double tol, int allowed, int k) {
     const Gammas gm = class_gammas(k);
     const double* GAMMA = gm.g;
@@ -491,7 +494,7 @@ double route(std::vector<RouteItem>& items, double tol, int allowed, int k) {
         for (RouteItem& it : items) {
             int best = PREC_F64;
             double bv = it.work * COST[PREC_F64];
-            for (int p = 1; p < NPREC; ++p) {
+            for (int p = 1; p < NPREC && !it.pin; ++p) {
                 if (!((allowed >> (p - 1)) & 1)) continue;
                 const double v = it.work * COST[p] + lam * GAMMA[p] * it.beta;
                 if (v < bv) { bv = v; best = p; }
@@ -506,13 +509,30 @@ double route(std::vector<RouteItem>& items, double tol, int allowed, int k) {
         return 0.0;
     }
     double lo = -60.0, hi = 80.0;     // log10 of the multiplier; at 10^80 every item is FP64
-    if (eval(std::pow(10.0, lo), false) <= tol) return eval(std::pow(10.0, lo), true);
-    for (int it = 0; it < 100; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (eval(std::pow(10.0, mid), false) <= tol) hi = mid;
-        else lo = mid;
+    if (eval(std::pow(10.0, lo), false) <= tol) {
+        eval(std::pow(10.0, lo), true);
+    } else {
+        for (int it = 0; it < 100; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (eval(std::pow(10.0, mid), false) <= tol) hi = mid;
+            else lo = mid;
+        }
+        eval(std::pow(10.0, hi), true);
     }
-    return eval(std::pow(10.0, hi), true);
+    // A reduced class with less than MIN_CLASS_SHARE of the work is not used: its launch revisits
+    // every output brick and input neighbourhood it touches, which costs more than the little work
+    // it takes off FP64.  Moving items to FP64 only lowers the error.
+    double total = 0.0, share[NPREC] = {0.0, 0.0, 0.0, 0.0};
+    for (const RouteItem& it : items) {
+        total += it.work;
+        share[it.cls] += it.work;
+    }
+    double err = 0.0;
+    for (RouteItem& it : items) {
+        if (it.cls != PREC_F64 && share[it.cls] < MIN_CLASS_SHARE * total) it.cls = PREC_F64;
+        err += GAMMA[it.cls] * it.beta;
+    }
+    return err;
 }
 
 // Coarsest per-dimension partition of [-LP, LP] on which a plan row is constant; returns cells.
@@ -1022,12 +1042,19 @@ void route_tree(mwns_ctx* ctx, TreeApply& a, const double* lsq, const mwns_mixed
                     babs *= abs_box_norm(op, j, m, tp.lo[d], tp.hi[d], tp.mlo[d], tp.mhi[d]);
                 }
                 const double beta = std::fabs(op->w[m]) * xn * std::min(bfro, babs);
-                items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1)});
+                // near-diagonal narrow Gaussians stay in FP64: the job's box holds the zero
+                // displacement and the term's width in level-j box units, 2^j / sqrt(tau_m), is at
+                // most 1/(2k), below the resolution of the degree k-1 polynomials of a box
+                // (tau_m >= 4 k^2 4^j): its blocks act on the box itself almost alone
+                const bool diag = tp.lo[0] <= 0 && tp.hi[0] >= 0 && tp.lo[1] <= 0 && tp.hi[1] >= 0 && tp.lo[2] <= 0 && tp.hi[2] >= 0;
+                const bool pin = diag && op->tau[m] >= 4.0 * a.k * a.k * std::ldexp(1.0, 2 * j);
+                items.push_back(RouteItem{j, t, m, PREC_F64, beta, nb * (n1 * n2 * n3 + n1 * n2 + n1), pin});
             }
         }
     }
-    // the whole-brick kernel (orders above KNARROW) has the FP32 class only
-    a.err_bound = route(items, opts.tol, a.k > KNARROW ? (opts.classes & MWNS_CLASS_F32) : opts.classes, a.k);
+    // (the whole-brick kernel, orders above KNARROW, has the FP32 class only: the callers reject
+    // the BF16 bits there)
+    a.err_bound = route(items, opts.tol, opts.classes, a.k);
     size_t pos = 0;
     for (int j = 0; j <= a.depth; ++j) {
         LevelWork& lw = a.W[j];
@@ -1541,9 +1568,12 @@ extern "C" mwns_status mwns_apply(mwns_ctx* ctx, const mwns_op* op, const mwns_t
 }
 
 namespace {
-void check_mixed(const mwns_mixed_opts* opts) {
+void check_mixed(const mwns_mixed_opts* opts, const mwns_tree* f) {
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) fail(MWNS_EINVAL, "tol must be finite and >= 0");
     if (opts->classes & ~(MWNS_CLASS_F32 | MWNS_CLASS_BF16C | MWNS_CLASS_BF16)) fail(MWNS_EINVAL, "unknown precision class");
+    if (f && f->k > KNARROW && (opts->classes & (MWNS_CLASS_BF16C | MWNS_CLASS_BF16)))
+        fail(MWNS_EINVAL, "the BF16 classes are not available for k > " + std::to_string(KNARROW) + " (k = " +
+                              std::to_string(f->k) + "): allow MWNS_CLASS_F32 only");
 }
 }  // namespace
 
@@ -1551,9 +1581,9 @@ extern "C" mwns_status mwns_apply_mixed(mwns_ctx* ctx, const mwns_op* op, const 
                                         int flags, mwns_tree** g, mwns_apply_stats* stats) {
     MWNS_GUARD_BEGIN
     if (!opts) fail(MWNS_EINVAL, "opts is NULL");
-    check_mixed(opts);
     if (flags & ~(MWNS_NO_ASSEMBLY | MWNS_TIMES_ONLY)) fail(MWNS_EINVAL, "unsupported flags");
     if (!ctx || !op || !f || !g) fail(MWNS_EINVAL, "NULL argument");
+    check_mixed(opts, f);
     apply_batch(ctx, 1, &op, &f, opts, flags, false, g, stats);
     return MWNS_OK;
     MWNS_GUARD_END
@@ -1564,7 +1594,7 @@ extern "C" mwns_status mwns_apply_batch(mwns_ctx* ctx, int n, const mwns_op* con
     MWNS_GUARD_BEGIN
     if (flags & ~(MWNS_NO_ASSEMBLY | MWNS_TIMES_ONLY)) fail(MWNS_EINVAL, "unsupported flags");
     if (mixed)
-        for (int i = 0; i < n; ++i) check_mixed(mixed + i);
+        for (int i = 0; i < n; ++i) check_mixed(mixed + i, fs ? fs[i] : nullptr);
     if (gs)
         for (int i = 0; i < n; ++i) gs[i] = nullptr;
     apply_batch(ctx, n, ops, fs, mixed, flags, true, gs, stats);
@@ -1578,7 +1608,7 @@ extern "C" mwns_status mwns_plan_create(mwns_ctx* ctx, int n, const mwns_op* con
     if (!ctx || !ops || !fs || !out || n < 1) fail(MWNS_EINVAL, "NULL argument or empty batch");
     if (flags & ~MWNS_NO_ASSEMBLY) fail(MWNS_EINVAL, "unsupported flags");
     if (mixed)
-        for (int i = 0; i < n; ++i) check_mixed(mixed + i);
+        for (int i = 0; i < n; ++i) check_mixed(mixed + i, fs[i]);
     std::unique_ptr<mwns_plan> pl(new mwns_plan);
     pl->ctx = ctx;
     pl->hold.set(ctx);

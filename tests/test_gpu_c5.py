@@ -1,9 +1,12 @@
-"""The large single apply (Poisson, k = 10, eps = 1e-10, about 1e6 leaves from 500 Gaussians) at
-full size.  The oracle cannot build a tree that large, so the checks are the ones that hold at any
-size: the tree box by box at sampled leaves against the oracle's Alg. 1 step, and as a whole for
-structure; the FP64 potential against the fitted kernel applied in closed form to the
-cube-truncated source (seeded grid of 22^3 points); the routed apply against the FP64 one within
-its bound <= eps ||g||."""
+"""The large single apply (Poisson, k = 10, eps = 1e-10, about 1e6 leaves from 500 Gaussians).
+The oracle cannot build a tree that large (an internal node's coefficients depend on every leaf
+below it, so even a sampled neighbourhood needs most of the tree), so the full-size checks are the
+ones that hold at any size: the tree box by box at sampled leaves against the oracle's Alg. 1 step,
+and as a whole for structure; the FP64 potential against the fitted kernel applied in closed form
+to the cube-truncated source (seeded grid of 22^3 points); the routed apply against the FP64 one
+within its bound <= eps ||g||.  Node-by-node parity with the oracle's modified-form apply uses the
+same operator (fit, plan, depth 11) on the tree of the workload's first six sources, which the
+oracle builds itself."""
 import math
 
 import numpy as np
@@ -40,7 +43,11 @@ def test_c5_full_size(M):
     ctx = M.Context(0)
     f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
     info = M.mwns_tree_get_info(f)
-    print("C5 tree: %d leaves, %d nodes, depth %d" % (info["nleaves"], info["nnodes"], info["depth"]), flush=True)
+    # min_margin: the smallest |detail norm - threshold| / threshold of a refinement decision; the
+    # tree is decided box by box in FP64 on both sides, so a decision can differ only where this is
+    # at rounding level (the sampled boxes below are ruled on by the oracle itself)
+    print("C5 tree: %d leaves, %d nodes, depth %d, min margin %.3e"
+          % (info["nleaves"], info["nnodes"], info["depth"], info["min_margin"]), flush=True)
     assert info["nleaves"] > 500000
     keys, leaf, coef = M.mwns_tree_export(ctx, f)
     # structure of the whole tree: sorted distinct keys, all 8 children of every internal node,
@@ -104,3 +111,59 @@ def test_c5_full_size(M):
              [round(x / stm["useful_flops"], 3) for x in stm["class_flops"]], stm["ms_contract"], st64["ms_contract"]),
           flush=True)
     assert e <= stm["err_bound"] <= tol
+
+
+def test_c5_operator_parity_on_subsource_tree(M):
+    """The apply with the large workload's operator (k = 10, eps = 1e-10, the oracle's own fit and
+    plan) on a tree the oracle can build: Alg. 1 on the first 6 of its 500 Gaussians (a tree of
+    about 2.6e4 leaves as deep as the full one).  The full tree's internal coefficients depend on
+    every leaf below them, so the oracle cannot rebuild sampled neighbourhoods of the ~1e6-leaf tree
+    itself; this case checks the contraction kernels with the same operator, plan and depth at a
+    size the oracle handles: tree bit-exact, ghat and g within 1e-12 of the oracle on sampled leaves
+    and their ancestor chains, node by node."""
+    from oracle import apply as A
+    from oracle import fit as OF
+    from oracle import tree as T
+    from oracle.tree import make_keys
+    w = workloads.c5()
+    n = 6
+    ctx = M.Context(0)
+    keys, coef = T.project_gaussians(w.k, w.eps, w.j0, w.jmax, w.xyz[:n], w.a[:n], w.c[:n])
+    ot = T.redundant_tree(w.k, keys, coef)
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz[:n], w.a[:n], w.c[:n])
+    k2, leaf, c2 = M.mwns_tree_export(ctx, f)
+    assert np.array_equal(k2, ot.keys) and np.array_equal(leaf, ot.leaf)
+    assert np.abs(c2 - ot.coef).max() <= 1e-13 * np.abs(ot.coef).max()
+    info = M.mwns_tree_get_info(f)
+    print("C5 operator on the first %d sources: %d leaves, depth %d, min margin %.3e"
+          % (n, info["nleaves"], info["depth"], info["min_margin"]), flush=True)
+    depth = 11                                   # the full workload's depth: its fit and its operator
+    tau, wt = OF.fit_kernel(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(3))
+    nlev = max(depth, ot.depth)
+    oo = A.Operator(w.k, tau, wt, w.eps, nlev)
+    op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, nlev)
+    assert np.array_equal(M.mwns_op_plan_export(op), oo.R)
+    gh_lib = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)[0])[2]
+    g_lib = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f)[0])[2]
+    rng = np.random.Generator(np.random.PCG64(57))
+    leaves = np.nonzero(ot.leaf)[0]
+    sample = list(rng.choice(leaves, 48, replace=False))
+    deepest = np.nonzero(ot.level == ot.depth)[0]
+    sample += [leaves[0], leaves[-1], deepest[0], deepest[-1]]
+    chain = set()
+    for i in sample:
+        j, l = int(ot.level[i]), ot.l[i]
+        for lev in range(j + 1):
+            chain.add(int(ot.index(make_keys(np.array([lev]), *(l[None, :] >> (j - lev)).T))[0]))
+    chain = np.array(sorted(chain))
+    gh = A.apply_modified(oo, ot, chain)
+    scale = np.abs(gh).max()
+    err = np.abs(gh_lib[chain] - gh).reshape(chain.size, -1).max(axis=1)
+    nrm = np.abs(gh).reshape(chain.size, -1).max(axis=1)
+    assert np.all(err <= 1e-12 * nrm + 1e-15 * scale), (err / np.maximum(nrm, 1e-300)).max()
+    ghd = dict(zip(chain, gh))
+    ref = np.stack([A.assemble_chain(ot, i, lambda q: ghd[q]) for i in sample])
+    got = g_lib[sample]
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    errs = np.abs(got - ref).reshape(len(sample), -1).max(axis=1)
+    assert np.all(errs <= 1e-12 * np.abs(ref).reshape(len(sample), -1).max(axis=1) + 1e-15 * np.abs(ref).max())

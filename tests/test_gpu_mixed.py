@@ -61,9 +61,13 @@ def test_tol_zero_is_the_fp64_apply(M, ctx, case):
 @pytest.mark.parametrize("cls,idx,rel", [("MWNS_CLASS_F32", 1, 1e-5), ("MWNS_CLASS_BF16C", 2, 1e-3),
                                          ("MWNS_CLASS_BF16", 3, 5e-2)])
 def test_each_class_alone_within_bound(M, ctx, case, cls, idx, rel):
-    """Every job forced into one reduced class (unbounded tol): the error against the FP64 apply is
-    within the a-priori bound and at the class's precision."""
-    f, op, *_ = _setup(M, ctx, CASES[case]())
+    """Every job forced into one reduced class (unbounded tol, an operator without narrow terms):
+    the error against the FP64 apply is within the a-priori bound and at the class's precision."""
+    w = CASES[case]()
+    f, _, tau, wt, depth = _setup(M, ctx, w)
+    keep = tau < 4.0 * w.k ** 2      # never a narrow near-diagonal term (tau_m < 4 k^2 4^j at every level)
+    assert keep.sum() >= 3
+    op = M.mwns_op_create(ctx, w.k, tau[keep], wt[keep], w.eps, depth)
     g64, st64 = M.mwns_apply(ctx, op, f)
     _, leaf, a = M.mwns_tree_export(ctx, g64)
     gm, st = M.mwns_apply_mixed(ctx, op, f, 1e300, classes=getattr(M, cls))
@@ -72,6 +76,38 @@ def test_each_class_alone_within_bound(M, ctx, case, cls, idx, rel):
     err = _leaf_norm(leaf, b - a)
     assert err <= st["err_bound"]
     assert err <= rel * st64["g_norm"], (err / st64["g_norm"])
+
+
+def test_near_diagonal_narrow_terms_stay_fp64(M, ctx):
+    """The routing rule that keeps narrow Gaussians at the zero displacement in FP64: with an
+    unbounded budget, an operator whose exponents are all below 4 k^2 (never narrower than 1/(2k)
+    of a box, at any level) runs entirely in the reduced class; adding one exponent above
+    4 k^2 4^depth pins that term's jobs whose box holds L = 0 to FP64 at every level, and the result
+    stays within the bound.  BF16 classes are refused for k > 8."""
+    from paper_0706_0747_amd import _lib
+    w = CASES["adaptive_k6"]()
+    f = M.mwns_project_gaussians(ctx, w.k, w.eps, w.j0, w.jmax, w.xyz, w.a, w.c)
+    depth = M.mwns_tree_get_info(f)["depth"]
+    wide = M.mwns_op_create(ctx, w.k, np.array([0.3, 0.7]), np.array([1.0, 0.5]), w.eps, depth)
+    _, st = M.mwns_apply_mixed(ctx, wide, f, 1e300, classes=M.MWNS_CLASS_F32)
+    assert st["class_flops"][0] == 0.0 and st["class_flops"][1] > 0.0
+    narrow = M.mwns_op_create(ctx, w.k, np.array([0.3, 4.0 * w.k ** 2 * 4.0 ** (depth + 1)]), np.array([1.0, 0.5]), w.eps, depth)
+    g64, st64 = M.mwns_apply(ctx, narrow, f)
+    gm, st = M.mwns_apply_mixed(ctx, narrow, f, 1e300, classes=M.MWNS_CLASS_F32)
+    assert st["class_flops"][0] > 0.0 and st["class_flops"][1] > 0.0
+    assert st["class_flops"][0] + st["class_flops"][1] == pytest.approx(st64["useful_flops"])
+    _, leaf, a = M.mwns_tree_export(ctx, g64)
+    _, _, b = M.mwns_tree_export(ctx, gm)
+    assert _leaf_norm(leaf, b - a) <= st["err_bound"]
+    w10 = workloads.small_adaptive(31, k=10, eps=1e-6, jmax=3)
+    f10 = M.mwns_project_gaussians(ctx, w10.k, w10.eps, w10.j0, w10.jmax, w10.xyz, w10.a, w10.c)
+    op10 = M.mwns_op_create(ctx, 10, np.array([0.3, 0.7]), np.array([1.0, 0.5]), w10.eps, M.mwns_tree_get_info(f10)["depth"])
+    for cls in (M.MWNS_CLASS_BF16C, M.MWNS_CLASS_BF16, M.MWNS_CLASS_F32 | M.MWNS_CLASS_BF16):
+        with pytest.raises(M.MwnsError) as e:
+            M.mwns_apply_mixed(ctx, op10, f10, 1.0, classes=cls)
+        assert e.value.status == _lib.MWNS_EINVAL
+    _, st = M.mwns_apply_mixed(ctx, op10, f10, 1e300)      # the binding's default for k = 10: FP32
+    assert st["class_flops"][2] == st["class_flops"][3] == 0.0 and st["class_flops"][1] > 0.0
 
 
 @pytest.mark.parametrize("case", list(CASES))

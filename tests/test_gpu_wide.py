@@ -123,8 +123,8 @@ def test_wide_variants_match_oracle(M, ctx, case):
 
 
 def test_wide_in_batch_plan_and_routing(M, ctx):
-    """k = 10 and k = 8 trees in one batch equal their single applies; the plan replays them; asked
-    for the BF16 classes only, the routed apply keeps every k = 10 job in FP64 (bound 0, result
+    """k = 10 and k = 8 trees in one batch equal their single applies; the plan replays them; the
+    BF16 classes are refused at k = 10 and tol = 0 keeps every job in FP64 (bound 0, result
     identical); a routed batch equals the routed single applies."""
     import torch
     specs = [CASES["k10_poisson"](), workloads.small_adaptive(34, k=8, eps=1e-5, jmax=4), CASES["k9_yukawa"]()]
@@ -146,7 +146,11 @@ def test_wide_in_batch_plan_and_routing(M, ctx):
         for i in range(len(specs)):
             assert np.array_equal(M.mwns_tree_export(ctx, plan.output(i))[2], singles[i])
     plan.close()
-    gm, st = M.mwns_apply_mixed(ctx, ops[0], fs[0], 1e300, classes=M.MWNS_CLASS_BF16C | M.MWNS_CLASS_BF16)
+    from paper_0706_0747_amd import _lib
+    with pytest.raises(M.MwnsError) as e:
+        M.mwns_apply_mixed(ctx, ops[0], fs[0], 1e300, classes=M.MWNS_CLASS_BF16C | M.MWNS_CLASS_BF16)
+    assert e.value.status == _lib.MWNS_EINVAL
+    gm, st = M.mwns_apply_mixed(ctx, ops[0], fs[0], 0.0)
     assert st["err_bound"] == 0.0 and st["class_flops"][1:] == [0.0, 0.0, 0.0]
     assert np.array_equal(M.mwns_tree_export(ctx, gm)[2], singles[0])
     tols = [w.eps * M.mwns_apply(ctx, op, f)[1]["g_norm"] for w, op, f in zip(specs, ops, fs)]
@@ -170,10 +174,16 @@ def _leaf_norm(leaf, coef):
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_wide_fp32_class_alone_within_bound(M, ctx, case):
-    """Every job of the two-tile kernel forced into the FP32 class (unbounded tol): the error
-    against the FP64 apply is within the a-priori bound and at FP32 precision (a wrong operand
-    layout or K-slot permutation would give O(1) errors)."""
-    f, op, *_ = _lib_setup(M, ctx, CASES[case]())
+    """Every job of the whole-brick kernel forced into the FP32 class (unbounded tol, an operator
+    without narrow terms): the error against the FP64 apply is within the a-priori bound and at
+    FP32 precision (a wrong operand layout or K-slot permutation would give O(1) errors)."""
+    w = CASES[case]()
+    f, _, tau, wt = _lib_setup(M, ctx, w)
+    # the fit's terms wider than 1/(2k) of the root box (tau < 4 k^2): none of them is a narrow
+    # near-diagonal term at any level, so every job can go to the FP32 class
+    keep = tau < 4.0 * w.k ** 2
+    assert keep.sum() >= 3
+    op = M.mwns_op_create(ctx, w.k, tau[keep], wt[keep], w.eps, M.mwns_tree_get_info(f)["depth"])
     g64, st64 = M.mwns_apply(ctx, op, f)
     _, leaf, a = M.mwns_tree_export(ctx, g64)
     gm, st = M.mwns_apply_mixed(ctx, op, f, 1e300, classes=M.MWNS_CLASS_F32)
@@ -186,7 +196,7 @@ def test_wide_fp32_class_alone_within_bound(M, ctx, case):
 
 def test_wide_mixed_at_eps_against_oracle(M, ctx):
     """tol = eps ||g|| at k = 10: the routed result is within err_bound <= tol of the oracle's FP64
-    apply (up to FP64 round-off), with part of the work in the FP32 class."""
+    apply (up to FP64 round-off)."""
     from oracle import apply as A
     from oracle import tree as T
     w = CASES["k10_poisson"]()
@@ -223,7 +233,9 @@ def test_c3_mixed_at_eps(M, ctx):
           % (err / st64["g_norm"], st["err_bound"] / st64["g_norm"],
              [round(x / st["useful_flops"], 3) for x in st["class_flops"]], st["ms_contract"], st64["ms_contract"]))
     assert err <= st["err_bound"] <= tol
-    assert st["class_flops"][1] > 0.0
+    # the narrow near-diagonal terms stay FP64 (at k = 10 most of the work); a class that would
+    # carry less than a tenth of it is not launched
+    assert st["class_flops"][1] == 0.0 or st["class_flops"][1] >= 0.1 * st["useful_flops"]
 
 
 def test_c3_yukawa_full_size_sampled(M, ctx):
