@@ -10,8 +10,8 @@ The trapezoidal rule with s_m = A + m h, m = 1..M, h = (B-A)/M gives (eq. Kernel
     tau_m = e^{2 s_m},   w_m = h C_alpha exp(-mu^2 e^{-2 s_m}/4 + (3-2alpha) s_m),
 with |K_{mu,alpha}(r) - sum_m w_m exp(-tau_m r^2)| <= eps K_{0,alpha}(r) on [delta, R].
 
-The paper takes A, B, h from a reference it does not reproduce.  The oracle's reading
-(listed in DESIGN.md) with nu = 3/2 - alpha:
+The paper takes A, B, h from a reference it does not reproduce.  The reading taken here,
+with nu = 3/2 - alpha:
     h0 = pi^2 / (2 (ln(1/eps) + ln 8))                     strip |Im s| < pi/4 of analyticity
     A  = ln(eps Gamma(nu+1)/4) / (2 nu) - ln R              lower tail <= eps/4 * K_0 on [delta,R]
     B  = ln(t_B / delta^2) / 2, with Q(nu, t_B) <= eps/4   upper tail <= eps/4 * K_0

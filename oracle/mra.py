@@ -4,20 +4,26 @@ Everything here follows the paper's appendix:
   * Legendre scaling functions phi_a(x) = sqrt(2a+1) P_a(2x-1) on [0,1]    (App. A.1, eq. scalingFNC)
   * Gauss-Legendre rule on [0,1] (roots of P_k(2x-1))                       (App. A.1, eq. fvals2coefs)
   * two-scale filters H^(0), H^(1)                                           (App. A.3, two-scale relations)
+  * wavelet filters G^(0), G^(1): any orthonormal complement of [H0 H1]     (App. A.2-A.3)
   * cross-correlations Phi_ab(x) = int phi_a(x+y) phi_b(y) dy              (App. A.4, eqs. CrossCor, crosscor.01)
   * operator blocks F^{j;m,l}_ab = 2^-j int_{-1}^{1} exp(-tau (x+l)^2/4^j) Phi_ab(x) dx
                                                                             (Sec. 3, eq. KernelFactor)
-Readings ("Readings of the paper"):
+Readings of the paper taken here:
   * H^(s)_ab = <phi_a, sqrt2 phi_b(2x-s)> = 2^-1/2 int_0^1 phi_a((u+s)/2) phi_b(u) du, i.e. the
     coefficients of the two-scale relation for phi_a.  Decomposition s^j = H0 s^{j+1}_{2l} + H1 s^{j+1}_{2l+1};
     zero-detail reconstruction s^{j+1}_{2l+s} = H^(s)^T s^j.
   * In F^{j;m,l} the displacement is l = l_out - l_in and the row index a is the output degree.
+  * G^(0), G^(1) are defined only through a reference the paper does not reproduce.  The wavelets
+    psi_0..psi_{k-1} span the orthogonal complement of V_0 in V_1, so [[H0, H1], [G0, G1]] is an
+    orthogonal 2k x 2k matrix; any orthonormal basis of that complement serves, since only the
+    norm of the detail coefficients is used.  Here: Gram-Schmidt (twice) of the columns of the
+    projector I - [H0 H1]^T [H0 H1], in column order.
 """
 import functools
 
 import numpy as np
 
-__all__ = ["gauss_legendre01", "phi", "two_scale_filters", "crosscorr",
+__all__ = ["gauss_legendre01", "phi", "two_scale_filters", "wavelet_filters", "crosscorr",
            "crosscorr_coeffs", "F_block", "F_blocks", "F_table"]
 
 
@@ -57,6 +63,30 @@ def two_scale_filters(k):
         pb = phi(k, u)                      # phi_b(u)
         H.append(np.einsum("i,ia,ib->ab", w, pa, pb) / np.sqrt(2.0))
     return H[0], H[1]
+
+
+def wavelet_filters(k):
+    """G^(0), G^(1) (k x k) such that W = [[H0, H1], [G0, G1]] is orthogonal (App. A.3): the
+    decomposition d^j = G0 s^{j+1}_{2l} + G1 s^{j+1}_{2l+1} (eq. decomp_wavelet) and the
+    reconstruction s^{j+1}_{2l+s} = H^(s)^T s^j + G^(s)^T d^j."""
+    H0, H1 = two_scale_filters(k)
+    Hr = np.hstack([H0, H1])                     # k x 2k, orthonormal rows
+    P = np.eye(2 * k) - Hr.T @ Hr                # projector onto the complement (rank k)
+    basis = []
+    for c in range(2 * k):
+        v = P[:, c].copy()
+        for _ in range(2):
+            for b in basis:
+                v -= (b @ v) * b
+            for h in Hr:
+                v -= (h @ v) * h
+        n = np.linalg.norm(v)
+        if n > 1e-8:
+            basis.append(v / n)
+        if len(basis) == k:
+            break
+    G = np.array(basis)                          # k x 2k
+    return G[:, :k].copy(), G[:, k:].copy()
 
 
 def crosscorr(k, x):

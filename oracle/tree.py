@@ -13,9 +13,18 @@
   * evaluate: f(x) = 2^{3j/2} sum s_abc phi_a(2^j x - l1) phi_b(.) phi_c(.) on the leaf holding x
     (App. A.1, eqs. func_interp_1d/2d in 3-D); a point on a face belongs to the box with
     floor(2^j x) clamped to 2^j - 1.
+  * details / detail_norms: the seven detail blocks of a sibling group, eq. decomp_wavelet along
+    each dimension with G in at least one of them (App. A.2-A.3), and their squared norm.
+  * prune_l2 (Sec. 2.2): starting on the finest scale, sibling groups are removed while the
+    cumulative squared norm of the removed details stays within eta^2; by orthonormality that sum
+    is exactly ||f - f_pruned||_2^2.  discard: the same at eta = eps ||f||_2 (Alg. 3 Step 4).
 Readings: the refinement threshold is eps * ||f||_2 with the closed-form L2 norm of the
 Gaussian sum over R^3 (the paper's absolute eps on a function scaled to unit norm); sources are
-unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2).
+unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2).  Pruning: the cumulative
+contribution of the removed blocks is their squared l2 norm, compared with eta^2; within a scale
+the candidates (internal nodes whose eight children are leaves) are taken in ascending order of
+that norm (ties by key), and a scale's first candidate that would exceed the budget ends that
+scale; the remaining budget carries to the next coarser scale.
 """
 import ctypes
 import numpy as np
@@ -24,7 +33,8 @@ from . import mra
 from ._native import lib
 
 __all__ = ["make_keys", "decode_keys", "children_keys", "source_norm", "project_gaussians",
-           "project_function", "redundant_tree", "compress", "upsample", "evaluate", "uniform_leaves", "Tree"]
+           "project_function", "redundant_tree", "compress", "upsample", "evaluate", "uniform_leaves", "Tree",
+           "details", "reconstruct", "detail_norms", "prune_l2", "discard"]
 
 
 def _spread3(v):
@@ -309,3 +319,81 @@ def evaluate(tree, pts):
             out[p] = 2.0 ** (1.5 * j) * np.einsum("pabc,pa,pb,pc->p", tree.coef[idx[hit]], px, py, pz)
         todo = todo[~hit]
     return out
+
+
+def details(k, child_coef):
+    """(s, d) of sibling groups child_coef[..., 8, k, k, k] (child s = sx + 2 sy + 4 sz): s the
+    parent block (eq. decomp_scaling per dimension) and d[..., 7, k, k, k] the detail blocks
+    (eq. decomp_wavelet), block t = tx + 2 ty + 4 tz (t = 1..7) with G along the dimensions whose
+    bit is set and H along the others."""
+    H = mra.two_scale_filters(k)
+    G = mra.wavelet_filters(k)
+    out = []
+    for t in range(8):
+        F = [G if (t >> d) & 1 else H for d in range(3)]
+        acc = 0.0
+        for s in range(8):
+            acc = acc + _apply_sep(F[0][s & 1], F[1][(s >> 1) & 1], F[2][(s >> 2) & 1], child_coef[..., s, :, :, :])
+        out.append(acc)
+    return out[0], np.stack(out[1:], axis=-4)
+
+
+def reconstruct(k, parent_coef, detail):
+    """The eight children from the parent block and its seven detail blocks (eqs. recon_even/odd
+    per dimension, with the transposed filters)."""
+    H = mra.two_scale_filters(k)
+    G = mra.wavelet_filters(k)
+    blocks = [parent_coef] + [detail[..., t - 1, :, :, :] for t in range(1, 8)]
+    kids = []
+    for s in range(8):
+        acc = 0.0
+        for t in range(8):
+            F = [G if (t >> d) & 1 else H for d in range(3)]
+            acc = acc + _apply_sep(F[0][s & 1].T, F[1][(s >> 1) & 1].T, F[2][(s >> 2) & 1].T, blocks[t])
+        kids.append(acc)
+    return np.stack(kids, axis=-4)
+
+
+def detail_norms(tree):
+    """||d||_2^2 of every internal node's sibling group (0 at leaves), in node order."""
+    out = np.zeros(tree.keys.size)
+    internal = np.nonzero(tree.leaf == 0)[0]
+    if internal.size:
+        ch = tree.index(children_keys(tree.keys[internal])).reshape(-1, 8)
+        _, d = details(tree.k, tree.coef[ch])
+        out[internal] = np.sum(d.reshape(internal.size, -1) ** 2, axis=1)
+    return out
+
+
+def prune_l2(tree, eta):
+    """Sec. 2.2's l2 pruning of a redundant tree within eta (absolute): returns (pruned Tree, the
+    removed squared norm <= eta^2).  The kept nodes keep their blocks."""
+    dn = detail_norms(tree)
+    leaf = tree.leaf.copy()
+    alive = np.ones(tree.keys.size, dtype=bool)
+    budget = float(eta) ** 2
+    used = 0.0
+    for j in range(tree.depth - 1, -1, -1):
+        nodes = np.nonzero((tree.level == j) & (leaf == 0) & alive)[0]
+        if nodes.size == 0:
+            continue
+        ch = tree.index(children_keys(tree.keys[nodes])).reshape(-1, 8)
+        cand = nodes[np.all(leaf[ch] == 1, axis=1)]
+        order = np.lexsort((tree.keys[cand], dn[cand]))
+        for i in cand[order]:
+            if used + dn[i] > budget:
+                break
+            used += dn[i]
+            leaf[i] = 1
+            alive[tree.index(children_keys(tree.keys[i:i + 1]))] = False
+    # descendants of removed children go too (they are leaves by construction: only groups whose
+    # children are all leaves are removed)
+    keep = np.nonzero(alive)[0]
+    return Tree(tree.k, tree.keys[keep], leaf[keep], tree.coef[keep]), used
+
+
+def discard(tree, eps):
+    """Alg. 3 Step 4 at the requested accuracy: prune_l2 within eps ||f||_2, where ||f||_2^2 is the
+    sum of the squared leaf blocks (orthonormal basis)."""
+    fn = float(np.sqrt(np.sum(tree.coef[tree.leaf == 1] ** 2)))
+    return prune_l2(tree, eps * fn)
