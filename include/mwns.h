@@ -327,6 +327,31 @@ void mwns_plan_destroy(mwns_plan* plan);
  * EDEVICE. */
 mwns_status mwns_tree_eval(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out);
 
+/* ----------------------------------------------------------- (6) details and pruning */
+
+/* Squared l2 norm of the detail coefficients of every node (App. A.2-A.3, eq. decomp_wavelet in
+ * each dimension) of the function that t's leaves represent: out[nnodes] (host, canonical order)
+ * receives, for an internal node, the sum of squares of the seven detail blocks of its sibling
+ * group of children (the internal nodes rebuilt from the leaves by the two-scale decomposition,
+ * since an applied output holds assembled partial sums there), and 0 for a leaf.  The wavelet filters are any
+ * orthonormal complement of the two-scale filters; the norms do not depend on that choice.
+ * Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_tree_detail_norms(mwns_ctx* ctx, const mwns_tree* t, double* out);
+/* l2 pruning (Sec. 2.2): a new tree from t with sibling groups removed, starting on the finest
+ * scale, while the cumulative squared detail norm of what was removed stays <= eta^2 (eta >= 0,
+ * absolute).  Candidates are internal nodes whose eight children are leaves; within a scale they
+ * are taken in ascending order of their detail norm (ties by key), the first that would exceed the
+ * budget ends that scale, and the rest of the budget carries to the next coarser scale.  By
+ * orthonormality ||f_t - f_pruned||_2^2 equals the removed sum, returned in *removed (may be NULL).
+ * Acts on the function t's leaves represent: kept leaves keep their coefficients, internal nodes
+ * and new leaves hold the two-scale projections of t's leaves.  Synchronises.  Errors: EINVAL,
+ * ENOMEM, EDEVICE. */
+mwns_status mwns_tree_prune(mwns_ctx* ctx, const mwns_tree* t, double eta, mwns_tree** out, double* removed);
+/* Alg. 3 Step 4's discard of unnecessary blocks at accuracy eps: mwns_tree_prune with
+ * eta = eps ||f_t||_2 (the root block's norm and every detail norm, Parseval).  Errors: as
+ * mwns_tree_prune. */
+mwns_status mwns_tree_discard(mwns_ctx* ctx, const mwns_tree* t, double eps, mwns_tree** out, double* removed);
+
 /* mwns_tree_eval for callers that cannot allocate memory -- code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation: it calls no allocator (neither hipMalloc nor the
  * context's), copies nothing between host and device and does not synchronise.  Its working memory

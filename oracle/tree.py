@@ -15,9 +15,10 @@
     floor(2^j x) clamped to 2^j - 1.
   * details / detail_norms: the seven detail blocks of a sibling group, eq. decomp_wavelet along
     each dimension with G in at least one of them (App. A.2-A.3), and their squared norm.
-  * prune_l2 (Sec. 2.2): starting on the finest scale, sibling groups are removed while the
-    cumulative squared norm of the removed details stays within eta^2; by orthonormality that sum
-    is exactly ||f - f_pruned||_2^2.  discard: the same at eta = eps ||f||_2 (Alg. 3 Step 4).
+  * prune_l2 (Sec. 2.2): on the redundant tree rebuilt from the leaves, starting on the finest
+    scale, sibling groups are removed while the cumulative squared norm of the removed details
+    stays within eta^2; by orthonormality that sum is exactly ||f - f_pruned||_2^2.  discard: the
+    same at eta = eps ||f||_2 (Alg. 3 Step 4).
 Readings: the refinement threshold is eps * ||f||_2 with the closed-form L2 norm of the
 Gaussian sum over R^3 (the paper's absolute eps on a function scaled to unit norm); sources are
 unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2).  Pruning: the cumulative
@@ -321,6 +322,13 @@ def evaluate(tree, pts):
     return out
 
 
+def _modes3(A1, A2, A3, x):
+    """(A1 (x) A2 (x) A3) applied to blocks x[..., a, b, c], one dimension at a time."""
+    y = np.einsum("ia,...abc->...ibc", A1, x)
+    y = np.einsum("jb,...ibc->...ijc", A2, y)
+    return np.einsum("kc,...ijc->...ijk", A3, y)
+
+
 def details(k, child_coef):
     """(s, d) of sibling groups child_coef[..., 8, k, k, k] (child s = sx + 2 sy + 4 sz): s the
     parent block (eq. decomp_scaling per dimension) and d[..., 7, k, k, k] the detail blocks
@@ -333,7 +341,7 @@ def details(k, child_coef):
         F = [G if (t >> d) & 1 else H for d in range(3)]
         acc = 0.0
         for s in range(8):
-            acc = acc + _apply_sep(F[0][s & 1], F[1][(s >> 1) & 1], F[2][(s >> 2) & 1], child_coef[..., s, :, :, :])
+            acc = acc + _modes3(F[0][s & 1], F[1][(s >> 1) & 1], F[2][(s >> 2) & 1], child_coef[..., s, :, :, :])
         out.append(acc)
     return out[0], np.stack(out[1:], axis=-4)
 
@@ -349,7 +357,7 @@ def reconstruct(k, parent_coef, detail):
         acc = 0.0
         for t in range(8):
             F = [G if (t >> d) & 1 else H for d in range(3)]
-            acc = acc + _apply_sep(F[0][s & 1].T, F[1][(s >> 1) & 1].T, F[2][(s >> 2) & 1].T, blocks[t])
+            acc = acc + _modes3(F[0][s & 1].T, F[1][(s >> 1) & 1].T, F[2][(s >> 2) & 1].T, blocks[t])
         kids.append(acc)
     return np.stack(kids, axis=-4)
 
@@ -366,8 +374,12 @@ def detail_norms(tree):
 
 
 def prune_l2(tree, eta):
-    """Sec. 2.2's l2 pruning of a redundant tree within eta (absolute): returns (pruned Tree, the
-    removed squared norm <= eta^2).  The kept nodes keep their blocks."""
+    """Sec. 2.2's l2 pruning, within eta (absolute), of the function that the tree's leaves
+    represent: returns (pruned Tree, the removed squared norm <= eta^2).  The internal nodes are
+    first rebuilt from the leaves by the two-scale decomposition (a tree from an apply holds the
+    assembled partial sums there, which are not the leaves' coarse projections); the kept nodes
+    then keep those blocks."""
+    tree = redundant_tree(tree.k, tree.keys[tree.leaf == 1], tree.coef[tree.leaf == 1])
     dn = detail_norms(tree)
     leaf = tree.leaf.copy()
     alive = np.ones(tree.keys.size, dtype=bool)

@@ -21,7 +21,8 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
                    lib)
 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
-           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes",
+           "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes", "mwns_tree_detail_norms", "mwns_tree_prune",
+           "mwns_tree_discard",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
@@ -406,3 +407,26 @@ def mwns_tree_eval_noalloc(ctx, tree, npts, xyz_dev, out_dev):
     waited for (the values are ready when the context's stream passes the call)."""
     check(lib.mwns_tree_eval_noalloc(ctx.h, tree.h, int(npts), ctypes.c_void_p(int(xyz_dev)), ctypes.c_void_p(int(out_dev))),
           "mwns_tree_eval_noalloc")
+
+
+def mwns_tree_detail_norms(ctx, tree):
+    """Squared detail norm of every node in canonical order (0 at leaves)."""
+    out = np.zeros(mwns_tree_get_info(tree)["nnodes"])
+    check(lib.mwns_tree_detail_norms(ctx.h, tree.h, out.ctypes.data), "mwns_tree_detail_norms")
+    return out
+
+
+def mwns_tree_prune(ctx, tree, eta):
+    """l2 pruning within eta (absolute); returns (pruned Tree, removed squared norm)."""
+    h = ctypes.c_void_p()
+    removed = ctypes.c_double()
+    check(lib.mwns_tree_prune(ctx.h, tree.h, float(eta), ctypes.byref(h), ctypes.byref(removed)), "mwns_tree_prune")
+    return Tree(ctx, h), removed.value
+
+
+def mwns_tree_discard(ctx, tree, eps):
+    """Alg. 3 Step 4: pruning within eps ||tree||_2; returns (pruned Tree, removed squared norm)."""
+    h = ctypes.c_void_p()
+    removed = ctypes.c_double()
+    check(lib.mwns_tree_discard(ctx.h, tree.h, float(eps), ctypes.byref(h), ctypes.byref(removed)), "mwns_tree_discard")
+    return Tree(ctx, h), removed.value

@@ -91,6 +91,9 @@ SIGNATURES = {
     "mwns_tune_apply": (c_int, [c_vp, c_vp, c_vp, c_int, P(c_int), c_vp]),
     "mwns_tree_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "mwns_tree_eval_noalloc": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "mwns_tree_detail_norms": (c_int, [c_vp, c_vp, c_vp]),
+    "mwns_tree_prune": (c_int, [c_vp, c_vp, ctypes.c_double, P(c_vp), P(ctypes.c_double)]),
+    "mwns_tree_discard": (c_int, [c_vp, c_vp, ctypes.c_double, P(c_vp), P(ctypes.c_double)]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

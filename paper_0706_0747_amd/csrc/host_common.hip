@@ -180,6 +180,53 @@ void two_scale_filters(int k, double* H0, double* H1) {
     }
 }
 
+// G^(0), G^(1): the wavelets' two-scale coefficients (App. A.2-A.3).  The paper defines them only
+// through a reference it does not reproduce; any orthonormal basis of the complement of V_0 in V_1
+// serves here, since only the norm of the detail coefficients is used.  The k columns of [H0 H1]^T
+// are orthonormal in R^{2k}; Householder reflections that triangularise them give an orthogonal
+// Q = P_0 ... P_{k-1} whose last k columns span their orthogonal complement: G = those columns^T.
+void wavelet_filters(int k, double* G0, double* G1) {
+    const int n = 2 * k;
+    std::vector<double> H(2 * k * k), A(n * k), Q(n * n, 0.0), v(n);
+    two_scale_filters(k, H.data(), H.data() + k * k);
+    for (int c = 0; c < k; ++c)
+        for (int b = 0; b < k; ++b) {
+            A[b * k + c] = H[c * k + b];                 // rows 0..k-1: H0^T
+            A[(k + b) * k + c] = H[k * k + c * k + b];   // rows k..2k-1: H1^T
+        }
+    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+    for (int c = 0; c < k; ++c) {
+        double norm = 0.0;
+        for (int i = c; i < n; ++i) norm += A[i * k + c] * A[i * k + c];
+        norm = std::sqrt(norm);
+        const double alpha = A[c * k + c] > 0.0 ? -norm : norm;
+        std::fill(v.begin(), v.end(), 0.0);
+        for (int i = c; i < n; ++i) v[i] = A[i * k + c];
+        v[c] -= alpha;
+        double vv = 0.0;
+        for (int i = c; i < n; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        // A <- (I - 2 v v^T / v^T v) A ; Q <- Q (I - 2 v v^T / v^T v)
+        for (int cc = c; cc < k; ++cc) {
+            double d = 0.0;
+            for (int i = c; i < n; ++i) d += v[i] * A[i * k + cc];
+            d *= 2.0 / vv;
+            for (int i = c; i < n; ++i) A[i * k + cc] -= d * v[i];
+        }
+        for (int r = 0; r < n; ++r) {
+            double d = 0.0;
+            for (int i = c; i < n; ++i) d += Q[r * n + i] * v[i];
+            d *= 2.0 / vv;
+            for (int i = c; i < n; ++i) Q[r * n + i] -= d * v[i];
+        }
+    }
+    for (int r = 0; r < k; ++r)
+        for (int b = 0; b < k; ++b) {
+            G0[r * k + b] = Q[b * n + k + r];
+            G1[r * k + b] = Q[(k + b) * n + k + r];
+        }
+}
+
 // Phi^+_ab(x) = int_0^{1-x} phi_a(x+y) phi_b(y) dy on [0,1] is a polynomial of degree <= 2k-1
 // (App. A.4), so Phi^+_ab = sum_{n<2k} C[a][b][n] phi_n with C from a 2k-point rule; the inner
 // integral uses the k-point rule on [0, 1-x] (exact, degree a+b <= 2k-2).

@@ -96,6 +96,7 @@ struct Quad {
 Quad gauss_legendre01(int n);
 void legendre_phi(int k, double x, double* out);        // phi_a(x), a < k (no support cut)
 void two_scale_filters(int k, double* H0, double* H1);  // k x k row-major
+void wavelet_filters(int k, double* G0, double* G1);    // k x k row-major: [[H0 H1], [G0 G1]] orthogonal
 void crosscorr_plus_coeffs(int k, double* C);          // C[a][b][n], Phi^+_ab = sum_n C phi_n on [0,1]
 
 // Context / allocation -----------------------------------------------------------------------
