@@ -11,12 +11,14 @@ parents of the fine output and input boxes) the oracle follows Sec. 4:
                  N_dif(p) N_F(q) N_F(r) + N_upF(p) N_dif(q) N_F(r) + N_upF(p) N_upF(q) N_dif(r)
   term range: e_m = w_m est_m(L); the longest prefix and the longest suffix of m whose
       cumulative sums stay <= theta/2 are discarded, leaving [m1, m2]; the range is empty when
-      sum_m e_m <= theta ("discard terms whose cumulative contribution is below eps").
+      sum_m e_m <= theta (Sec. 4's term screening: terms whose summed contribution is small
+      against eps are dropped).
   theta = eps * sum_m w_m ||F^{0;m,0}||_F^3 (a scale-independent operator norm; reading).
   The kernel is radial, so norms are taken at |L| and the 3-D estimate at the sorted |L_d|;
   every sign/permutation variant of L gets the range of its canonical representative.
-  Grouping (Sec. 4, "Core / Boundary-1/2/3"): with group=True every L gets the union (hull) of
-  the ranges of the set it belongs to, where a coordinate is "core" when |L_d| <= 1.
+  Grouping (Sec. 4, the Core and Boundary-1/2/3 sets): with group=True every L gets the union
+  (hull) of the ranges of the set it belongs to, where a coordinate is in the core when
+  |L_d| <= 1.
 The plan is returned as an int32 array R[j, L1+Lmax, L2+Lmax, L3+Lmax, 2] of inclusive 0-based
 (m1, m2); an empty range is (0, -1).  Row j = 0 holds the root: all terms at L = 0.
 """
