@@ -1183,11 +1183,56 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                     }
             nested[ti] = in;
         }
+        // Whole-band pairs with net coefficient 0: at an internal child s, the pair (L, input child
+        // s', term m) with m in R_{j+1}(2L + s - s') is cancelled by the down band.  ov[t] holds, per
+        // coarse L of whole-band job t's box and per fine offset delta = s - s' in {-1,0,1}^3, how
+        // many of the job's terms lie in R_{j+1}(2L + delta); ovsum[t] the sums over the box.
+        const bool has_down = j > 0 && j < a.depth && j + 1 <= a.op->max_level;
+        const int32_t* rown = has_down ? a.op->plan.data() + (int64_t)(j + 1) * NLP3 * 2 : nullptr;
+        std::vector<std::vector<int>> ov(lw.tpl.size());
+        std::vector<std::array<double, 27>> ovsum(lw.tpl.size());
+        for (size_t ti = 0; ti < lw.tpl.size() && has_down; ++ti) {
+            const Tpl& t = lw.tpl[ti];
+            ovsum[ti].fill(0.0);
+            if (t.dpart) continue;
+            const int n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
+            ov[ti].assign((size_t)n1 * n2 * n3 * 27, 0);
+            for (int x = 0; x < n1; ++x)
+                for (int y = 0; y < n2; ++y)
+                    for (int z = 0; z < n3; ++z)
+                        for (int dl = 0; dl < 27; ++dl) {
+                            const int l0 = 2 * (t.lo[0] + x) + dl / 9 - 1, l1 = 2 * (t.lo[1] + y) + (dl / 3) % 3 - 1;
+                            const int l2 = 2 * (t.lo[2] + z) + dl % 3 - 1;
+                            if (std::abs(l0) > LP || std::abs(l1) > LP || std::abs(l2) > LP) continue;
+                            const int32_t* r = rown + (((l0 + LP) * NLP + (l1 + LP)) * NLP + (l2 + LP)) * 2;
+                            const int o = std::max(0, std::min(r[1], t.m2) - std::max(r[0], t.m1) + 1);
+                            ov[ti][((size_t)(x * n2 + y) * n3 + z) * 27 + dl] = o;
+                            ovsum[ti][dl] += o;
+                        }
+        }
         const int64_t pside = j > 0 ? ((int64_t)1 << (j - 1)) : 1;
         for (int64_t b = 0; b < lw.nout; ++b) {
             int64_t pp[3] = {0, 0, 0};
             if (j > 0) key_coords(lw.pk[b], pp);
             double c[NPREC] = {0.0, 0.0, 0.0, 0.0};
+            // cnt[delta]: pairs (internal child s, input child s') with s - s' = delta (child bit d = s_d)
+            double cnt[27];
+            const int cmb = lw.cm[b];
+            if (has_down && cmb != 0)
+                for (int dl = 0; dl < 27; ++dl) {
+                    const int dd[3] = {dl / 9 - 1, (dl / 3) % 3 - 1, dl % 3 - 1};
+                    int n = 0;
+                    for (int s = 0; s < 8; ++s) {
+                        if (!(cmb >> s & 1)) continue;
+                        bool ok = true;
+                        for (int e = 0; e < 3; ++e) {
+                            const int sp = ((s >> e) & 1) - dd[e];
+                            ok = ok && sp >= 0 && sp <= 1;
+                        }
+                        n += ok;
+                    }
+                    cnt[dl] = n;
+                }
             for (size_t ti = 0; ti < lw.tpl.size(); ++ti) {
                 const Tpl& t = lw.tpl[ti];
                 if (t.dpart && lw.cm[b] == 0) continue;
@@ -1203,7 +1248,30 @@ void build_descs(mwns_ctx* ctx, TreeApply& a, std::vector<LevelDesc>& descs,
                 const double fl = nt * 2.0 * D2 * D2 * D2 * D2 * steps;
                 a.flops += fl;
                 a.class_flops[t.prec] += fl;
-                if (!nested[ti]) a.own_flops += fl;
+                if (!nested[ti]) {
+                    double own = fl;
+                    if (has_down && cmb != 0 && !t.dpart) {
+                        // share of the job's (child, L, s', m) pairs whose net coefficient is 0
+                        const int n1 = t.hi[0] - t.lo[0] + 1, n2 = t.hi[1] - t.lo[1] + 1, n3 = t.hi[2] - t.lo[2] + 1;
+                        double canc = 0.0;
+                        if (nin[0] == n1 && nin[1] == n2 && nin[2] == n3) {
+                            for (int dl = 0; dl < 27; ++dl) canc += ovsum[ti][dl] * cnt[dl];
+                        } else {
+                            for (int x = 0; x < n1; ++x)
+                                for (int y = 0; y < n2; ++y)
+                                    for (int z = 0; z < n3; ++z) {
+                                        const int64_t L[3] = {t.lo[0] + x, t.lo[1] + y, t.lo[2] + z};
+                                        bool in = true;
+                                        for (int e = 0; e < 3; ++e) in = in && pp[e] - L[e] >= 0 && pp[e] - L[e] < pside;
+                                        if (!in) continue;
+                                        const int* o = ov[ti].data() + ((size_t)(x * n2 + y) * n3 + z) * 27;
+                                        for (int dl = 0; dl < 27; ++dl) canc += o[dl] * cnt[dl];
+                                    }
+                        }
+                        own *= 1.0 - canc / (64.0 * nt * nin[0] * nin[1] * nin[2]);
+                    }
+                    a.own_flops += own;
+                }
                 if (t.prec == PREC_F64 || (k > KNARROW && t.prec == PREC_F32)) {
                     const double f16 = t.prec == PREC_F64 ? 1.0 : 0.0;
                     if (k > KNARROW && t.dpart && lw.cm[b] != 0xff)
