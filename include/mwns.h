@@ -228,11 +228,14 @@ typedef struct {
     double err_bound;         /* a-priori bound on ||g - g_F64||_2 of the precision routing (0: all FP64) */
     double g_norm;            /* ||g||_2 over [0,1]^3 (0 with MWNS_NO_ASSEMBLY) */
     double class_flops[4];    /* useful_flops by precision class: FP64, FP32, BF16 compensated, BF16 */
-    double own_flops;         /* the method's own share of useful_flops: without the down-band jobs whose
-                                 terms all lie in the whole band's range at every coarse displacement of
-                                 their box (at internal children such a job only cancels whole-band terms
-                                 whose net coefficient c_m is 0; the brick-wide whole-band job computes
-                                 them because the leaf children of the same sibling group need them) */
+    double own_flops;         /* the method's own share of useful_flops (eq. apply_algo's net coefficients):
+                                 without the down-band jobs whose terms all lie in the whole band's range at
+                                 every coarse displacement of their box, and, of each whole-band job at a
+                                 sibling group with internal children, without the share of its (output
+                                 child, L, input child, term) block pairs whose net coefficient is 0 (an
+                                 internal child and a term in the finer band R_{j+1}(l)); the brick-wide
+                                 whole-band job computes those because the leaf children need the same
+                                 super-block products, and the down band cancels them */
     double f64_mfma_flops;    /* FP64 matrix-core flops issued by the FP64 class's contraction launches,
                                  padding of the 16 x 16 and 4 x 4 tiles included (what the hardware's
                                  FP64 MFMA operation counter reports, times 512 per operation) */
@@ -368,6 +371,65 @@ mwns_status mwns_tree_discard(mwns_ctx* ctx, const mwns_tree* t, double eps, mwn
  * caller.  Errors: EINVAL (NULL pointers, npts < 0, tree of another context), ERANGE (more nodes than
  * the array holds), ESTATE (no array address for the device), EDEVICE (launch failure). */
 mwns_status mwns_tree_eval_noalloc(mwns_ctx* ctx, const mwns_tree* t, int64_t npts, const double* xyz, double* out);
+
+/* ---- (7) The 1-D cotangent operator (Sec. 2.4, Alg. 2; the example of Sec. 2.4.2) -----------------
+ * (C f)(y) = p.v. int_0^1 cot(pi (y - x)) f(x) dx on the periodic unit interval (eq. CotangetKernel),
+ * applied in the modified ns-form.  1-D keys: level << 57 | translation (translation < 2^level),
+ * nodes in ascending key order; coefficient blocks are k doubles (row a = degree). */
+typedef struct mwns_op1 mwns_op1;
+typedef struct mwns_tree1 mwns_tree1;
+/* The operator for scales 0..max_level (0 <= max_level <= 40), order k (1..16), accuracy eps > 0:
+ * blocks r^{j;l}_ab = 2^-j p.v. int_{-1}^{1} cot(pi 2^-j (x + l)) Phi_ab(x) dx (eq. cot.01) for
+ * l = -65..65 on every scale (the device computes them by a 64-point Gauss-Legendre rule over the
+ * two polynomial pieces of the cross-correlation Phi, App. A.4), and the bands: B_j (j >= 1) is the
+ * smallest B such that the Frobenius norms of the difference super-blocks S^{j;L} - [H0 H1]^T
+ * r^{j-1;L} [H0 H1] (the blocks of T_j minus those of the up-sampled T_{j-1} between the children
+ * of two scale-(j-1) boxes at displacement L) sum to at most eps over the coarse periodic
+ * distances B < |L| <= min(32, 2^(j-2)).  The whole band of scale j holds the pairs of boxes whose
+ * parents are at periodic distance <= B_j (the band b_j = 2 B_j + 1 of eq. fine_scale_band).
+ * Errors: EINVAL, ENOMEM, EDEVICE, ERANGE (a band wider than 32 would be needed). */
+mwns_status mwns_cot1d_op_create(mwns_ctx* ctx, int k, double eps, int max_level, mwns_op1** out);
+/* bands[max_level + 2] (host): bands[j] = B_j for j = 1..max_level, bands[0] = bands[max_level+1] = 0;
+ * two-call size query: bands = NULL sets *count.  Errors: EINVAL, ERANGE (*count too small). */
+mwns_status mwns_cot1d_op_bands(const mwns_op1* op, int32_t* bands, int* count);
+/* Replaces the bands (count = max_level + 2 entries, each 0..32; entries 0 and max_level+1 ignored):
+ * any bands give an exact apply of the banded modified form.  Errors: EINVAL. */
+mwns_status mwns_cot1d_op_set_bands(mwns_op1* op, const int32_t* bands, int count);
+/* The blocks R[max_level + 1][131][k][k] (host, l = -65..65, row = output degree a); two-call size
+ * query (R = NULL sets *count).  Synchronises.  Errors: EINVAL, ERANGE. */
+mwns_status mwns_cot1d_op_blocks(mwns_ctx* ctx, const mwns_op1* op, double* R, size_t* count);
+void mwns_cot1d_op_destroy(mwns_op1* op);
+/* Alg. 1 in one dimension for f(x) = sum_i weights_i sum_n exp(-exps_i (x + n - centers_i)^2) (host
+ * arrays of n entries; exps > 0): boxes from level j0 (0 <= j0 <= jmax <= 40) are refined while the
+ * largest difference between f and the box's polynomial at both children's k Gauss-Legendre nodes
+ * exceeds the absolute threshold thr (>= 0); boxes at jmax are leaves.  A leaf keeps its own
+ * coefficients (eq. fvals2coefs); internal nodes hold the two-scale projections (eq.
+ * decomp_scaling).  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_cot1d_project(mwns_ctx* ctx, int k, double thr, int j0, int jmax, int n, const double* centers,
+                               const double* exps, const double* weights, mwns_tree1** out);
+/* A tree from leaves (host keys[nleaves], coeffs[nleaves][k]) that tile [0,1): ancestors added,
+ * internal nodes by the two-scale relation.  Errors: EINVAL (keys that do not form a tree). */
+mwns_status mwns_cot1d_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
+                                   mwns_tree1** out);
+/* g = C f in the modified ns-form (eq. apply_algo, Alg. 2).  The output tree is f's tree refined
+ * until no leaf's whole band holds an internal node of its scale (a coarse leaf beside refined input
+ * then receives the finer scales' terms at its children); input blocks missing from f come from
+ * their nearest ancestor by zero-detail reconstruction (Step 2).  At scale j >= 1 a leaf takes the
+ * pairs with parents at periodic distance <= B_j and an internal node those minus the pairs at fine
+ * periodic distance <= B_{j+1}; the root takes T_0 f_0 only when it is a leaf; g is then assembled
+ * top-down (eq. g_assemble): leaves hold g, internal nodes the partial sums.  *ms_contract (may be
+ * NULL) receives the device time of the contraction kernel.  Synchronises.  Errors: EINVAL (orders
+ * differ, tree deeper than the operator), ENOMEM, EDEVICE. */
+mwns_status mwns_cot1d_apply(mwns_ctx* ctx, const mwns_op1* op, const mwns_tree1* f, mwns_tree1** g,
+                             double* ms_contract);
+/* Nodes of t: keys, leaf flags and coefficient blocks (host arrays of *nnodes entries, each may be
+ * NULL); two-call size query with all three NULL.  Synchronises.  Errors: EINVAL, ERANGE. */
+mwns_status mwns_cot1d_export(mwns_ctx* ctx, const mwns_tree1* t, int64_t* nnodes, uint64_t* keys, uint8_t* is_leaf,
+                              double* coeffs);
+/* Values of t's leaf expansions at npts points x in [0,1] (host arrays; the leaf containing x, App.
+ * A.1).  Synchronises.  Errors: EINVAL (a point outside [0,1]), ENOMEM, EDEVICE. */
+mwns_status mwns_cot1d_eval(mwns_ctx* ctx, const mwns_tree1* t, int64_t npts, const double* x, double* out);
+void mwns_tree1_destroy(mwns_tree1* t);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,9 @@ from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, 
 
 __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes", "mwns_tree_detail_norms", "mwns_tree_prune",
-           "mwns_tree_discard",
+           "mwns_tree_discard", "Op1", "Tree1", "mwns_cot1d_op_create", "mwns_cot1d_op_bands", "mwns_cot1d_op_set_bands",
+           "mwns_cot1d_op_blocks", "mwns_cot1d_project", "mwns_cot1d_from_leaves", "mwns_cot1d_apply", "mwns_cot1d_export",
+           "mwns_cot1d_eval",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
@@ -430,3 +432,106 @@ def mwns_tree_discard(ctx, tree, eps):
     removed = ctypes.c_double()
     check(lib.mwns_tree_discard(ctx.h, tree.h, float(eps), ctypes.byref(h), ctypes.byref(removed)), "mwns_tree_discard")
     return Tree(ctx, h), removed.value
+
+
+# ---- the 1-D cotangent operator (Sec. 2.4, Alg. 2) ---------------------------------------------
+
+
+class Op1:
+    def __init__(self, ctx, h, k, max_level):
+        self.ctx, self.h, self.k, self.max_level = ctx, h, k, max_level
+
+    def close(self, _destroy=lib.mwns_cot1d_op_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Tree1:
+    def __init__(self, ctx, h, k):
+        self.ctx, self.h, self.k = ctx, h, k
+
+    def close(self, _destroy=lib.mwns_tree1_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def mwns_cot1d_op_create(ctx, k, eps, max_level):
+    h = ctypes.c_void_p()
+    check(lib.mwns_cot1d_op_create(ctx.h, int(k), float(eps), int(max_level), ctypes.byref(h)), "mwns_cot1d_op_create")
+    return Op1(ctx, h, int(k), int(max_level))
+
+
+def mwns_cot1d_op_bands(op):
+    n = ctypes.c_int(0)
+    check(lib.mwns_cot1d_op_bands(op.h, None, ctypes.byref(n)), "mwns_cot1d_op_bands")
+    out = np.zeros(n.value, dtype=np.int32)
+    check(lib.mwns_cot1d_op_bands(op.h, out.ctypes.data, ctypes.byref(n)), "mwns_cot1d_op_bands")
+    return out
+
+
+def mwns_cot1d_op_set_bands(op, bands):
+    b = np.ascontiguousarray(bands, dtype=np.int32)
+    check(lib.mwns_cot1d_op_set_bands(op.h, b.ctypes.data, int(b.size)), "mwns_cot1d_op_set_bands")
+
+
+def mwns_cot1d_op_blocks(ctx, op):
+    """R[max_level + 1][131][k][k] for l = -65..65."""
+    n = ctypes.c_size_t(0)
+    check(lib.mwns_cot1d_op_blocks(ctx.h, op.h, None, ctypes.byref(n)), "mwns_cot1d_op_blocks")
+    out = np.zeros(n.value)
+    check(lib.mwns_cot1d_op_blocks(ctx.h, op.h, out.ctypes.data, ctypes.byref(n)), "mwns_cot1d_op_blocks")
+    return out.reshape(op.max_level + 1, 131, op.k, op.k)
+
+
+def mwns_cot1d_project(ctx, k, thr, j0, jmax, centers, exps, weights):
+    c = np.ascontiguousarray(centers, dtype=np.float64)
+    a = np.ascontiguousarray(exps, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    h = ctypes.c_void_p()
+    check(lib.mwns_cot1d_project(ctx.h, int(k), float(thr), int(j0), int(jmax), int(c.size), c.ctypes.data,
+                                 a.ctypes.data, w.ctypes.data, ctypes.byref(h)), "mwns_cot1d_project")
+    return Tree1(ctx, h, int(k))
+
+
+def mwns_cot1d_from_leaves(ctx, k, keys, coeffs):
+    kk = np.ascontiguousarray(keys, dtype=np.uint64)
+    cc = np.ascontiguousarray(coeffs, dtype=np.float64)
+    h = ctypes.c_void_p()
+    check(lib.mwns_cot1d_from_leaves(ctx.h, int(k), int(kk.size), kk.ctypes.data, cc.ctypes.data, ctypes.byref(h)),
+          "mwns_cot1d_from_leaves")
+    return Tree1(ctx, h, int(k))
+
+
+def mwns_cot1d_apply(ctx, op, f):
+    """(g, device ms of the contraction kernel)."""
+    h = ctypes.c_void_p()
+    ms = ctypes.c_double()
+    check(lib.mwns_cot1d_apply(ctx.h, op.h, f.h, ctypes.byref(h), ctypes.byref(ms)), "mwns_cot1d_apply")
+    return Tree1(ctx, h, f.k), ms.value
+
+
+def mwns_cot1d_export(ctx, t):
+    """(keys, is_leaf, coeffs[N, k]) in key order."""
+    n = ctypes.c_int64(0)
+    check(lib.mwns_cot1d_export(ctx.h, t.h, ctypes.byref(n), None, None, None), "mwns_cot1d_export")
+    keys = np.zeros(n.value, dtype=np.uint64)
+    leaf = np.zeros(n.value, dtype=np.uint8)
+    coef = np.zeros((n.value, t.k))
+    check(lib.mwns_cot1d_export(ctx.h, t.h, ctypes.byref(n), keys.ctypes.data, leaf.ctypes.data, coef.ctypes.data),
+          "mwns_cot1d_export")
+    return keys, leaf, coef
+
+
+def mwns_cot1d_eval(ctx, t, x):
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(xx.size)
+    check(lib.mwns_cot1d_eval(ctx.h, t.h, int(xx.size), xx.ctypes.data, out.ctypes.data), "mwns_cot1d_eval")
+    return out

@@ -94,6 +94,17 @@ SIGNATURES = {
     "mwns_tree_detail_norms": (c_int, [c_vp, c_vp, c_vp]),
     "mwns_tree_prune": (c_int, [c_vp, c_vp, ctypes.c_double, P(c_vp), P(ctypes.c_double)]),
     "mwns_tree_discard": (c_int, [c_vp, c_vp, ctypes.c_double, P(c_vp), P(ctypes.c_double)]),
+    "mwns_cot1d_op_create": (c_int, [c_vp, c_int, c_dbl, c_int, P(c_vp)]),
+    "mwns_cot1d_op_bands": (c_int, [c_vp, c_vp, P(c_int)]),
+    "mwns_cot1d_op_set_bands": (c_int, [c_vp, c_vp, c_int]),
+    "mwns_cot1d_op_blocks": (c_int, [c_vp, c_vp, c_vp, P(c_size)]),
+    "mwns_cot1d_op_destroy": (None, [c_vp]),
+    "mwns_cot1d_project": (c_int, [c_vp, c_int, c_dbl, c_int, c_int, c_int, c_vp, c_vp, c_vp, P(c_vp)]),
+    "mwns_cot1d_from_leaves": (c_int, [c_vp, c_int, c_i64, c_vp, c_vp, P(c_vp)]),
+    "mwns_cot1d_apply": (c_int, [c_vp, c_vp, c_vp, P(c_vp), P(c_dbl)]),
+    "mwns_cot1d_export": (c_int, [c_vp, c_vp, P(c_i64), c_vp, c_vp, c_vp]),
+    "mwns_cot1d_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "mwns_tree1_destroy": (None, [c_vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():
