@@ -411,9 +411,10 @@ mwns_status mwns_cot1d_project(mwns_ctx* ctx, int k, double thr, int j0, int jma
  * internal nodes by the two-scale relation.  Errors: EINVAL (keys that do not form a tree). */
 mwns_status mwns_cot1d_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
                                    mwns_tree1** out);
-/* g = C f in the modified ns-form (eq. apply_algo, Alg. 2).  The output tree is f's tree refined
- * until no leaf's whole band holds an internal node of its scale (a coarse leaf beside refined input
- * then receives the finer scales' terms at its children); input blocks missing from f come from
+/* g = C f in the modified ns-form (eq. apply_algo, Alg. 2).  The output tree is f's tree with every
+ * leaf of scale j refined whose whole band holds an internal node of f of scale j, and so on for
+ * the added children (a coarse leaf beside refined input then receives the finer scales' terms at
+ * its children); input blocks missing from f come from
  * their nearest ancestor by zero-detail reconstruction (Step 2).  At scale j >= 1 a leaf takes the
  * pairs with parents at periodic distance <= B_j and an internal node those minus the pairs at fine
  * periodic distance <= B_{j+1}; the root takes T_0 f_0 only when it is a leaf; g is then assembled

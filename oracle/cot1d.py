@@ -35,9 +35,10 @@ Readings of the paper taken here:
   * The output tree (Alg. 2 copies the redundant tree of f and assumes it suffices for g): for the
     cotangent kernel a coarse leaf next to refined input would take P_j C P_j f, which misses the
     finer scales' difference terms at its (absent) children; the output tree here is the redundant
-    tree refined until no leaf's whole band holds an internal node (`skeleton`).  On Table 1's
-    inputs this reproduces the printed E_2 (absolute l2 error) to two digits for p = 5, 8, 11 and
-    stays below it for p = 14; without it the coarse leaves carry errors 100-1000 times larger.
+    tree with every leaf refined whose whole band holds an internal node of f of its scale, and so
+    on for the added children (`skeleton`).  On Table 1's inputs this reproduces the printed E_2
+    (absolute l2 error) to two digits for p = 5, 8, 11 and stays below it for p = 14; without it the
+    coarse leaves carry errors 100-1000 times larger.
   * The closed form: near x = y, cot(pi (y - x)) behaves as 1 / (pi (y - x)), so C acts on
     exp(-a x^2) as the Hilbert transform with that kernel, which gives + exp(-a y^2) Erfi(sqrt(a) y);
     eq. cot_gauss prints the opposite sign.  Its Fourier form also omits the factor (-1)^n that the
@@ -70,9 +71,19 @@ def cot_blocks(k, j, ls, ngl=64):
     return s * (np.einsum("q,iq,qab->iab", w, cp, pp) + np.einsum("q,iq,qab->iab", w, cm, pm))
 
 
-def cot_table(k, nmax, ngl=64):
-    """[r^{j;l} for l = 0..2^j - 1] for j = 0..nmax (a list of arrays (2^j, k, k))."""
-    return [cot_blocks(k, j, list(range(2 ** j)), ngl) for j in range(nmax + 1)]
+def cot_table(k, nmax, ngl=64, lmax=None):
+    """r^{j;l} for j = 0..nmax, indexed by l mod 2^j: per scale an array (2^j, k, k) of every l, or,
+    with lmax, a dict of the residues of l = -lmax..lmax (enough for bands up to (lmax - 1) / 2 and
+    difference norms up to distance (lmax - 1) / 2)."""
+    out = []
+    for j in range(nmax + 1):
+        n = 2 ** j
+        if lmax is None or n <= 2 * lmax + 1:
+            out.append(cot_blocks(k, j, list(range(n)), ngl))
+        else:
+            ls = list(range(-lmax, lmax + 1))
+            out.append({l % n: b for l, b in zip(ls, cot_blocks(k, j, ls, ngl))})
+    return out
 
 
 def super_blocks(k, R, j, L):
@@ -245,29 +256,32 @@ def _input_block(tree, j, l):
 
 
 def skeleton(tree, B):
-    """The output tree: the redundant tree of f, refined until no leaf's whole band (coarse periodic
-    distance <= B_j) holds an internal node of its scale; the blocks of f at added nodes come from
-    their nearest ancestor (Alg. 2, Step 2).  A coarse leaf next to refined input then receives the
-    finer scales' difference terms at its children; with the redundant tree alone it would take
-    P_j C P_j f, whose error near the refined neighbour is not bounded by eps for this singular
-    kernel."""
+    """The output tree: the redundant tree of f where a leaf b of scale j is refined when an internal
+    node of f of scale j lies in its whole band (parents at periodic distance <= B_j), and so on for
+    the children this adds (each checked against f's internal nodes of its own scale).  The blocks
+    of f at added nodes come from their nearest ancestor (Alg. 2, Step 2).  f has finer details in
+    that band, and the difference operators of the finer scales carry them to b's (absent) children;
+    with f's tree alone b would take P_j C P_j f, whose error next to refined input is not bounded by
+    eps for this singular kernel.  Where f has no details within the band those terms project to
+    zero on b."""
+    finternal = {}
+    for j, l, lf in zip(tree.level, tree.trans, tree.leaf):
+        if not lf:
+            finternal.setdefault(int(j), []).append(int(l) >> 1)
     nodes = {(int(j), int(l)): bool(lf) for j, l, lf in zip(tree.level, tree.trans, tree.leaf)}
-    changed = True
-    while changed:
-        changed = False
-        internal = {}
-        for (j, l), lf in nodes.items():
-            if not lf:
-                internal.setdefault(j, []).append(l)
-        for (j, l), lf in sorted(nodes.items()):
-            if not lf or j == 0 or j not in internal:
+    todo = sorted(key for key, lf in nodes.items() if lf)
+    while todo:
+        nxt = []
+        for (j, l) in todo:
+            if j == 0 or j not in finternal:
                 continue
-            n = 2 ** j
-            if any(periodic_distance((l >> 1) - (bp >> 1), n // 2) <= B[j] for bp in internal[j]):
+            nc = 2 ** (j - 1)
+            if any(periodic_distance((l >> 1) - cp, nc) <= B[j] for cp in finternal[j]):
                 nodes[(j, l)] = False
                 nodes[(j + 1, 2 * l)] = True
                 nodes[(j + 1, 2 * l + 1)] = True
-                changed = True
+                nxt += [(j + 1, 2 * l), (j + 1, 2 * l + 1)]
+        todo = nxt
     keys = sorted(nodes)
     coef = np.array([_input_block(tree, j, l) for (j, l) in keys])
     return Tree1(tree.k, [q[0] for q in keys], [q[1] for q in keys], [1 if nodes[q] else 0 for q in keys], coef)
@@ -290,12 +304,19 @@ def apply_modified(tree, R, B, out=None):
             continue
         n = 2 ** j
         acc = np.zeros(k)
-        for l in range(n):
+        # the coefficient is 0 unless the fine distance is <= 2 B_j + 1 (coarse distance <= B_j) or
+        # <= B_{j+1} (internal nodes); each residue l mod 2^j once
+        reach = max(2 * B[j] + 1, 0 if lf else B[j + 1])
+        seen = set()
+        for l in range(-reach, reach + 1):
+            if l % n in seen:
+                continue
+            seen.add(l % n)
             bp = (b - l) % n
             L = periodic_distance((b >> 1) - (bp >> 1), n // 2)
             c = (1 if L <= B[j] else 0) - (0 if lf else (1 if periodic_distance(l, n) <= B[j + 1] else 0))
             if c:
-                acc += c * (R[j][l] @ _input_block(tree, j, bp))
+                acc += c * (R[j][l % n] @ _input_block(tree, j, bp))
         ghat[i] = acc
     return ghat
 

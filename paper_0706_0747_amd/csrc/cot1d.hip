@@ -9,8 +9,8 @@
 //     S^{j;L} - [H0 H1]^T r^{j-1;L} [H0 H1] (Sec. 2.3-2.4).
 //   * projection: Alg. 1 in one dimension with an absolute threshold; compression to the
 //     redundant tree (eq. decomp_scaling).
-//   * apply: the output tree is the redundant tree of f refined until no leaf's whole band holds an
-//     internal node of its scale; input blocks from the tree or from the nearest ancestor by
+//   * apply: the output tree is the redundant tree of f with every leaf refined whose whole band
+//     holds an internal node of f of its scale (and so on for the added children); input blocks from the tree or from the nearest ancestor by
 //     zero-detail reconstruction (Alg. 2 Step 2); the banded contraction of eq. apply_algo (leaf:
 //     coarse distance <= B_j; internal: minus fine distance <= B_{j+1}); assembly (eq. g_assemble).
 //   * evaluation at points (App. A.1).
@@ -618,46 +618,50 @@ mwns_status mwns_cot1d_apply(mwns_ctx* ctx, const mwns_op1* op, const mwns_tree1
     if (f->depth > op->max_level) fail(MWNS_EINVAL, "the tree is deeper than the operator's max_level");
     const int k = f->k;
     const std::vector<int32_t>& B = op->band;
-    // output tree: f's nodes, refined until no leaf's whole band holds an internal node of its scale
+    // output tree: f's nodes; a leaf of scale j is refined when an internal node of f of scale j
+    // lies in its whole band (parents at periodic distance <= B_j), and so on for the added children
     std::map<uint64_t, uint8_t> nodes;
-    for (size_t i = 0; i < f->keys.size(); ++i) nodes[f->keys[i]] = f->leaf[i];
-    for (bool changed = true; changed;) {
-        changed = false;
-        std::map<int, std::vector<int64_t>> ipar;   // per level: parents (scale j-1) of internal nodes, sorted
-        for (const auto& kv : nodes)
-            if (!kv.second && key1_level(kv.first) > 0) ipar[key1_level(kv.first)].push_back(key1_trans(kv.first) >> 1);
-        for (auto& kv : ipar) {
-            std::sort(kv.second.begin(), kv.second.end());
-            kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
-        }
-        // is there a parent cp of an internal node with periodic distance |c - cp| <= b on nc boxes?
-        auto near = [](const std::vector<int64_t>& v, int64_t c, int64_t b, int64_t nc) {
-            if (2 * b + 1 >= nc) return !v.empty();
-            auto any_in = [&](int64_t lo, int64_t hi) {   // some entry in [lo, hi]
-                auto it = std::lower_bound(v.begin(), v.end(), lo);
-                return it != v.end() && *it <= hi;
-            };
-            const int64_t lo = c - b, hi = c + b;
-            if (lo < 0) return any_in(0, hi) || any_in(lo + nc, nc - 1);
-            if (hi >= nc) return any_in(lo, nc - 1) || any_in(0, hi - nc);
-            return any_in(lo, hi);
+    std::map<int, std::vector<int64_t>> ipar;   // per scale: parents of f's internal nodes, sorted
+    for (size_t i = 0; i < f->keys.size(); ++i) {
+        nodes[f->keys[i]] = f->leaf[i];
+        if (!f->leaf[i] && key1_level(f->keys[i]) > 0)
+            ipar[key1_level(f->keys[i])].push_back(key1_trans(f->keys[i]) >> 1);
+    }
+    for (auto& kv : ipar) {
+        std::sort(kv.second.begin(), kv.second.end());
+        kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
+    }
+    // is there an entry cp of v with periodic distance |c - cp| <= b on nc boxes?
+    auto near = [](const std::vector<int64_t>& v, int64_t c, int64_t b, int64_t nc) {
+        if (2 * b + 1 >= nc) return !v.empty();
+        auto any_in = [&](int64_t lo, int64_t hi) {
+            auto it = std::lower_bound(v.begin(), v.end(), lo);
+            return it != v.end() && *it <= hi;
         };
-        std::vector<uint64_t> refine;
-        for (const auto& kv : nodes) {
-            const int j = key1_level(kv.first);
-            if (!kv.second || j == 0) continue;
-            auto it = ipar.find(j);
-            if (it == ipar.end()) continue;
-            if (near(it->second, key1_trans(kv.first) >> 1, B[j], (int64_t)1 << (j - 1))) refine.push_back(kv.first);
-        }
-        for (uint64_t kk : refine) {
+        const int64_t lo = c - b, hi = c + b;
+        if (lo < 0) return any_in(0, hi) || any_in(lo + nc, nc - 1);
+        if (hi >= nc) return any_in(lo, nc - 1) || any_in(0, hi - nc);
+        return any_in(lo, hi);
+    };
+    std::vector<uint64_t> todo;
+    for (const auto& kv : nodes)
+        if (kv.second) todo.push_back(kv.first);
+    while (!todo.empty()) {
+        std::vector<uint64_t> next;
+        for (uint64_t kk : todo) {
             const int j = key1_level(kk);
+            auto it = ipar.find(j);
+            if (j == 0 || it == ipar.end()) continue;
+            if (!near(it->second, key1_trans(kk) >> 1, B[j], (int64_t)1 << (j - 1))) continue;
             if (j + 1 > op->max_level) fail(MWNS_ERANGE, "the output tree would be deeper than the operator's max_level");
             nodes[kk] = 0;
-            nodes[key1(j + 1, 2 * key1_trans(kk))] = 1;
-            nodes[key1(j + 1, 2 * key1_trans(kk) + 1)] = 1;
-            changed = true;
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t ck = key1(j + 1, 2 * key1_trans(kk) + c);
+                nodes[ck] = 1;
+                next.push_back(ck);
+            }
         }
+        todo.swap(next);
     }
     std::vector<uint64_t> okeys;
     std::vector<uint8_t> oleaf;

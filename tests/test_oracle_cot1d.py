@@ -144,22 +144,28 @@ def test_full_bands_on_a_uniform_tree_equal_the_dense_operator():
     assert np.abs(g[lv] - dense).max() < 1e-13
 
 
-def test_skeleton_leaves_see_no_internal_node_in_their_band():
+def test_skeleton_leaves_see_no_internal_node_of_f_in_their_band():
     rng = np.random.default_rng(5)
     tr = _random_tree(rng, 3, 7)
     B = [0, 0, 1, 1, 1, 2, 1, 1, 0]
     sk = C.skeleton(tr, B)
-    internal = {(int(j), int(l)) for j, l, lf in zip(sk.level, sk.trans, sk.leaf) if not lf}
+    finternal = {(int(j), int(l)) for j, l, lf in zip(tr.level, tr.trans, tr.leaf) if not lf}
     for j, l, lf in zip(sk.level, sk.trans, sk.leaf):
         if lf and j > 0:
             n = 2 ** int(j)
-            for (jj, bp) in internal:
+            for (jj, bp) in finternal:
                 if jj == j:
                     assert C.periodic_distance((int(l) >> 1) - (bp >> 1), n // 2) > B[j]
-    # every node of f's tree is in the skeleton, and siblings come in pairs
-    keys = {(int(j), int(l)) for j, l in zip(sk.level, sk.trans)}
+    # every node of f's tree is in the skeleton, siblings come in pairs, and every added internal
+    # node has an internal node of f of its scale in its band
+    keys = {(int(j), int(l)): int(lf) for j, l, lf in zip(sk.level, sk.trans, sk.leaf)}
     assert all((int(j), int(l)) in keys for j, l in zip(tr.level, tr.trans))
     assert all((j, l ^ 1) in keys for (j, l) in keys if j > 0)
+    fkeys = {(int(j), int(l)): int(lf) for j, l, lf in zip(tr.level, tr.trans, tr.leaf)}
+    for (j, l), lf in keys.items():
+        if not lf and fkeys.get((j, l), 1):
+            assert any(jj == j and C.periodic_distance((l >> 1) - (bp >> 1), 2 ** (j - 1)) <= B[j]
+                       for (jj, bp) in finternal)
 
 
 @pytest.mark.parametrize("row", _table1())
