@@ -9,9 +9,12 @@ Sources are sums of unit-mass Gaussians c_i (a_i/pi)^{3/2} exp(-a_i |x - x_i|^2)
 Kernels are (-Delta + mu^2)^(-alpha): Poisson (mu=0, alpha=1, 1/(4 pi r)), Yukawa / bound-state
 Helmholtz (alpha=1, e^{-mu r}/(4 pi r)) and fractional (mu=0).
 """
+import json
+import os
+
 import numpy as np
 
-__all__ = ["Workload", "c1", "c2", "c3", "c4_member", "c5", "small_adaptive", "points"]
+__all__ = ["Workload", "c1", "c2", "c3", "c4_draw", "c4_member", "c5", "cot1d_example", "cot1d_many", "small_adaptive", "points"]
 
 
 class Workload(dict):
@@ -61,11 +64,18 @@ def c3(seed=3, n=20):
                     alpha=1.0, xyz=xyz, a=a, c=c)
 
 
-def c4_member(i):
-    """Member i (0..63) of the batch of uneven solves: kernel uniform over {Poisson, Yukawa
-    mu~U[0.5,10], fractional alpha~U(0.2,1.4)}; (k, eps) uniform over (6,1e-4), (8,1e-6),
-    (10,1e-8); Gaussian count log-uniform in [1, 64] with exponents log-uniform in [10, 10^u],
-    u ~ U[2,4]."""
+C4_POOL = 1024                 # Gaussians drawn per batch member; a member uses a prefix of them
+C4_LEAVES = (1e3, 2e5)         # range of the members' leaf counts (log-uniform targets)
+C4_SIZES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_sizes.json")
+
+
+def c4_draw(i):
+    """The random part of batch member i (0..63), in draw order: kernel uniform over {Poisson,
+    Yukawa mu~U[0.5,10], fractional alpha~U(0.2,1.4)}; (k, eps) uniform over (6,1e-4), (8,1e-6),
+    (10,1e-8); a target leaf count log-uniform in C4_LEAVES; the exponents' upper limit 10^u with u
+    rising linearly from 2 to 5 over the log of that range (more leaves need narrower Gaussians);
+    a pool of C4_POOL Gaussians (exponents log-uniform in [10, 10^u], centres in [0.2, 0.8]^3,
+    weights N(0,1))."""
     rng = _rng(1000 + i)
     kind = int(rng.integers(0, 3))
     mu, alpha = 0.0, 1.0
@@ -74,11 +84,24 @@ def c4_member(i):
     elif kind == 2:
         alpha = float(rng.uniform(0.2, 1.4))
     k, eps = [(6, 1e-4), (8, 1e-6), (10, 1e-8)][int(rng.integers(0, 3))]
-    n = int(round(10.0 ** rng.uniform(0.0, np.log10(64.0))))
-    hi = float(rng.uniform(2.0, 4.0))
-    xyz, a, c = _gauss_sum(rng, n, 1.0, hi)
-    return Workload(name="batch_member_%d" % i, seed=1000 + i, k=k, eps=eps, j0=2, jmax=12, mu=mu,
-                    alpha=alpha, xyz=xyz, a=a, c=c)
+    lo, hi = np.log10(C4_LEAVES[0]), np.log10(C4_LEAVES[1])
+    target = float(10.0 ** rng.uniform(lo, hi))
+    u = 2.0 + 3.0 * (np.log10(target) - lo) / (hi - lo)
+    xyz, a, c = _gauss_sum(rng, C4_POOL, 1.0, u)
+    return Workload(seed=1000 + i, k=k, eps=eps, j0=2, jmax=12, mu=mu, alpha=alpha, target=target, u=u,
+                    xyz=xyz, a=a, c=c)
+
+
+def c4_member(i, n=None):
+    """Member i of the batch of uneven solves: the first n Gaussians of c4_draw(i)'s pool, n as
+    calibrated per member (stored in c4_sizes.json by calibrate_c4.py, beside this file) so that
+    the members' leaf counts spread log-uniformly over C4_LEAVES."""
+    d = c4_draw(i)
+    if n is None:
+        with open(C4_SIZES) as fh:
+            n = int(json.load(fh)["members"][str(i)]["n"])
+    return Workload(name="batch_member_%d" % i, seed=d.seed, k=d.k, eps=d.eps, j0=d.j0, jmax=d.jmax, mu=d.mu,
+                    alpha=d.alpha, xyz=d.xyz[:n], a=d.a[:n], c=d.c[:n])
 
 
 def c5(seed=5, n=500):
@@ -88,6 +111,24 @@ def c5(seed=5, n=500):
     xyz, a, c = _gauss_sum(rng, n, 1.0, 5.0)
     return Workload(name="poisson_k10_eps1e-10_500gauss", seed=seed, k=10, eps=1e-10, j0=2, jmax=14, mu=0.0,
                     alpha=1.0, xyz=xyz, a=a, c=c)
+
+
+def cot1d_example(k, eps):
+    """The 1-D cotangent example (Sec. 2.4.2): f(x) = sum_n exp(-300 (x + n - 1/2)^2) on the periodic
+    unit interval, order k, accuracy eps (also the absolute refinement threshold), from level 2."""
+    return Workload(name="cot1d_gauss300_k%d" % k, seed=None, k=k, eps=eps, thr=eps, j0=2, jmax=30,
+                    centers=np.array([0.5]), exps=np.array([300.0]), weights=np.array([1.0]))
+
+
+def cot1d_many(seed=11, n=128):
+    """A larger 1-D input for the cotangent operator: n periodized Gaussians with exponents
+    log-uniform in [1e2, 1e7], centres uniform in [0,1), weights N(0,1); k = 10, eps = 1e-9."""
+    rng = _rng(seed)
+    exps = 10.0 ** rng.uniform(2.0, 7.0, n)
+    centers = rng.uniform(0.0, 1.0, n)
+    weights = rng.normal(0.0, 1.0, n)
+    return Workload(name="cot1d_%dgauss_k10" % n, seed=seed, k=10, eps=1e-9, thr=1e-9, j0=2, jmax=30,
+                    centers=centers, exps=exps, weights=weights)
 
 
 def small_adaptive(seed, k=6, eps=1e-4, n=3, jmax=6, mu=0.0, alpha=1.0):
