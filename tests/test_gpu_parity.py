@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
+from parity_util import per_node_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -105,9 +106,11 @@ def test_apply_matches_oracle(M, ctx, case):
     gt, st = M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)
     _, _, ghat = M.mwns_tree_export(ctx, gt)
     assert np.linalg.norm(ghat - gh) <= 1e-12 * np.linalg.norm(gh)
+    assert per_node_ok(ghat, gh)
     gt2, st2 = M.mwns_apply(ctx, op, f)
     _, _, gg = M.mwns_tree_export(ctx, gt2)
     assert np.linalg.norm(gg - g) <= 1e-12 * np.linalg.norm(g)
+    assert per_node_ok(gg, g)
     assert st2["useful_flops"] > 0
     # the device's contraction count equals the count of non-zero coefficients from the plan
     import bench
@@ -222,6 +225,7 @@ def test_c2_full_size_sampled(M, ctx):
     ref = np.stack([A.assemble_chain(ot, i, lambda n: gh[n]) for i in sample])
     got = gg[sample]
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert per_node_ok(got, ref)
 
 
 @pytest.mark.parametrize("k", [1, 3, 5, 7])

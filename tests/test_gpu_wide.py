@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads
+from parity_util import per_node_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +59,11 @@ def test_wide_orders_match_oracle(M, ctx, case):
     g = A.assemble(ot, gh)
     _, _, ghat = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)[0])
     assert np.linalg.norm(ghat - gh) <= 1e-12 * np.linalg.norm(gh)
+    assert per_node_ok(ghat, gh)
     gt, st = M.mwns_apply(ctx, op, f)
     _, _, gg = M.mwns_tree_export(ctx, gt)
     assert np.linalg.norm(gg - g) <= 1e-12 * np.linalg.norm(g)
+    assert per_node_ok(gg, g)
     import bench
     assert st["contractions"] == bench._count_contractions(oo.R, ot, np.arange(ot.keys.size))
 
@@ -116,6 +119,7 @@ def test_wide_variants_match_oracle(M, ctx, case):
             M.mwns_ctx_set_variant(ctx, w.k, v)
             _, _, ghat = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)[0])
             assert np.linalg.norm(ghat - gh) <= 1e-12 * np.linalg.norm(gh), "variant %d" % v
+            assert per_node_ok(ghat, gh), "variant %d" % v
             out.append(ghat)
     finally:
         M.mwns_ctx_set_variant(ctx, w.k, -1)
@@ -271,3 +275,4 @@ def test_c3_yukawa_full_size_sampled(M, ctx):
     gh = dict(zip(chain, A.apply_modified(oo, ot, chain)))
     ref = np.stack([A.assemble_chain(ot, i, lambda n: gh[n]) for i in sample])
     assert np.linalg.norm(gg[sample] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert per_node_ok(gg[sample], ref)
