@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 METRIC = "NS apply block-contractions/s + FP64-MFMA util; mixed-vs-FP64 speedup at eps"
 
 # Sec. 6.1, Table 2 of the paper: the 3-D Poisson test (rho = -Laplacian of three Gaussians,
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cot1d-only", action="store_true",
+                    help="only the 1-D cotangent section (--steps applies per case); prints its JSON")
     return ap.parse_args()
 
 
@@ -250,13 +253,20 @@ def cot1d_measurement(M, ctx, reps):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / reps
         gk, gl, _ = M.mwns_cot1d_export(ctx, g)
+        kms = float(np.median(con))
+        # algorithmic bytes of the contraction launch: each output block's input block read once and
+        # the output block written once (k doubles each)
+        alg = 2.0 * gk.size * w.k * 8
         out.append({"workload": w.name, "k": w.k, "eps": w.eps, "depth": depth, "input_leaves": int(leaf.sum()),
                     "input_nodes": int(keys.size), "output_leaves": int(gl.sum()), "output_nodes": int(gk.size),
                     "bands": [int(b) for b in M.mwns_cot1d_op_bands(op)], "apply_ms": ms,
-                    "contract_kernel_ms": float(np.median(con))})
+                    "contract_kernel_ms": kms,
+                    "roofline": {"bound": "hbm", "achieved": alg / (kms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": alg / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": None,
+                                 "algorithmic_bytes_per_launch": alg}})
     return {"cases": out, "paper_table1": PAPER_TABLE1,
-            "note": "launch- and latency-bound at these sizes (tens of blocks of k doubles); E2 against the closed "
-                    "form is asserted in tests/test_gpu_cot1d.py"}
+            "note": "launch- and latency-bound at these sizes (tens to thousands of blocks of k doubles): the roofline "
+                    "fractions are far below 1; E2 against the closed form is asserted in tests/test_gpu_cot1d.py"}
 
 
 def cot1d_oracle_time(reps=1):
@@ -455,6 +465,10 @@ def main():
         return
     if args.cpu_baseline_only:
         cpu_baseline_only(args)
+        return
+    if args.cot1d_only:
+        import paper_0706_0747_amd as M
+        print(json.dumps(cot1d_measurement(M, M.Context(0), args.steps)))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
