@@ -432,6 +432,70 @@ mwns_status mwns_cot1d_export(mwns_ctx* ctx, const mwns_tree1* t, int64_t* nnode
 mwns_status mwns_cot1d_eval(mwns_ctx* ctx, const mwns_tree1* t, int64_t npts, const double* x, double* out);
 void mwns_tree1_destroy(mwns_tree1* t);
 
+/* ---- (8) Alg. 3 in two dimensions ----------------------------------------------------------------
+ * The paper writes Alg. 3 for d = 2 and notes the apply exists for d = 2; it gives no 2-D kernel.
+ * The plane's kernels of (-Delta + mu^2)^(-alpha) follow from Sec. 3's representation with the
+ * dimension 2: K(r) = C2 int exp(-r^2 e^{2s} - mu^2 e^{-2s}/4 + (2 - 2 alpha) s) ds, C2 = 2^{1 - 2 alpha}
+ * / (pi Gamma(alpha)); alpha = 1 gives K_0(mu r) / (2 pi).  2-D keys: level << 57 | morton(x, y) with x
+ * in bit 0; coefficient blocks [k][k] (a = degree in x, b = degree in y). */
+typedef struct mwns_op2 mwns_op2;
+typedef struct mwns_tree2 mwns_tree2;
+/* Gaussian-sum fit in the plane (host FP64): the trapezoidal rule s_m = A + m h, tau_m = e^{2 s_m},
+ * w_m = h C2 e^{-mu^2 e^{-2 s_m}/4 + (2 - 2 alpha) s_m}, terms whose weight underflows to zero dropped,
+ * |K(r) - sum w_m e^{-tau_m r^2}| <= eps K(r) on [delta, R] (relative to K itself), checked on 64 and
+ * 256 points per decade; h = pi^2 / (2 (ln(1/eps) + ln 8)), B = ln(ln(4/eps) / delta^2) / 2 + 1, A the
+ * smaller of ln mu - ln(4 ln(1e30/eps)) / 2 (mu > 0) and ln(eps K(R) (2 - 2 alpha) / (C2 e)) / (2 - 2 alpha)
+ * (alpha < 1); h shrinks by 0.9 and [A, B] widens by 1 until the checks pass.  Needs 0 < alpha <= 1,
+ * mu >= 0 (mu > 0 when alpha = 1).  Two-call use as mwns_fit_kernel: tau = w = NULL returns *M.
+ * Errors: EINVAL, ERANGE (cap too small: *M set; or no convergence). */
+mwns_status mwns_fit_kernel2d(double mu, double alpha, double eps, double delta, double R, int cap, int* M, double* tau,
+                              double* w);
+/* The 2-D operator for scales 0..max_level (<= 19), order k (1..10): the 1-D blocks F^{j;m,l} of
+ * eq. KernelFactor (the same as in 3-D; built on the device) and the 2-D plan of Sec. 4 with two
+ * factors: theta = eps sum_m w_m ||F^{0;m,0}||_F^2; per |L| class the estimate
+ * 1/2 sum over the orderings (p, q) of N_dif(p) N_F(q) + N_upF(p) N_dif(q) (the 2k x 2k super-block
+ * norms of the 3-D plan); the range [m1, m2] after dropping the prefix and suffix whose cumulative
+ * contributions stay <= theta/2 (empty when the total is <= theta); ranges grouped by the number of
+ * |L_d| > 1 (Core, Boundary-1, Boundary-2).  ERANGE when a term is kept at the band's edge max |L_d| = 3
+ * unless allow_band_overflow.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE. */
+mwns_status mwns_op2d_create(mwns_ctx* ctx, int k, int M, const double* tau, const double* w, double eps, int max_level,
+                             int allow_band_overflow, mwns_op2** out);
+/* The plan as int32 [max_level + 1][7][7][2] (inclusive term ranges per scale and coarse displacement
+ * L = -3..3 in each dimension; empty = (0, -1)); two-call size query.  Errors: EINVAL, ERANGE. */
+mwns_status mwns_op2d_plan_export(const mwns_op2* op, int32_t* plan, size_t* count);
+/* Replaces the plan (same layout; any plan gives an exact apply of its banded modified form).
+ * Errors: EINVAL (size or a range outside 0..M-1). */
+mwns_status mwns_op2d_plan_import(mwns_op2* op, const int32_t* plan, size_t count);
+void mwns_op2d_destroy(mwns_op2* op);
+/* Alg. 1 in the plane for f = sum_i c_i (a_i / pi) exp(-a_i |p - p_i|^2) (host: xy[n][2], a[n] > 0, c[n]):
+ * boxes from level j0 are refined (all four children) while f and the box's polynomial differ by more
+ * than eps ||f||_2 (closed-form norm) at some child's k x k Gauss-Legendre nodes; boxes at jmax
+ * (<= 19) are leaves; leaves keep their own coefficients, internal nodes the two-scale projections.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_project2d(mwns_ctx* ctx, int k, double eps, int j0, int jmax, int n, const double* xy, const double* a,
+                           const double* c, mwns_tree2** out);
+/* A tree from leaves (host keys[nleaves], coeffs[nleaves][k][k]) that tile [0,1)^2.  Errors: EINVAL. */
+mwns_status mwns_tree2d_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
+                                    mwns_tree2** out);
+/* g = T f in the modified ns-form (eq. apply_algo, Alg. 3) on f's tree: node b of scale j >= 1 takes,
+ * for each fine displacement l in [-7, 7]^2 with b - l in the square and L = floor(b/2) - floor((b-l)/2),
+ * the terms of R_j(L) with + and, at internal nodes, those of R_{j+1}(l) with - (their common part
+ * cancels and is skipped), each as c w_m F^{j;m,l1} X F^{j;m,l2}^T; the root takes R_0 minus R_1(0)
+ * when internal; inputs missing from f's tree by zero-detail reconstruction from the nearest ancestor;
+ * then the assembly from the root (eq. g_assemble): leaves hold g.  *ms_contract (may be NULL): device
+ * time of the contraction kernel; *flops (may be NULL): 4 k^3 per (node, l, term).  Synchronises.
+ * Errors: EINVAL (orders differ, tree deeper than the operator), ENOMEM, EDEVICE. */
+mwns_status mwns_apply2d(mwns_ctx* ctx, const mwns_op2* op, const mwns_tree2* f, mwns_tree2** g, double* ms_contract,
+                         double* flops);
+/* Nodes of t (host arrays of *nnodes entries, each may be NULL; two-call size query).  Errors: EINVAL,
+ * ERANGE. */
+mwns_status mwns_tree2d_export(mwns_ctx* ctx, const mwns_tree2* t, int64_t* nnodes, uint64_t* keys, uint8_t* is_leaf,
+                               double* coeffs);
+/* Values at npts points (host pts[npts][2] in [0,1]^2) from the leaf containing each.  Errors: EINVAL
+ * (a point outside the square), ENOMEM, EDEVICE. */
+mwns_status mwns_tree2d_eval(mwns_ctx* ctx, const mwns_tree2* t, int64_t npts, const double* pts, double* out);
+void mwns_tree2d_destroy(mwns_tree2* t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,9 @@ __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSE
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes", "mwns_tree_detail_norms", "mwns_tree_prune",
            "mwns_tree_discard", "Op1", "Tree1", "mwns_cot1d_op_create", "mwns_cot1d_op_bands", "mwns_cot1d_op_set_bands",
            "mwns_cot1d_op_blocks", "mwns_cot1d_project", "mwns_cot1d_from_leaves", "mwns_cot1d_apply", "mwns_cot1d_export",
-           "mwns_cot1d_eval",
+           "mwns_cot1d_eval", "Op2", "Tree2", "mwns_fit_kernel2d", "mwns_op2d_create", "mwns_op2d_plan_export",
+           "mwns_op2d_plan_import", "mwns_project2d", "mwns_tree2d_from_leaves", "mwns_apply2d", "mwns_tree2d_export",
+           "mwns_tree2d_eval",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
            "mwns_ctx_get_variant",
@@ -534,4 +536,112 @@ def mwns_cot1d_eval(ctx, t, x):
     xx = np.ascontiguousarray(x, dtype=np.float64)
     out = np.zeros(xx.size)
     check(lib.mwns_cot1d_eval(ctx.h, t.h, int(xx.size), xx.ctypes.data, out.ctypes.data), "mwns_cot1d_eval")
+    return out
+
+
+# ---- Alg. 3 in two dimensions ------------------------------------------------------------------
+
+
+class Op2:
+    def __init__(self, ctx, h, k, M, max_level):
+        self.ctx, self.h, self.k, self.M, self.max_level = ctx, h, k, M, max_level
+
+    def close(self, _destroy=lib.mwns_op2d_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Tree2:
+    def __init__(self, ctx, h, k):
+        self.ctx, self.h, self.k = ctx, h, k
+
+    def close(self, _destroy=lib.mwns_tree2d_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def mwns_fit_kernel2d(mu, alpha, eps, delta, R):
+    n = ctypes.c_int(0)
+    check(lib.mwns_fit_kernel2d(float(mu), float(alpha), float(eps), float(delta), float(R), 0, ctypes.byref(n), None,
+                                None), "mwns_fit_kernel2d")
+    tau = np.zeros(n.value)
+    w = np.zeros(n.value)
+    check(lib.mwns_fit_kernel2d(float(mu), float(alpha), float(eps), float(delta), float(R), n.value, ctypes.byref(n),
+                                tau.ctypes.data, w.ctypes.data), "mwns_fit_kernel2d")
+    return tau, w
+
+
+def mwns_op2d_create(ctx, k, tau, w, eps, max_level, allow_band_overflow=False):
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    h = ctypes.c_void_p()
+    check(lib.mwns_op2d_create(ctx.h, int(k), int(t.size), t.ctypes.data, ww.ctypes.data, float(eps), int(max_level),
+                               int(bool(allow_band_overflow)), ctypes.byref(h)), "mwns_op2d_create")
+    return Op2(ctx, h, int(k), int(t.size), int(max_level))
+
+
+def mwns_op2d_plan_export(op):
+    n = ctypes.c_size_t(0)
+    check(lib.mwns_op2d_plan_export(op.h, None, ctypes.byref(n)), "mwns_op2d_plan_export")
+    out = np.zeros(n.value, dtype=np.int32)
+    check(lib.mwns_op2d_plan_export(op.h, out.ctypes.data, ctypes.byref(n)), "mwns_op2d_plan_export")
+    return out.reshape(op.max_level + 1, 7, 7, 2)
+
+
+def mwns_op2d_plan_import(op, plan):
+    p = np.ascontiguousarray(plan, dtype=np.int32)
+    check(lib.mwns_op2d_plan_import(op.h, p.ctypes.data, int(p.size)), "mwns_op2d_plan_import")
+
+
+def mwns_project2d(ctx, k, eps, j0, jmax, xy, a, c):
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    h = ctypes.c_void_p()
+    check(lib.mwns_project2d(ctx.h, int(k), float(eps), int(j0), int(jmax), int(a.size), xy.ctypes.data, a.ctypes.data,
+                             c.ctypes.data, ctypes.byref(h)), "mwns_project2d")
+    return Tree2(ctx, h, int(k))
+
+
+def mwns_tree2d_from_leaves(ctx, k, keys, coeffs):
+    kk = np.ascontiguousarray(keys, dtype=np.uint64)
+    cc = np.ascontiguousarray(coeffs, dtype=np.float64)
+    h = ctypes.c_void_p()
+    check(lib.mwns_tree2d_from_leaves(ctx.h, int(k), int(kk.size), kk.ctypes.data, cc.ctypes.data, ctypes.byref(h)),
+          "mwns_tree2d_from_leaves")
+    return Tree2(ctx, h, int(k))
+
+
+def mwns_apply2d(ctx, op, f):
+    """(g, device ms of the contraction kernel, flops)."""
+    h = ctypes.c_void_p()
+    ms = ctypes.c_double()
+    fl = ctypes.c_double()
+    check(lib.mwns_apply2d(ctx.h, op.h, f.h, ctypes.byref(h), ctypes.byref(ms), ctypes.byref(fl)), "mwns_apply2d")
+    return Tree2(ctx, h, f.k), ms.value, fl.value
+
+
+def mwns_tree2d_export(ctx, t):
+    n = ctypes.c_int64(0)
+    check(lib.mwns_tree2d_export(ctx.h, t.h, ctypes.byref(n), None, None, None), "mwns_tree2d_export")
+    keys = np.zeros(n.value, dtype=np.uint64)
+    leaf = np.zeros(n.value, dtype=np.uint8)
+    coef = np.zeros((n.value, t.k, t.k))
+    check(lib.mwns_tree2d_export(ctx.h, t.h, ctypes.byref(n), keys.ctypes.data, leaf.ctypes.data, coef.ctypes.data),
+          "mwns_tree2d_export")
+    return keys, leaf, coef
+
+
+def mwns_tree2d_eval(ctx, t, pts):
+    p = np.ascontiguousarray(pts, dtype=np.float64)
+    out = np.zeros(p.shape[0])
+    check(lib.mwns_tree2d_eval(ctx.h, t.h, int(p.shape[0]), p.ctypes.data, out.ctypes.data), "mwns_tree2d_eval")
     return out

@@ -105,6 +105,17 @@ SIGNATURES = {
     "mwns_cot1d_export": (c_int, [c_vp, c_vp, P(c_i64), c_vp, c_vp, c_vp]),
     "mwns_cot1d_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "mwns_tree1_destroy": (None, [c_vp]),
+    "mwns_fit_kernel2d": (c_int, [c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_int, P(c_int), c_vp, c_vp]),
+    "mwns_op2d_create": (c_int, [c_vp, c_int, c_int, c_vp, c_vp, c_dbl, c_int, c_int, P(c_vp)]),
+    "mwns_op2d_plan_export": (c_int, [c_vp, c_vp, P(c_size)]),
+    "mwns_op2d_plan_import": (c_int, [c_vp, c_vp, c_size]),
+    "mwns_op2d_destroy": (None, [c_vp]),
+    "mwns_project2d": (c_int, [c_vp, c_int, c_dbl, c_int, c_int, c_int, c_vp, c_vp, c_vp, P(c_vp)]),
+    "mwns_tree2d_from_leaves": (c_int, [c_vp, c_int, c_i64, c_vp, c_vp, P(c_vp)]),
+    "mwns_apply2d": (c_int, [c_vp, c_vp, c_vp, P(c_vp), P(c_dbl), P(c_dbl)]),
+    "mwns_tree2d_export": (c_int, [c_vp, c_vp, P(c_i64), c_vp, c_vp, c_vp]),
+    "mwns_tree2d_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "mwns_tree2d_destroy": (None, [c_vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():
