@@ -10,7 +10,8 @@ time), the precision-routed apply against the FP64 one on the same tree at tol =
 ("mixed"), and the CPU oracle timed on a bounded sample with the same operator.  Beside it
 ("extra"): the Poisson k = 8 and bound-state Helmholtz k = 10 workloads; the batch of 64 uneven
 solves (1e3 to 2e5 leaves each) applied one by one, as one persistent batched launch and as
-replays of a captured plan; the 1-D cotangent operator of Sec. 2.4 ("cot1d").  Accuracy against
+replays of a captured plan; the 1-D cotangent operator of Sec. 2.4 ("cot1d"); Alg. 3 in two
+dimensions ("ns2d").  Accuracy against
 closed forms is asserted by the GPU tests.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c2|c3]
@@ -71,6 +72,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB elementwise copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--ns2d-only", action="store_true",
+                    help="only the 2-D section (--steps applies per case); prints its JSON")
     ap.add_argument("--cot1d-only", action="store_true",
                     help="only the 1-D cotangent section (--steps applies per case); prints its JSON")
     return ap.parse_args()
@@ -267,6 +270,60 @@ def cot1d_measurement(M, ctx, reps):
     return {"cases": out, "paper_table1": PAPER_TABLE1,
             "note": "launch- and latency-bound at these sizes (tens to thousands of blocks of k doubles): the roofline "
                     "fractions are far below 1; E2 against the closed form is asserted in tests/test_gpu_cot1d.py"}
+
+
+def ns2d_measurement(M, ctx, reps):
+    """Alg. 3 in two dimensions on two seeded inputs (the 2-D analogue of the k = 8 workload, and a
+    larger one): the library's fit, operator, projection and apply; tree sizes, the apply's wall time
+    and the contraction kernel's device time and FP64 rate (vector FMAs: 4 k^3 flops per (node, l,
+    term))."""
+    import numpy as np
+    import torch
+    import workloads
+    out = []
+    for w in (workloads.ns2d(), workloads.ns2d(seed=3, n=400, log10_hi=5.0)):
+        f = M.mwns_project2d(ctx, w.k, w.eps, w.j0, w.jmax, w.xy, w.a, w.c)
+        keys, leaf, _ = M.mwns_tree2d_export(ctx, f)
+        depth = int((keys >> np.uint64(57)).max())
+        tau, wt = M.mwns_fit_kernel2d(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -depth, math.sqrt(2.0))
+        op = M.mwns_op2d_create(ctx, w.k, tau, wt, w.eps, depth)
+        g, ms_con, fl = M.mwns_apply2d(ctx, op, f)
+        torch.cuda.synchronize()
+        con = []
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g, ms_con, fl = M.mwns_apply2d(ctx, op, f)
+            con.append(ms_con)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        kms = float(np.median(con))
+        ach = fl / (kms * 1e-3) / 1e12
+        out.append({"workload": w.name, "k": w.k, "eps": w.eps, "mu": w.mu, "leaves": int(leaf.sum()), "nodes": int(keys.size),
+                    "depth": depth, "terms": int(tau.size), "apply_ms": ms, "contract_kernel_ms": kms,
+                    "flops_per_apply": fl,
+                    "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": ach / PEAK_FP64_TFLOPS, "traffic": None}})
+    return {"cases": out, "note": "accuracy against the fitted kernel in closed form and node-by-node parity with the "
+                                  "d = 2 oracle are asserted in tests/test_gpu_ns2d.py"}
+
+
+def ns2d_oracle_time():
+    """The d = 2 oracle's apply (numpy, modified form, then assembly) on the first 2-D input: its own
+    tree, fit and plan; the apply timed alone."""
+    import numpy as np
+    from oracle import mra
+    from oracle import ns2d as N
+    import workloads
+    w = workloads.ns2d()
+    tr = N.project2d(w.k, w.eps, w.j0, w.jmax, w.xy, w.a, w.c)
+    tau, wt = N.fit_kernel2d(w.mu, w.alpha, w.eps, math.sqrt(w.eps) * 2.0 ** -tr.depth, math.sqrt(2.0))
+    F = mra.F_table(w.k, tau, tr.depth)
+    H0, H1 = mra.two_scale_filters(w.k)
+    R, _ = N.make_plan2d(F, H0, H1, wt, w.eps, tr.depth)
+    t0 = time.perf_counter()
+    N.assemble2d(tr, N.apply_modified2d(tr, F, wt, R))
+    dt = time.perf_counter() - t0
+    return {"workload": w.name, "nodes": int(tr.keys.size), "apply_s": dt, "cores": 1, "kind": "oracle (numpy, one process)"}
 
 
 def cot1d_oracle_time(reps=1):
@@ -470,6 +527,10 @@ def main():
         import paper_0706_0747_amd as M
         print(json.dumps(cot1d_measurement(M, M.Context(0), args.steps)))
         return
+    if args.ns2d_only:
+        import paper_0706_0747_amd as M
+        print(json.dumps(ns2d_measurement(M, M.Context(0), args.steps)))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -528,10 +589,14 @@ def main():
         progress("batch done")
     line["cot1d"] = cot1d_measurement(M, ctx, 5)
     progress("1-D cotangent operator done")
+    line["ns2d"] = ns2d_measurement(M, ctx, 5)
+    progress("2-D apply done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, line["config"]["depth"], args.cpu_sample_nodes)
         line["cpu_baseline"]["cot1d"] = cot1d_oracle_time()
         progress("1-D oracle timed")
+        line["cpu_baseline"]["ns2d"] = ns2d_oracle_time()
+        progress("2-D oracle timed")
     print(json.dumps(line))
 
 

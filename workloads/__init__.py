@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Workload", "c1", "c2", "c3", "c4_draw", "c4_member", "c5", "cot1d_example", "cot1d_many", "small_adaptive", "points"]
+__all__ = ["Workload", "c1", "c2", "c3", "c4_draw", "c4_member", "c5", "cot1d_example", "cot1d_many", "ns2d", "small_adaptive", "points"]
 
 
 class Workload(dict):
@@ -129,6 +129,18 @@ def cot1d_many(seed=11, n=128):
     weights = rng.normal(0.0, 1.0, n)
     return Workload(name="cot1d_%dgauss_k10" % n, seed=seed, k=10, eps=1e-9, thr=1e-9, j0=2, jmax=30,
                     centers=centers, exps=exps, weights=weights)
+
+
+def ns2d(seed=2, n=50, log10_hi=4.0, k=8, eps=1e-6, mu=5.0):
+    """A 2-D input for Alg. 3 in the plane: n unit-mass Gaussians (a/pi) exp(-a |p - p_i|^2) with
+    exponents log-uniform in [10, 10^log10_hi], centres uniform in [0.2, 0.8]^2, weights N(0,1); the
+    plane's bound-state Helmholtz kernel K_0(mu r) / (2 pi); order k, accuracy eps, j0 = 2, jmax = 12."""
+    rng = _rng(seed)
+    a = 10.0 ** rng.uniform(1.0, log10_hi, n)
+    xy = rng.uniform(0.2, 0.8, (n, 2))
+    c = rng.normal(0.0, 1.0, n)
+    return Workload(name="ns2d_yukawa_k%d_%dgauss" % (k, n), seed=seed, k=k, eps=eps, j0=2, jmax=12, mu=mu, alpha=1.0,
+                    xy=xy, a=a, c=c)
 
 
 def small_adaptive(seed, k=6, eps=1e-4, n=3, jmax=6, mu=0.0, alpha=1.0):
