@@ -198,8 +198,9 @@ struct Job2 {
     int l1, l2, m1, m2, sign, pad;
 };
 
-// One workgroup per output node: for each job and term, T = X F2^T, then y += c w_m F1 T, with
-// F1 = F^{j;m,l1}, F2 = F^{j;m,l2} (row = output degree); jobs and terms in a fixed order.
+// Orders 9, 10: one workgroup per output node: for each job and term, T = X F2^T, then
+// y += c w_m F1 T, with F1 = F^{j;m,l1}, F2 = F^{j;m,l2} (row = output degree); jobs and terms in a
+// fixed order.
 __global__ void contract2_kernel(int k, int M, const int* __restrict__ nlev, const int64_t* __restrict__ off,
                                  const Job2* __restrict__ jobs, const double* __restrict__ F, const double* __restrict__ w,
                                  const double* __restrict__ X, double* __restrict__ out) {
@@ -230,6 +231,74 @@ __global__ void contract2_kernel(int k, int M, const int* __restrict__ nlev, con
         }
     }
     if (e < kk) out[(int64_t)node * kk + e] = acc;
+}
+
+// Orders k <= 8 (k^2 <= 64): one wavefront per output node, four nodes per workgroup, no workgroup
+// barriers.  Lane e = a k + b holds y[a][b]; per job the lane keeps row a of X (gathered by lane
+// shuffles).  The blocks F1 and F2 of four terms at a time go to the wave's own LDS region (lane e
+// loads element e of each; the next four terms' blocks are loaded into registers while these are
+// used); per term the lane forms T[a][b] = sum_d X[a][d] F2[b][d] and reads column b of T from
+// lanes c k + b by shuffles for y[a][b] += c w sum_c F1[a][c] T[c][b].  Lanes e >= k^2 compute on row
+// and column 0 and write nothing.
+template <int K>
+__global__ void __launch_bounds__(256) contract2_wave_kernel(int n, int M, const int* __restrict__ nlev,
+                                                             const int64_t* __restrict__ off, const Job2* __restrict__ jobs,
+                                                             const double* __restrict__ F, const double* __restrict__ w,
+                                                             const double* __restrict__ X, double* __restrict__ out) {
+    constexpr int KK = K * K, C = 4;
+    __shared__ double fs[4][2][C][KK];
+    const int wv = threadIdx.x >> 6;
+    const int node = blockIdx.x * 4 + wv;
+    if (node >= n) return;                          // whole waves only: no workgroup barrier below
+    const int e = threadIdx.x & 63;
+    const bool act = e < KK;
+    const int a = act ? e / K : 0, b = act ? e % K : 0;
+    const int j = nlev[node];
+    const int64_t stride = (int64_t)15 * KK;        // from term m to m + 1
+    double (*f1s)[KK] = fs[wv][0];
+    double (*f2s)[KK] = fs[wv][1];
+    double acc = 0.0;
+    for (int64_t q = off[node]; q < off[node + 1]; ++q) {
+        const Job2 jb = jobs[q];
+        const double x = X[jb.in * KK + (act ? e : 0)];
+        double xr[K];
+#pragma unroll
+        for (int d = 0; d < K; ++d) xr[d] = __shfl(x, a * K + d);
+        const double* F1b = F + (((int64_t)j * M) * 15 + (jb.l1 + 7)) * KK + (act ? e : 0);
+        const double* F2b = F + (((int64_t)j * M) * 15 + (jb.l2 + 7)) * KK + (act ? e : 0);
+        double p1[C], p2[C];
+        auto fetch = [&](int m0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int m = m0 + c <= jb.m2 ? m0 + c : jb.m2;
+                p1[c] = F1b[m * stride];
+                p2[c] = F2b[m * stride];
+            }
+        };
+        fetch(jb.m1);
+        for (int m0 = jb.m1; m0 <= jb.m2; m0 += C) {
+            __builtin_amdgcn_wave_barrier();         // the previous chunk's reads of this region are done
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                f1s[c][e < KK ? e : 0] = p1[c];
+                f2s[c][e < KK ? e : 0] = p2[c];
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0): this wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+            if (m0 + C <= jb.m2) fetch(m0 + C);
+            const int nc = jb.m2 - m0 + 1 < C ? jb.m2 - m0 + 1 : C;
+            for (int c = 0; c < nc; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int d = 0; d < K; ++d) t += xr[d] * f2s[c][b * K + d];
+                double v = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < K; ++cc) v += f1s[c][a * K + cc] * __shfl(t, cc * K + b);
+                acc += jb.sign * w[m0 + c] * v;
+            }
+        }
+    }
+    if (act) out[(int64_t)node * KK + e] = acc;
 }
 
 // g[node] += H^(sx)^T g[parent] H^(sy) for the nodes of one level
@@ -876,7 +945,17 @@ mwns_status mwns_apply2d(mwns_ctx* ctx, const mwns_op2* op, const mwns_tree2* f,
     MWNS_HIP(hipEventCreate(&e0));
     MWNS_HIP(hipEventCreate(&e1));
     MWNS_HIP(hipEventRecord(e0, st));
-    contract2_kernel<<<(unsigned)no, 128, 0, st>>>(k, op->M, dnl.p, doff.p, djobs.p, op->F.p, op->dw.p, X.p, out.p);
+    switch (k) {
+#define MWNS_C2W(KV) \
+    case KV: \
+        contract2_wave_kernel<KV><<<(unsigned)((no + 3) / 4), 256, 0, st>>>((int)no, op->M, dnl.p, doff.p, djobs.p, op->F.p, \
+                                                                          op->dw.p, X.p, out.p); \
+        break;
+        MWNS_C2W(1) MWNS_C2W(2) MWNS_C2W(3) MWNS_C2W(4) MWNS_C2W(5) MWNS_C2W(6) MWNS_C2W(7) MWNS_C2W(8)
+#undef MWNS_C2W
+        default:
+            contract2_kernel<<<(unsigned)no, 128, 0, st>>>(k, op->M, dnl.p, doff.p, djobs.p, op->F.p, op->dw.p, X.p, out.p);
+    }
     MWNS_HIP(hipGetLastError());
     MWNS_HIP(hipEventRecord(e1, st));
     for (int j = 1; j <= f->depth; ++j) {
