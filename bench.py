@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--ns2d-only", action="store_true",
                     help="only the 2-D section (--steps applies per case); prints its JSON")
+    ap.add_argument("--hydrogen-only", action="store_true",
+                    help="only the hydrogen section; prints its JSON")
+    ap.add_argument("--hydrogen-cfg", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cot1d-only", action="store_true",
                     help="only the 1-D cotangent section (--steps applies per case); prints its JSON")
     return ap.parse_args()
@@ -307,6 +310,41 @@ def ns2d_measurement(M, ctx, reps):
                                   "d = 2 oracle are asserted in tests/test_gpu_ns2d.py"}
 
 
+HYDROGEN = dict(k=10, eps=1e-6, L=16.0, jmax=15, mu0=0.8, iters=14)
+HYDROGEN_SMALL = dict(k=5, eps=1e-3, L=10.0, jmax=7, mu0=0.8, iters=2)
+
+
+def hydrogen_measurement(M, ctx, cfg=None):
+    """Sec. 6.2's iteration in the library at the paper's requested accuracy 1e-6 (the figure of the
+    iteration's convergence): |E + 1/2| after each step, rho's leaves, the device time of each apply
+    and the wall time of the whole call (fit, operator, apply, discard, products, inner products)."""
+    import torch
+    c = dict(HYDROGEN if cfg is None else cfg)
+    M.mwns_hydrogen_kalos(ctx, c["k"], c["eps"], c["L"], c["jmax"], mu0=c["mu0"], iters=1)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, leaves, ms = M.mwns_hydrogen_kalos(ctx, c["k"], c["eps"], c["L"], c["jmax"], mu0=c["mu0"], iters=c["iters"])
+    wall = time.perf_counter() - t0
+    sm = dict(HYDROGEN_SMALL)
+    t1 = time.perf_counter()
+    M.mwns_hydrogen_kalos(ctx, sm["k"], sm["eps"], sm["L"], sm["jmax"], mu0=sm["mu0"], iters=sm["iters"])
+    small = time.perf_counter() - t1
+    return {"config": c, "mu": [m for m, _ in hist], "E": [e for _, e in hist], "E_error": [abs(e + 0.5) for _, e in hist],
+            "rho_leaves": leaves, "apply_device_ms": ms, "wall_s": wall, "wall_ms_per_step": 1e3 * wall / c["iters"],
+            "small": {"config": sm, "wall_s": small},
+            "note": "the exact ground-state energy is -1/2; parity of mu, E and the trees with the oracle is asserted in "
+                    "tests/test_gpu_hydrogen.py"}
+
+
+def hydrogen_oracle_time():
+    """The oracle's iteration (numpy) on the small hydrogen configuration, the whole call timed."""
+    from oracle import hydrogen as H
+    sm = dict(HYDROGEN_SMALL)
+    t0 = time.perf_counter()
+    H.kalos(sm["k"], sm["eps"], sm["L"], sm["jmax"], mu0=sm["mu0"], iters=sm["iters"])
+    return {"config": sm, "wall_s": time.perf_counter() - t0, "cores": 1, "kind": "oracle (numpy, one process)"}
+
+
 def ns2d_oracle_time():
     """The d = 2 oracle's apply (numpy, modified form, then assembly) on the first 2-D input: its own
     tree, fit and plan; the apply timed alone."""
@@ -527,6 +565,11 @@ def main():
         import paper_0706_0747_amd as M
         print(json.dumps(cot1d_measurement(M, M.Context(0), args.steps)))
         return
+    if args.hydrogen_only:
+        import paper_0706_0747_amd as M
+        cfg = json.loads(args.hydrogen_cfg) if args.hydrogen_cfg else None
+        print(json.dumps(hydrogen_measurement(M, M.Context(0), cfg)))
+        return
     if args.ns2d_only:
         import paper_0706_0747_amd as M
         print(json.dumps(ns2d_measurement(M, M.Context(0), args.steps)))
@@ -591,12 +634,16 @@ def main():
     progress("1-D cotangent operator done")
     line["ns2d"] = ns2d_measurement(M, ctx, 5)
     progress("2-D apply done")
+    line["hydrogen"] = hydrogen_measurement(M, ctx)
+    progress("hydrogen iteration done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, line["config"]["depth"], args.cpu_sample_nodes)
         line["cpu_baseline"]["cot1d"] = cot1d_oracle_time()
         progress("1-D oracle timed")
         line["cpu_baseline"]["ns2d"] = ns2d_oracle_time()
         progress("2-D oracle timed")
+        line["cpu_baseline"]["hydrogen"] = hydrogen_oracle_time()
+        progress("hydrogen oracle timed")
     print(json.dumps(line))
 
 

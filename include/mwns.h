@@ -496,6 +496,47 @@ mwns_status mwns_tree2d_export(mwns_ctx* ctx, const mwns_tree2* t, int64_t* nnod
 mwns_status mwns_tree2d_eval(mwns_ctx* ctx, const mwns_tree2* t, int64_t npts, const double* pts, double* out);
 void mwns_tree2d_destroy(mwns_tree2* t);
 
+/* ---- (9) The hydrogen ground state (Sec. 6.2) -----------------------------------------------------
+ * phi = -2 G_mu V phi, G_mu = (-Delta + mu^2)^(-1) (kernel e^{-mu r} / (4 pi r)), V = -Z / r, with mu
+ * moved to sqrt(-2 E) after each step.  The physical cube [-L, L]^3, nucleus at its centre, is the
+ * unit cube scaled by s = 2 L: a tree on [0,1]^3 holds the physical function's values, physical
+ * integrals are s^3 times unit-cube ones, and the kernel on the unit cube is s^2 e^{-(mu s) r} / (4 pi r). */
+/* rho = c / r * f with r = s |x - (1/2,1/2,1/2)| (the physical distance to the nucleus).  The paper
+ * refers to other work for products of adaptive functions; here rho lives on f's tree with every leaf
+ * split once and the boxes whose closure holds the centre split further down to level jmax; each new
+ * leaf's block is the k-point Gauss-Legendre rule of App. A.1 (eq. fvals2coefs) applied to c / r times
+ * f's polynomial (eq. func_interp) at the leaf's nodes (the centre is a corner of boxes on every scale,
+ * so no node falls on it); the ancestors hold the two-scale projections (a redundant tree).  f is not
+ * changed.  *out is a new tree of ctx.  1 <= jmax <= 19, f's depth <= 18, c finite, s > 0.
+ * Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+mwns_status mwns_tree_coulomb_product(mwns_ctx* ctx, const mwns_tree* f, double c, double s, int jmax,
+                                      mwns_tree** out);
+/* <u, v> over the unit cube as the sum, over u's leaves, of the dot product of u's block with v's block
+ * of the same box (orthonormal bases): exact when v's tree holds the projection of v onto every leaf
+ * box of u (a redundant tree built on a refinement of u's leaves, such as a product above, or the same
+ * leaves).  The sum is formed on the device in a fixed order.  *out on the host.  Synchronises.
+ * Errors: EINVAL (orders differ, a leaf box of u missing from v, trees of another context), ENOMEM,
+ * EDEVICE. */
+mwns_status mwns_tree_dot(mwns_ctx* ctx, const mwns_tree* u, const mwns_tree* v, double* out);
+/* The iteration of Sec. 6.2 in the library, `iters` steps from phi_0 = (2/pi)^{3/4} e^{-|x|^2} (projected
+ * by Alg. 1 at eps from level j0 down to at most jmax) and mu_0:
+ *   rho = -2 V phi / ||phi|| (the product above, finest level jmax);
+ *   each step: fit G_mu to eps on [sqrt(eps) 2^-depth, sqrt(3)] (depth of rho's tree; mwns_fit_kernel with
+ *   mu s and scale s^2), build the operator at eps (mwns_op_create, default options), phi_new = G_mu rho by
+ *   the modified ns-form (mwns_apply, FP64), then
+ *     E = (<phi_new, rho> / 2 - mu^2 ||phi_new||^2 / 2 - ||phi_new|| <phi_new, rho_new> / 2) / ||phi_new||^2
+ *   with rho_new = -2 V phi_new / ||phi_new|| formed on phi_new discarded to eps (mwns_tree_discard, Alg. 3
+ *   Step 4): since (-Delta + mu^2) phi_new = rho, the kinetic term 1/2 ||grad phi_new||^2 equals
+ *   <phi_new, rho> / 2 - mu^2 ||phi_new||^2 / 2 (the paper defers weak derivatives to other work);
+ *   mu <- sqrt(-2 E), rho <- rho_new.
+ * Outputs (host, caller-owned, iters entries): mu_out[i] = mu used by step i, E_out[i] = its energy;
+ * rho_leaves[i] (may be NULL) = leaves of the rho that step i applies to; ms_apply[i] (may be NULL) =
+ * device time of that apply (closure, contraction, assembly).  0 < eps < 1, L, mu0, Z > 0,
+ * 0 <= j0 <= jmax <= 18, iters >= 1, 1 <= k <= 10.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE (a fit above
+ * 4096 terms, a screening band overflow, or an energy E >= 0: no bound state to follow). */
+mwns_status mwns_hydrogen_kalos(mwns_ctx* ctx, int k, double eps, double L, int jmax, double mu0, double Z, int j0,
+                                int iters, double* mu_out, double* E_out, int64_t* rho_leaves, double* ms_apply);
+
 #ifdef __cplusplus
 }
 #endif

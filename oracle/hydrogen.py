@@ -81,8 +81,9 @@ def _leaf_dot(u, v):
     return float(np.sum(u.coef[u.leaf == 1] * v.coef[idx]))
 
 
-def kalos(k, eps, L, jmax, mu0=1.0, iters=6, Z=1.0, j0=2):
-    """The iteration of Sec. 6.2; returns the list of (mu, E) after each step."""
+def kalos(k, eps, L, jmax, mu0=1.0, iters=6, Z=1.0, j0=2, leaves=None):
+    """The iteration of Sec. 6.2; returns the list of (mu, E) after each step (and appends the leaf
+    count of the rho each step applies to onto `leaves` when given a list)."""
     s = 2.0 * L
     a = s * s
     keys, coef = T.project_gaussians(k, eps, j0, jmax, [[0.5, 0.5, 0.5]], [a], [(2.0 / math.pi) ** 0.75 * (math.pi / a) ** 1.5])
@@ -94,6 +95,8 @@ def kalos(k, eps, L, jmax, mu0=1.0, iters=6, Z=1.0, j0=2):
     for _ in range(iters):
         tau, w = fit.fit_kernel(mu * s, 1.0, eps, math.sqrt(eps) * 2.0 ** -rho.depth, math.sqrt(3.0), scale=s * s)
         op = A.Operator(k, tau, w, eps, rho.depth)
+        if leaves is not None:
+            leaves.append(int(np.sum(rho.leaf)))
         g = A.assemble(rho, A.apply_modified(op, rho))                          # phi_new on rho's tree
         lf = rho.leaf == 1
         n2 = s ** 3 * float(np.sum(g[lf] ** 2))

@@ -26,6 +26,7 @@ __all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSE
            "mwns_cot1d_op_blocks", "mwns_cot1d_project", "mwns_cot1d_from_leaves", "mwns_cot1d_apply", "mwns_cot1d_export",
            "mwns_cot1d_eval", "Op2", "Tree2", "mwns_fit_kernel2d", "mwns_op2d_create", "mwns_op2d_plan_export",
            "mwns_op2d_plan_import", "mwns_project2d", "mwns_tree2d_from_leaves", "mwns_apply2d", "mwns_tree2d_export",
+           "mwns_tree_coulomb_product", "mwns_tree_dot", "mwns_hydrogen_kalos",
            "mwns_tree2d_eval",
            "mwns_apply_batch", "Plan", "mwns_plan_create", "mwns_tree_set_leaves",
            "mwns_tune_apply", "autotune", "mwns_ctx_create", "mwns_num_variants", "mwns_num_variants_for", "mwns_variant_shape", "mwns_ctx_set_variant",
@@ -645,3 +646,33 @@ def mwns_tree2d_eval(ctx, t, pts):
     out = np.zeros(p.shape[0])
     check(lib.mwns_tree2d_eval(ctx.h, t.h, int(p.shape[0]), p.ctypes.data, out.ctypes.data), "mwns_tree2d_eval")
     return out
+
+
+# ---- the hydrogen ground state (Sec. 6.2) --------------------------------------------------------
+
+
+def mwns_tree_coulomb_product(ctx, f, c, s, jmax):
+    """rho = c / (s |x - 1/2|) * f on f's tree refined once and, at the centre, down to jmax."""
+    h = ctypes.c_void_p()
+    check(lib.mwns_tree_coulomb_product(ctx.h, f.h, float(c), float(s), int(jmax), ctypes.byref(h)),
+          "mwns_tree_coulomb_product")
+    return Tree(ctx, h)
+
+
+def mwns_tree_dot(ctx, u, v):
+    """<u, v> over the unit cube from u's leaves and v's blocks of the same boxes."""
+    out = ctypes.c_double()
+    check(lib.mwns_tree_dot(ctx.h, u.h, v.h, ctypes.byref(out)), "mwns_tree_dot")
+    return out.value
+
+
+def mwns_hydrogen_kalos(ctx, k, eps, L, jmax, mu0=1.0, iters=6, Z=1.0, j0=2):
+    """The iteration of Sec. 6.2: ([(mu, E) per step], rho's leaves per step, device ms of each apply)."""
+    mu = np.zeros(iters)
+    E = np.zeros(iters)
+    nl = np.zeros(iters, dtype=np.int64)
+    ms = np.zeros(iters)
+    check(lib.mwns_hydrogen_kalos(ctx.h, int(k), float(eps), float(L), int(jmax), float(mu0), float(Z), int(j0),
+                                  int(iters), mu.ctypes.data, E.ctypes.data, nl.ctypes.data, ms.ctypes.data),
+          "mwns_hydrogen_kalos")
+    return list(zip(mu.tolist(), E.tolist())), nl.tolist(), ms.tolist()

@@ -116,6 +116,10 @@ SIGNATURES = {
     "mwns_tree2d_export": (c_int, [c_vp, c_vp, P(c_i64), c_vp, c_vp, c_vp]),
     "mwns_tree2d_eval": (c_int, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "mwns_tree2d_destroy": (None, [c_vp]),
+    "mwns_tree_coulomb_product": (c_int, [c_vp, c_vp, c_dbl, c_dbl, c_int, P(c_vp)]),
+    "mwns_tree_dot": (c_int, [c_vp, c_vp, c_vp, P(c_dbl)]),
+    "mwns_hydrogen_kalos": (c_int, [c_vp, c_int, c_dbl, c_dbl, c_int, c_dbl, c_dbl, c_int, c_int, c_vp, c_vp, c_vp,
+                                    c_vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmwns.so")
 SOURCES = ["host_common.hip", "fit.hip", "operator.hip", "tree.hip", "contract.hip", "contract_wide.hip", "apply.hip",
-           "prune.hip", "cot1d.hip", "ns2d.hip"]
+           "prune.hip", "cot1d.hip", "ns2d.hip", "hydrogen.hip"]
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          # never let the compiler form packed FP32 instructions

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -233,4 +234,7 @@ void finalize_structure(mwns_tree* t);
 // compress internal nodes bottom-up on the device (eq. decomp_scaling, three dimensions)
 void compress_tree(mwns_tree* t, const double* dH /* H0,H1 device [2][k][k] */);
 DevArray<double> upload_filters(mwns_ctx* ctx, int k);
+// structure of the tree with leaves keys[nleaves] (any order); coefficients left to the caller
+std::unique_ptr<mwns_tree> skeleton_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys,
+                                               std::vector<int64_t>* order, std::vector<int64_t>* pos);
 }  // namespace mwns

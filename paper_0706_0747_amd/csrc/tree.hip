@@ -788,13 +788,15 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     MWNS_GUARD_END
 }
 
-mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
-                                  mwns_tree** out) {
-    MWNS_GUARD_BEGIN
-    if (!ctx || !out || !keys || !coeffs) fail(MWNS_EINVAL, "NULL argument");
-    if (k < 1 || k > KMAX || nleaves < 1) fail(MWNS_EINVAL, "k or nleaves out of range");
-    const int k3 = k * k * k;
-    std::vector<int64_t> order(nleaves);
+}  // extern "C"
+
+// The structure of the tree whose leaves are keys[] (validated as a tiling of the unit cube): all
+// ancestors, levels and bricks, keys and leaf flags on the device, and an uninitialised brick array.
+// order = the sort permutation of keys, pos[i] = node index of keys[order[i]].
+std::unique_ptr<mwns_tree> mwns::skeleton_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys,
+                                                     std::vector<int64_t>* order_out, std::vector<int64_t>* pos_out) {
+    std::vector<int64_t>& order = *order_out;
+    order.resize(nleaves);
     std::iota(order.begin(), order.end(), 0);
     for (int64_t i = 0; i < nleaves; ++i) {
         const int j = key_level(keys[i]);
@@ -826,7 +828,8 @@ mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const u
     t->k = k;
     t->keys = all;
     t->leaf.assign(all.size(), 0);
-    std::vector<int64_t> pos(nleaves);
+    std::vector<int64_t>& pos = *pos_out;
+    pos.assign(nleaves, 0);
     for (int64_t i = 0; i < nleaves; ++i) {
         const uint64_t key = keys[order[i]];
         if (i && key == keys[order[i - 1]]) fail(MWNS_EINVAL, "duplicate leaf key");
@@ -849,6 +852,20 @@ mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const u
     t->dkeys.upload(t->keys.data(), t->nnodes, st);
     t->dleaf.upload(t->leaf.data(), t->nnodes, st);
     t->coef.reset(ctx, (size_t)t->nbricks * brick_elems(k));
+    return t;
+}
+
+extern "C" {
+
+mwns_status mwns_tree_from_leaves(mwns_ctx* ctx, int k, int64_t nleaves, const uint64_t* keys, const double* coeffs,
+                                  mwns_tree** out) {
+    MWNS_GUARD_BEGIN
+    if (!ctx || !out || !keys || !coeffs) fail(MWNS_EINVAL, "NULL argument");
+    if (k < 1 || k > KMAX || nleaves < 1) fail(MWNS_EINVAL, "k or nleaves out of range");
+    const int k3 = k * k * k;
+    std::vector<int64_t> order, pos;
+    std::unique_ptr<mwns_tree> t = skeleton_from_leaves(ctx, k, nleaves, keys, &order, &pos);
+    hipStream_t st = ctx->stream;
     std::vector<double> hb(t->coef.n, 0.0);
     for (int64_t i = 0; i < nleaves; ++i) {
         int64_t brick;
