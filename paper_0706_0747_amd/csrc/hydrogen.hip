@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(PT) coulomb_product_kernel(const ProdJob* __re
     __shared__ double Ph[KK];          // Ph[a * K + q] = phi_a(x_q) (transposed: row = output degree)
     __shared__ double fac[3][K];       // per dimension: w_q and the node's coordinate offset from the centre
     __shared__ double off[3][K];
-    const ProdJob jb = jobs[blockIdx.x];
+    const ProdJob& jb = jobs[blockIdx.x];      // read in place: a private copy indexed by d would spill
     const int tid = threadIdx.x;
     for (int e = tid; e < K3; e += PT) {
         const int a = e / KK, b = (e / K) % K, c = e % K;

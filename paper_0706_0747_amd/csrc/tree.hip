@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(PT) compress_kernel(int j, const int64_t* __re
 
 // f at points from the leaf holding each point (App. A.1).
 template <int K>
-__global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const int32_t* __restrict__ child,
+__global__ void __launch_bounds__(64) eval_kernel(int64_t npts, const double* __restrict__ xyz, const int32_t* __restrict__ child,
                             const uint8_t* __restrict__ leaf, LevelTab lt, const double* __restrict__ coef,
                             double* __restrict__ out, int* __restrict__ bad) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,18 +356,22 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
             v = v < 0 ? 0 : (v > side - 1 ? side - 1 : v);
             u[d] = x[d] * side - v;
         }
+        // every loop over d and a is unrolled, so ph stays in registers (no private memory)
         double ph[3][K];
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             const double t = 2.0 * u[d] - 1.0;
             double p0 = 1.0, p1 = t;
             ph[d][0] = 1.0;
             if (K > 1) ph[d][1] = t;
+#pragma unroll
             for (int a = 2; a < K; ++a) {
                 const double p2 = ((2 * a - 1) * t * p1 - (a - 1) * p0) / a;
                 ph[d][a] = p2;
                 p0 = p1;
                 p1 = p2;
             }
+#pragma unroll
             for (int a = 0; a < K; ++a) ph[d][a] *= sqrt(2.0 * a + 1.0);
         }
         int64_t brick;
@@ -375,10 +379,13 @@ __global__ void eval_kernel(int64_t npts, const double* __restrict__ xyz, const 
         node_to_brick(lt, j, node, &brick, &sib);
         const double* cb = coef + brick * (int64_t)(8 * K * K * K);
         double s = 0.0;
+#pragma unroll
         for (int a = 0; a < K; ++a) {
             double sa = 0.0;
+#pragma unroll
             for (int b = 0; b < K; ++b) {
                 double sb = 0.0;
+#pragma unroll
                 for (int c = 0; c < K; ++c) sb += cb[brick_index(K, sib, a, b, c)] * ph[2][c];
                 sa += sb * ph[1][b];
             }
