@@ -77,7 +77,7 @@ __device__ inline void line_apply(const double* __restrict__ M, const double* in
 // formed in registers.
 template <int K>
 __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jmax, const uint64_t* __restrict__ keys, int nsrc,
-                                                     const double* __restrict__ src /* x,y,z,a,cf per term */,
+                                                     const double* __restrict__ src /* x,y,z,a,cf,lim per term */,
                                                      double nc3, double ni, const double* __restrict__ tab,
                                                      double* __restrict__ s_out, double* __restrict__ err_out) {
     // nc3 = 2^{-3j/2} and ni = 2^{3j/2}, the level's normalisation of the scaling functions
@@ -100,7 +100,8 @@ __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jma
     __shared__ double smem[(NE > NTR ? NE : NTR) + K3];
     __shared__ double red[NW];
     __shared__ double xq[3 * NQ];            // 1-D points [d][q]
-    __shared__ double st[CH * 5];            // the current chunk of terms
+    __shared__ double st[CH * 5];            // the current chunk of terms (x, y, z, a, cf)
+    __shared__ int chunk_n, cursor;          // kept terms in the chunk; next source to screen
     double* E = smem;
     double* t1 = smem;
     double* t2 = smem + 2 * K3;
@@ -130,11 +131,53 @@ __global__ void __launch_bounds__(proj_threads(K)) project_kernel(int j, int jma
         }
         xq[e] = x;
     }
-    for (int c0 = 0; c0 < nsrc; c0 += CH) {
-        const int nc = min(CH, nsrc - c0);
-        const int nc4 = (nc + 3) & ~3;       // whole steps of four terms; the padding terms are zero
-        for (int e = threadIdx.x; e < nc * 5; e += BT) st[e] = src[(int64_t)c0 * 5 + e];
+    // Source screening: a term whose largest value on the box, |cf| e^{-a d^2} (d the distance from its
+    // centre to the box), lies below 2^-64 of the refinement threshold is skipped (lim = ln(|cf| / thr)
+    // + 64 ln 2, precomputed per term: skip when a d^2 > lim).  The kept terms enter the chunks in
+    // their original order; wave 0 screens 64 sources per step and compacts them by ballot.
+    if (threadIdx.x == 0) cursor = 0;
+    __syncthreads();
+    for (;;) {
+        if (wave == 0) {
+            int cnt = 0, cur = cursor;
+            while (cnt < CH && cur < nsrc) {
+                const int i = cur + lane;
+                bool kp = false;
+                if (i < nsrc) {
+                    const double* sp = src + (int64_t)i * 6;
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double lo = h * (double)l[d], hi = h * (double)(l[d] + 1);
+                        const double dd = fmax(fmax(lo - sp[d], sp[d] - hi), 0.0);
+                        d2 += dd * dd;
+                    }
+                    kp = sp[3] * d2 <= sp[5];
+                }
+                const uint64_t m = __ballot(kp);
+                const int pre = __popcll(m & ((1ull << lane) - 1ull));
+                const int tot = __popcll(m);
+                const int take = min(tot, CH - cnt);
+                if (kp && pre < take)
+                    for (int e = 0; e < 5; ++e) st[(cnt + pre) * 5 + e] = src[(int64_t)i * 6 + e];
+                if (take < tot) {      // the chunk is full inside this window: resume at the first kept source left
+                    uint64_t rest = m;
+                    for (int q = 0; q < take; ++q) rest &= rest - 1ull;
+                    cur += __ffsll((long long)rest) - 1;
+                } else {
+                    cur += 64;
+                }
+                cnt += take;
+            }
+            if (lane == 0) {
+                chunk_n = cnt;
+                cursor = cur;
+            }
+        }
         __syncthreads();
+        const int nc = chunk_n;
+        if (nc == 0) break;
+        const int nc4 = (nc + 3) & ~3;       // whole steps of four terms; the padding terms are zero
         for (int e = threadIdx.x; e < nc4 * 3 * NQ; e += BT) {
             const int q = e % NQ, d = (e / NQ) % 3, i = e / (3 * NQ);
             double v = 0.0;
@@ -695,15 +738,19 @@ mwns_status mwns_project_gaussians(mwns_ctx* ctx, int k, double eps, int j0, int
     t->hold.set(ctx);
     t->k = k;
     const int k3 = k * k * k;
-    // source terms: x, y, z, a, c (a/pi)^{3/2}
-    std::vector<double> src(5 * n);
-    for (int i = 0; i < n; ++i) {
-        for (int d = 0; d < 3; ++d) src[5 * i + d] = xyz[3 * i + d];
-        src[5 * i + 3] = a[i];
-        src[5 * i + 4] = c[i] * std::pow(a[i] / M_PI, 1.5);
-    }
+    // source terms: x, y, z, a, cf = c (a/pi)^{3/2}, and the screening limit lim = ln(|cf| / thr) + 64 ln 2
+    // (a box at distance d from the centre skips the term when a d^2 > lim: its values there stay below
+    // 2^-64 thr; thr = 0 keeps every term, cf = 0 none)
     const double thr = eps * source_norm(n, xyz, a, c);
     t->threshold = thr;
+    std::vector<double> src(6 * n);
+    for (int i = 0; i < n; ++i) {
+        for (int d = 0; d < 3; ++d) src[6 * i + d] = xyz[3 * i + d];
+        src[6 * i + 3] = a[i];
+        const double cf = c[i] * std::pow(a[i] / M_PI, 1.5);
+        src[6 * i + 4] = cf;
+        src[6 * i + 5] = thr > 0.0 ? std::log(std::fabs(cf) / thr) + 64.0 * std::log(2.0) : INFINITY;
+    }
     std::vector<double> tab;
     projection_tables(k, tab);
     DevArray<double> dsrc(ctx, src.size()), dtab(ctx, tab.size());
