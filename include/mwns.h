@@ -95,10 +95,12 @@ const char* mwns_last_error(void);
  * [0, mwns_num_variants_for(k)), or -1 for the library's default.  For k <= 8 (the one-tile kernel,
  * mwns_num_variants() shapes, mwns_variant_shape) the default is the shape with two terms per pass
  * and a prefetched input slice for 6 <= k <= 8, variant 0 below; for k = 9, 10 (one workgroup of four
- * waves per sibling group, or two such groups on alternate terms) variant 0, the default, is one
- * group per workgroup loading the next input slice while computing the current one, variant 1 two
- * groups per workgroup (their sums are added at the end, so it agrees with variant 0 up to
- * rounding), variant 2 as 0 loading each slice when it is needed (bit for bit as 0).  Variants
+ * waves per sibling group, or two such groups on alternate terms) variant 0 is one group per
+ * workgroup loading the next input slice while computing the current one, variant 1 two groups per
+ * workgroup (their sums are added at the end, so it agrees with variant 0 up to rounding), variant 2
+ * as 0 loading each slice when it is needed (bit for bit as 0), and variant 3, the default, as 2 with
+ * one buffer for the exchanged slices instead of two, so that three workgroups share a compute unit
+ * (three waves per SIMD; bit for bit as 0).  Variants
  * differ in speed only: those with one term per pass compute the same result bit for bit; those
  * with several terms per pass add the plane results of consecutive terms in another order, so they
  * agree with the others up to rounding.  mwns_tune_apply picks one by timing.

@@ -870,7 +870,8 @@ int num_variants() { return NVARIANTS; }
 
 int variant_for(const mwns_ctx* ctx, int k) {
     const int v = ctx->variant[k];
-    return v >= 0 ? v : (k > KNARROW ? 0 : default_variant(k));
+    // k = 9, 10: variant 3 (three workgroups per compute unit), the fastest on the k = 10 workloads
+    return v >= 0 ? v : (k > KNARROW ? 3 : default_variant(k));
 }
 
 template <template <int> class Fn, class... Args>

@@ -82,10 +82,14 @@ struct BrickShape {
     static constexpr int SM_S = 3 * NMAX * BLK;  // staged super-blocks [d][L - lo_d][v][u]
     static constexpr int SM_X = 2 * 4 * BLK;     // exchange buffers [2][slot][u2][u3]
     static constexpr int SMEM = SM_S + SM_X;     // per term group
+    static constexpr int SMEM1 = SM_S + SM_X / 2;   // one exchange buffer: three workgroups per CU
+    template <int NXB>
+    static constexpr int smem() { return NXB == 2 ? SMEM : SMEM1; }
     static_assert(D > 16 && D <= DP, "rows and columns 16..D-1 are the 4-row tails");
     static_assert(SMEM * 8 + 1024 <= 80 * 1024, "one term group: two workgroups per CU");
     static_assert(2 * SMEM * 8 + 1024 <= 160 * 1024, "two term groups: one workgroup per CU");
     static_assert(4 * 35 * 64 <= 2 * SMEM, "the second group's accumulators fit the LDS of both");
+    static_assert(3 * (SMEM1 * 8 + 1024) <= 160 * 1024, "one exchange buffer: three workgroups per CU");
 };
 
 __device__ inline double mfma4(double a, double b, double c) { return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0); }
@@ -191,7 +195,7 @@ __device__ inline void brick_slice_load(const double* __restrict__ X, int v1, co
 // slice of the next item while the current one is computed, PF = 0 each slice when it is needed.
 // Down-band jobs whose brick has leaf children run mode 1 in two passes, one per half u1 < K,
 // u1 >= K, each with the output columns of leaf children masked out of the exchanged slices.
-template <int K, int PF, int TG, int PREC>
+template <int K, int PF, int TG, int PREC, int NXB>
 __device__ __forceinline__ void brick_job(const LevelDesc& lv, const Tpl& tp, int ns, const int2* __restrict__ steps,
                                           double* __restrict__ smem, int h, int wave, int g, int r, int cmb,
                                           d4 (&Yf)[5], double (&Yr)[5], double (&Yc)[5], double (&Yx)[5]) {
@@ -362,7 +366,10 @@ __device__ __forceinline__ void brick_job(const LevelDesc& lv, const Tpl& tp, in
                     Yr[q] = mfma4(ar, bf1, Yr[q]);
                     Yx[q] = mfma4(ar, bt1, Yx[q]);
                 }
-                buf ^= 1;
+                // two exchange buffers alternate; with one, the next round writes it only after every
+                // wave's mode 1 has read it
+                if (NXB == 2) buf ^= 1;
+                else wlds_barrier();
             }
             p0 = p1;
         }
@@ -371,7 +378,7 @@ __device__ __forceinline__ void brick_job(const LevelDesc& lv, const Tpl& tp, in
 
 // Every job of class PREC of one output brick, then the brick written (FP64: zero for children
 // the level does not hold, i.e. the siblings of the root) or added to (FP32).
-template <int K, int PF, int TG, int PREC>
+template <int K, int PF, int TG, int PREC, int NXB>
 __device__ __forceinline__ void brick_contract(const LevelDesc* __restrict__ levels, int2 job, double* smem, int2* steps,
                                                int* nsteps) {
     using B = BrickShape<K>;
@@ -400,7 +407,8 @@ __device__ __forceinline__ void brick_contract(const LevelDesc* __restrict__ lev
         if (tp.dpart && cmb == 0) continue;     // no internal child receives the down band
         const int ns = wide_steps(tp, nb, Lr, steps, nsteps);
         if (ns == 0) continue;
-        brick_job<K, PF, TG, PREC>(lv, tp, ns, steps, smem + h * B::SMEM, h, wave, g, r, cmb, Yf, Yr, Yc, Yx);
+        brick_job<K, PF, TG, PREC, NXB>(lv, tp, ns, steps, smem + h * B::template smem<NXB>(), h, wave, g, r, cmb, Yf, Yr,
+                                        Yc, Yx);
     }
     if (TG > 1) {      // the second group's accumulators added to the first's, through LDS
         wlds_barrier();
@@ -448,14 +456,16 @@ __device__ __forceinline__ void brick_contract(const LevelDesc* __restrict__ lev
 
 // order[] entries are (level descriptor, brick).  queues: as the one-tile kernel.  TG term groups
 // of four waves: 256 TG threads, one workgroup per CU for TG = 2, two for TG = 1.
-template <int K, int PF, int TG, int PREC>
-__global__ void __launch_bounds__(256 * TG) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// NXB exchange buffers: 2, two waves per SIMD; 1 (one term group only), three.
+template <int K, int PF, int TG, int PREC, int NXB>
+__global__ void __launch_bounds__(256 * TG) __attribute__((amdgpu_waves_per_eu(NXB == 1 ? 3 : 2, NXB == 1 ? 3 : 2)))
 ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restrict__ order, int* __restrict__ queues) {
-    __shared__ double smem[TG * BrickShape<K>::SMEM];
+    static_assert(NXB == 2 || TG == 1, "one exchange buffer takes one term group");
+    __shared__ double smem[TG * BrickShape<K>::template smem<NXB>()];
     __shared__ int2 steps[NMAX * NMAX * NMAX];
     __shared__ int nsteps_s, pos_s;
     if (!queues) {
-        brick_contract<K, PF, TG, PREC>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
+        brick_contract<K, PF, TG, PREC, NXB>(levels, order[blockIdx.x], smem, steps, &nsteps_s);
         return;
     }
     const int x0 = blockIdx.x % NXCD;
@@ -478,30 +488,34 @@ ns_apply_wide_kernel(const LevelDesc* __restrict__ levels, const int2* __restric
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0) break;
-        brick_contract<K, PF, TG, PREC>(levels, order[pos], smem, steps, &nsteps_s);
+        brick_contract<K, PF, TG, PREC, NXB>(levels, order[pos], smem, steps, &nsteps_s);
     }
 }
 
 // Variants: 0 (default) one term group of four waves, two workgroups per CU; 1 two term groups,
 // one workgroup per CU; both load the next item's input slice while computing the current one.
-// 2 as 0, loading each slice when it is needed.
-constexpr int WIDE_VARIANTS = 3;
+// 2 as 0, loading each slice when it is needed.  3 as 2 with one exchange buffer (an extra barrier
+// per round), which lets three workgroups share a CU (three waves per SIMD).
+constexpr int WIDE_VARIANTS = 4;
 
 template <int K, int PREC>
 struct WideLaunch {
     static void run(int variant, hipStream_t st, int64_t nblocks, const LevelDesc* levels, const int2* order, int* queues) {
-        if (variant == 1) ns_apply_wide_kernel<K, 1, 2, PREC><<<(unsigned)nblocks, 512, 0, st>>>(levels, order, queues);
-        else if (variant == 2) ns_apply_wide_kernel<K, 0, 1, PREC><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
-        else ns_apply_wide_kernel<K, 1, 1, PREC><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
+        if (variant == 1) ns_apply_wide_kernel<K, 1, 2, PREC, 2><<<(unsigned)nblocks, 512, 0, st>>>(levels, order, queues);
+        else if (variant == 2) ns_apply_wide_kernel<K, 0, 1, PREC, 2><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
+        else if (variant == 3) ns_apply_wide_kernel<K, 0, 1, PREC, 1><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
+        else ns_apply_wide_kernel<K, 1, 1, PREC, 2><<<(unsigned)nblocks, 256, 0, st>>>(levels, order, queues);
     }
     static int per_cu(int variant) {
         int n = 0;
         if (variant == 1)
-            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 1, 2, PREC>, 512, 0));
+            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 1, 2, PREC, 2>, 512, 0));
         else if (variant == 2)
-            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 0, 1, PREC>, 256, 0));
+            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 0, 1, PREC, 2>, 256, 0));
+        else if (variant == 3)
+            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 0, 1, PREC, 1>, 256, 0));
         else
-            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 1, 1, PREC>, 256, 0));
+            MWNS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ns_apply_wide_kernel<K, 1, 1, PREC, 2>, 256, 0));
         return n;
     }
 };

@@ -93,7 +93,7 @@ def test_wide_full_plan_random_coefficients(M, ctx):
 @pytest.mark.parametrize("case", ["k10_poisson", "k9_yukawa"])
 def test_wide_variants_match_oracle(M, ctx, case):
     """Every tile variant of the k = 9, 10 kernel (one term group with and without the slice
-    prefetch, two term groups) under the full plan on random leaf coefficients, so that every mask,
+    prefetch, two term groups, one term group with one exchange buffer) under the full plan on random leaf coefficients, so that every mask,
     the down band at bricks with leaf children (two-pass mode 1) and odd term counts (the second
     group idle for the last term) are exercised: each against the oracle within 1e-12; the
     one-group variants bit for bit equal."""
@@ -112,10 +112,10 @@ def test_wide_variants_match_oracle(M, ctx, case):
     f = M.mwns_tree_from_leaves(ctx, w.k, keys, coef)
     op = M.mwns_op_create(ctx, w.k, tau, wt, w.eps, ot.depth)
     M.mwns_op_plan_import(op, R)
-    assert M.mwns_num_variants_for(w.k) == 3
+    assert M.mwns_num_variants_for(w.k) == 4
     out = []
     try:
-        for v in range(3):
+        for v in range(4):
             M.mwns_ctx_set_variant(ctx, w.k, v)
             _, _, ghat = M.mwns_tree_export(ctx, M.mwns_apply(ctx, op, f, M.MWNS_NO_ASSEMBLY)[0])
             assert np.linalg.norm(ghat - gh) <= 1e-12 * np.linalg.norm(gh), "variant %d" % v
@@ -123,7 +123,7 @@ def test_wide_variants_match_oracle(M, ctx, case):
             out.append(ghat)
     finally:
         M.mwns_ctx_set_variant(ctx, w.k, -1)
-    assert np.array_equal(out[0], out[2])
+    assert np.array_equal(out[0], out[2]) and np.array_equal(out[0], out[3])
 
 
 def test_wide_in_batch_plan_and_routing(M, ctx):
