@@ -39,8 +39,9 @@ __device__ inline int64_t brick_index(int k, int child, int a, int b, int c) {
 namespace {
 
 constexpr int PT = 256;   // threads of the transform blocks
-// threads of a projection block: eight waves above k = 8, where a box has 48-57 MFMA tiles
-constexpr int proj_threads(int k) { return k >= 9 ? 512 : 256; }
+// threads of a projection block: sixteen waves above k = 8, where a box has 48-57 MFMA tiles (four per
+// wave keep the accumulators small enough for four waves per SIMD; eight waves held two)
+constexpr int proj_threads(int k) { return k >= 9 ? 1024 : 256; }
 // source terms per chunk: 64 above k = 8, where the term table still fits in the transform buffers
 constexpr int proj_chunk(int k) { return k >= 9 ? 64 : 32; }
 typedef double d4 __attribute__((ext_vector_type(4)));
