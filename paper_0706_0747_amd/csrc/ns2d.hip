@@ -301,6 +301,85 @@ __global__ void __launch_bounds__(256) contract2_wave_kernel(int n, int M, const
     if (act) out[(int64_t)node * KK + e] = acc;
 }
 
+// Orders 5..8 on the matrix cores: one workgroup of four wavefronts per output node; wave w takes
+// the (job, term) pairs of the node whose running index is w mod 4, and the four partial sums are
+// added in wave order at the end.  The k x k blocks are padded to 8 x 8 (zeros) and cut into 2 x 2
+// blocks of 4 x 4, one per block of the four-block v_mfma_f64_4x4x4 (A[i][k] of block b in lane
+// i + 4b + 16k, B[k][j] in lane j + 4b + 16k, D[i][j] in lane j + 4b + 16i); block b = 2 bi + bj is the
+// output block (rows 4 bi.., columns 4 bj..), and lane (x, b, y) = x + 4b + 16y.  Per job the lane
+// holds X[4 bi + x][4 kk + y] (kk = 0, 1); per term, with the wave's next term of the job loaded
+// meanwhile:
+//   T = X F2^T in two steps kk (B = F2[4 bj + x][4 kk + y]), which leaves T[4 bi + y][4 bj + x] in
+//   the lane;
+//   y += c w F1 T in two steps kk (A = c w F1[4 bi + x][4 kk + y], B = T[4 kk + y][4 bj + x], taken
+//   by a shuffle from the lane of block (kk, bj)).
+template <int K>
+__global__ void __launch_bounds__(256) contract2_mfma_kernel(int n, int M, const int* __restrict__ nlev,
+                                                             const int64_t* __restrict__ off, const Job2* __restrict__ jobs,
+                                                             const double* __restrict__ F, const double* __restrict__ w,
+                                                             const double* __restrict__ X, double* __restrict__ out) {
+    static_assert(K > 4 && K <= 8, "two 4 x 4 blocks per dimension");
+    constexpr int KK = K * K, NW = 4;
+    __shared__ double part[NW][64];
+    const int node = blockIdx.x;
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int x = lane & 3, bk = (lane >> 2) & 3, y = lane >> 4;
+    const int bi = bk >> 1, bj = bk & 1;
+    const int ra = 4 * bi + x, rb = 4 * bj + x;     // rows of the A operands (X, F1) and of F2
+    const bool va0 = ra < K && y < K, va1 = ra < K && 4 + y < K;
+    const bool vb0 = rb < K && y < K, vb1 = rb < K && 4 + y < K;
+    const int oa0 = va0 ? ra * K + y : 0, oa1 = va1 ? ra * K + 4 + y : 0;
+    const int ob0 = vb0 ? rb * K + y : 0, ob1 = vb1 ? rb * K + 4 + y : 0;
+    const int s0 = x + 4 * bj + 16 * y, s1 = x + 4 * (2 + bj) + 16 * y;   // lanes of blocks (0, bj), (1, bj)
+    const int j = nlev[node];
+    const int64_t stride = (int64_t)15 * KK;        // from term m to m + 1
+    double acc = 0.0;
+    int base = 0;                                   // running index of the node's (job, term) pairs
+    for (int64_t q = off[node]; q < off[node + 1]; ++q) {
+        const Job2 jb = jobs[q];
+        const int cnt = jb.m2 - jb.m1 + 1;
+        const int t0 = ((wv - base) % NW + NW) % NW;
+        base += cnt;
+        if (t0 >= cnt) continue;
+        const double* Xb = X + jb.in * KK;
+        const double xa0 = va0 ? Xb[oa0] : 0.0, xa1 = va1 ? Xb[oa1] : 0.0;
+        const double* F1b = F + (((int64_t)j * M) * 15 + (jb.l1 + 7)) * KK;
+        const double* F2b = F + (((int64_t)j * M) * 15 + (jb.l2 + 7)) * KK;
+        double f10, f11, f20, f21;
+        auto load = [&](int m, double& a0, double& a1, double& b0, double& b1) {
+            const double* p1 = F1b + m * stride;
+            const double* p2 = F2b + m * stride;
+            a0 = va0 ? p1[oa0] : 0.0;
+            a1 = va1 ? p1[oa1] : 0.0;
+            b0 = vb0 ? p2[ob0] : 0.0;
+            b1 = vb1 ? p2[ob1] : 0.0;
+        };
+        load(jb.m1 + t0, f10, f11, f20, f21);
+        for (int m = jb.m1 + t0; m <= jb.m2; m += NW) {
+            double n10, n11, n20, n21;
+            load(m + NW <= jb.m2 ? m + NW : m, n10, n11, n20, n21);
+            double t = __builtin_amdgcn_mfma_f64_4x4x4f64(xa0, f20, 0.0, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f64_4x4x4f64(xa1, f21, t, 0, 0, 0);
+            const double cw = jb.sign * w[m];
+            const double t0v = __shfl(t, s0), t1v = __shfl(t, s1);
+            acc = __builtin_amdgcn_mfma_f64_4x4x4f64(cw * f10, t0v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_4x4x4f64(cw * f11, t1v, acc, 0, 0, 0);
+            f10 = n10;
+            f11 = n11;
+            f20 = n20;
+            f21 = n21;
+        }
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+        const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const int ro = 4 * bi + y, co = 4 * bj + x;
+        if (ro < K && co < K) out[(int64_t)node * KK + ro * K + co] = sum;
+    }
+}
+
 // g[node] += H^(sx)^T g[parent] H^(sy) for the nodes of one level
 __global__ void assemble2_kernel(int k, int n, const int64_t* __restrict__ node, const int64_t* __restrict__ par,
                                  const int* __restrict__ sg, const double* __restrict__ H, double* __restrict__ g) {
@@ -951,8 +1030,15 @@ mwns_status mwns_apply2d(mwns_ctx* ctx, const mwns_op2* op, const mwns_tree2* f,
         contract2_wave_kernel<KV><<<(unsigned)((no + 3) / 4), 256, 0, st>>>((int)no, op->M, dnl.p, doff.p, djobs.p, op->F.p, \
                                                                           op->dw.p, X.p, out.p); \
         break;
-        MWNS_C2W(1) MWNS_C2W(2) MWNS_C2W(3) MWNS_C2W(4) MWNS_C2W(5) MWNS_C2W(6) MWNS_C2W(7) MWNS_C2W(8)
+        MWNS_C2W(1) MWNS_C2W(2) MWNS_C2W(3) MWNS_C2W(4)
 #undef MWNS_C2W
+#define MWNS_C2M(KV) \
+    case KV: \
+        contract2_mfma_kernel<KV><<<(unsigned)no, 256, 0, st>>>((int)no, op->M, dnl.p, doff.p, djobs.p, op->F.p, \
+                                                                          op->dw.p, X.p, out.p); \
+        break;
+        MWNS_C2M(5) MWNS_C2M(6) MWNS_C2M(7) MWNS_C2M(8)
+#undef MWNS_C2M
         default:
             contract2_kernel<<<(unsigned)no, 128, 0, st>>>(k, op->M, dnl.p, doff.p, djobs.p, op->F.p, op->dw.p, X.p, out.p);
     }
