@@ -265,6 +265,30 @@ def test_coarse_start_and_uniform_trees(M, ctx, j0, jmax):
     assert np.linalg.norm(gg - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+def test_projection_source_screening_edges(M, ctx):
+    """The projection skips, per box, the sources whose values there stay below 2^-64 of the threshold:
+    with 130 narrow Gaussians at k = 10 (two windows of 64 sources, chunks filled across windows) and
+    every fifth weight zero (never kept), the tree is the oracle's bit for bit and the coefficients agree
+    to 1e-13; with every weight zero (threshold 0: every source kept, nothing refined) the tree is the
+    level-j0 grid of zero blocks."""
+    from oracle import tree as T
+    rng = np.random.default_rng(21)
+    n = 130
+    xyz = rng.uniform(0.2, 0.8, (n, 3))
+    a = 10 ** rng.uniform(2.5, 4.5, n)
+    c = rng.normal(size=n)
+    c[::5] = 0.0
+    keys, coef = T.project_gaussians(10, 1e-6, 2, 5, xyz, a, c)
+    ot = T.redundant_tree(10, keys, coef)
+    g = M.mwns_project_gaussians(ctx, 10, 1e-6, 2, 5, xyz, a, c)
+    gk, gl, gc = M.mwns_tree_export(ctx, g)
+    assert np.array_equal(gk, ot.keys) and np.array_equal(gl, ot.leaf)
+    assert np.abs(gc - ot.coef).max() <= 1e-13 * np.abs(ot.coef).max()
+    z = M.mwns_project_gaussians(ctx, 6, 1e-6, 2, 6, xyz[:3], a[:3], np.zeros(3))
+    zk, zl, zc = M.mwns_tree_export(ctx, z)
+    assert int(zl.sum()) == 64 and np.all((zk >> np.uint64(57))[zl == 1] == 2) and not np.any(zc)
+
+
 def test_tree_from_leaves_full_plan_random_coefficients(M, ctx):
     """Imported leaves (random blocks on an adaptive structure) with screening off: every term on
     every coarse displacement, against the oracle."""
