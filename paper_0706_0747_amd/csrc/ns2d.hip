@@ -21,7 +21,9 @@
 // Keys: level << 57 | morton(x, y) with x in bit 0; blocks [k][k], a = degree in x, b = degree in y.
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <memory>
+#include <thread>
 #include <unordered_map>
 
 #include "mwns_internal.h"
@@ -930,75 +932,134 @@ mwns_status mwns_apply2d(mwns_ctx* ctx, const mwns_op2* op, const mwns_tree2* f,
         *m1 = r[0];
         *m2 = r[1];
     };
-    std::unordered_map<uint64_t, int64_t> inidx;
-    std::vector<int64_t> ianc, ixy;
-    std::vector<int> iup;
-    auto input = [&](int j, int64_t x, int64_t y) -> int64_t {
-        const uint64_t kk2 = key2(j, x, y);
-        auto it = inidx.find(kk2);
-        if (it != inidx.end()) return it->second;
-        int up = 0;
-        int64_t p;
-        while ((p = find_sorted(f->keys.data(), no, key2(j - up, x >> up, y >> up))) < 0) ++up;
-        const int64_t id = (int64_t)ianc.size();
-        ianc.push_back(p);
-        iup.push_back(up);
-        ixy.push_back(x);
-        ixy.push_back(y);
-        inidx.emplace(kk2, id);
-        return id;
+    // The job lists, built by several host threads over contiguous node ranges.  Each range keeps its
+    // own table of inputs (an input box seen by two ranges is gathered twice, with the same values),
+    // and the ranges are joined in node order, so the result does not depend on the thread count.
+    struct Part {
+        std::vector<Job2> jobs;
+        std::vector<int64_t> ends;                   // jobs.size() after each node of the range
+        std::unordered_map<uint64_t, int64_t> inidx;
+        std::vector<int64_t> ianc, ixy;
+        std::vector<int> iup;
+        double fl = 0.0;
     };
-    std::vector<int64_t> off(1, 0);
-    std::vector<Job2> jobs;
     std::vector<int> nl(no);
-    double fl = 0.0;
-    auto add = [&](int64_t in, int l1, int l2, int a, int b, int sign) {
-        if (b < a) return;
-        jobs.push_back(Job2{in, l1, l2, a, b, sign, 0});
-        fl += (double)(b - a + 1) * 4.0 * k * kk;
-    };
-    for (int64_t i = 0; i < no; ++i) {
-        const int j = key2_level(f->keys[i]);
-        int64_t bx, by;
-        key2_xy(f->keys[i], &bx, &by);
-        const bool lf = f->leaf[i] != 0;
-        nl[i] = j;
-        if (j == 0) {
-            int a1, b1, a2 = 0, b2 = -1;
-            range(0, 0, 0, &a1, &b1);
-            if (!lf) range(1, 0, 0, &a2, &b2);
-            const int64_t in = input(0, 0, 0);
-            // [a1, b1] minus [a2, b2] (R_1(0) lies inside R_0 = all terms)
-            if (b2 < a2) add(in, 0, 0, a1, b1, 1);
-            else {
-                add(in, 0, 0, a1, std::min(b1, a2 - 1), 1);
-                add(in, 0, 0, std::max(a1, b2 + 1), b1, 1);
-                add(in, 0, 0, std::max(a2, b1 + 1), b2, -1);
-                add(in, 0, 0, a2, std::min(b2, a1 - 1), -1);
-            }
-        } else {
-            const int64_t n = (int64_t)1 << j;
-            for (int l1 = -7; l1 <= 7; ++l1)
-                for (int l2 = -7; l2 <= 7; ++l2) {
-                    const int64_t px = bx - l1, py = by - l2;
-                    if (px < 0 || px >= n || py < 0 || py >= n) continue;
-                    int a1, b1, a2 = 0, b2 = -1;
-                    range(j, (int)((bx >> 1) - (px >> 1)), (int)((by >> 1) - (py >> 1)), &a1, &b1);
-                    if (!lf) range(j + 1, l1, l2, &a2, &b2);
-                    if (b1 < a1 && b2 < a2) continue;
-                    const int64_t in = input(j, px, py);
-                    if (b2 < a2 || b1 < a1 || b1 < a2 || b2 < a1) {        // disjoint or one empty
-                        add(in, l1, l2, a1, b1, 1);
-                        add(in, l1, l2, a2, b2, -1);
-                    } else {                                               // the overlap cancels
-                        add(in, l1, l2, a1, std::min(b1, a2 - 1), 1);
-                        add(in, l1, l2, std::max(a1, b2 + 1), b1, 1);
-                        add(in, l1, l2, a2, std::min(b2, a1 - 1), -1);
-                        add(in, l1, l2, std::max(a2, b1 + 1), b2, -1);
-                    }
+    auto build = [&](int64_t lo, int64_t hi, Part& P) {
+        auto input = [&](int j, int64_t x, int64_t y) -> int64_t {
+            const uint64_t kk2 = key2(j, x, y);
+            auto it = P.inidx.find(kk2);
+            if (it != P.inidx.end()) return it->second;
+            int up = 0;
+            int64_t p;
+            while ((p = find_sorted(f->keys.data(), no, key2(j - up, x >> up, y >> up))) < 0) ++up;
+            const int64_t id = (int64_t)P.ianc.size();
+            P.ianc.push_back(p);
+            P.iup.push_back(up);
+            P.ixy.push_back(x);
+            P.ixy.push_back(y);
+            P.inidx.emplace(kk2, id);
+            return id;
+        };
+        auto add = [&](int64_t in, int l1, int l2, int a, int b, int sign) {
+            if (b < a) return;
+            P.jobs.push_back(Job2{in, l1, l2, a, b, sign, 0});
+            P.fl += (double)(b - a + 1) * 4.0 * k * kk;
+        };
+        for (int64_t i = lo; i < hi; ++i) {
+            const int j = key2_level(f->keys[i]);
+            int64_t bx, by;
+            key2_xy(f->keys[i], &bx, &by);
+            const bool lf = f->leaf[i] != 0;
+            nl[i] = j;
+            if (j == 0) {
+                int a1, b1, a2 = 0, b2 = -1;
+                range(0, 0, 0, &a1, &b1);
+                if (!lf) range(1, 0, 0, &a2, &b2);
+                const int64_t in = input(0, 0, 0);
+                // [a1, b1] minus [a2, b2] (R_1(0) lies inside R_0 = all terms)
+                if (b2 < a2) add(in, 0, 0, a1, b1, 1);
+                else {
+                    add(in, 0, 0, a1, std::min(b1, a2 - 1), 1);
+                    add(in, 0, 0, std::max(a1, b2 + 1), b1, 1);
+                    add(in, 0, 0, std::max(a2, b1 + 1), b2, -1);
+                    add(in, 0, 0, a2, std::min(b2, a1 - 1), -1);
                 }
+            } else {
+                const int64_t n = (int64_t)1 << j;
+                for (int l1 = -7; l1 <= 7; ++l1)
+                    for (int l2 = -7; l2 <= 7; ++l2) {
+                        const int64_t px = bx - l1, py = by - l2;
+                        if (px < 0 || px >= n || py < 0 || py >= n) continue;
+                        int a1, b1, a2 = 0, b2 = -1;
+                        range(j, (int)((bx >> 1) - (px >> 1)), (int)((by >> 1) - (py >> 1)), &a1, &b1);
+                        if (!lf) range(j + 1, l1, l2, &a2, &b2);
+                        if (b1 < a1 && b2 < a2) continue;
+                        const int64_t in = input(j, px, py);
+                        if (b2 < a2 || b1 < a1 || b1 < a2 || b2 < a1) {        // disjoint or one empty
+                            add(in, l1, l2, a1, b1, 1);
+                            add(in, l1, l2, a2, b2, -1);
+                        } else {                                               // the overlap cancels
+                            add(in, l1, l2, a1, std::min(b1, a2 - 1), 1);
+                            add(in, l1, l2, std::max(a1, b2 + 1), b1, 1);
+                            add(in, l1, l2, a2, std::min(b2, a1 - 1), -1);
+                            add(in, l1, l2, std::max(a2, b1 + 1), b2, -1);
+                        }
+                    }
+            }
+            P.ends.push_back((int64_t)P.jobs.size());
         }
-        off.push_back((int64_t)jobs.size());
+    };
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::max(1u, std::thread::hardware_concurrency()), 16,
+                                                                (no + 511) / 512}));
+    std::vector<Part> parts(nth);
+    {
+        std::vector<std::exception_ptr> errs(nth);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                try {
+                    build(no * t / nth, no * (t + 1) / nth, parts[t]);
+                } catch (...) {
+                    errs[t] = std::current_exception();
+                }
+            });
+        for (auto& th : pool) th.join();
+        for (auto& e : errs)
+            if (e) std::rethrow_exception(e);
+    }
+    // the jobs of all ranges, their inputs renumbered, written by the same threads straight into the
+    // context's pinned staging block (one DMA to the device)
+    std::vector<int64_t> jbase(nth + 1, 0), ibase(nth + 1, 0);
+    for (int t = 0; t < nth; ++t) {
+        jbase[t + 1] = jbase[t] + (int64_t)parts[t].jobs.size();
+        ibase[t + 1] = ibase[t] + (int64_t)parts[t].ianc.size();
+    }
+    const int64_t njobs = jbase[nth];
+    Job2* hjobs = static_cast<Job2*>(pinned_staging(ctx, (size_t)std::max<int64_t>(njobs, 1) * sizeof(Job2)));
+    {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                Job2* dst = hjobs + jbase[t];
+                for (const Job2& jb : parts[t].jobs) {
+                    *dst = jb;
+                    dst->in += ibase[t];
+                    ++dst;
+                }
+            });
+        for (auto& th : pool) th.join();
+    }
+    std::vector<int64_t> off(1, 0), ianc, ixy;
+    std::vector<int> iup;
+    double fl = 0.0;
+    for (int t = 0; t < nth; ++t) {
+        Part& P = parts[t];
+        for (int64_t e : P.ends) off.push_back(jbase[t] + e);
+        ianc.insert(ianc.end(), P.ianc.begin(), P.ianc.end());
+        ixy.insert(ixy.end(), P.ixy.begin(), P.ixy.end());
+        iup.insert(iup.end(), P.iup.begin(), P.iup.end());
+        fl += P.fl;
+        P = Part();
     }
     const int64_t nin = (int64_t)ianc.size();
     hipStream_t st = ctx->stream;
@@ -1014,10 +1075,10 @@ mwns_status mwns_apply2d(mwns_ctx* ctx, const mwns_op2* op, const mwns_tree2* f,
         MWNS_HIP(hipStreamSynchronize(st));
     }
     DevArray<int64_t> doff(ctx, off.size());
-    DevArray<Job2> djobs(ctx, std::max<size_t>(jobs.size(), 1));
+    DevArray<Job2> djobs(ctx, (size_t)std::max<int64_t>(njobs, 1));
     DevArray<int> dnl(ctx, no);
     doff.upload(off.data(), off.size(), st);
-    djobs.upload(jobs.data(), jobs.size(), st);
+    djobs.upload(hjobs, (size_t)njobs, st);
     dnl.upload(nl.data(), no, st);
     DevArray<double> out(ctx, (size_t)no * kk);
     hipEvent_t e0, e1;
