@@ -90,6 +90,12 @@ size_t mwns_ctx_bytes_cached(const mwns_ctx* ctx);
 mwns_status mwns_ctx_release_cache(mwns_ctx* ctx);
 /* Thread-local text for the last non-OK status returned on this thread ("" if none). */
 const char* mwns_last_error(void);
+/* Version of this interface: the entry points, their structs, and the layouts of the arrays they
+ * export and import (plans of mwns_op_plan_export / mwns_op2d_plan_export, trees of
+ * mwns_tree_export and its 1-D and 2-D forms).  A caller that stores such arrays stores the version
+ * beside them and compares it before importing; the library returns MWNS_ABI_VERSION. */
+#define MWNS_ABI_VERSION 3
+int mwns_abi_version(void);
 
 /* Tile variant of the FP64 contraction kernel used by this context for basis order k: an index in
  * [0, mwns_num_variants_for(k)), or -1 for the library's default.  For k <= 8 (the one-tile kernel,

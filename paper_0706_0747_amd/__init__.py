@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (MWNS_CLASS_BF16, MWNS_CLASS_BF16C, MWNS_CLASS_F32, MWNS_F64, MWNS_NO_ASSEMBLY, MWNS_TIMES_ONLY, MwnsError, check,
                    lib)
 
-__all__ = ["Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
+__all__ = ["mwns_abi_version", "Context", "Operator", "Tree", "MwnsError", "MWNS_F64", "MWNS_NO_ASSEMBLY", "MWNS_TIMES_ONLY", "MWNS_CLASS_F32",
            "MWNS_CLASS_BF16C", "MWNS_CLASS_BF16", "mwns_apply_mixed", "default_classes", "mwns_tree_detail_norms", "mwns_tree_prune",
            "mwns_tree_discard", "Op1", "Tree1", "mwns_cot1d_op_create", "mwns_cot1d_op_bands", "mwns_cot1d_op_set_bands",
            "mwns_cot1d_op_blocks", "mwns_cot1d_project", "mwns_cot1d_from_leaves", "mwns_cot1d_apply", "mwns_cot1d_export",
@@ -266,6 +266,11 @@ def ctx_device(ctx):
 
 def mwns_ctx_create(device=0, use_torch=True, byte_budget=0):
     return Context(device, use_torch, byte_budget)
+
+
+def mwns_abi_version():
+    """The version of the C interface and of the array layouts it exports."""
+    return int(lib.mwns_abi_version())
 
 
 def mwns_num_variants():

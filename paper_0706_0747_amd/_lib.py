@@ -62,6 +62,7 @@ SIGNATURES = {
     "mwns_ctx_bytes_cached": (c_size, [c_vp]),
     "mwns_ctx_release_cache": (c_int, [c_vp]),
     "mwns_last_error": (ctypes.c_char_p, []),
+    "mwns_abi_version": (c_int, []),
     "mwns_num_variants": (c_int, []),
     "mwns_num_variants_for": (c_int, [c_int]),
     "mwns_variant_shape": (c_int, [c_int, P(c_int), P(c_int), P(c_int), P(c_int)]),

@@ -272,6 +272,7 @@ using namespace mwns;
 extern "C" {
 
 const char* mwns_last_error(void) { return g_last_error.c_str(); }
+int mwns_abi_version(void) { return MWNS_ABI_VERSION; }
 
 mwns_status mwns_ctx_create(int device, void* stream, mwns_alloc_fn alloc, mwns_free_fn free_fn, void* user,
                             size_t byte_budget, mwns_ctx** out) {

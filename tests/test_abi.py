@@ -24,6 +24,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(M.lib, n), n
 
 
+def test_abi_version_matches_the_header():
+    """The library reports the interface version the header defines."""
+    import paper_0706_0747_amd as M
+    src = open(os.path.join(ROOT, "include", "mwns.h")).read()
+    want = int(re.search(r"#define MWNS_ABI_VERSION (\d+)", src).group(1))
+    assert M.mwns_abi_version() == want
+
+
 def test_binding_names_match_the_abi():
     import paper_0706_0747_amd as M
     for n in ["mwns_fit_kernel", "mwns_op_create", "mwns_project_gaussians", "mwns_apply", "mwns_tree_eval",
